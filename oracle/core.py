@@ -1,0 +1,138 @@
+"""ctypes front end of the C oracle (test infrastructure only)."""
+import ctypes
+import os
+
+import numpy as np
+
+from .build import LIB, SRC, build
+
+_lib = None
+
+# Same 84-byte record layout as the input generator's view dtype.
+VIEW_FIELDS = [("width", "<i4"), ("height", "<i4"),
+               ("o0", "<i4", 3), ("o_px", "<i4", 3), ("o_py", "<i4", 3),
+               ("d0", "<i4", 3), ("d_px", "<i4", 3), ("d_py", "<i4", 3),
+               ("flags", "<u4")]
+VIEW_DT = np.dtype(VIEW_FIELDS)
+MISS = 0xFFFFFFFF
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        L = ctypes.CDLL(LIB)
+        p = ctypes.c_void_p
+        L.or_render_rows.restype = ctypes.c_int64
+        L.or_render_rows.argtypes = [ctypes.c_int32, ctypes.c_int32, p, p, p,
+                                     p, ctypes.c_int, ctypes.c_int32,
+                                     ctypes.c_int32, ctypes.c_int32, p, p,
+                                     ctypes.c_int]
+        L.or_cast_list.restype = None
+        L.or_cast_list.argtypes = [ctypes.c_int32, ctypes.c_int32, p, p, p, p,
+                                   p, ctypes.c_int64, p, p]
+        L.or_cast_list_exact.restype = None
+        L.or_cast_list_exact.argtypes = [ctypes.c_int32, ctypes.c_int32, p, p,
+                                         p, p, p, ctypes.c_int64, p, p, p, p]
+        L.or_cast_pixels.restype = None
+        L.or_cast_pixels.argtypes = [ctypes.c_int32, ctypes.c_int32, p, p, p,
+                                     p, p, p, p, ctypes.c_int64, p, p]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _map(F, B, T):
+    F = np.ascontiguousarray(F, np.uint8)
+    B = np.ascontiguousarray(B, np.uint8)
+    T = np.ascontiguousarray(T, np.uint8)
+    assert F.shape == B.shape == T.shape and F.ndim == 2
+    return F, B, T
+
+
+def _views(views):
+    v = np.ascontiguousarray(np.asarray(views).astype(VIEW_DT))
+    return v.reshape(-1)
+
+
+def render(F, B, T, views, threads=None, rows=None):
+    """Hit records of every pixel of every view, views concatenated, rows
+    top-down.  Returns (word uint32[n], depth float64[n]).  `rows` =
+    (row0, row1, step) restricts the rows cast in each view."""
+    F, B, T = _map(F, B, T)
+    v = _views(views)
+    H, W = F.shape
+    r0, r1, st = rows if rows is not None else (0, 1 << 30, 1)
+    n = 0
+    for x in v:
+        hh = min(int(x["height"]), r1)
+        n += int(x["width"]) * len(range(r0, hh, st)) if hh > r0 else 0
+    word = np.empty(n, np.uint32)
+    depth = np.empty(n, np.float64)
+    th = threads if threads else (os.cpu_count() or 1)
+    got = lib().or_render_rows(W, H, _ptr(F), _ptr(B), _ptr(T), _ptr(v),
+                               len(v), r0, r1, st, _ptr(word), _ptr(depth), th)
+    if got != n:
+        raise RuntimeError("oracle render failed")
+    return word, depth
+
+
+def cast_rays(F, B, T, O, D):
+    """Cast explicit rays: O, D int64 arrays of shape (n, 3)."""
+    F, B, T = _map(F, B, T)
+    H, W = F.shape
+    O = np.ascontiguousarray(O, np.int64).reshape(-1, 3)
+    D = np.ascontiguousarray(D, np.int64).reshape(-1, 3)
+    n = O.shape[0]
+    word = np.empty(n, np.uint32)
+    depth = np.empty(n, np.float64)
+    lib().or_cast_list(W, H, _ptr(F), _ptr(B), _ptr(T), _ptr(O), _ptr(D), n,
+                       _ptr(word), _ptr(depth))
+    return word, depth
+
+
+def cast_rays_exact(F, B, T, O, D):
+    """Like cast_rays, also returning the exact hit time numerator and
+    denominator (tn = -1 on a miss)."""
+    F, B, T = _map(F, B, T)
+    H, W = F.shape
+    O = np.ascontiguousarray(O, np.int64).reshape(-1, 3)
+    D = np.ascontiguousarray(D, np.int64).reshape(-1, 3)
+    n = O.shape[0]
+    word = np.empty(n, np.uint32)
+    depth = np.empty(n, np.float64)
+    tn = np.empty(n, np.int64)
+    td = np.empty(n, np.int64)
+    lib().or_cast_list_exact(W, H, _ptr(F), _ptr(B), _ptr(T), _ptr(O), _ptr(D),
+                             n, _ptr(word), _ptr(depth), _ptr(tn), _ptr(td))
+    return word, depth, tn, td
+
+
+def cast_pixels(F, B, T, views, vi, px, py):
+    """Cast selected pixels (view index, column, row) of a list of views."""
+    F, B, T = _map(F, B, T)
+    H, W = F.shape
+    v = _views(views)
+    vi = np.ascontiguousarray(vi, np.int32)
+    px = np.ascontiguousarray(px, np.int32)
+    py = np.ascontiguousarray(py, np.int32)
+    n = vi.size
+    word = np.empty(n, np.uint32)
+    depth = np.empty(n, np.float64)
+    lib().or_cast_pixels(W, H, _ptr(F), _ptr(B), _ptr(T), _ptr(v), _ptr(vi),
+                         _ptr(px), _ptr(py), n, _ptr(word), _ptr(depth))
+    return word, depth
+
+
+def decode(word):
+    """Split hit words into (cell, face, layer, miss) arrays."""
+    word = np.asarray(word, np.uint32)
+    miss = word == MISS
+    cell = (word & 0x07FFFFFF).astype(np.int64)
+    face = ((word >> 27) & 7).astype(np.int32)
+    layer = ((word >> 30) & 1).astype(np.int32)
+    return cell, face, layer, miss

@@ -1,0 +1,49 @@
+"""Definition of the per-layer min/max pyramid (test infrastructure).
+
+The acceleration structure is the maximum-mipmap idea that Section 1.1
+cites, extended to the two intervals of a column.  Level L >= 1 has one node
+per 2^L x 2^L block of cells (blocks clipped to the map).  A node stores
+  fmax = max F over the block,
+  smin = min B over the block's two-layer cells (255 when there are none),
+  smax = max T over the block's two-layer cells (0 when there are none),
+packed as fmax | smin << 8 | smax << 16 (uint32), row-major [y][x].
+"""
+import numpy as np
+
+
+def pyramid_level(F, B, T, L):
+    H, W = F.shape
+    n = 1 << L
+    HL = (H + n - 1) // n
+    WL = (W + n - 1) // n
+    out = np.zeros((HL, WL), np.uint32)
+    for j in range(HL):
+        for i in range(WL):
+            f = F[j * n:(j + 1) * n, i * n:(i + 1) * n]
+            b = B[j * n:(j + 1) * n, i * n:(i + 1) * n]
+            t = T[j * n:(j + 1) * n, i * n:(i + 1) * n]
+            two = b > 0
+            fmax = int(f.max())
+            smin = int(b[two].min()) if two.any() else 255
+            smax = int(t[two].max()) if two.any() else 0
+            out[j, i] = fmax | (smin << 8) | (smax << 16)
+    return out
+
+
+def pyramid_level_fast(F, B, T, L):
+    """Same result as pyramid_level via padded reshapes (for large maps)."""
+    H, W = F.shape
+    n = 1 << L
+    HL = (H + n - 1) // n
+    WL = (W + n - 1) // n
+    pad = ((0, HL * n - H), (0, WL * n - W))
+    f = np.pad(F, pad, constant_values=0).reshape(HL, n, WL, n)
+    two = B > 0
+    b = np.pad(np.where(two, B, 255).astype(np.uint8), pad,
+               constant_values=255).reshape(HL, n, WL, n)
+    t = np.pad(np.where(two, T, 0).astype(np.uint8), pad,
+               constant_values=0).reshape(HL, n, WL, n)
+    fmax = f.max(axis=(1, 3)).astype(np.uint32)
+    smin = b.min(axis=(1, 3)).astype(np.uint32)
+    smax = t.max(axis=(1, 3)).astype(np.uint32)
+    return fmax | (smin << 8) | (smax << 16)

@@ -1,0 +1,89 @@
+"""Pins of the oracle's edit semantics and pyramid definition."""
+import json
+import os
+
+import numpy as np
+
+import oracle
+import synth
+
+
+def test_crater_hand_case(golden_dir):
+    g = json.load(open(os.path.join(golden_dir, "crater_s4_d40.json")))
+    W, H = g["W"], g["H"]
+    F = np.full((H, W), g["F0"], np.uint8)
+    B = np.full((H, W), g["B0"], np.uint8)
+    T = np.full((H, W), g["T0"], np.uint8)
+    F2, B2, T2 = oracle.apply_edits(F, B, T, [g["edit"]])
+    assert np.array_equal(F2, np.array(g["F"], np.uint8))
+    assert np.array_equal(B2, np.array(g["B"], np.uint8))
+    assert np.array_equal(T2, np.where(B2 > 0, g["T0"], 0).astype(np.uint8))
+    assert oracle.valid_columns(F2, B2, T2)
+
+
+def test_crater_saturates_at_zero_and_clips():
+    F = np.full((10, 10), 5, np.uint8)
+    Z = np.zeros_like(F)
+    F2, B2, T2 = oracle.apply_edits(F, Z, Z, [dict(kind=2, x0=-3, y0=7, w=8, h=8, depth=255)])
+    assert F2.min() == 0
+    # nothing outside the clipped patch changes
+    assert np.all(F2[:7, :] == 5) and np.all(F2[:, 5:] == 5)
+
+
+def test_set_patch_clipped_and_ordered():
+    F = np.full((8, 8), 10, np.uint8)
+    Z = np.zeros_like(F)
+    p = dict(kind=1, x0=6, y0=-1, w=4, h=3, depth=0,
+             F=np.full((3, 4), 50, np.uint8), B=np.full((3, 4), 60, np.uint8),
+             T=np.full((3, 4), 70, np.uint8))
+    c = dict(kind=2, x0=5, y0=0, w=4, h=4, depth=100)
+    Fa, Ba, Ta = oracle.apply_edits(F, Z, Z, [p, c])
+    Fb, Bb, Tb = oracle.apply_edits(F, Z, Z, [c, p])
+    # the SET rectangle covers x 6..7, y 0..1 only
+    assert np.all(Fb[0:2, 6:8] == 50) and np.all(Bb[0:2, 6:8] == 60)
+    assert Fb[2, 6] != 50
+    # order matters where they overlap
+    assert not np.array_equal(Fa, Fb) or not np.array_equal(Ba, Bb)
+    assert oracle.valid_columns(Fa, Ba, Ta) and oracle.valid_columns(Fb, Bb, Tb)
+
+
+def test_pyramid_hand_case():
+    F = np.array([[1, 2, 3, 4, 5],
+                  [6, 7, 8, 9, 10],
+                  [0, 0, 0, 0, 0]], np.uint8)
+    B = np.zeros_like(F)
+    T = np.zeros_like(F)
+    B[0, 1], T[0, 1] = 20, 25
+    B[1, 4], T[1, 4] = 30, 31
+    B[2, 2], T[2, 2] = 9, 40
+    p1 = oracle.pyramid_level(F, B, T, 1)
+    assert p1.shape == (2, 3)
+    node = lambda f, lo, hi: f | (lo << 8) | (hi << 16)
+    assert p1[0, 0] == node(7, 20, 25)
+    assert p1[0, 1] == node(9, 255, 0)
+    assert p1[0, 2] == node(10, 30, 31)
+    assert p1[1, 1] == node(0, 9, 40)
+    assert p1[1, 2] == node(0, 255, 0)
+    p2 = oracle.pyramid_level(F, B, T, 2)
+    assert p2.shape == (1, 2)
+    assert p2[0, 0] == node(9, 9, 40)
+    assert p2[0, 1] == node(10, 30, 31)
+    p3 = oracle.pyramid_level(F, B, T, 3)
+    assert p3[0, 0] == node(10, 9, 40)
+
+
+def test_pyramid_two_definitions_agree():
+    for seed, (W, H) in enumerate([(37, 23), (64, 64), (5, 130), (1, 1)]):
+        F, B, T = synth.make_map(W, H, 500 + seed, dual=0.3, period=8)
+        L = 0
+        while (1 << L) < max(W, H):
+            L += 1
+            assert np.array_equal(oracle.pyramid_level(F, B, T, L),
+                                  oracle.pyramid_level_fast(F, B, T, L))
+
+
+def test_synthetic_edits_keep_invariants():
+    F, B, T = synth.make_map_from_config(1)
+    eds = synth.crater_list(1, 256, 256, 10) + synth.random_set_patches(2, 256, 256, 10)
+    F2, B2, T2 = oracle.apply_edits(F, B, T, eds)
+    assert oracle.valid_columns(F2, B2, T2)

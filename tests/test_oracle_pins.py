@@ -1,0 +1,325 @@
+"""Pins of the CPU oracle against facts fixed independently of it:
+hand-worked cases, brute force over every solid box in exact rationals,
+closed forms, invariants, and the camera pitfalls the paper reports."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import bruteforce as bf
+import synth
+
+S = 65536
+
+
+def _decode(w):
+    c, f, l, m = oracle.decode(np.array([w], np.uint32))
+    return int(c[0]), int(f[0]), int(l[0]), bool(m[0])
+
+
+def test_hand_cases(golden_dir):
+    cases = json.load(open(os.path.join(golden_dir, "hand_cases.json")))["cases"]
+    assert len(cases) >= 12
+    for c in cases:
+        F = np.array(c["F"], np.uint8)
+        B = np.array(c["B"], np.uint8)
+        T = np.array(c["T"], np.uint8)
+        O = [int(round(v * S)) for v in c["O"]]
+        w, d = oracle.cast_rays(F, B, T, [O], [c["D"]])
+        cell, face, layer, miss = _decode(w[0])
+        if c["expect"] == "miss":
+            assert miss, c["name"]
+            assert math.isinf(d[0])
+            continue
+        x, y, ef, el, ed = c["expect"]
+        W = F.shape[1]
+        assert not miss, c["name"]
+        assert (cell % W, cell // W, face, layer) == (x, y, ef, el), c["name"]
+        assert d[0] == pytest.approx(ed, rel=1e-12, abs=1e-12), c["name"]
+
+
+def _random_map(rng, W, H, hmax=24):
+    F = rng.integers(0, hmax, (H, W)).astype(np.uint8)
+    two = rng.random((H, W)) < 0.45
+    B = np.where(two, F.astype(int) + rng.integers(1, 8, (H, W)), 0)
+    T = np.where(two, B + rng.integers(0, 6, (H, W)), 0)
+    return F, B.astype(np.uint8), T.astype(np.uint8)
+
+
+def _adversarial_rays(rng, W, H, n):
+    O, D = [], []
+    for k in range(n):
+        kind = k % 8
+        ox = int(rng.integers(-S, (W + 1) * S))
+        oy = int(rng.integers(-S, (H + 1) * S))
+        oz = int(rng.integers(0, 32 * S))
+        d = [int(v) for v in rng.integers(-2000, 2001, 3)]
+        if kind == 1:      # origin on a lattice corner, 45 degree diagonal
+            ox, oy = int(rng.integers(0, W + 1)) * S, int(rng.integers(0, H + 1)) * S
+            s = int(rng.integers(1, 50))
+            d = [s * int(rng.choice([-1, 1])), s * int(rng.choice([-1, 1])), d[2]]
+        elif kind == 2:    # axis aligned in x or y
+            if rng.random() < 0.5:
+                d[1] = 0
+            else:
+                d[0] = 0
+        elif kind == 3:    # vertical
+            d[0] = d[1] = 0
+        elif kind == 4:    # horizontal at integer height
+            d[2] = 0
+            oz = int(rng.integers(0, 30)) * S
+        elif kind == 5:    # origin on a cell edge, running along it
+            ox = int(rng.integers(0, W + 1)) * S
+            d[0] = 0
+        elif kind == 6:    # through lattice corners with a rational slope
+            ox, oy = int(rng.integers(0, W)) * S + S // 2, int(rng.integers(0, H)) * S + S // 2
+            a, b = int(rng.integers(1, 4)), int(rng.integers(1, 4))
+            d = [a * 64 * int(rng.choice([-1, 1])), b * 64 * int(rng.choice([-1, 1])), d[2]]
+        elif kind == 7:    # integer heights at the origin and slopes hitting tops exactly
+            oz = int(rng.integers(0, 30)) * S
+        O.append([ox, oy, oz])
+        D.append(d)
+    return np.array(O, np.int64), np.array(D, np.int64)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_bruteforce_random_and_adversarial(seed):
+    rng = np.random.default_rng(100 + seed)
+    n_rays = 0
+    for trial in range(40):
+        W, H = int(rng.integers(1, 9)), int(rng.integers(1, 9))
+        F, B, T = _random_map(rng, W, H)
+        O, D = _adversarial_rays(rng, W, H, 40)
+        w, d, tn, td = oracle.cast_rays_exact(F, B, T, O, D)
+        Fl, Bl, Tl = F.tolist(), B.tolist(), T.tolist()
+        for i in range(len(O)):
+            msg = bf.check_ray(Fl, Bl, Tl, tuple(int(v) for v in O[i]),
+                               tuple(int(v) for v in D[i]), int(w[i]),
+                               int(tn[i]), int(td[i]))
+            assert msg is None, (msg, F, B, T, O[i], D[i])
+            n_rays += 1
+    assert n_rays == 1600
+
+
+def test_bruteforce_larger_maps():
+    rng = np.random.default_rng(7)
+    for trial in range(6):
+        W, H = 16, 16
+        F, B, T = _random_map(rng, W, H, hmax=40)
+        O, D = _adversarial_rays(rng, W, H, 30)
+        w, d, tn, td = oracle.cast_rays_exact(F, B, T, O, D)
+        for i in range(len(O)):
+            msg = bf.check_ray(F.tolist(), B.tolist(), T.tolist(),
+                               tuple(int(v) for v in O[i]),
+                               tuple(int(v) for v in D[i]), int(w[i]),
+                               int(tn[i]), int(td[i]))
+            assert msg is None, (msg, O[i], D[i])
+
+
+def test_bruteforce_catches_planted_mistakes():
+    """The brute-force checker must reject wrong answers of each kind."""
+    F = np.array([[0, 5, 0]], np.uint8)
+    B = np.zeros_like(F)
+    T = np.zeros_like(F)
+    O = (S // 2, S // 2, 3 * S)
+    D = (1000, 0, 0)
+    good = 1 | (3 << 27)
+    assert bf.check_ray(F.tolist(), B.tolist(), T.tolist(), O, D, good, S // 2, 1000) is None
+    # wrong cell, wrong face, wrong layer, late time, a miss
+    assert bf.check_ray(F.tolist(), B.tolist(), T.tolist(), O, D, 2 | (3 << 27), S // 2, 1000)
+    assert bf.check_ray(F.tolist(), B.tolist(), T.tolist(), O, D, 1 | (1 << 27), S // 2, 1000)
+    assert bf.check_ray(F.tolist(), B.tolist(), T.tolist(), O, D, 1 | (3 << 27) | (1 << 30), S // 2, 1000)
+    assert bf.check_ray(F.tolist(), B.tolist(), T.tolist(), O, D, good, S, 1000)
+    assert bf.check_ray(F.tolist(), B.tolist(), T.tolist(), O, D, 0xFFFFFFFF, -1, 1)
+
+
+def _exact_floor_cell(o, d, t_num, t_den):
+    """Cell along one axis containing the hit point, from the side the ray
+    arrives from; t = t_num / t_den."""
+    num = o * t_den + t_num * d        # coordinate * t_den, S units
+    den = S * t_den
+    q, r = divmod(num, den)
+    if r == 0 and d > 0:
+        return q - 1
+    return q
+
+
+def test_flat_floor_closed_form():
+    """Flat floor of height h, no slabs: a descending ray hits the plane at
+    t = (Oz - hS)/|Dz| in the cell it reaches the plane from; others miss."""
+    W = H = 40
+    h = 17
+    F = np.full((H, W), h, np.uint8)
+    Z = np.zeros_like(F)
+    views = [synth.perspective_view((20.3, 3.7, h + 9.0), 12, -25, 64, 48),
+             synth.perspective_view((5.5, 5.5, h + 30.0), 225, -60, 33, 29),
+             synth.perspective_view((20.0, 20.0, h + 4.0), 90, 3, 40, 30)]
+    word, depth = oracle.render(F, Z, Z, views)
+    k = 0
+    for v in views:
+        for py in range(int(v["height"])):
+            for px in range(int(v["width"])):
+                a, b = 2 * px + 1, 2 * py + 1
+                O = [int(v["o0"][c]) + a * int(v["o_px"][c]) + b * int(v["o_py"][c]) for c in range(3)]
+                D = [int(v["d0"][c]) + a * int(v["d_px"][c]) + b * int(v["d_py"][c]) for c in range(3)]
+                exp = None
+                if D[2] < 0:
+                    tn, td = O[2] - h * S, -D[2]
+                    x = _exact_floor_cell(O[0], D[0], tn, td)
+                    y = _exact_floor_cell(O[1], D[1], tn, td)
+                    if 0 <= x < W and 0 <= y < H:
+                        exp = (y * W + x, tn / td * math.sqrt(sum(c * c for c in D)) / S)
+                w = int(word[k])
+                if exp is None:
+                    assert w == oracle.MISS, (px, py)
+                else:
+                    assert w == exp[0] | (1 << 27), (px, py, hex(w), exp)
+                    assert depth[k] == pytest.approx(exp[1], rel=1e-12)
+                k += 1
+
+
+def test_straight_down_ortho_image():
+    """Rays from z = 256 straight down over every cell centre hit the
+    column's topmost solid (T if it has a slab, else F) through its top, at
+    depth 256 - height exactly."""
+    F, B, T = synth.make_map(96, 80, 12345, dual=0.3, period=32)
+    H, W = F.shape
+    v = synth.ortho_view((0, 0, 256 * S), (S // 2, 0, 0), (0, S // 2, 0),
+                         (0, 0, -1), W, H)
+    word, depth = oracle.render(F, B, T, [v])
+    top = np.where(B > 0, T, F).astype(np.int64).reshape(-1)
+    layer = (B > 0).astype(np.uint32).reshape(-1)
+    exp = np.arange(W * H, dtype=np.uint32) | (1 << 27) | (layer << 30)
+    assert np.array_equal(word, exp)
+    assert np.array_equal(depth, (256 - top).astype(np.float64))
+
+
+def test_horizontal_axis_rays_reduce_to_scan():
+    """A horizontal ray along +x at height z (non-integer) through row y hits
+    the first column at or after the start whose solid set contains z."""
+    F, B, T = synth.make_map(64, 8, 99, dual=0.4, period=16)
+    H, W = F.shape
+    rng = np.random.default_rng(3)
+    O, D, exp = [], [], []
+    for _ in range(300):
+        y = int(rng.integers(0, H))
+        x0 = int(rng.integers(0, W))
+        z = int(rng.integers(0, 255)) + 0.5
+        O.append([x0 * S + S // 2, y * S + S // 2, int(z * S)])
+        D.append([int(rng.integers(1, 5000)), 0, 0])
+        hit = None
+        for x in range(x0, W):
+            f, b, t = int(F[y, x]), int(B[y, x]), int(T[y, x])
+            if z <= f or (b > 0 and b <= z <= t):
+                hit = (x, 0 if z <= f else 1, 7 if x == x0 else 3, x - x0 - 0.5 if x > x0 else 0.0)
+                break
+        exp.append(hit)
+    w, d = oracle.cast_rays(F, B, T, O, D)
+    for i, e in enumerate(exp):
+        cell, face, layer, miss = _decode(w[i])
+        if e is None:
+            assert miss
+        else:
+            y = O[i][1] // S
+            assert (cell, layer, face) == (y * W + e[0], e[1], e[2])
+            assert d[i] == pytest.approx(e[3], abs=1e-12)
+
+
+def test_translation_invariance_non_descending():
+    """Embedding the map at an integer offset inside a larger map of
+    height-0 floors and shifting the origin by the same offset leaves every
+    non-descending ray's hit unchanged (the added cells are never solid for
+    a ray that stays above z = 0)."""
+    rng = np.random.default_rng(11)
+    F, B, T = synth.make_map(48, 40, 77, dual=0.3, period=16)
+    H, W = F.shape
+    kx, ky = 13, 7
+    F2 = np.zeros((H + 20, W + 30), np.uint8)
+    B2 = np.zeros_like(F2)
+    T2 = np.zeros_like(F2)
+    F2[ky:ky + H, kx:kx + W] = F
+    B2[ky:ky + H, kx:kx + W] = B
+    T2[ky:ky + H, kx:kx + W] = T
+    n = 2000
+    O = np.stack([rng.integers(0, W * S, n), rng.integers(0, H * S, n),
+                  rng.integers(1, 260 * S, n)], 1)
+    D = rng.integers(-3000, 3001, (n, 3))
+    D[:, 2] = np.abs(D[:, 2])
+    O2 = O + np.array([kx * S, ky * S, 0])
+    w1, d1 = oracle.cast_rays(F, B, T, O, D)
+    w2, d2 = oracle.cast_rays(F2, B2, T2, O2, D)
+    c1, f1, l1, m1 = oracle.decode(w1)
+    c2, f2, l2, m2 = oracle.decode(w2)
+    assert np.array_equal(m1, m2)
+    h = ~m1
+    assert np.array_equal((c1 % W + kx)[h], (c2 % (W + 30))[h])
+    assert np.array_equal((c1 // W + ky)[h], (c2 // (W + 30))[h])
+    assert np.array_equal(f1[h], f2[h]) and np.array_equal(l1[h], l2[h])
+    assert np.array_equal(d1, d2)
+
+
+def test_camera_focal_length_in_pixels():
+    """Section 4.1: the reference scaled its focal length by the render
+    height; the vertical field of view must be 60 degrees at every
+    resolution.  The angle between the rays through the centres of the top
+    and bottom rows is 2 atan((H-1)/2 / f) with f = (H/2) / tan 30deg."""
+    for (w, h) in [(320, 240), (640, 480), (1920, 1080), (3840, 2160), (64, 16)]:
+        v = synth.perspective_view((10.5, 10.5, 50.0), 0, 0, w, h)
+        px = w // 2
+        rays = []
+        for py in (0, h - 1):
+            a, b = 2 * px + 1, 2 * py + 1
+            rays.append(np.array([int(v["d0"][c]) + a * int(v["d_px"][c]) + b * int(v["d_py"][c])
+                                  for c in range(3)], float))
+        cosang = rays[0] @ rays[1] / np.linalg.norm(rays[0]) / np.linalg.norm(rays[1])
+        ang = math.degrees(math.acos(min(1.0, cosang)))
+        f = (h / 2) / math.tan(math.radians(30))
+        expect = 2 * math.degrees(math.atan(((h - 1) / 2) / f))
+        # integer quantisation of the pixel step costs < 0.1 deg; the bug
+        # this guards against is a factor of several in field of view
+        assert abs(ang - expect) < 0.1, (w, h, ang, expect)
+
+
+def test_camera_screen_x_basis():
+    """Section 5.6: the screen-X basis.  A camera turned toward +x sees the
+    +y side of the world on the left half of the image."""
+    v = synth.perspective_view((50.5, 50.5, 20.0), 90, 0, 100, 50)
+    a, b = 1, 51
+    left = int(v["d0"][1]) + a * int(v["d_px"][1]) + b * int(v["d_py"][1])
+    a = 199
+    right = int(v["d0"][1]) + a * int(v["d_px"][1]) + b * int(v["d_py"][1])
+    assert left > 0 > right
+    assert int(v["d0"][0]) + 101 * int(v["d_px"][0]) > 0   # looks along +x
+
+
+def test_zero_height_floors_all_hit():
+    """Section 4.1: sea level is a real height; straight-down rays over a
+    map of height-0 floors must all hit."""
+    F = np.zeros((30, 30), np.uint8)
+    v = synth.ortho_view((0, 0, 10 * S), (S // 2, 0, 0), (0, S // 2, 0), (1, 2, -5), 30, 30)
+    word, depth = oracle.render(F, F, F, [v])
+    cell, face, layer, miss = oracle.decode(word)
+    # rays that reach z = 0 before leaving the map hit the floor top
+    assert (~miss).sum() > 0.5 * word.size
+    assert np.all(face[~miss] == 1)
+
+
+def test_zero_direction_misses():
+    F = np.full((4, 4), 3, np.uint8)
+    w, d = oracle.cast_rays(F, F * 0, F * 0, [[S, S, 10 * S]], [[0, 0, 0]])
+    assert w[0] == oracle.MISS and math.isinf(d[0])
+
+
+def test_render_rows_matches_single_rays():
+    F, B, T = synth.make_map(64, 64, 5, dual=0.2, period=16)
+    v = synth.perspective_view(synth.eye_above_floor(F, B, 30.5, 10.5), 10, -5, 37, 23)
+    word, depth = oracle.render(F, B, T, [v], threads=3)
+    py, px = np.divmod(np.arange(37 * 23), 37)
+    w2, d2 = oracle.cast_pixels(F, B, T, [v], np.zeros(37 * 23, np.int32), px, py)
+    assert np.array_equal(word, w2) and np.array_equal(depth, d2)
+    w3, d3 = oracle.render(F, B, T, [v], rows=(3, 23, 5))
+    rows = list(range(3, 23, 5))
+    assert np.array_equal(w3, word.reshape(23, 37)[rows].reshape(-1))

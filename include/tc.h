@@ -1,0 +1,217 @@
+/*
+ * tc -- ray casting of editable two-layer height-column terrain on MI355X.
+ *
+ * C ABI of the library.  Plain pointers and sizes only.
+ *
+ * The problem (paper, Section 1: the three system constraints; Section 2:
+ * the data): a map of W x H columns, each holding a floor interval and, on
+ * some columns, an upper slab; every ray must find the first solid point it
+ * meets, and a bounded edit of heights and slab metadata must be visible on
+ * the next render without reloading or rebuilding the level.
+ *
+ * Geometry (the solid set is the paper's SOLID predicate, Section 3.1):
+ *   world x = east (map width W), y = north (map height H), z = up;
+ *   column (x, y) covers the closed square [x, x+1] x [y, y+1];
+ *   it is solid for z <= F (floor, unbounded below) and, when B > 0, for
+ *   B <= z <= T (upper slab).  Heights are integers 0..255.  Nothing is
+ *   solid outside the map.
+ *
+ * Rays use Q16 fixed-point origins (S = 65536 per cell) and integer
+ * directions.  The hit of a ray is the first point of the cell walk that
+ * starts in floor(O / S), tests each cell over the closed parameter interval
+ * the ray spends in it, and, when an x and a y boundary are crossed at the
+ * same instant, steps x first.  Results are bit-exact: the same integers in
+ * give the same hit word out, on any launch shape.
+ *
+ * Threading: a context is used by one host thread at a time.  Calls that
+ * take a stream enqueue work on it and return without waiting for the GPU
+ * unless stated otherwise; results are ready when the stream's work up to
+ * that point completes.  A stream argument of NULL is HIP's null stream.
+ *
+ * Errors: every call returns a tc_status.  On failure no work has been
+ * enqueued and the context state is unchanged (except where stated); the
+ * message is available from tc_last_error().  No call aborts or throws.
+ */
+#ifndef TC_H
+#define TC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tc_status;
+#define TC_OK 0
+#define TC_INVALID_ARG (-1)
+#define TC_OUT_OF_MEMORY (-2)
+#define TC_NO_MAP (-3)
+#define TC_DEVICE_ERROR (-4)
+#define TC_OVER_BUDGET (-5)
+
+#define TC_S 65536                 /* fixed-point cells per unit */
+#define TC_MAX_DIM 16384           /* max W and H */
+#define TC_MAX_CELLS (1 << 27)     /* max W * H */
+#define TC_MAX_DIR ((1 << 23) - 1) /* max |direction component| */
+
+/* Hit record (8 bytes).  word: bits 0-26 cell index y*W + x, bits 27-29
+ * face, bit 30 layer (0 floor, 1 slab).  A miss is word 0xFFFFFFFF with
+ * depth +inf.  depth is the Euclidean distance from the ray origin in world
+ * units (float); 0 for TC_FACE_INSIDE.  Misses keep the cleared far depth
+ * and hits carry the reconstructed depth (Section 3.1). */
+typedef struct tc_hit {
+  uint32_t word;
+  float depth;
+} tc_hit;
+
+#define TC_MISS 0xFFFFFFFFu
+#define TC_FACE_TOP 1    /* +Z: floor top or slab top, ray descending */
+#define TC_FACE_UNDER 2  /* -Z: slab underside, ray ascending */
+#define TC_FACE_WMX 3    /* wall facing -X, ray moving +x */
+#define TC_FACE_WPX 4    /* wall facing +X, ray moving -x */
+#define TC_FACE_WMY 5    /* wall facing -Y, ray moving +y */
+#define TC_FACE_WPY 6    /* wall facing +Y, ray moving -y */
+#define TC_FACE_INSIDE 7 /* ray origin inside solid */
+
+/* A view: width x height pixels, rows top-down.  Pixel (px, py) casts
+ *   O = o0 + (2px+1) o_px + (2py+1) o_py     (Q16 fixed point)
+ *   D = d0 + (2px+1) d_px + (2py+1) d_py     (integers)
+ * in 64-bit arithmetic.  A pinhole camera has o_px = o_py = 0; an
+ * orthographic pass (e.g. a directional shadow pass) has d_px = d_py = 0.
+ * Every pixel's O must fit in int32 and every |D_c| must be <= TC_MAX_DIR
+ * (both are linear in px, py, so the library checks the four corners).
+ * flags must be 0. */
+typedef struct tc_view {
+  int32_t width, height;
+  int32_t o0[3], o_px[3], o_py[3];
+  int32_t d0[3], d_px[3], d_py[3];
+  uint32_t flags;
+} tc_view;
+
+/* An edit (Section 2: the renderer receives a dirty rectangle and the
+ * modified rows; Section 4.4: the dig operation removes altitude and the
+ * upper layer inside a crater).
+ *   TC_EDIT_SET:    overwrite [x0, x0+w) x [y0, y0+h) with the host patch
+ *                   floor_top / slab_bottom / slab_top (each w*h bytes,
+ *                   row-major, copied before tc_apply_edit returns).  The
+ *                   patch must satisfy the column invariants of
+ *                   tc_load_columns.  depth is ignored.
+ *   TC_EDIT_CRATER: w == h == s (1..4096), depth 0..255.  For patch cell
+ *                   (i, j): r2 = (2i+1-s)^2 + (2j+1-s)^2, R2 = s^2; if
+ *                   r2 < R2 the floor drops by floor(depth (R2-r2) / R2),
+ *                   saturating at 0, and the slab is removed.  Pointers are
+ *                   ignored.
+ * Rectangles may hang over the map edge; they are clipped. */
+#define TC_EDIT_SET 1
+#define TC_EDIT_CRATER 2
+typedef struct tc_edit {
+  int32_t kind;
+  int32_t x0, y0, w, h;
+  int32_t depth;
+  const uint8_t *floor_top, *slab_bottom, *slab_top;
+} tc_edit;
+
+typedef struct tc_context tc_context;
+
+/* Create a context on HIP device `hip_device`.  *out receives the handle.
+ * Errors: TC_INVALID_ARG (null out, bad device), TC_DEVICE_ERROR. */
+tc_status tc_create(int hip_device, tc_context **out);
+
+/* Destroy a context: waits for its outstanding work, then frees every
+ * device and pinned buffer it owns.  NULL is a no-op. */
+void tc_destroy(tc_context *ctx);
+
+/* Message of the last failed call on this context ("" if none).  Owned by
+ * the context, valid until the next call on it.  With a NULL context:
+ * the message of the last failed tc_create. */
+const char *tc_last_error(const tc_context *ctx);
+
+/* Load a map (Section 2: height and metadata arrays).  Host arrays,
+ * row-major with element (x, y) at y * row_stride + x (row_stride >= W),
+ * are copied before return; the caller keeps ownership.  Builds the packed
+ * tiled columns and the min/max pyramid on `hip_stream` and replaces any
+ * previous map.  Validation (TC_INVALID_ARG, state unchanged):
+ *   1 <= W, H <= TC_MAX_DIM, W * H <= TC_MAX_CELLS, non-null arrays, and per
+ *   cell  B == 0 => T == 0  and  B > 0 => B > F and T >= B. */
+tc_status tc_load_columns(tc_context *ctx, int32_t W, int32_t H,
+                          const uint8_t *floor_top, const uint8_t *slab_bottom,
+                          const uint8_t *slab_top, size_t row_stride,
+                          void *hip_stream);
+
+/* Apply n edits in array order (Section 2; Section 4.4), then update only
+ * the pyramid nodes over the edited rectangles.  Stream-ordered: every later
+ * render on the same stream sees the edits; the result is byte-identical to
+ * loading the edited map from scratch.  Validation of the whole list happens
+ * before anything is enqueued: kind, crater size and depth, SET pointers and
+ * patch invariants (TC_INVALID_ARG), n in 0..65536, a map must be loaded
+ * (TC_NO_MAP). */
+tc_status tc_apply_edit(tc_context *ctx, const tc_edit *edits, int32_t n,
+                        void *hip_stream);
+
+/* Render n views (Section 3.1: one ray per pixel) into out_device, a
+ * device buffer of sum(width*height) tc_hit records owned by the caller:
+ * views concatenated in order, each row-major with rows top-down.  No host
+ * synchronisation.  Errors before launch: TC_NO_MAP; TC_INVALID_ARG for
+ * n < 1, null pointers, a view with width or height < 1 or > 16384, flags
+ * != 0, |D| > TC_MAX_DIR or O outside int32 at a corner pixel, or more than
+ * 2^31 rays in total. */
+tc_status tc_render_views(tc_context *ctx, const tc_view *views, int32_t n,
+                          tc_hit *out_device, void *hip_stream);
+
+/* ---- options ---------------------------------------------------------- */
+/* Tuning knobs of the render path.  Each takes effect for later calls. */
+#define TC_OPT_RENDER_MODE 1   /* 0 hierarchical (default), 1 flat walk,
+                                  2 persistent packet queue */
+#define TC_OPT_START_LEVEL 2   /* pyramid level a ray starts at (default 0);
+                                  clamped to the top level */
+#define TC_OPT_MAX_LEVEL 3     /* highest level a ray ascends to (default
+                                  top level) */
+#define TC_OPT_XCD_REMAP 4     /* 1: group neighbouring screen tiles on one
+                                  XCD (default 1) */
+#define TC_OPT_PERSIST_WAVES 5 /* waves per CU of the persistent launch
+                                  (default 8) */
+#define TC_OPT_REFILL_MIN 6    /* persistent mode: idle lanes that trigger a
+                                  refill (1..64, default 16) */
+#define TC_OPT_REFILL_ITERS 7  /* persistent mode: traversal iterations
+                                  between refill checks (default 16) */
+#define TC_OPT_COUNT_READS 8   /* 1: renders add the number of pyramid nodes
+                                  and cells each ray reads to a context
+                                  counter (diagnostic; default 0) */
+tc_status tc_set_option(tc_context *ctx, int32_t key, int64_t value);
+tc_status tc_get_option(const tc_context *ctx, int32_t key, int64_t *value);
+
+/* ---- inspection (tests, checkpoints) ---------------------------------- */
+/* Copy the w x h rectangle at (x0, y0) of the current map into host arrays
+ * (row-major, w bytes per row).  Synchronises `hip_stream`.  The rectangle
+ * must lie inside the map. */
+tc_status tc_read_columns(tc_context *ctx, int32_t x0, int32_t y0, int32_t w,
+                          int32_t h, uint8_t *floor_top, uint8_t *slab_bottom,
+                          uint8_t *slab_top, void *hip_stream);
+
+/* Number of pyramid levels above the cells (level 1 .. tc_levels), and the
+ * node grid of a level: ceil(W / 2^L) x ceil(H / 2^L). */
+tc_status tc_pyramid_info(const tc_context *ctx, int32_t *levels);
+tc_status tc_pyramid_dims(const tc_context *ctx, int32_t level, int32_t *w,
+                          int32_t *h);
+
+/* Copy pyramid level L (1..levels) into host memory as row-major uint32
+ * nodes fmax | smin << 8 | smax << 16, where over the node's block of
+ * cells fmax = max F, smin = min B of two-layer cells (255 if none), smax =
+ * max T of two-layer cells (0 if none).  Synchronises `hip_stream`. */
+tc_status tc_read_pyramid(tc_context *ctx, int32_t level, uint32_t *out,
+                          void *hip_stream);
+
+/* Read and reset the counter of TC_OPT_COUNT_READS: the number of
+ * pyramid nodes and cells read by all rays rendered since the last reset.
+ * Synchronises `hip_stream`.  0 if counting was never enabled. */
+tc_status tc_read_counters(tc_context *ctx, uint64_t *reads, void *hip_stream);
+
+/* Device bytes held by the map: packed columns plus every pyramid level. */
+tc_status tc_map_bytes(const tc_context *ctx, uint64_t *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TC_H */

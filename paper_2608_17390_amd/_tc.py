@@ -1,0 +1,300 @@
+"""ctypes binding of libtc.so: the C ABI of include/tc.h, same names.
+
+Argument marshalling only: every step of the ray cast, the edits and the
+pyramid maintenance runs in the library's HIP kernels.  torch supplies
+device memory (tensor data pointers) and streams (their HIP handles).  If
+the library has not been built, importing the binding fails loudly; there
+is no other execution path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtc.so")
+
+TC_OK = 0
+TC_INVALID_ARG = -1
+TC_OUT_OF_MEMORY = -2
+TC_NO_MAP = -3
+TC_DEVICE_ERROR = -4
+TC_OVER_BUDGET = -5
+TC_S = 65536
+TC_MISS = 0xFFFFFFFF
+TC_EDIT_SET = 1
+TC_EDIT_CRATER = 2
+
+TC_OPT_RENDER_MODE = 1
+TC_OPT_START_LEVEL = 2
+TC_OPT_MAX_LEVEL = 3
+TC_OPT_XCD_REMAP = 4
+TC_OPT_PERSIST_WAVES = 5
+TC_OPT_REFILL_MIN = 6
+TC_OPT_REFILL_ITERS = 7
+TC_OPT_COUNT_READS = 8
+
+_STATUS = {0: "TC_OK", -1: "TC_INVALID_ARG", -2: "TC_OUT_OF_MEMORY",
+           -3: "TC_NO_MAP", -4: "TC_DEVICE_ERROR", -5: "TC_OVER_BUDGET"}
+
+
+class tc_view(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("o0", ctypes.c_int32 * 3), ("o_px", ctypes.c_int32 * 3),
+                ("o_py", ctypes.c_int32 * 3), ("d0", ctypes.c_int32 * 3),
+                ("d_px", ctypes.c_int32 * 3), ("d_py", ctypes.c_int32 * 3),
+                ("flags", ctypes.c_uint32)]
+
+
+class tc_edit(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("x0", ctypes.c_int32),
+                ("y0", ctypes.c_int32), ("w", ctypes.c_int32),
+                ("h", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("floor_top", ctypes.c_void_p), ("slab_bottom", ctypes.c_void_p),
+                ("slab_top", ctypes.c_void_p)]
+
+
+assert ctypes.sizeof(tc_view) == 84
+
+# (name, restype, argtypes) of every exported symbol of include/tc.h
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+SIGNATURES = [
+    ("tc_create", _I32, [ctypes.c_int, ctypes.POINTER(_P)]),
+    ("tc_destroy", None, [_P]),
+    ("tc_last_error", ctypes.c_char_p, [_P]),
+    ("tc_load_columns", _I32, [_P, _I32, _I32, _P, _P, _P, ctypes.c_size_t, _P]),
+    ("tc_apply_edit", _I32, [_P, ctypes.POINTER(tc_edit), _I32, _P]),
+    ("tc_render_views", _I32, [_P, ctypes.POINTER(tc_view), _I32, _P, _P]),
+    ("tc_set_option", _I32, [_P, _I32, ctypes.c_int64]),
+    ("tc_get_option", _I32, [_P, _I32, ctypes.POINTER(ctypes.c_int64)]),
+    ("tc_read_columns", _I32, [_P, _I32, _I32, _I32, _I32, _P, _P, _P, _P]),
+    ("tc_pyramid_info", _I32, [_P, ctypes.POINTER(_I32)]),
+    ("tc_pyramid_dims", _I32, [_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    ("tc_read_pyramid", _I32, [_P, _I32, _P, _P]),
+    ("tc_read_counters", _I32, [_P, ctypes.POINTER(ctypes.c_uint64), _P]),
+    ("tc_map_bytes", _I32, [_P, ctypes.POINTER(ctypes.c_uint64)]),
+]
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libtc.so (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(
+            "libtc.so is not built (%s); run `python -m paper_2608_17390_amd.build`"
+            % path)
+    try:
+        import torch  # noqa: F401  -- load torch's HIP runtime first
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(path)
+    for name, res, args in SIGNATURES:
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+class TCError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (_STATUS.get(status, status), msg))
+        self.status = status
+
+
+def _check(ctx, st):
+    if st != TC_OK:
+        msg = load_library().tc_last_error(ctx)
+        raise TCError(st, msg.decode() if msg else "")
+
+
+def _stream_handle(stream):
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        except ImportError:
+            pass
+        return ctypes.c_void_p(0)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _views_struct(views):
+    from numpy.lib import recfunctions  # noqa: F401
+    a = np.asarray(views)
+    a = a.reshape(-1)
+    arr = (tc_view * len(a))()
+    for i, v in enumerate(a):
+        t = arr[i]
+        t.width = int(v["width"])
+        t.height = int(v["height"])
+        for f in ("o0", "o_px", "o_py", "d0", "d_px", "d_py"):
+            src = v[f]
+            dst = getattr(t, f)
+            for c in range(3):
+                dst[c] = int(src[c])
+        t.flags = int(v["flags"])
+    return arr
+
+
+def _edits_struct(edits):
+    arr = (tc_edit * max(1, len(edits)))()
+    keep = []
+    for i, e in enumerate(edits):
+        t = arr[i]
+        t.kind = int(e["kind"])
+        t.x0 = int(e["x0"])
+        t.y0 = int(e["y0"])
+        t.w = int(e["w"])
+        t.h = int(e["h"])
+        t.depth = int(e.get("depth", 0))
+        if t.kind == TC_EDIT_SET:
+            planes = [np.ascontiguousarray(e[k], np.uint8) for k in ("F", "B", "T")]
+            keep.extend(planes)
+            t.floor_top = planes[0].ctypes.data
+            t.slab_bottom = planes[1].ctypes.data
+            t.slab_top = planes[2].ctypes.data
+    return arr, keep
+
+
+class Context:
+    """One library context on one HIP device."""
+
+    def __init__(self, device=0):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        st = lib.tc_create(int(device), ctypes.byref(h))
+        if st != TC_OK:
+            raise TCError(st, lib.tc_last_error(None).decode())
+        self._h = h
+        self.W = self.H = 0
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            load_library().tc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- C ABI calls ------------------------------------------------------
+    def tc_load_columns(self, F, B, T, stream=None):
+        F = np.ascontiguousarray(F, np.uint8)
+        B = np.ascontiguousarray(B, np.uint8)
+        T = np.ascontiguousarray(T, np.uint8)
+        H, W = F.shape
+        st = load_library().tc_load_columns(
+            self._h, W, H, F.ctypes.data, B.ctypes.data, T.ctypes.data, W,
+            _stream_handle(stream))
+        _check(self._h, st)
+        self.W, self.H = W, H
+
+    def tc_apply_edit(self, edits, stream=None):
+        arr, keep = _edits_struct(list(edits))
+        st = load_library().tc_apply_edit(self._h, arr, len(edits),
+                                          _stream_handle(stream))
+        del keep
+        _check(self._h, st)
+
+    def tc_render_views(self, views, out_ptr, stream=None):
+        arr = _views_struct(views)
+        st = load_library().tc_render_views(self._h, arr, len(arr),
+                                            ctypes.c_void_p(int(out_ptr)),
+                                            _stream_handle(stream))
+        _check(self._h, st)
+
+    def tc_set_option(self, key, value):
+        _check(self._h, load_library().tc_set_option(self._h, int(key), int(value)))
+
+    def tc_get_option(self, key):
+        v = ctypes.c_int64()
+        _check(self._h, load_library().tc_get_option(self._h, int(key), ctypes.byref(v)))
+        return v.value
+
+    def tc_read_columns(self, x0, y0, w, h, stream=None):
+        F = np.empty((h, w), np.uint8)
+        B = np.empty((h, w), np.uint8)
+        T = np.empty((h, w), np.uint8)
+        st = load_library().tc_read_columns(self._h, x0, y0, w, h, F.ctypes.data,
+                                            B.ctypes.data, T.ctypes.data,
+                                            _stream_handle(stream))
+        _check(self._h, st)
+        return F, B, T
+
+    def tc_pyramid_info(self):
+        n = ctypes.c_int32()
+        _check(self._h, load_library().tc_pyramid_info(self._h, ctypes.byref(n)))
+        return n.value
+
+    def tc_pyramid_dims(self, level):
+        w, h = ctypes.c_int32(), ctypes.c_int32()
+        _check(self._h, load_library().tc_pyramid_dims(self._h, level, ctypes.byref(w),
+                                                       ctypes.byref(h)))
+        return w.value, h.value
+
+    def tc_read_pyramid(self, level, stream=None):
+        w, h = self.tc_pyramid_dims(level)
+        out = np.empty((h, w), np.uint32)
+        st = load_library().tc_read_pyramid(self._h, level, out.ctypes.data,
+                                            _stream_handle(stream))
+        _check(self._h, st)
+        return out
+
+    def tc_read_counters(self, stream=None):
+        v = ctypes.c_uint64()
+        _check(self._h, load_library().tc_read_counters(self._h, ctypes.byref(v),
+                                                        _stream_handle(stream)))
+        return v.value
+
+    def tc_map_bytes(self):
+        v = ctypes.c_uint64()
+        _check(self._h, load_library().tc_map_bytes(self._h, ctypes.byref(v)))
+        return v.value
+
+
+def tc_create(device=0):
+    return Context(device)
+
+
+def view_total_rays(views):
+    a = np.asarray(views).reshape(-1)
+    return int((a["width"].astype(np.int64) * a["height"].astype(np.int64)).sum())
+
+
+def render(ctx, views, stream=None, out=None):
+    """Render views into a (rays, 2) int32 torch tensor on the current
+    device: column 0 the hit word (as int32 bits), column 1 the float depth
+    bits.  Returns the tensor."""
+    import torch
+    n = view_total_rays(views)
+    if out is None:
+        out = torch.empty((n, 2), dtype=torch.int32, device="cuda")
+    ctx.tc_render_views(views, out.data_ptr(), stream)
+    return out
+
+
+def split_hits(out):
+    """(words uint32, depth float32) numpy arrays from a render tensor."""
+    a = out.cpu().numpy()
+    return a[:, 0].view(np.uint32).copy(), a[:, 1].view(np.float32).copy()

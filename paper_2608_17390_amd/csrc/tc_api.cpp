@@ -1,0 +1,674 @@
+// Host runtime of the library: the C ABI declared in include/tc.h.
+//
+// Owns the device copy of the map (packed columns plus the min/max pyramid,
+// one allocation), validates every call before enqueueing anything, stages
+// small per-call tables (views, edit lists) through a ring of pinned host
+// buffers with matching device buffers, and launches the kernels of
+// tc_map.hip and tc_render.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "tc.h"
+#include "tc_internal.h"
+
+namespace {
+
+constexpr int kRing = 16;
+
+struct Slot {
+  void* host = nullptr;
+  void* dev = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+  bool pending = false;
+};
+
+std::string g_create_error;
+
+}  // namespace
+
+struct tc_context {
+  int device = 0;
+  int num_cu = 256;
+  std::string err;
+  // map
+  int32_t W = 0, H = 0;
+  uint32_t* map = nullptr;  // all levels
+  size_t map_words = 0;
+  tci_map desc{};
+  // staging ring
+  Slot ring[kRing];
+  int ring_next = 0;
+  // options
+  int32_t render_mode = 0;
+  int32_t start_level = 0;
+  int32_t max_level = TCI_MAX_LEVELS - 1;
+  int32_t xcd_remap = 1;
+  int32_t persist_waves = 16;
+  int32_t refill_min = 16;
+  int32_t refill_iters = 16;
+  int32_t count_reads = 0;
+  unsigned long long* d_count = nullptr;
+};
+
+namespace {
+
+tc_status fail(tc_context* c, tc_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return st;
+}
+
+tc_status hip_fail(tc_context* c, hipError_t e, const char* what) {
+  return fail(c, e == hipErrorOutOfMemory ? TC_OUT_OF_MEMORY : TC_DEVICE_ERROR,
+              "%s: %s", what, hipGetErrorString(e));
+}
+
+#define TC_HIP(call, what)                              \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+  } while (0)
+
+tc_status set_device(tc_context* ctx) {
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  return TC_OK;
+}
+
+// Acquire a staging slot of at least `bytes`; waits until its previous use
+// (copy and kernels) has finished.
+tc_status acquire(tc_context* ctx, size_t bytes, Slot** out) {
+  Slot& s = ctx->ring[ctx->ring_next];
+  ctx->ring_next = (ctx->ring_next + 1) % kRing;
+  if (s.pending) {
+    TC_HIP(hipEventSynchronize(s.ev), "hipEventSynchronize(staging)");
+    s.pending = false;
+  }
+  if (s.cap < bytes) {
+    size_t cap = std::max<size_t>(bytes, 64 << 10);
+    cap = (cap + 4095) & ~(size_t)4095;
+    if (s.host) { (void)hipHostFree(s.host); s.host = nullptr; }
+    if (s.dev) { (void)hipFree(s.dev); s.dev = nullptr; }
+    s.cap = 0;
+    TC_HIP(hipHostMalloc(&s.host, cap, hipHostMallocDefault), "hipHostMalloc(staging)");
+    TC_HIP(hipMalloc(&s.dev, cap), "hipMalloc(staging)");
+    s.cap = cap;
+  }
+  if (!s.ev) TC_HIP(hipEventCreateWithFlags(&s.ev, hipEventDisableTiming), "hipEventCreate");
+  *out = &s;
+  return TC_OK;
+}
+
+tc_status release(tc_context* ctx, Slot* s, hipStream_t st) {
+  TC_HIP(hipEventRecord(s->ev, st), "hipEventRecord(staging)");
+  s->pending = true;
+  return TC_OK;
+}
+
+bool columns_valid(const uint8_t* F, const uint8_t* B, const uint8_t* T,
+                   int32_t w, int32_t h, size_t stride, int32_t* bad_x,
+                   int32_t* bad_y) {
+  for (int32_t y = 0; y < h; ++y) {
+    const uint8_t* f = F + (size_t)y * stride;
+    const uint8_t* b = B + (size_t)y * stride;
+    const uint8_t* t = T + (size_t)y * stride;
+    for (int32_t x = 0; x < w; ++x) {
+      bool ok = b[x] == 0 ? t[x] == 0 : (b[x] > f[x] && t[x] >= b[x]);
+      if (!ok) {
+        *bad_x = x;
+        *bad_y = y;
+        return false;
+      }
+    }
+  }
+  return true;
+}
+
+int32_t top_level(int32_t W, int32_t H) {
+  int32_t m = std::max(W, H), L = 0;
+  while ((1 << L) < m) ++L;
+  return L;
+}
+
+tci_render_opts render_opts(const tc_context* c) {
+  tci_render_opts o;
+  o.start_level = c->start_level;
+  o.max_level = c->max_level;
+  o.xcd_remap = c->xcd_remap;
+  o.refill_min = c->refill_min;
+  o.refill_iters = c->refill_iters;
+  o.count = c->count_reads ? c->d_count : nullptr;
+  return o;
+}
+
+}  // namespace
+
+extern "C" {
+
+tc_status tc_create(int hip_device, tc_context** out) {
+  if (!out) {
+    g_create_error = "tc_create: out is NULL";
+    return TC_INVALID_ARG;
+  }
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n == 0) {
+    g_create_error = std::string("tc_create: no HIP device: ") + hipGetErrorString(e);
+    return TC_DEVICE_ERROR;
+  }
+  if (hip_device < 0 || hip_device >= n) {
+    g_create_error = "tc_create: device index out of range";
+    return TC_INVALID_ARG;
+  }
+  tc_context* ctx = new (std::nothrow) tc_context();
+  if (!ctx) {
+    g_create_error = "tc_create: out of host memory";
+    return TC_OUT_OF_MEMORY;
+  }
+  ctx->device = hip_device;
+  if (hipSetDevice(hip_device) != hipSuccess ||
+      hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount,
+                            hip_device) != hipSuccess) {
+    g_create_error = "tc_create: cannot query the device";
+    delete ctx;
+    return TC_DEVICE_ERROR;
+  }
+  g_create_error.clear();
+  *out = ctx;
+  return TC_OK;
+}
+
+void tc_destroy(tc_context* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  for (Slot& s : ctx->ring) {
+    if (s.ev) (void)hipEventDestroy(s.ev);
+    if (s.host) (void)hipHostFree(s.host);
+    if (s.dev) (void)hipFree(s.dev);
+  }
+  if (ctx->map) (void)hipFree(ctx->map);
+  if (ctx->d_count) (void)hipFree(ctx->d_count);
+  delete ctx;
+}
+
+const char* tc_last_error(const tc_context* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+tc_status tc_load_columns(tc_context* ctx, int32_t W, int32_t H,
+                          const uint8_t* floor_top, const uint8_t* slab_bottom,
+                          const uint8_t* slab_top, size_t row_stride,
+                          void* hip_stream) {
+  if (!ctx) return TC_INVALID_ARG;
+  try {
+    ctx->err.clear();
+    if (W < 1 || H < 1 || W > TC_MAX_DIM || H > TC_MAX_DIM ||
+        (int64_t)W * H > TC_MAX_CELLS)
+      return fail(ctx, TC_INVALID_ARG, "tc_load_columns: bad map size %dx%d", W, H);
+    if (!floor_top || !slab_bottom || !slab_top)
+      return fail(ctx, TC_INVALID_ARG, "tc_load_columns: null array");
+    if (row_stride < (size_t)W)
+      return fail(ctx, TC_INVALID_ARG, "tc_load_columns: row_stride < W");
+    int32_t bx = 0, by = 0;
+    if (!columns_valid(floor_top, slab_bottom, slab_top, W, H, row_stride, &bx, &by))
+      return fail(ctx, TC_INVALID_ARG,
+                  "tc_load_columns: column (%d,%d) violates B==0 => T==0, "
+                  "B>0 => B>F and T>=B", bx, by);
+    tc_status st = set_device(ctx);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)hip_stream;
+
+    // level layout
+    tci_map d{};
+    d.W = W;
+    d.H = H;
+    d.top = top_level(W, H);
+    size_t words = 0;
+    for (int32_t L = 0; L < TCI_MAX_LEVELS; ++L) {
+      tci_level& l = d.lv[L];
+      if (L > d.top) {
+        l = tci_level{0, 0, 0, 0};
+        continue;
+      }
+      l.w = (int32_t)(((int64_t)W + (1 << L) - 1) >> L);
+      l.h = (int32_t)(((int64_t)H + (1 << L) - 1) >> L);
+      l.tiles_x = (l.w + 7) >> 3;
+      l.off = (uint32_t)words;
+      words += (size_t)l.tiles_x * ((l.h + 7) >> 3) * 64;
+    }
+    uint32_t* map = nullptr;
+    uint8_t* planes = nullptr;
+    TC_HIP(hipMalloc(&map, words * 4), "hipMalloc(map)");
+    hipError_t e = hipMalloc(&planes, (size_t)3 * W * H);
+    if (e != hipSuccess) {
+      (void)hipFree(map);
+      return hip_fail(ctx, e, "hipMalloc(load staging)");
+    }
+    d.base = map;
+    const uint8_t* src[3] = {floor_top, slab_bottom, slab_top};
+    for (int k = 0; k < 3 && e == hipSuccess; ++k)
+      e = hipMemcpy2DAsync(planes + (size_t)k * W * H, W, src[k], row_stride, W,
+                           H, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = tci_launch_repack(planes, W, H, map, d.lv[0], s);
+    for (int32_t L = 1; L <= d.top && e == hipSuccess; ++L)
+      e = tci_launch_build_level(d, map, L, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(planes);
+    if (e != hipSuccess) {
+      (void)hipFree(map);
+      return hip_fail(ctx, e, "tc_load_columns");
+    }
+    if (ctx->map) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(ctx->map);
+    }
+    ctx->map = map;
+    ctx->map_words = words;
+    ctx->desc = d;
+    ctx->W = W;
+    ctx->H = H;
+    return TC_OK;
+  } catch (...) {
+    return fail(ctx, TC_OUT_OF_MEMORY, "tc_load_columns: host allocation failed");
+  }
+}
+
+tc_status tc_apply_edit(tc_context* ctx, const tc_edit* edits, int32_t n,
+                        void* hip_stream) {
+  if (!ctx) return TC_INVALID_ARG;
+  try {
+    ctx->err.clear();
+    if (!ctx->map) return fail(ctx, TC_NO_MAP, "tc_apply_edit: no map loaded");
+    if (n < 0 || n > 65536) return fail(ctx, TC_INVALID_ARG, "tc_apply_edit: bad n %d", n);
+    if (n == 0) return TC_OK;
+    if (!edits) return fail(ctx, TC_INVALID_ARG, "tc_apply_edit: edits is NULL");
+    size_t patch_bytes = 0;
+    for (int32_t i = 0; i < n; ++i) {
+      const tc_edit& e = edits[i];
+      if (e.kind == TC_EDIT_SET) {
+        if (e.w < 1 || e.h < 1 || e.w > TC_MAX_DIM || e.h > TC_MAX_DIM)
+          return fail(ctx, TC_INVALID_ARG, "tc_apply_edit: edit %d bad size", i);
+        if (!e.floor_top || !e.slab_bottom || !e.slab_top)
+          return fail(ctx, TC_INVALID_ARG, "tc_apply_edit: edit %d null patch", i);
+        int32_t bx, by;
+        if (!columns_valid(e.floor_top, e.slab_bottom, e.slab_top, e.w, e.h, e.w, &bx, &by))
+          return fail(ctx, TC_INVALID_ARG,
+                      "tc_apply_edit: edit %d patch cell (%d,%d) violates the "
+                      "column invariants", i, bx, by);
+        patch_bytes += (size_t)3 * e.w * e.h;
+      } else if (e.kind == TC_EDIT_CRATER) {
+        if (e.w < 1 || e.w > 4096 || e.h != e.w)
+          return fail(ctx, TC_INVALID_ARG, "tc_apply_edit: edit %d bad crater size", i);
+        if (e.depth < 0 || e.depth > 255)
+          return fail(ctx, TC_INVALID_ARG, "tc_apply_edit: edit %d bad crater depth", i);
+      } else {
+        return fail(ctx, TC_INVALID_ARG, "tc_apply_edit: edit %d bad kind %d", i, e.kind);
+      }
+      if ((int64_t)e.x0 + e.w > INT32_MAX || (int64_t)e.y0 + e.h > INT32_MAX ||
+          e.x0 < -(1 << 28) || e.y0 < -(1 << 28))
+        return fail(ctx, TC_INVALID_ARG, "tc_apply_edit: edit %d rectangle overflows", i);
+    }
+    tc_status st = set_device(ctx);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const tci_map& d = ctx->desc;
+    const int32_t top = d.top;
+
+    // staging layout: [edits][rects level 1..top][patch bytes]
+    size_t off_edits = 0;
+    size_t off_rects = off_edits + sizeof(tci_edit) * (size_t)n;
+    off_rects = (off_rects + 15) & ~(size_t)15;
+    size_t rect_bytes = sizeof(int32_t) * 4 * (size_t)n * (size_t)std::max(top, 1);
+    size_t off_patch = off_rects + rect_bytes;
+    size_t total = off_patch + patch_bytes;
+    Slot* slot = nullptr;
+    st = acquire(ctx, total, &slot);
+    if (st) return st;
+    char* h = (char*)slot->host;
+    tci_edit* he = (tci_edit*)(h + off_edits);
+    int32_t* hr = (int32_t*)(h + off_rects);
+    uint8_t* hp = (uint8_t*)(h + off_patch);
+    size_t po = 0;
+    int32_t max_w = 1, max_h = 1;
+    std::vector<int32_t> nrect(top + 1, 0), rmw(top + 1, 1), rmh(top + 1, 1);
+    for (int32_t i = 0; i < n; ++i) {
+      const tc_edit& e = edits[i];
+      tci_edit& o = he[i];
+      o.kind = e.kind;
+      o.x0 = e.x0;
+      o.y0 = e.y0;
+      o.w = e.w;
+      o.h = e.h;
+      o.depth = e.depth;
+      o.data_off = (int64_t)po;
+      if (e.kind == TC_EDIT_SET) {
+        size_t m = (size_t)e.w * e.h;
+        memcpy(hp + po, e.floor_top, m);
+        memcpy(hp + po + m, e.slab_bottom, m);
+        memcpy(hp + po + 2 * m, e.slab_top, m);
+        po += 3 * m;
+      }
+      int32_t x0 = std::max(e.x0, 0), y0 = std::max(e.y0, 0);
+      int32_t x1 = std::min(e.x0 + e.w, d.W), y1 = std::min(e.y0 + e.h, d.H);
+      if (x0 >= x1 || y0 >= y1) continue;
+      max_w = std::max(max_w, x1 - x0);
+      max_h = std::max(max_h, y1 - y0);
+      for (int32_t L = 1; L <= top; ++L) {
+        int32_t* r = hr + 4 * ((size_t)(L - 1) * n + nrect[L]);
+        r[0] = x0 >> L;
+        r[1] = y0 >> L;
+        r[2] = (x1 - 1) >> L;
+        r[3] = (y1 - 1) >> L;
+        rmw[L] = std::max(rmw[L], r[2] - r[0] + 1);
+        rmh[L] = std::max(rmh[L], r[3] - r[1] + 1);
+        nrect[L]++;
+      }
+    }
+    char* dv = (char*)slot->dev;
+    hipError_t e = hipMemcpyAsync(dv, h, total, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = tci_launch_edits((const tci_edit*)(dv + off_edits), n,
+                           (const uint8_t*)(dv + off_patch), ctx->map, d.lv[0],
+                           d.W, d.H, max_w, max_h, s);
+    for (int32_t L = 1; L <= top && e == hipSuccess; ++L)
+      e = tci_launch_update_level(d, ctx->map, L,
+                                  (const int32_t*)(dv + off_rects) + 4 * (size_t)(L - 1) * n,
+                                  nrect[L], rmw[L], rmh[L], s);
+    st = release(ctx, slot, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "tc_apply_edit");
+    return st;
+  } catch (...) {
+    return fail(ctx, TC_OUT_OF_MEMORY, "tc_apply_edit: host allocation failed");
+  }
+}
+
+// Validate views and fill the device view table; returns total rays.
+static tc_status prepare_views(tc_context* ctx, const tc_view* views, int32_t n,
+                               std::vector<tci_view>& dv,
+                               std::vector<int64_t>& prefix, int64_t* rays,
+                               int64_t* npkt) {
+  if (n < 1 || !views) return fail(ctx, TC_INVALID_ARG, "render: no views");
+  dv.resize(n);
+  prefix.resize((size_t)n + 1);
+  int64_t out = 0, pk = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const tc_view& v = views[i];
+    if (v.width < 1 || v.height < 1 || v.width > 16384 || v.height > 16384)
+      return fail(ctx, TC_INVALID_ARG, "render: view %d bad size %dx%d", i, v.width, v.height);
+    if (v.flags != 0) return fail(ctx, TC_INVALID_ARG, "render: view %d flags != 0", i);
+    for (int cx = 0; cx < 2; ++cx)
+      for (int cy = 0; cy < 2; ++cy) {
+        int64_t a = cx ? 2 * (int64_t)v.width - 1 : 1;
+        int64_t b = cy ? 2 * (int64_t)v.height - 1 : 1;
+        for (int c = 0; c < 3; ++c) {
+          int64_t O = (int64_t)v.o0[c] + a * v.o_px[c] + b * v.o_py[c];
+          int64_t D = (int64_t)v.d0[c] + a * v.d_px[c] + b * v.d_py[c];
+          if (O < INT32_MIN || O > INT32_MAX)
+            return fail(ctx, TC_INVALID_ARG, "render: view %d origin overflows int32", i);
+          if (D < -TC_MAX_DIR || D > TC_MAX_DIR)
+            return fail(ctx, TC_INVALID_ARG, "render: view %d |direction| > 2^23-1", i);
+        }
+      }
+    tci_view& o = dv[i];
+    o.w = v.width;
+    o.h = v.height;
+    for (int c = 0; c < 3; ++c) {
+      o.o0[c] = v.o0[c]; o.opx[c] = v.o_px[c]; o.opy[c] = v.o_py[c];
+      o.d0[c] = v.d0[c]; o.dpx[c] = v.d_px[c]; o.dpy[c] = v.d_py[c];
+    }
+    o.tiles_x = (v.width + 7) >> 3;
+    o.out_base = out;
+    o.pkt_base = pk;
+    prefix[i] = pk;
+    out += (int64_t)v.width * v.height;
+    pk += (int64_t)o.tiles_x * ((v.height + 7) >> 3);
+  }
+  prefix[n] = pk;
+  if (out > ((int64_t)1 << 31))
+    return fail(ctx, TC_INVALID_ARG, "render: more than 2^31 rays");
+  *rays = out;
+  *npkt = pk;
+  return TC_OK;
+}
+
+tc_status tc_render_views(tc_context* ctx, const tc_view* views, int32_t n,
+                          tc_hit* out_device, void* hip_stream) {
+  if (!ctx) return TC_INVALID_ARG;
+  try {
+    ctx->err.clear();
+    if (!ctx->map) return fail(ctx, TC_NO_MAP, "tc_render_views: no map loaded");
+    if (!out_device) return fail(ctx, TC_INVALID_ARG, "tc_render_views: out is NULL");
+    std::vector<tci_view> dv;
+    std::vector<int64_t> prefix;
+    int64_t rays = 0, npkt = 0;
+    tc_status st = prepare_views(ctx, views, n, dv, prefix, &rays, &npkt);
+    if (st) return st;
+    st = set_device(ctx);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)hip_stream;
+    size_t off_views = 0;
+    size_t off_prefix = (sizeof(tci_view) * (size_t)n + 15) & ~(size_t)15;
+    size_t off_counter = (off_prefix + sizeof(int64_t) * ((size_t)n + 1) + 15) & ~(size_t)15;
+    size_t total = off_counter + 64;
+    Slot* slot = nullptr;
+    st = acquire(ctx, total, &slot);
+    if (st) return st;
+    char* h = (char*)slot->host;
+    memcpy(h + off_views, dv.data(), sizeof(tci_view) * (size_t)n);
+    memcpy(h + off_prefix, prefix.data(), sizeof(int64_t) * ((size_t)n + 1));
+    char* d = (char*)slot->dev;
+    hipError_t e = hipMemcpyAsync(d, h, off_counter, hipMemcpyHostToDevice, s);
+    tci_render_opts o = render_opts(ctx);
+    if (e == hipSuccess) {
+      if (ctx->render_mode == 2) {
+        uint64_t* counter = (uint64_t*)(d + off_counter);
+        e = tci_launch_zero_u64(counter, 1, s);
+        int64_t blocks = (int64_t)ctx->num_cu * ctx->persist_waves / 4;
+        blocks = std::max<int64_t>(1, std::min<int64_t>(blocks, (npkt + 3) / 4));
+        if (e == hipSuccess)
+          e = tci_launch_render_persistent(ctx->desc, (const tci_view*)(d + off_views), n,
+                                           (const int64_t*)(d + off_prefix), npkt,
+                                           out_device, counter, (int32_t)blocks, o, s);
+      } else {
+        e = tci_launch_render(ctx->desc, (const tci_view*)(d + off_views), n,
+                              (const int64_t*)(d + off_prefix), npkt, out_device,
+                              ctx->render_mode == 1, o, s);
+      }
+    }
+    tc_status rs = release(ctx, slot, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "tc_render_views");
+    return rs;
+  } catch (...) {
+    return fail(ctx, TC_OUT_OF_MEMORY, "tc_render_views: host allocation failed");
+  }
+}
+
+tc_status tc_set_option(tc_context* ctx, int32_t key, int64_t value) {
+  if (!ctx) return TC_INVALID_ARG;
+  ctx->err.clear();
+  switch (key) {
+    case TC_OPT_RENDER_MODE:
+      if (value < 0 || value > 2) break;
+      ctx->render_mode = (int32_t)value;
+      return TC_OK;
+    case TC_OPT_START_LEVEL:
+      if (value < 0 || value >= TCI_MAX_LEVELS) break;
+      ctx->start_level = (int32_t)value;
+      return TC_OK;
+    case TC_OPT_MAX_LEVEL:
+      if (value < 0 || value >= TCI_MAX_LEVELS) break;
+      ctx->max_level = (int32_t)value;
+      return TC_OK;
+    case TC_OPT_XCD_REMAP:
+      if (value < 0 || value > 1) break;
+      ctx->xcd_remap = (int32_t)value;
+      return TC_OK;
+    case TC_OPT_PERSIST_WAVES:
+      if (value < 4 || value > 64) break;
+      ctx->persist_waves = (int32_t)value;
+      return TC_OK;
+    case TC_OPT_REFILL_MIN:
+      if (value < 1 || value > 64) break;
+      ctx->refill_min = (int32_t)value;
+      return TC_OK;
+    case TC_OPT_REFILL_ITERS:
+      if (value < 1 || value > 4096) break;
+      ctx->refill_iters = (int32_t)value;
+      return TC_OK;
+    case TC_OPT_COUNT_READS:
+      if (value < 0 || value > 1) break;
+      if (value && !ctx->d_count) {
+        if (set_device(ctx)) return TC_DEVICE_ERROR;
+        hipError_t e = hipMalloc(&ctx->d_count, sizeof(unsigned long long));
+        if (e == hipSuccess) e = hipMemset(ctx->d_count, 0, sizeof(unsigned long long));
+        if (e != hipSuccess) return hip_fail(ctx, e, "tc_set_option(count)");
+      }
+      ctx->count_reads = (int32_t)value;
+      return TC_OK;
+    default:
+      return fail(ctx, TC_INVALID_ARG, "tc_set_option: unknown key %d", key);
+  }
+  return fail(ctx, TC_INVALID_ARG, "tc_set_option: value %lld out of range for key %d",
+              (long long)value, key);
+}
+
+tc_status tc_get_option(const tc_context* ctx, int32_t key, int64_t* value) {
+  if (!ctx || !value) return TC_INVALID_ARG;
+  switch (key) {
+    case TC_OPT_RENDER_MODE: *value = ctx->render_mode; return TC_OK;
+    case TC_OPT_START_LEVEL: *value = ctx->start_level; return TC_OK;
+    case TC_OPT_MAX_LEVEL: *value = ctx->max_level; return TC_OK;
+    case TC_OPT_XCD_REMAP: *value = ctx->xcd_remap; return TC_OK;
+    case TC_OPT_PERSIST_WAVES: *value = ctx->persist_waves; return TC_OK;
+    case TC_OPT_REFILL_MIN: *value = ctx->refill_min; return TC_OK;
+    case TC_OPT_REFILL_ITERS: *value = ctx->refill_iters; return TC_OK;
+    case TC_OPT_COUNT_READS: *value = ctx->count_reads; return TC_OK;
+    default: return TC_INVALID_ARG;
+  }
+}
+
+// Copy tile rows [ty0, ty1] of a level to the host.
+static tc_status read_level_rows(tc_context* ctx, int32_t L, int32_t ty0, int32_t ty1,
+                                 std::vector<uint32_t>& buf, hipStream_t s) {
+  const tci_level& l = ctx->desc.lv[L];
+  size_t row_words = (size_t)l.tiles_x * 64;
+  size_t n = row_words * (size_t)(ty1 - ty0 + 1);
+  buf.resize(n);
+  TC_HIP(hipMemcpyAsync(buf.data(), ctx->map + l.off + row_words * ty0, n * 4,
+                        hipMemcpyDeviceToHost, s), "hipMemcpyAsync(read)");
+  TC_HIP(hipStreamSynchronize(s), "hipStreamSynchronize(read)");
+  return TC_OK;
+}
+
+tc_status tc_read_columns(tc_context* ctx, int32_t x0, int32_t y0, int32_t w,
+                          int32_t h, uint8_t* floor_top, uint8_t* slab_bottom,
+                          uint8_t* slab_top, void* hip_stream) {
+  if (!ctx) return TC_INVALID_ARG;
+  try {
+    ctx->err.clear();
+    if (!ctx->map) return fail(ctx, TC_NO_MAP, "tc_read_columns: no map loaded");
+    if (w < 1 || h < 1 || x0 < 0 || y0 < 0 || x0 + w > ctx->W || y0 + h > ctx->H)
+      return fail(ctx, TC_INVALID_ARG, "tc_read_columns: rectangle outside the map");
+    if (!floor_top || !slab_bottom || !slab_top)
+      return fail(ctx, TC_INVALID_ARG, "tc_read_columns: null output");
+    tc_status st = set_device(ctx);
+    if (st) return st;
+    std::vector<uint32_t> buf;
+    int32_t ty0 = y0 >> 3, ty1 = (y0 + h - 1) >> 3;
+    st = read_level_rows(ctx, 0, ty0, ty1, buf, (hipStream_t)hip_stream);
+    if (st) return st;
+    tci_level l = ctx->desc.lv[0];
+    l.off = 0;
+    for (int32_t j = 0; j < h; ++j)
+      for (int32_t i = 0; i < w; ++i) {
+        int32_t x = x0 + i, y = y0 + j;
+        uint32_t v = buf[tci_tile_index(l, x, y - ty0 * 8)];
+        size_t o = (size_t)j * w + i;
+        floor_top[o] = v & 0xFF;
+        slab_bottom[o] = (v >> 8) & 0xFF;
+        slab_top[o] = (v >> 16) & 0xFF;
+      }
+    return TC_OK;
+  } catch (...) {
+    return fail(ctx, TC_OUT_OF_MEMORY, "tc_read_columns: host allocation failed");
+  }
+}
+
+tc_status tc_pyramid_info(const tc_context* ctx, int32_t* levels) {
+  if (!ctx || !levels) return TC_INVALID_ARG;
+  if (!ctx->map) return TC_NO_MAP;
+  *levels = ctx->desc.top;
+  return TC_OK;
+}
+
+tc_status tc_pyramid_dims(const tc_context* ctx, int32_t level, int32_t* w, int32_t* h) {
+  if (!ctx || !w || !h) return TC_INVALID_ARG;
+  if (!ctx->map) return TC_NO_MAP;
+  if (level < 0 || level > ctx->desc.top) return TC_INVALID_ARG;
+  *w = ctx->desc.lv[level].w;
+  *h = ctx->desc.lv[level].h;
+  return TC_OK;
+}
+
+tc_status tc_read_pyramid(tc_context* ctx, int32_t level, uint32_t* out, void* hip_stream) {
+  if (!ctx) return TC_INVALID_ARG;
+  try {
+    ctx->err.clear();
+    if (!ctx->map) return fail(ctx, TC_NO_MAP, "tc_read_pyramid: no map loaded");
+    if (level < 1 || level > ctx->desc.top || !out)
+      return fail(ctx, TC_INVALID_ARG, "tc_read_pyramid: bad level %d", level);
+    tc_status st = set_device(ctx);
+    if (st) return st;
+    tci_level l = ctx->desc.lv[level];
+    std::vector<uint32_t> buf;
+    st = read_level_rows(ctx, level, 0, (l.h - 1) >> 3, buf, (hipStream_t)hip_stream);
+    if (st) return st;
+    l.off = 0;
+    for (int32_t j = 0; j < l.h; ++j)
+      for (int32_t i = 0; i < l.w; ++i) out[(size_t)j * l.w + i] = buf[tci_tile_index(l, i, j)];
+    return TC_OK;
+  } catch (...) {
+    return fail(ctx, TC_OUT_OF_MEMORY, "tc_read_pyramid: host allocation failed");
+  }
+}
+
+tc_status tc_read_counters(tc_context* ctx, uint64_t* reads, void* hip_stream) {
+  if (!ctx || !reads) return TC_INVALID_ARG;
+  ctx->err.clear();
+  *reads = 0;
+  if (!ctx->d_count) return TC_OK;
+  tc_status st = set_device(ctx);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  unsigned long long v = 0;
+  TC_HIP(hipMemcpyAsync(&v, ctx->d_count, sizeof(v), hipMemcpyDeviceToHost, s),
+         "hipMemcpyAsync(counter)");
+  TC_HIP(hipStreamSynchronize(s), "hipStreamSynchronize(counter)");
+  TC_HIP(hipMemsetAsync(ctx->d_count, 0, sizeof(v), s), "hipMemsetAsync(counter)");
+  TC_HIP(hipStreamSynchronize(s), "hipStreamSynchronize(counter)");
+  *reads = v;
+  return TC_OK;
+}
+
+tc_status tc_map_bytes(const tc_context* ctx, uint64_t* bytes) {
+  if (!ctx || !bytes) return TC_INVALID_ARG;
+  if (!ctx->map) return TC_NO_MAP;
+  *bytes = (uint64_t)ctx->map_words * 4;
+  return TC_OK;
+}
+
+}  // extern "C"

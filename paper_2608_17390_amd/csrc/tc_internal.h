@@ -1,0 +1,94 @@
+// Internal declarations shared by the host runtime and the kernels of the
+// library.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define TCI_MAX_LEVELS 16  // level 0 = cells, levels 1..15 = pyramid
+
+// One level of the map in HBM.  Level 0 holds packed columns
+// F | B << 8 | T << 16; levels >= 1 hold nodes fmax | smin << 8 | smax << 16.
+// Every level is tiled in 8 x 8 blocks of 32-bit words (256 bytes, one
+// wave's worth of coalesced reads): element (i, j) lives at
+//   off + (((j >> 3) * tiles_x + (i >> 3)) << 6) + ((j & 7) << 3) + (i & 7).
+struct tci_level {
+  uint32_t off;      // offset in words from the start of the map buffer
+  int32_t w, h;      // elements per row / rows
+  int32_t tiles_x;   // ceil(w / 8)
+};
+
+struct tci_map {
+  const uint32_t* base;           // all levels, one allocation
+  tci_level lv[TCI_MAX_LEVELS];
+  int32_t W, H;
+  int32_t top;                    // highest stored level (0 if none)
+};
+
+__host__ __device__ inline uint32_t tci_tile_index(const tci_level& L,
+                                                   int32_t i, int32_t j) {
+  return L.off + ((uint32_t)((j >> 3) * L.tiles_x + (i >> 3)) << 6) +
+         (uint32_t)((j & 7) << 3) + (uint32_t)(i & 7);
+}
+
+// Device copy of a view plus the first ray index of the view and the
+// first 64-ray packet of the view.
+struct tci_view {
+  int32_t w, h;
+  int32_t o0[3], opx[3], opy[3];
+  int32_t d0[3], dpx[3], dpy[3];
+  int32_t tiles_x;     // ceil(w / 8)
+  int64_t out_base;    // first output record of the view
+  int64_t pkt_base;    // first 8x8 packet of the view
+};
+
+// Device edit descriptor; SET data lives at data_off in the patch buffer
+// as three planes of w*h bytes (F, then B, then T).
+struct tci_edit {
+  int32_t kind;
+  int32_t x0, y0, w, h;
+  int32_t depth;
+  int64_t data_off;
+};
+
+// Render tuning.
+struct tci_render_opts {
+  int32_t start_level;
+  int32_t max_level;
+  int32_t xcd_remap;
+  int32_t refill_min;
+  int32_t refill_iters;
+  unsigned long long* count;   // if set: add each ray's node/cell reads
+};
+
+// ---- launchers (return hipError_t of the launch) -------------------------
+hipError_t tci_launch_repack(const uint8_t* planes, int32_t W, int32_t H,
+                             uint32_t* base, tci_level l0, hipStream_t s);
+hipError_t tci_launch_build_level(const tci_map& m, uint32_t* base, int32_t L,
+                                  hipStream_t s);
+hipError_t tci_launch_edits(const tci_edit* edits, int32_t n,
+                            const uint8_t* patch, uint32_t* base,
+                            tci_level l0, int32_t W, int32_t H,
+                            int32_t max_w, int32_t max_h, hipStream_t s);
+// Recompute the nodes of level L listed as rectangles (x0, y0, x1, y1
+// inclusive, in level-L node coordinates), nrect of them, the largest
+// spanning max_w x max_h nodes.
+hipError_t tci_launch_update_level(const tci_map& m, uint32_t* base,
+                                   int32_t L, const int32_t* rects,
+                                   int32_t nrect, int32_t max_w,
+                                   int32_t max_h, hipStream_t s);
+
+// Render: views on the device, one thread per pixel.
+hipError_t tci_launch_render(const tci_map& m, const tci_view* views,
+                             int32_t nviews, const int64_t* pkt_prefix,
+                             int64_t npkt, void* out, int32_t flat,
+                             const tci_render_opts& o, hipStream_t s);
+// Render: persistent waves pulling 64-ray packets from a queue counter.
+hipError_t tci_launch_render_persistent(const tci_map& m,
+                                        const tci_view* views, int32_t nviews,
+                                        const int64_t* pkt_prefix,
+                                        int64_t npkt, void* out,
+                                        uint64_t* counter, int32_t nblocks,
+                                        const tci_render_opts& o,
+                                        hipStream_t s);
+hipError_t tci_launch_zero_u64(uint64_t* p, int32_t n, hipStream_t s);

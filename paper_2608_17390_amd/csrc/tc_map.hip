@@ -1,0 +1,218 @@
+// Map maintenance kernels: column repack, pyramid build, ordered edits and
+// the dirty-node pyramid update.
+//
+// The pyramid is the maximum-mipmap structure cited in Section 1.1,
+// extended to the two solid intervals of a column: a node of level L covers
+// a 2^L x 2^L block of cells and keeps the largest floor top (fmax), the
+// smallest slab bottom (smin) and the largest slab top (smax) of the block.
+// A ray whose height range over the node's time span stays above fmax and
+// either above smax or below smin cannot meet solid in the block.
+//
+// Edits follow Section 2 (a dirty rectangle with new heights and slab
+// metadata) and Section 4.4 (the dig crater).  Only the nodes above the
+// edited rectangles are recomputed, from the same 2x2 reduction as the full
+// build, so the updated pyramid is byte-identical to a rebuild.
+#include "tc_internal.h"
+
+namespace {
+
+constexpr int kEditSet = 1;
+
+__device__ inline uint32_t cell_to_node(uint32_t c) {
+  // packed column F | B << 8 | T << 16 -> node fmax | smin << 8 | smax << 16
+  uint32_t F = c & 0xFF, B = (c >> 8) & 0xFF, T = (c >> 16) & 0xFF;
+  return B ? (F | (B << 8) | (T << 16)) : (F | (255u << 8));
+}
+
+__device__ inline uint32_t node_merge(uint32_t a, uint32_t b) {
+  uint32_t f = max(a & 0xFF, b & 0xFF);
+  uint32_t lo = min((a >> 8) & 0xFF, (b >> 8) & 0xFF);
+  uint32_t hi = max((a >> 16) & 0xFF, (b >> 16) & 0xFF);
+  return f | (lo << 8) | (hi << 16);
+}
+
+// Node (i, j) of level L from its up-to-four children at level L-1.
+__device__ inline uint32_t reduce_node(const tci_map& m, const uint32_t* base,
+                                       int32_t L, int32_t i, int32_t j) {
+  const tci_level& c = m.lv[L - 1];
+  uint32_t acc = 0u | (255u << 8);  // empty: fmax 0, smin 255, smax 0
+  #pragma unroll
+  for (int dj = 0; dj < 2; ++dj) {
+    #pragma unroll
+    for (int di = 0; di < 2; ++di) {
+      int32_t ci = 2 * i + di, cj = 2 * j + dj;
+      if (ci < c.w && cj < c.h) {
+        uint32_t v = base[tci_tile_index(c, ci, cj)];
+        acc = node_merge(acc, L == 1 ? cell_to_node(v) : v);
+      }
+    }
+  }
+  return acc;
+}
+
+__global__ void repack_kernel(const uint8_t* __restrict__ planes, int32_t W,
+                              int32_t H, uint32_t* __restrict__ base,
+                              tci_level l0) {
+  // one thread per word of the tiled level-0 array
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t ntiles = (int64_t)l0.tiles_x * ((H + 7) >> 3);
+  if (k >= ntiles * 64) return;
+  int32_t tile = (int32_t)(k >> 6), e = (int32_t)(k & 63);
+  int32_t x = (tile % l0.tiles_x) * 8 + (e & 7);
+  int32_t y = (tile / l0.tiles_x) * 8 + (e >> 3);
+  uint32_t v = 0;
+  if (x < W && y < H) {
+    size_t idx = (size_t)y * W + x;
+    size_t plane = (size_t)W * H;
+    uint32_t F = planes[idx], B = planes[plane + idx], T = planes[2 * plane + idx];
+    v = F | (B << 8) | (T << 16);
+  }
+  base[l0.off + k] = v;
+}
+
+__global__ void build_level_kernel(tci_map m, uint32_t* __restrict__ base,
+                                   int32_t L) {
+  const tci_level& l = m.lv[L];
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t total = (int64_t)l.tiles_x * ((l.h + 7) >> 3) * 64;
+  if (k >= total) return;
+  int32_t tile = (int32_t)(k >> 6), e = (int32_t)(k & 63);
+  int32_t i = (tile % l.tiles_x) * 8 + (e & 7);
+  int32_t j = (tile / l.tiles_x) * 8 + (e >> 3);
+  uint32_t v = 0;
+  if (i < l.w && j < l.h) v = reduce_node(m, base, L, i, j);
+  base[l.off + k] = v;
+}
+
+__device__ inline bool covers(const tci_edit& e, int32_t x, int32_t y) {
+  return x >= e.x0 && x < e.x0 + e.w && y >= e.y0 && y < e.y0 + e.h;
+}
+
+// Apply edit e to a packed column at cell (x, y) inside e's rectangle.
+__device__ inline uint32_t apply_one(const tci_edit& e,
+                                     const uint8_t* __restrict__ patch,
+                                     uint32_t col, int32_t x, int32_t y) {
+  int32_t i = x - e.x0, j = y - e.y0;
+  if (e.kind == kEditSet) {
+    int64_t n = (int64_t)e.w * e.h;
+    int64_t o = e.data_off + (int64_t)j * e.w + i;
+    uint32_t F = patch[o], B = patch[o + n], T = patch[o + 2 * n];
+    return F | (B << 8) | (T << 16);
+  }
+  // crater of size s = w = h
+  int32_t s = e.w;
+  int64_t a = 2 * i + 1 - s, b = 2 * j + 1 - s;
+  int64_t r2 = a * a + b * b, R2 = (int64_t)s * s;
+  if (r2 >= R2) return col;
+  int64_t drop = ((int64_t)e.depth * (R2 - r2)) / R2;
+  int64_t F = (int64_t)(col & 0xFF) - drop;
+  return (uint32_t)(F < 0 ? 0 : F);  // slab removed: B = T = 0
+}
+
+// grid.x = edit index; threads stride over that edit's clipped rectangle.
+// A cell is owned by the first edit that covers it; the owner applies all
+// covering edits in list order, so the result is the sequential one and no
+// two threads write the same cell.
+__global__ void edits_kernel(const tci_edit* __restrict__ edits, int32_t n,
+                             const uint8_t* __restrict__ patch,
+                             uint32_t* __restrict__ base, tci_level l0,
+                             int32_t W, int32_t H) {
+  int32_t ei = blockIdx.x;
+  tci_edit e = edits[ei];
+  int32_t x0 = max(e.x0, 0), y0 = max(e.y0, 0);
+  int32_t x1 = min(e.x0 + e.w, W), y1 = min(e.y0 + e.h, H);
+  if (x0 >= x1 || y0 >= y1) return;
+  int32_t cw = x1 - x0;
+  int64_t cells = (int64_t)cw * (y1 - y0);
+  for (int64_t k = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; k < cells;
+       k += (int64_t)gridDim.y * blockDim.x) {
+    int32_t x = x0 + (int32_t)(k % cw), y = y0 + (int32_t)(k / cw);
+    bool owned = true;
+    for (int32_t p = 0; p < ei; ++p)
+      if (covers(edits[p], x, y)) { owned = false; break; }
+    if (!owned) continue;
+    uint32_t idx = tci_tile_index(l0, x, y);
+    uint32_t col = base[idx];
+    col = apply_one(e, patch, col, x, y);
+    for (int32_t q = ei + 1; q < n; ++q) {
+      tci_edit f = edits[q];
+      if (covers(f, x, y)) col = apply_one(f, patch, col, x, y);
+    }
+    base[idx] = col;
+  }
+}
+
+// grid.x = rectangle index; threads stride over that rectangle's nodes.
+__global__ void update_level_kernel(tci_map m, uint32_t* __restrict__ base,
+                                    int32_t L, const int32_t* __restrict__ rects) {
+  const int32_t* r = rects + 4 * blockIdx.x;
+  int32_t x0 = r[0], y0 = r[1], x1 = r[2], y1 = r[3];
+  int32_t rw = x1 - x0 + 1;
+  int64_t nodes = (int64_t)rw * (y1 - y0 + 1);
+  const tci_level& l = m.lv[L];
+  for (int64_t k = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; k < nodes;
+       k += (int64_t)gridDim.y * blockDim.x) {
+    int32_t i = x0 + (int32_t)(k % rw), j = y0 + (int32_t)(k / rw);
+    base[tci_tile_index(l, i, j)] = reduce_node(m, base, L, i, j);
+  }
+}
+
+__global__ void zero_u64_kernel(uint64_t* p, int32_t n) {
+  int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = 0;
+}
+
+inline int32_t blocks_for(int64_t items, int32_t per, int32_t cap) {
+  int64_t b = (items + per - 1) / per;
+  if (b < 1) b = 1;
+  return (int32_t)(b > cap ? cap : b);
+}
+
+}  // namespace
+
+hipError_t tci_launch_repack(const uint8_t* planes, int32_t W, int32_t H,
+                             uint32_t* base, tci_level l0, hipStream_t s) {
+  int64_t words = (int64_t)l0.tiles_x * ((H + 7) >> 3) * 64;
+  int32_t blocks = blocks_for(words, 256, 1 << 30);
+  hipLaunchKernelGGL(repack_kernel, dim3(blocks), dim3(256), 0, s, planes, W,
+                     H, base, l0);
+  return hipGetLastError();
+}
+
+hipError_t tci_launch_build_level(const tci_map& m, uint32_t* base, int32_t L,
+                                  hipStream_t s) {
+  const tci_level& l = m.lv[L];
+  int64_t words = (int64_t)l.tiles_x * ((l.h + 7) >> 3) * 64;
+  int32_t blocks = blocks_for(words, 256, 1 << 30);
+  hipLaunchKernelGGL(build_level_kernel, dim3(blocks), dim3(256), 0, s, m,
+                     base, L);
+  return hipGetLastError();
+}
+
+hipError_t tci_launch_edits(const tci_edit* edits, int32_t n,
+                            const uint8_t* patch, uint32_t* base,
+                            tci_level l0, int32_t W, int32_t H,
+                            int32_t max_w, int32_t max_h, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int32_t gy = blocks_for((int64_t)max_w * max_h, 256, 64);
+  hipLaunchKernelGGL(edits_kernel, dim3(n, gy), dim3(256), 0, s, edits, n,
+                     patch, base, l0, W, H);
+  return hipGetLastError();
+}
+
+hipError_t tci_launch_update_level(const tci_map& m, uint32_t* base,
+                                   int32_t L, const int32_t* rects,
+                                   int32_t nrect, int32_t max_w,
+                                   int32_t max_h, hipStream_t s) {
+  if (nrect <= 0) return hipSuccess;
+  int32_t gy = blocks_for((int64_t)max_w * max_h, 256, 64);
+  hipLaunchKernelGGL(update_level_kernel, dim3(nrect, gy), dim3(256), 0, s, m,
+                     base, L, rects);
+  return hipGetLastError();
+}
+
+hipError_t tci_launch_zero_u64(uint64_t* p, int32_t n, hipStream_t s) {
+  hipLaunchKernelGGL(zero_u64_kernel, dim3((n + 255) / 256), dim3(256), 0, s,
+                     p, n);
+  return hipGetLastError();
+}

@@ -1,0 +1,59 @@
+"""The C-ABI library builds, loads and exports every symbol the header
+declares (no GPU needed, no compute calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2608_17390_amd as tc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "tc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tc_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_core_calls():
+    names = _declared_functions()
+    for n in ("tc_create", "tc_destroy", "tc_last_error", "tc_load_columns",
+              "tc_apply_edit", "tc_render_views"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(tc.LIB_PATH)
+    missing = [n for n in _declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol():
+    bound = {s[0] for s in tc.SIGNATURES}
+    assert set(_declared_functions()) <= bound
+
+
+def test_struct_layouts():
+    assert ctypes.sizeof(tc.tc_view) == 84
+    assert ctypes.sizeof(tc.tc_edit) == 6 * 4 + 3 * 8
+
+
+def test_null_safety_without_device():
+    lib = tc.load_library()
+    lib.tc_destroy(None)                      # NULL-safe
+    assert lib.tc_create(0, None) == tc.TC_INVALID_ARG
+    assert lib.tc_load_columns(None, 1, 1, None, None, None, 1, None) == tc.TC_INVALID_ARG
+    assert lib.tc_render_views(None, None, 0, None, None) == tc.TC_INVALID_ARG
+    assert lib.tc_apply_edit(None, None, 0, None) == tc.TC_INVALID_ARG
+
+
+def test_create_fails_cleanly_without_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    st = tc.load_library().tc_create(0, ctypes.byref(h))
+    assert st == tc.TC_DEVICE_ERROR
+    assert tc.load_library().tc_last_error(None)

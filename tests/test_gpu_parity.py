@@ -1,0 +1,374 @@
+"""GPU parity: the HIP library against the CPU oracle, through the C ABI.
+
+Hit words (cell, face, layer) must match bit for bit; FP32 depth must be
+within 1e-5 relative of the oracle's FP64 depth (exactly 0 for inside hits
+and +inf for misses)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+tc = pytest.importorskip("paper_2608_17390_amd")
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+S = 65536
+MODES = {"hier": 0, "flat": 1, "persistent": 2}
+DEPTH_RTOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = tc.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_render(ctx, views, mode="hier"):
+    ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, MODES[mode])
+    out = tc.render(ctx, views)
+    torch.cuda.synchronize()
+    return tc.split_hits(out)
+
+
+def assert_parity(wg, dg, wo, do, what=""):
+    assert wg.shape == wo.shape
+    bad = np.nonzero(wg != wo)[0]
+    assert bad.size == 0, "%s: %d word mismatches, first at %d: gpu %08x oracle %08x" % (
+        what, bad.size, bad[0], wg[bad[0]], wo[bad[0]])
+    miss = wo == oracle.MISS
+    assert np.all(np.isinf(dg[miss]))
+    hit = ~miss
+    dg64 = dg[hit].astype(np.float64)
+    ref = do[hit]
+    err = np.abs(dg64 - ref)
+    tol = DEPTH_RTOL * np.abs(ref)
+    worst = np.argmax(err - tol) if err.size else 0
+    assert np.all(err <= tol), "%s: depth off by %g at %g" % (what, err[worst], ref[worst])
+    assert np.all(dg64[ref == 0] == 0)
+
+
+def load(ctx, F, B, T):
+    ctx.tc_load_columns(F, B, T)
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+def test_c1_full_image(ctx, mode):
+    F, B, T = synth.make_map_from_config(1)
+    views = synth.config_views(1, F, B)
+    load(ctx, F, B, T)
+    wo, do = oracle.render(F, B, T, views)
+    wg, dg = gpu_render(ctx, views, mode)
+    assert_parity(wg, dg, wo, do, "c1 " + mode)
+
+
+def _random_views(rng, F, B, n, sizes):
+    H, W = F.shape
+    out = []
+    for k in range(n):
+        w, h = sizes[k % len(sizes)]
+        if k % 3 == 2:
+            x0 = int(rng.integers(-10, W))
+            y0 = int(rng.integers(-10, H))
+            el = rng.uniform(20, 89)
+            out.append(synth.shadow_view(x0, y0, max(w, h), el, rng.uniform(0, 360)))
+            continue
+        eye = synth.eye_above_floor(F, B, rng.uniform(0, W), rng.uniform(0, H),
+                                    dz=float(rng.uniform(0.5, 40)))
+        out.append(synth.perspective_view(eye, rng.uniform(0, 360),
+                                          rng.uniform(-89, 60), w, h,
+                                          vfov_deg=rng.uniform(20, 120)))
+    return out
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+def test_ragged_multi_view_batch(ctx, mode):
+    """Many views of ragged sizes (partial 8x8 tiles, 1x1, thin strips) in
+    one call; views concatenated in order."""
+    rng = np.random.default_rng(21)
+    F, B, T = synth.make_map_from_config(1)
+    load(ctx, F, B, T)
+    sizes = [(77, 53), (1, 1), (8, 9), (13, 200), (300, 2), (64, 64), (9, 8)]
+    views = _random_views(rng, F, B, 21, sizes)
+    wo, do = oracle.render(F, B, T, views)
+    wg, dg = gpu_render(ctx, views, mode)
+    assert_parity(wg, dg, wo, do, "ragged " + mode)
+
+
+@pytest.mark.parametrize("mode", ["hier", "persistent"])
+def test_c2_full_image(ctx, mode):
+    F, B, T = synth.make_map_from_config(2)
+    views = synth.config_views(2, F, B)
+    load(ctx, F, B, T)
+    wo, do = oracle.render(F, B, T, views)
+    wg, dg = gpu_render(ctx, views, mode)
+    assert_parity(wg, dg, wo, do, "c2 " + mode)
+
+
+def test_modes_identical_bytes(ctx):
+    F, B, T = synth.make_map_from_config(2)
+    load(ctx, F, B, T)
+    rng = np.random.default_rng(5)
+    views = _random_views(rng, F, B, 9, [(640, 480), (256, 256), (333, 97)])
+    res = [gpu_render(ctx, views, m) for m in MODES]
+    for w, d in res[1:]:
+        assert np.array_equal(w, res[0][0])
+        assert np.array_equal(d.view(np.uint32), res[0][1].view(np.uint32))
+    # run-to-run determinism
+    w2, d2 = gpu_render(ctx, views, "persistent")
+    assert np.array_equal(w2, res[0][0])
+
+
+def test_level_options_do_not_change_results(ctx):
+    F, B, T = synth.make_map_from_config(1)
+    load(ctx, F, B, T)
+    rng = np.random.default_rng(8)
+    views = _random_views(rng, F, B, 6, [(128, 96), (50, 70)])
+    base = gpu_render(ctx, views, "flat")
+    for start, top in [(0, 3), (4, 15), (8, 8), (15, 1), (2, 0)]:
+        ctx.tc_set_option(tc.TC_OPT_START_LEVEL, start)
+        ctx.tc_set_option(tc.TC_OPT_MAX_LEVEL, top)
+        for mode in ("hier", "persistent"):
+            w, d = gpu_render(ctx, views, mode)
+            assert np.array_equal(w, base[0]), (start, top, mode)
+    ctx.tc_set_option(tc.TC_OPT_START_LEVEL, 0)
+    ctx.tc_set_option(tc.TC_OPT_MAX_LEVEL, 15)
+    for rmin, iters, waves in [(1, 1, 4), (64, 3, 8), (7, 200, 32)]:
+        ctx.tc_set_option(tc.TC_OPT_REFILL_MIN, rmin)
+        ctx.tc_set_option(tc.TC_OPT_REFILL_ITERS, iters)
+        ctx.tc_set_option(tc.TC_OPT_PERSIST_WAVES, waves)
+        w, d = gpu_render(ctx, views, "persistent")
+        assert np.array_equal(w, base[0]), (rmin, iters, waves)
+    ctx.tc_set_option(tc.TC_OPT_REFILL_MIN, 16)
+    ctx.tc_set_option(tc.TC_OPT_REFILL_ITERS, 16)
+    ctx.tc_set_option(tc.TC_OPT_PERSIST_WAVES, 16)
+
+
+def test_straight_down_closed_form_large_map(ctx):
+    """Straight-down orthographic image over the whole 2048x16384 map: each
+    hit is the column's topmost solid, face top, depth 256 - height."""
+    F, B, T = synth.make_map_from_config(3)
+    H, W = F.shape
+    load(ctx, F, B, T)
+    v = synth.ortho_view((0, 0, 256 * S), (S // 2, 0, 0), (0, S // 2, 0),
+                         (0, 0, -1), W, H)
+    wg, dg = gpu_render(ctx, [v], "hier")
+    top = np.where(B > 0, T, F).reshape(-1).astype(np.float32)
+    layer = (B > 0).reshape(-1).astype(np.uint32)
+    exp = np.arange(W * H, dtype=np.uint32) | np.uint32(1 << 27) | (layer << np.uint32(30))
+    assert np.array_equal(wg, exp)
+    assert np.array_equal(dg, np.float32(256) - top)
+
+
+def test_edge_rays(ctx):
+    """Origins outside the map, vertical rays, zero directions, rays
+    running exactly along cell edges and through lattice corners."""
+    rng = np.random.default_rng(9)
+    F, B, T = synth.make_map(61, 45, 3, dual=0.35, period=16)
+    load(ctx, F, B, T)
+    views = [
+        # zero direction: every ray misses
+        synth.ortho_view((S, S, 10 * S), (S // 2, 0, 0), (0, S // 2, 0), (0, 0, 0), 9, 9),
+        # vertical up and down from cell corners and centres
+        synth.ortho_view((0, 0, 3 * S), (S // 2, 0, 0), (0, S // 2, 0), (0, 0, 1), 61, 45),
+        synth.ortho_view((-S, -S, 300 * S), (S, 0, 0), (0, S, 0), (0, 0, -7), 40, 30),
+        # along cell edges (integer x, dx = 0) and along rows
+        synth.ortho_view((0, -5 * S, 40 * S), (S, 0, 0), (0, S // 4, 0), (0, 3, -1), 62, 60),
+        synth.ortho_view((-5 * S, 0, 80 * S), (0, S, 0), (0, 0, S // 2), (5, 0, -2), 46, 70),
+        # 45 degree diagonals through lattice corners
+        synth.ortho_view((0, 0, 60 * S), (S, 0, 0), (0, S, 0), (1, 1, -1), 61, 45),
+        synth.ortho_view((61 * S, 45 * S, 60 * S), (-S, 0, 0), (0, -S, 0), (-1, -1, -1), 61, 45),
+        # from far outside the map, toward it and away from it
+        synth.perspective_view((-500.0, -300.0, 90.0), 45, -3, 64, 48),
+        synth.perspective_view((700.0, 20.0, 50.0), 90, 0, 32, 32),
+        synth.perspective_view((30.5, 22.5, 400.0), 10, -89.9, 50, 50),
+    ]
+    for _ in range(6):
+        views.append(synth.perspective_view(
+            (rng.uniform(-100, 160), rng.uniform(-100, 140), rng.uniform(-20, 300)),
+            rng.uniform(0, 360), rng.uniform(-90, 90), 31, 17))
+    wo, do = oracle.render(F, B, T, views)
+    for mode in MODES:
+        wg, dg = gpu_render(ctx, views, mode)
+        assert_parity(wg, dg, wo, do, "edge " + mode)
+    assert np.all(wo[:81] == oracle.MISS)
+
+
+def test_single_cell_and_odd_maps(ctx):
+    rng = np.random.default_rng(4)
+    for (W, H) in [(1, 1), (1, 9), (9, 1), (17, 3), (129, 65)]:
+        F, B, T = synth.make_map(W, H, 40 + W, dual=0.4, period=4)
+        load(ctx, F, B, T)
+        views = _random_views(rng, F, B, 5, [(23, 19), (8, 8)])
+        wo, do = oracle.render(F, B, T, views)
+        for mode in MODES:
+            wg, dg = gpu_render(ctx, views, mode)
+            assert_parity(wg, dg, wo, do, "map %dx%d %s" % (W, H, mode))
+
+
+def test_widest_view(ctx):
+    F, B, T = synth.make_map_from_config(1)
+    load(ctx, F, B, T)
+    v = synth.perspective_view(synth.eye_above_floor(F, B, 40.5, 10.5), 0, 0, 16384, 2,
+                               vfov_deg=1.0)
+    wo, do = oracle.render(F, B, T, [v])
+    wg, dg = gpu_render(ctx, [v], "hier")
+    assert_parity(wg, dg, wo, do, "16384x2")
+
+
+@pytest.mark.parametrize("shape", [(256, 256), (2048, 2048), (77, 1000)])
+def test_pyramid_matches_definition(ctx, shape):
+    W, H = shape
+    F, B, T = synth.make_map(W, H, 600 + W, dual=0.3, period=32)
+    load(ctx, F, B, T)
+    levels = ctx.tc_pyramid_info()
+    assert (1 << levels) >= max(W, H) > (1 << (levels - 1)) or max(W, H) == 1
+    for L in range(1, levels + 1):
+        assert np.array_equal(ctx.tc_read_pyramid(L), oracle.pyramid_level_fast(F, B, T, L)), L
+    f2, b2, t2 = ctx.tc_read_columns(0, 0, W, H)
+    assert np.array_equal(f2, F) and np.array_equal(b2, B) and np.array_equal(t2, T)
+
+
+def _edited_checks(ctx, F, B, T, edits, views, sample_rows=None):
+    """Apply edits on the GPU; compare the map with the oracle's edit, the
+    pyramid with a fresh build of the edited map, and renders with both the
+    oracle and a fresh load."""
+    H, W = F.shape
+    load(ctx, F, B, T)
+    ctx.tc_apply_edit(edits)
+    F2, B2, T2 = oracle.apply_edits(F, B, T, edits)
+    g = ctx.tc_read_columns(0, 0, W, H)
+    assert np.array_equal(g[0], F2) and np.array_equal(g[1], B2) and np.array_equal(g[2], T2)
+    levels = ctx.tc_pyramid_info()
+    pyr_edit = [ctx.tc_read_pyramid(L) for L in range(1, levels + 1)]
+    res_edit = {m: gpu_render(ctx, views, m) for m in ("hier", "persistent")}
+    load(ctx, F2, B2, T2)
+    for L in range(1, levels + 1):
+        assert np.array_equal(ctx.tc_read_pyramid(L), pyr_edit[L - 1]), L
+    w_fresh, d_fresh = gpu_render(ctx, views, "hier")
+    for m, (w, d) in res_edit.items():
+        assert np.array_equal(w, w_fresh), m
+        assert np.array_equal(d.view(np.uint32), d_fresh.view(np.uint32)), m
+    if sample_rows is None:
+        wo, do = oracle.render(F2, B2, T2, views)
+        assert_parity(w_fresh, d_fresh, wo, do, "edited")
+    else:
+        r0, st = sample_rows
+        wo, do = oracle.render(F2, B2, T2, views, rows=(r0, 1 << 30, st))
+        sel = []
+        base = 0
+        for v in views:
+            w, h = int(v["width"]), int(v["height"])
+            for r in range(r0, h, st):
+                sel.append(np.arange(base + r * w, base + r * w + w))
+            base += w * h
+        sel = np.concatenate(sel)
+        assert_parity(w_fresh[sel], d_fresh[sel], wo, do, "edited sampled")
+
+
+def test_edits_small_map(ctx):
+    F, B, T = synth.make_map_from_config(1)
+    edits = (synth.crater_list(31, 256, 256, 20, size=(4, 64), depth=(0, 255)) +
+             synth.random_set_patches(32, 256, 256, 15, max_size=40))
+    rng = np.random.default_rng(33)
+    rng.shuffle(edits)
+    # overlapping edits on one spot, and patches hanging over every edge
+    edits += [dict(kind=2, x0=100, y0=100, w=32, h=32, depth=50),
+              dict(kind=2, x0=110, y0=104, w=16, h=16, depth=90),
+              dict(kind=2, x0=-10, y0=250, w=20, h=20, depth=30),
+              dict(kind=2, x0=250, y0=-7, w=12, h=12, depth=30)]
+    edits += synth.random_set_patches(34, 256, 256, 3, max_size=12)
+    views = synth.config_views(1, F, B) + _random_views(rng, F, B, 5, [(96, 64)])
+    _edited_checks(ctx, F, B, T, edits, views)
+
+
+def test_edit_sequences_accumulate(ctx):
+    """Several apply calls in a row equal one call with the concatenated
+    list, and equal the oracle's sequential application."""
+    F, B, T = synth.make_map_from_config(1)
+    e1 = synth.crater_list(41, 256, 256, 8)
+    e2 = synth.random_set_patches(42, 256, 256, 8)
+    e3 = synth.crater_list(43, 256, 256, 8, size=(16, 64))
+    load(ctx, F, B, T)
+    for e in (e1, e2, e3):
+        ctx.tc_apply_edit(e)
+    g = ctx.tc_read_columns(0, 0, 256, 256)
+    F2, B2, T2 = oracle.apply_edits(F, B, T, e1 + e2 + e3)
+    assert np.array_equal(g[0], F2) and np.array_equal(g[1], B2) and np.array_equal(g[2], T2)
+
+
+def test_c3_frame_edits_then_views(ctx):
+    """Configuration 3: 64 craters of size 32 on the 2048x16384 map, dirty
+    pyramid update, then the grazing and oblique views; checked on every
+    16th row against the oracle."""
+    F, B, T = synth.make_map_from_config(3)
+    H, W = F.shape
+    edits = synth.crater_list(synth.SEEDS[3]["edits"], W, H, 64, size=32)
+    views = synth.config_views(3, F, B)
+    _edited_checks(ctx, F, B, T, edits, views, sample_rows=(5, 16))
+
+
+def test_c4_batched_sampled(ctx):
+    """Configuration 4 batch (64 views of uneven sizes plus 8 shadow passes)
+    in one persistent launch, checked on sampled pixels."""
+    F, B, T = synth.make_map_from_config(4)
+    load(ctx, F, B, T)
+    views = synth.config_views(4, F, B)
+    assert len(views) == 72
+    wg, dg = gpu_render(ctx, views, "persistent")
+    va = synth.views_array(views)
+    sizes = va["width"].astype(np.int64) * va["height"]
+    base = np.concatenate([[0], np.cumsum(sizes)])
+    rng = np.random.default_rng(44)
+    n = 40000
+    vi = rng.integers(0, len(views), n).astype(np.int32)
+    px = (rng.random(n) * va["width"][vi]).astype(np.int32)
+    py = (rng.random(n) * va["height"][vi]).astype(np.int32)
+    wo, do = oracle.cast_pixels(F, B, T, views, vi, px, py)
+    idx = base[vi] + py.astype(np.int64) * va["width"][vi] + px
+    assert_parity(wg[idx], dg[idx], wo, do, "c4 sampled")
+
+
+def test_error_paths(ctx):
+    ctx2 = tc.Context(0)
+    F = np.zeros((4, 4), np.uint8)
+    v = synth.perspective_view((1.5, 1.5, 5.0), 0, 0, 8, 8)
+    out = torch.empty((64, 2), dtype=torch.int32, device="cuda")
+    with pytest.raises(tc.TCError) as e:
+        ctx2.tc_render_views([v], out.data_ptr())
+    assert e.value.status == tc.TC_NO_MAP
+    with pytest.raises(tc.TCError) as e:
+        ctx2.tc_apply_edit([dict(kind=2, x0=0, y0=0, w=4, h=4, depth=3)])
+    assert e.value.status == tc.TC_NO_MAP
+    bad = np.zeros((4, 4), np.uint8)
+    bad[1, 1] = 3        # B > 0 but T < B and B <= F? F = 0 so B > F ok, T = 0 < B
+    with pytest.raises(tc.TCError) as e:
+        ctx2.tc_load_columns(F, bad, F)
+    assert e.value.status == tc.TC_INVALID_ARG
+    ctx2.tc_load_columns(F, F, F)
+    big = v.copy()
+    big["d0"] = [1 << 23, 0, 0]
+    with pytest.raises(tc.TCError) as e:
+        ctx2.tc_render_views([big], out.data_ptr())
+    assert e.value.status == tc.TC_INVALID_ARG
+    for ed in [dict(kind=2, x0=0, y0=0, w=0, h=0, depth=3),
+               dict(kind=2, x0=0, y0=0, w=4, h=5, depth=3),
+               dict(kind=2, x0=0, y0=0, w=4, h=4, depth=256),
+               dict(kind=9, x0=0, y0=0, w=4, h=4, depth=3),
+               dict(kind=1, x0=0, y0=0, w=2, h=2, depth=0,
+                    F=np.array([[5, 5], [5, 5]], np.uint8),
+                    B=np.array([[5, 0], [0, 0]], np.uint8),
+                    T=np.array([[6, 0], [0, 0]], np.uint8))]:
+        with pytest.raises(tc.TCError) as e:
+            ctx2.tc_apply_edit([ed])
+        assert e.value.status == tc.TC_INVALID_ARG
+    # a failed call leaves the map unchanged
+    g = ctx2.tc_read_columns(0, 0, 4, 4)
+    assert not g[0].any() and not g[1].any()
+    with pytest.raises(tc.TCError):
+        ctx2.tc_set_option(tc.TC_OPT_RENDER_MODE, 7)
+    ctx2.close()

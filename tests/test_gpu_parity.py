@@ -77,8 +77,11 @@ def _random_views(rng, F, B, n, sizes):
             el = rng.uniform(20, 89)
             out.append(synth.shadow_view(x0, y0, max(w, h), el, rng.uniform(0, 360)))
             continue
-        eye = synth.eye_above_floor(F, B, rng.uniform(0, W), rng.uniform(0, H),
-                                    dz=float(rng.uniform(0.5, 40)))
+        try:
+            eye = synth.eye_above_floor(F, B, rng.uniform(0, W), rng.uniform(0, H),
+                                        dz=float(rng.uniform(0.5, 40)))
+        except ValueError:   # every cell has a slab: look from above
+            eye = (rng.uniform(0, W), rng.uniform(0, H), 300.0)
         out.append(synth.perspective_view(eye, rng.uniform(0, 360),
                                           rng.uniform(-89, 60), w, h,
                                           vfov_deg=rng.uniform(20, 120)))

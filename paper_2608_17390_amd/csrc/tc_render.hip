@@ -36,24 +36,34 @@ namespace {
 constexpr uint32_t kMiss = 0xFFFFFFFFu;
 constexpr uint32_t kStuck = 0xFFFFFFFEu;   // iteration cap reached (never
                                            // expected; guards against hangs)
-constexpr int64_t kNever = INT64_MAX;
+// Key of a crossing that never happens (axis with zero direction).  Real
+// keys stay below 2^58 and a node adds at most 2^54, so no sum overflows.
+constexpr int64_t kNever = (int64_t)1 << 62;
 constexpr int32_t kIterCap = 1 << 22;
 
 enum : int32_t { kTop = 1, kUnder = 2, kWmx = 3, kWpx = 4, kWmy = 5,
                  kWpy = 6, kInside = 7 };
+enum : int32_t { kWalking = 0, kHitCell = 1, kMissed = 2, kCapped = 3 };
 
 struct lvl_t {
   uint32_t off;
   int32_t w, h, tiles_x;
 };
 
-__device__ __forceinline__ uint64_t umul24_64(uint32_t a, uint32_t b) {
-  return (uint64_t)(a & 0xFFFFFFu) * (uint64_t)(b & 0xFFFFFFu);
+// a * b for a < 2^24, b < 2^24 as a 48-bit product: two full-rate 24-bit
+// multiplies instead of a quarter-rate 64-bit one.
+__device__ __forceinline__ uint64_t mul48(uint32_t a, uint32_t b) {
+  uint32_t lo, hi;
+  asm("v_mul_u32_u24 %0, %1, %2" : "=v"(lo) : "v"(a), "v"(b));
+  asm("v_mul_hi_u32_u24 %0, %1, %2" : "=v"(hi) : "v"(a), "v"(b));
+  return ((uint64_t)hi << 32) | lo;
 }
-__device__ __forceinline__ int64_t smul24_64(int32_t a, int32_t b) {
-  a = (a << 8) >> 8;
-  b = (b << 8) >> 8;
-  return (int64_t)a * (int64_t)b;
+// a * b for 0 <= a < 2^23 and |b| < 2^23, signed 48-bit product.
+__device__ __forceinline__ int64_t smul48(int32_t a, int32_t b) {
+  int32_t lo, hi;
+  asm("v_mul_i32_i24 %0, %1, %2" : "=v"(lo) : "v"(a), "v"(b));
+  asm("v_mul_hi_i32_i24 %0, %1, %2" : "=v"(hi) : "v"(a), "v"(b));
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 // h * S * d for a height h <= 255 and d < 2^23
 __device__ __forceinline__ int64_t hS(uint32_t h, uint32_t d) {
@@ -124,7 +134,7 @@ __device__ __forceinline__ void set_hit(const ray_t& r, int32_t W, int32_t x,
                   : (float)(((double)tn / (double)td) * len / 65536.0);
 }
 
-// First hit inside cell (x, y) with packed column v, given that the ray's
+// First hit inside the current cell (packed column v), given that the ray's
 // height range over the cell meets solid.
 __device__ __forceinline__ void resolve_hit(const ray_t& r, const walk_t& s,
                                             int32_t W, uint32_t v,
@@ -160,6 +170,21 @@ __device__ __forceinline__ void resolve_hit(const ray_t& r, const walk_t& s,
   set_hit(r, W, s.cx, s.cy, face, layer, tn, td, word, depth);
 }
 
+// Hit record of a finished walk.
+__device__ __forceinline__ void finish(const ray_t& r, const walk_t& s,
+                                       int32_t W, int32_t state, uint32_t v,
+                                       uint32_t& word, float& depth) {
+  if (state == kHitCell) {
+    resolve_hit(r, s, W, v, word, depth);
+  } else if (state == kCapped) {
+    word = kStuck;
+    depth = __builtin_nanf("");
+  } else {
+    word = kMiss;
+    depth = __builtin_inff();
+  }
+}
+
 // Vertical ray (Dx = Dy = 0): only the start column can be met.
 __device__ __forceinline__ void trace_vertical(const tci_map& m,
                                                const lvl_t* lv,
@@ -173,7 +198,7 @@ __device__ __forceinline__ void trace_vertical(const tci_map& m,
   const lvl_t l = lv[0];
   uint32_t v = m.base[l.off + ((uint32_t)((cy >> 3) * l.tiles_x + (cx >> 3)) << 6) +
                       ((cy & 7) << 3) + (cx & 7)];
-  uint32_t F = v & 0xFF, B = (v >> 8) & 0xFF, T = (v >> 16) & 0xFF;
+  uint32_t B = (v >> 8) & 0xFF, F = v & 0xFF, T = (v >> 16) & 0xFF;
   walk_t s;
   s.cx = cx; s.cy = cy; s.Zin = r.Oz; s.Din = 1; s.entry = kInside;
   bool in_floor = r.Oz <= ((int64_t)F << 16);
@@ -182,37 +207,35 @@ __device__ __forceinline__ void trace_vertical(const tci_map& m,
     resolve_hit(r, s, m.W, v, word, depth);
 }
 
-// floor(num / den) for 0 <= num < 2^24 * den, den > 0 (den = ak << 16).
-// Float estimate corrected with exact integer products.
-__device__ __forceinline__ uint32_t floor_div_small(int64_t num, uint32_t ak,
-                                                    int64_t& prod) {
-  int64_t den = (int64_t)ak << 16;
-  float qf = (float)num * __builtin_amdgcn_rcpf((float)den);
-  int32_t q = (int32_t)qf;
-  if (q < 0) q = 0;
-  int64_t p = (int64_t)(umul24_64((uint32_t)q, ak) << 16);
-  while (p > num) { q -= 1; p -= den; }
-  while (p + den <= num) { q += 1; p += den; }
-  prod = p;
-  return (uint32_t)q;
+// Number of terms K + j*(a<<16), j >= 0, strictly below E (E, K < 2^62;
+// the count is < 2^15 when E is a node exit).  Float estimate of the
+// quotient, then one exact correction.
+__device__ __forceinline__ int32_t count_below(int64_t E, int64_t K,
+                                               uint32_t a) {
+  if (E <= K) return 0;
+  const int64_t n = E - K - 1;             // count = floor(n / step) + 1
+  const int64_t step = (int64_t)a << 16;
+  const float nf = (float)(uint32_t)(n >> 32) * 4294967296.0f +
+                   (float)(uint32_t)n;
+  int32_t q = (int32_t)(nf * __builtin_amdgcn_rcpf((float)a * 65536.0f));
+  q = q < 0 ? 0 : q;
+  const int64_t p = (int64_t)(mul48((uint32_t)q, a) << 16);
+  q += (p > n) ? -1 : ((n - p >= step) ? 1 : 0);
+  return q + 1;
 }
 
-// Advance the walk by up to `budget` iterations.  Returns true when the
-// ray is finished (word / depth written).
+// Advance the walk by up to `budget` iterations.  Returns kWalking if the
+// budget ran out, else the final state; on kHitCell, `col` holds the
+// column of the current cell.
 template <bool kFlat>
-__device__ __forceinline__ bool walk_steps(const tci_map& m, const lvl_t* lv,
-                                           const ray_t& r, walk_t& s,
-                                           int32_t max_level, int32_t budget,
-                                           uint32_t& word, float& depth) {
-  const int64_t SKx = (int64_t)r.ay << 16;   // key step per x crossing
-  const int64_t SKy = (int64_t)r.ax << 16;   // key step per y crossing
+__device__ __forceinline__ int32_t walk_steps(const tci_map& m,
+                                              const lvl_t* lv, const ray_t& r,
+                                              walk_t& s, int32_t max_level,
+                                              int32_t budget, uint32_t& col) {
   const bool desc = r.Dz < 0;
+  const int64_t SZ = (int64_t)r.Dz << 16;
   for (int32_t it = 0; it < budget; ++it) {
-    if (++s.iters > kIterCap) {
-      word = kStuck;
-      depth = __builtin_nanf("");
-      return true;
-    }
+    if (++s.iters > kIterCap) return kCapped;
     const int32_t L = kFlat ? 0 : s.L;
     const lvl_t l = lv[L];
     const int32_t ni = s.cx >> L, nj = s.cy >> L;
@@ -220,27 +243,23 @@ __device__ __forceinline__ bool walk_steps(const tci_map& m, const lvl_t* lv,
     uint32_t v = 0;
     s.reads += inmap ? 1 : 0;
     if (inmap)
-      v = m.base[l.off + ((uint32_t)((nj >> 3) * l.tiles_x + (ni >> 3)) << 6) +
+      v = m.base[l.off + ((__umul24((uint32_t)nj >> 3, (uint32_t)l.tiles_x) +
+                           ((uint32_t)ni >> 3)) << 6) +
                  ((nj & 7) << 3) + (ni & 7)];
-    // crossings to leave the node on each axis (>= 1)
-    const int32_t kxf = r.Dx > 0 ? ((ni + 1) << L) - s.cx : s.cx - (ni << L) + 1;
-    const int32_t kyf = r.Dy > 0 ? ((nj + 1) << L) - s.cy : s.cy - (nj << L) + 1;
-    int64_t Kxe = s.Kx, Kye = s.Ky, Zxe = s.Zx, Zye = s.Zy;
-    if (kFlat || L == 0) {
-      // one cell: the exit is the next crossing
-    } else {
-      if (r.Dx != 0) {
-        Kxe += (int64_t)(umul24_64((uint32_t)(kxf - 1), r.ay) << 16);
-        Zxe += smul24_64(kxf - 1, r.Dz) << 16;
-      }
-      if (r.Dy != 0) {
-        Kye += (int64_t)(umul24_64((uint32_t)(kyf - 1), r.ax) << 16);
-        Zye += smul24_64(kyf - 1, r.Dz) << 16;
-      }
+    // crossings before the node's far face on each axis
+    int32_t kxm1 = 0, kym1 = 0;
+    int64_t Kxe = s.Kx, Kye = s.Ky;
+    if (!kFlat) {
+      kxm1 = r.Dx > 0 ? ((ni + 1) << L) - 1 - s.cx : s.cx - (ni << L);
+      kym1 = r.Dy > 0 ? ((nj + 1) << L) - 1 - s.cy : s.cy - (nj << L);
+      Kxe += (int64_t)(mul48((uint32_t)kxm1, r.ay) << 16);
+      Kye += (int64_t)(mul48((uint32_t)kym1, r.ax) << 16);
     }
-    const bool exit_x = Kxe <= Kye;
-    const int64_t Ze = exit_x ? Zxe : Zye;
-    const uint32_t De = exit_x ? r.ax : r.ay;
+    const bool ex = Kxe <= Kye;               // leave through an x face
+    const int32_t km1 = ex ? kxm1 : kym1;
+    int64_t Ze = ex ? s.Zx : s.Zy;
+    if (!kFlat) Ze += smul48(km1, r.Dz) << 16;
+    const uint32_t De = ex ? r.ax : r.ay;
     bool occ = false;
     if (inmap) {
       const int64_t Zlo = desc ? Ze : s.Zin;
@@ -252,62 +271,44 @@ __device__ __forceinline__ bool walk_steps(const tci_map& m, const lvl_t* lv,
     }
     if (occ) {
       if (L == 0) {
-        resolve_hit(r, s, m.W, v, word, depth);
-        return true;
+        col = v;
+        return kHitCell;
       }
       s.L = L - 1;
       continue;
     }
-    // skip to the node exit
-    int32_t kx, ky;
-    if (exit_x) {
-      kx = kxf;
-      ky = 0;
-      if (!kFlat && L > 0 && r.Dy != 0 && Kxe > s.Ky) {
-        // y crossings strictly before the exit: ceil((Kxe - Ky) / SKy)
-        int64_t num = Kxe - s.Ky, p;
-        uint32_t q = floor_div_small(num, r.ax, p);
-        ky = (int32_t)q + (p != num ? 1 : 0);
-      }
+    // jump to the node exit: km1 + 1 crossings on the exit axis and, on
+    // the other axis, those strictly before it (x first on ties)
+    int32_t ko = 0;
+    if (!kFlat && L > 0)
+      ko = ex ? count_below(Kxe, s.Ky, r.ax) : count_below(Kye + 1, s.Kx, r.ay);
+    const int32_t kx = ex ? km1 + 1 : ko;
+    const int32_t ky = ex ? ko : km1 + 1;
+    if (kFlat) {
+      if (ex) { s.Kx += (int64_t)r.ay << 16; s.Zx += SZ; }
+      else    { s.Ky += (int64_t)r.ax << 16; s.Zy += SZ; }
     } else {
-      ky = kyf;
-      kx = 0;
-      if (!kFlat && L > 0 && r.Dx != 0 && Kye >= s.Kx) {
-        // x crossings at or before the exit: floor((Kye - Kx) / SKx) + 1
-        int64_t num = Kye - s.Kx, p;
-        kx = (int32_t)floor_div_small(num, r.ay, p) + 1;
-      }
+      s.Kx += (int64_t)(mul48((uint32_t)kx, r.ay) << 16);
+      s.Ky += (int64_t)(mul48((uint32_t)ky, r.ax) << 16);
+      s.Zx += smul48(kx, r.Dz) << 16;
+      s.Zy += smul48(ky, r.Dz) << 16;
     }
-    if (kFlat || L == 0) {
-      if (exit_x) { s.Kx += SKx; s.Zx += (int64_t)r.Dz << 16; }
-      else        { s.Ky += SKy; s.Zy += (int64_t)r.Dz << 16; }
-    } else {
-      if (kx) {
-        s.Kx += (int64_t)(umul24_64((uint32_t)kx, r.ay) << 16);
-        s.Zx += smul24_64(kx, r.Dz) << 16;
-      }
-      if (ky) {
-        s.Ky += (int64_t)(umul24_64((uint32_t)ky, r.ax) << 16);
-        s.Zy += smul24_64(ky, r.Dz) << 16;
-      }
-    }
+    const int32_t pcx = s.cx, pcy = s.cy;
     s.cx += r.Dx > 0 ? kx : -kx;
     s.cy += r.Dy > 0 ? ky : -ky;
     s.Zin = Ze;
     s.Din = De;
-    s.entry = exit_x ? (r.Dx > 0 ? kWmx : kWpx) : (r.Dy > 0 ? kWmy : kWpy);
+    s.entry = ex ? (r.Dx > 0 ? kWmx : kWpx) : (r.Dy > 0 ? kWmy : kWpy);
     // the ray cannot come back into the map, or is above all solid
     const bool away = (s.cx < 0 && r.Dx <= 0) || (s.cx >= m.W && r.Dx >= 0) ||
                       (s.cy < 0 && r.Dy <= 0) || (s.cy >= m.H && r.Dy >= 0);
     const bool above = r.Dz >= 0 && s.Zin > hS(255, s.Din);
-    if (away || above) {
-      word = kMiss;
-      depth = __builtin_inff();
-      return true;
-    }
-    if (!kFlat) s.L = L + 1 > max_level ? max_level : L + 1;
+    if (away || above) return kMissed;
+    // go up one level when the jump left the parent node
+    if (!kFlat && L < max_level && (((pcx ^ s.cx) | (pcy ^ s.cy)) >> (L + 1)) != 0)
+      s.L = L + 1;
   }
-  return false;
+  return kWalking;
 }
 
 __device__ __forceinline__ void load_levels(const tci_map& m, lvl_t* lv) {
@@ -375,8 +376,11 @@ __global__ __launch_bounds__(256) void render_kernel(
     walk_t s;
     const int32_t top = kFlat ? 0 : m.top;
     walk_init(r, kFlat ? 0 : clamp_level(o.start_level, top), s);
-    walk_steps<kFlat>(m, lv, r, s, kFlat ? 0 : clamp_level(o.max_level, top),
-                      kIterCap + 1, word, depth);
+    uint32_t col = 0;
+    const int32_t st = walk_steps<kFlat>(m, lv, r, s,
+                                         kFlat ? 0 : clamp_level(o.max_level, top),
+                                         kIterCap + 1, col);
+    finish(r, s, m.W, st, col, word, depth);
     if (o.count) atomicAdd(o.count, (unsigned long long)s.reads);
   }
   store_hit(out, v.out_base + (int64_t)py * v.w + px, word, depth);
@@ -455,14 +459,16 @@ __global__ __launch_bounds__(256) void render_persistent_kernel(
       }
     }
     if (drained && __ballot(active) == 0) break;
-    if (active) {
+    int32_t st = kWalking;
+    uint32_t col = 0;
+    if (active) st = walk_steps<false>(m, lv, r, s, Lmax, iters, col);
+    if (st != kWalking) {
       uint32_t word;
       float depth;
-      if (walk_steps<false>(m, lv, r, s, Lmax, iters, word, depth)) {
-        store_hit(out, out_idx, word, depth);
-        if (o.count) atomicAdd(o.count, (unsigned long long)s.reads);
-        active = false;
-      }
+      finish(r, s, m.W, st, col, word, depth);
+      store_hit(out, out_idx, word, depth);
+      if (o.count) atomicAdd(o.count, (unsigned long long)s.reads);
+      active = false;
     }
   }
 }

@@ -68,6 +68,105 @@ def cpu_baseline(oracle, F, B, T, views, rays_per_frame, budget_s=12.0):
             "sample": "%d full renders of the 1920x1080 headline view (%.1f s)" % (done, dt)}
 
 
+def c3_frame(torch, tc, synth, steps, warmup):
+    """Configuration 3: 64 size-32 craters, dirty pyramid update, then the
+    2560x1440 grazing and 1920x1080 oblique views, as one captured frame."""
+    F, B, T = synth.make_map_from_config(3)
+    H, W = F.shape
+    views = synth.config_views(3, F, B)
+    edits = synth.crater_list(synth.SEEDS[3]["edits"], W, H, 64, size=32)
+    rays = synth.view_rays(views)
+    ctx = tc.Context(0)
+    ctx.tc_load_columns(F, B, T)
+    out = torch.empty((rays, 2), dtype=torch.int32, device="cuda")
+    frame = ctx.tc_frame_create(views, edits, out.data_ptr())
+    for _ in range(warmup):
+        frame.launch()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    for a, b in ev:
+        a.record()
+        frame.launch()
+        b.record()
+    torch.cuda.synchronize()
+    ms = np.array([a.elapsed_time(b) for a, b in ev])
+    frame.close()
+    ctx.close()
+    return {"workload": "c3: 2048x16384 map, 64 craters + dirty update + 2560x1440 "
+                        "grazing + 1920x1080 oblique views, one graph launch",
+            "rays_per_frame": rays, "frame_ms_median": float(np.median(ms)),
+            "frame_ms_p99": float(np.percentile(ms, 99)),
+            "grays_per_s": rays / (np.median(ms) * 1e-3) / 1e9}
+
+
+def c4_batched(torch, tc, synth, steps, warmup):
+    """Configuration 4: 64 views of uneven sizes + 8 shadow passes + 16
+    craters.  Plain: tc_apply_edit then one tc_render_views per view,
+    serialized on one stream; a view's latency runs from the frame start to
+    its render's end.  Batched: the same work as one captured frame; every
+    view completes with the frame."""
+    from paper_2608_17390_amd import tune
+    F, B, T = synth.make_map_from_config(4)
+    H, W = F.shape
+    views = synth.config_views(4, F, B)
+    edits = synth.crater_list(synth.SEEDS[4]["edits"], W, H, 16, size=32)
+    va = synth.views_array(views)
+    sizes = va["width"].astype(np.int64) * va["height"]
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    rays = int(offs[-1])
+    ctx = tc.Context(0)
+    ctx.tc_load_columns(F, B, T)
+    out = torch.empty((rays, 2), dtype=torch.int32, device="cuda")
+    knobs, cached = tune.autotune(ctx, views, out.data_ptr(), "c4-batched")
+    log("[bench] c4 knobs %s (cached %s)" % (knobs, cached))
+    # plain
+    nv = len(views)
+    plain_lat, plain_frame = [], []
+    for it in range(warmup + steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(nv)]
+        e0.record()
+        ctx.tc_apply_edit(edits)
+        for i in range(nv):
+            ptr = out.data_ptr() + int(offs[i]) * 8
+            ctx.tc_render_views(views[i:i + 1], ptr)
+            evs[i].record()
+        torch.cuda.synchronize()
+        if it >= warmup:
+            lat = [e0.elapsed_time(e) for e in evs]
+            plain_lat.extend(lat)
+            plain_frame.append(lat[-1])
+    # batched
+    frame = ctx.tc_frame_create(views, edits, out.data_ptr())
+    for _ in range(warmup):
+        frame.launch()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    for a, b in ev:
+        a.record()
+        frame.launch()
+        b.record()
+    torch.cuda.synchronize()
+    bms = np.array([a.elapsed_time(b) for a, b in ev])
+    frame.close()
+    ctx.close()
+    batched_lat = np.repeat(bms, nv)
+    pf = np.array(plain_frame)
+    return {"workload": "c4: 2048x16384 map, 64 views (256^2/640x480/1280x720/1920x1080) "
+                        "+ 8 x 2048^2 shadow passes + 16 craters per frame",
+            "rays_per_frame": rays, "views": nv, "knobs": knobs,
+            "plain": {"frame_ms_median": float(np.median(pf)),
+                      "view_latency_ms_p50": float(np.percentile(plain_lat, 50)),
+                      "view_latency_ms_p99": float(np.percentile(plain_lat, 99)),
+                      "grays_per_s": rays / (np.median(pf) * 1e-3) / 1e9},
+            "batched": {"frame_ms_median": float(np.median(bms)),
+                        "view_latency_ms_p50": float(np.percentile(batched_lat, 50)),
+                        "view_latency_ms_p99": float(np.percentile(batched_lat, 99)),
+                        "grays_per_s": rays / (np.median(bms) * 1e-3) / 1e9}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +176,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--extra", action="store_true",
                     help="also time every render mode")
+    ap.add_argument("--no-growth", action="store_true",
+                    help="skip the edit frame (c3) and batched frame (c4)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU; --gpus %d is not supported (the method "
@@ -143,6 +244,11 @@ def main():
             mm, _ = time_renders(torch, ctx, tc, views, out, 10, 2)
             modes[m] = float(np.median(mm))
         res["mode_ms_median"] = modes
+    if not args.no_growth:
+        log("[bench] c3 edit frame")
+        res["c3_frame"] = c3_frame(torch, tc, synth, 10, 2)
+        log("[bench] c4 batched vs plain")
+        res["c4_batched"] = c4_batched(torch, tc, synth, 10, 2)
     if not args.no_cpu:
         import oracle
         log("[bench] CPU oracle baseline")

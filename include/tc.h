@@ -163,12 +163,13 @@ tc_status tc_render_views(tc_context *ctx, const tc_view *views, int32_t n,
 /* Tuning knobs of the render path.  Each takes effect for later calls. */
 #define TC_OPT_RENDER_MODE 1   /* 0 hierarchical (default), 1 flat walk,
                                   2 persistent packet queue */
-#define TC_OPT_START_LEVEL 2   /* pyramid level a ray starts at (default 0);
+#define TC_OPT_START_LEVEL 2   /* pyramid level a ray starts at (default 2);
                                   clamped to the top level */
 #define TC_OPT_MAX_LEVEL 3     /* highest level a ray ascends to (default
                                   top level) */
-#define TC_OPT_XCD_REMAP 4     /* 1: group neighbouring screen tiles on one
-                                  XCD (default 1) */
+#define TC_OPT_XCD_REMAP 4     /* G > 0: each XCD runs G consecutive blocks
+                                  of 4 packets at a time (L2 locality);
+                                  0: hardware round-robin (default 0) */
 #define TC_OPT_PERSIST_WAVES 5 /* waves per CU of the persistent launch
                                   (default 8) */
 #define TC_OPT_REFILL_MIN 6    /* persistent mode: idle lanes that trigger a
@@ -178,8 +179,51 @@ tc_status tc_render_views(tc_context *ctx, const tc_view *views, int32_t n,
 #define TC_OPT_COUNT_READS 8   /* 1: renders add the number of pyramid nodes
                                   and cells each ray reads to a context
                                   counter (diagnostic; default 0) */
+#define TC_OPT_TILE_ORDER 9    /* order of 8x8 pixel packets within a view:
+                                  0 row-major, 1 column-major (default 1) */
 tc_status tc_set_option(tc_context *ctx, int32_t key, int64_t value);
 tc_status tc_get_option(const tc_context *ctx, int32_t key, int64_t *value);
+
+/* ---- batched frames ---------------------------------------------------- */
+/* A frame: n edits (applied in order, then the dirty-node pyramid update)
+ * followed by the render of nviews views into out_device, captured once
+ * into a HIP graph with its tables copied to device memory, and replayed
+ * with one graph launch.  Every launch applies the edits again (a crater
+ * list digs deeper each frame) and renders the edited map.  The render
+ * knobs in force at creation are baked in.  A frame is tied to the map it
+ * was created on: after tc_load_columns, tc_frame_launch fails with
+ * TC_INVALID_ARG.  Validation as for tc_apply_edit and tc_render_views.
+ * The paper renders each frame in isolation with nothing overlapping
+ * (Section 7); a frame batches views, shadow passes and edits instead. */
+typedef struct tc_frame tc_frame;
+tc_status tc_frame_create(tc_context *ctx, const tc_view *views, int32_t nviews,
+                          const tc_edit *edits, int32_t nedits,
+                          tc_hit *out_device, void *hip_stream, tc_frame **out);
+/* Enqueue one replay of the frame on hip_stream (no host synchronisation). */
+tc_status tc_frame_launch(tc_frame *frame, void *hip_stream);
+/* Total rays of the frame's views. */
+tc_status tc_frame_rays(const tc_frame *frame, int64_t *rays);
+/* Wait for the device, then free the graph and tables.  NULL is a no-op. */
+void tc_frame_destroy(tc_frame *frame);
+
+/* ---- autotuning ----------------------------------------------------------- */
+/* Time tc_render_views on these views (reps timed calls per setting, median)
+ * over a grid of the render knobs -- traversal mode, start level, packet
+ * order, XCD grouping, and the persistent queue's waves per CU, refill
+ * threshold and refill interval -- then keep the fastest setting on the
+ * context and report it.  Results are those of tc_render_views for every
+ * setting (bit-identical); only the time differs.  Synchronises
+ * hip_stream.  The paper picks each method's knob by a sweep on a fixed
+ * fixture (Section 5.6); this tunes on the caller's workload. */
+typedef struct tc_tune_result {
+  int32_t render_mode, start_level, tile_order, xcd_remap;
+  int32_t persist_waves, refill_min, refill_iters;
+  float ms;      /* median time per call of the chosen setting */
+  int32_t tried; /* settings timed */
+} tc_tune_result;
+tc_status tc_autotune(tc_context *ctx, const tc_view *views, int32_t n,
+                      tc_hit *out_device, int32_t reps, void *hip_stream,
+                      tc_tune_result *best);
 
 /* ---- inspection (tests, checkpoints) ---------------------------------- */
 /* Copy the w x h rectangle at (x0, y0) of the current map into host arrays

@@ -33,6 +33,7 @@ TC_OPT_PERSIST_WAVES = 5
 TC_OPT_REFILL_MIN = 6
 TC_OPT_REFILL_ITERS = 7
 TC_OPT_COUNT_READS = 8
+TC_OPT_TILE_ORDER = 9
 
 _STATUS = {0: "TC_OK", -1: "TC_INVALID_ARG", -2: "TC_OUT_OF_MEMORY",
            -3: "TC_NO_MAP", -4: "TC_DEVICE_ERROR", -5: "TC_OVER_BUDGET"}
@@ -52,6 +53,14 @@ class tc_edit(ctypes.Structure):
                 ("h", ctypes.c_int32), ("depth", ctypes.c_int32),
                 ("floor_top", ctypes.c_void_p), ("slab_bottom", ctypes.c_void_p),
                 ("slab_top", ctypes.c_void_p)]
+
+
+class tc_tune_result(ctypes.Structure):
+    _fields_ = [("render_mode", ctypes.c_int32), ("start_level", ctypes.c_int32),
+                ("tile_order", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
+                ("persist_waves", ctypes.c_int32), ("refill_min", ctypes.c_int32),
+                ("refill_iters", ctypes.c_int32), ("ms", ctypes.c_float),
+                ("tried", ctypes.c_int32)]
 
 
 assert ctypes.sizeof(tc_view) == 84
@@ -74,6 +83,13 @@ SIGNATURES = [
     ("tc_read_pyramid", _I32, [_P, _I32, _P, _P]),
     ("tc_read_counters", _I32, [_P, ctypes.POINTER(ctypes.c_uint64), _P]),
     ("tc_map_bytes", _I32, [_P, ctypes.POINTER(ctypes.c_uint64)]),
+    ("tc_frame_create", _I32, [_P, ctypes.POINTER(tc_view), _I32, ctypes.POINTER(tc_edit),
+                               _I32, _P, _P, ctypes.POINTER(_P)]),
+    ("tc_frame_launch", _I32, [_P, _P]),
+    ("tc_frame_rays", _I32, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    ("tc_frame_destroy", None, [_P]),
+    ("tc_autotune", _I32, [_P, ctypes.POINTER(tc_view), _I32, _P, _I32, _P,
+                           ctypes.POINTER(tc_tune_result)]),
 ]
 
 _lib = None
@@ -267,10 +283,56 @@ class Context:
                                                         _stream_handle(stream)))
         return v.value
 
+    def tc_frame_create(self, views, edits, out_ptr, stream=None):
+        varr = _views_struct(views)
+        earr, keep = _edits_struct(list(edits))
+        h = ctypes.c_void_p()
+        st = load_library().tc_frame_create(self._h, varr, len(varr), earr, len(edits),
+                                            ctypes.c_void_p(int(out_ptr)),
+                                            _stream_handle(stream), ctypes.byref(h))
+        del keep
+        _check(self._h, st)
+        rays = ctypes.c_int64()
+        load_library().tc_frame_rays(h, ctypes.byref(rays))
+        return Frame(self, h, rays.value)
+
+    def tc_autotune(self, views, out_ptr, reps=5, stream=None):
+        arr = _views_struct(views)
+        r = tc_tune_result()
+        st = load_library().tc_autotune(self._h, arr, len(arr), ctypes.c_void_p(int(out_ptr)),
+                                        int(reps), _stream_handle(stream), ctypes.byref(r))
+        _check(self._h, st)
+        return {f: getattr(r, f) for f, _ in tc_tune_result._fields_}
+
     def tc_map_bytes(self):
         v = ctypes.c_uint64()
         _check(self._h, load_library().tc_map_bytes(self._h, ctypes.byref(v)))
         return v.value
+
+
+class Frame:
+    """A captured frame (edits, dirty update, render) replayed by launch()."""
+
+    def __init__(self, ctx, handle, rays):
+        self._ctx = ctx
+        self._h = handle
+        self.rays = rays
+
+    def tc_frame_launch(self, stream=None):
+        _check(self._ctx.handle, load_library().tc_frame_launch(self._h, _stream_handle(stream)))
+
+    launch = tc_frame_launch
+
+    def close(self):
+        if self._h:
+            load_library().tc_frame_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def tc_create(device=0):

@@ -15,50 +15,44 @@
 #include <string>
 #include <vector>
 
-#include "tc.h"
-#include "tc_internal.h"
+#include "tc_context.h"
+
+using tci::fail;
+using tci::hip_fail;
+using tci::set_device;
 
 namespace {
-
-constexpr int kRing = 16;
-
-struct Slot {
-  void* host = nullptr;
-  void* dev = nullptr;
-  size_t cap = 0;
-  hipEvent_t ev = nullptr;
-  bool pending = false;
-};
 
 std::string g_create_error;
 
+bool columns_valid(const uint8_t* F, const uint8_t* B, const uint8_t* T,
+                   int32_t w, int32_t h, size_t stride, int32_t* bad_x,
+                   int32_t* bad_y) {
+  for (int32_t y = 0; y < h; ++y) {
+    const uint8_t* f = F + (size_t)y * stride;
+    const uint8_t* b = B + (size_t)y * stride;
+    const uint8_t* t = T + (size_t)y * stride;
+    for (int32_t x = 0; x < w; ++x) {
+      bool ok = b[x] == 0 ? t[x] == 0 : (b[x] > f[x] && t[x] >= b[x]);
+      if (!ok) {
+        *bad_x = x;
+        *bad_y = y;
+        return false;
+      }
+    }
+  }
+  return true;
+}
+
+int32_t top_level(int32_t W, int32_t H) {
+  int32_t m = std::max(W, H), L = 0;
+  while ((1 << L) < m) ++L;
+  return L;
+}
+
 }  // namespace
 
-struct tc_context {
-  int device = 0;
-  int num_cu = 256;
-  std::string err;
-  // map
-  int32_t W = 0, H = 0;
-  uint32_t* map = nullptr;  // all levels
-  size_t map_words = 0;
-  tci_map desc{};
-  // staging ring
-  Slot ring[kRing];
-  int ring_next = 0;
-  // options
-  int32_t render_mode = 0;
-  int32_t start_level = 0;
-  int32_t max_level = TCI_MAX_LEVELS - 1;
-  int32_t xcd_remap = 1;
-  int32_t persist_waves = 16;
-  int32_t refill_min = 16;
-  int32_t refill_iters = 16;
-  int32_t count_reads = 0;
-  unsigned long long* d_count = nullptr;
-};
-
-namespace {
+namespace tci {
 
 tc_status fail(tc_context* c, tc_status st, const char* fmt, ...) {
   char buf[512];
@@ -75,20 +69,12 @@ tc_status hip_fail(tc_context* c, hipError_t e, const char* what) {
               "%s: %s", what, hipGetErrorString(e));
 }
 
-#define TC_HIP(call, what)                              \
-  do {                                                  \
-    hipError_t e_ = (call);                             \
-    if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
-  } while (0)
-
 tc_status set_device(tc_context* ctx) {
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
   return TC_OK;
 }
 
-// Acquire a staging slot of at least `bytes`; waits until its previous use
-// (copy and kernels) has finished.
 tc_status acquire(tc_context* ctx, size_t bytes, Slot** out) {
   Slot& s = ctx->ring[ctx->ring_next];
   ctx->ring_next = (ctx->ring_next + 1) % kRing;
@@ -117,31 +103,6 @@ tc_status release(tc_context* ctx, Slot* s, hipStream_t st) {
   return TC_OK;
 }
 
-bool columns_valid(const uint8_t* F, const uint8_t* B, const uint8_t* T,
-                   int32_t w, int32_t h, size_t stride, int32_t* bad_x,
-                   int32_t* bad_y) {
-  for (int32_t y = 0; y < h; ++y) {
-    const uint8_t* f = F + (size_t)y * stride;
-    const uint8_t* b = B + (size_t)y * stride;
-    const uint8_t* t = T + (size_t)y * stride;
-    for (int32_t x = 0; x < w; ++x) {
-      bool ok = b[x] == 0 ? t[x] == 0 : (b[x] > f[x] && t[x] >= b[x]);
-      if (!ok) {
-        *bad_x = x;
-        *bad_y = y;
-        return false;
-      }
-    }
-  }
-  return true;
-}
-
-int32_t top_level(int32_t W, int32_t H) {
-  int32_t m = std::max(W, H), L = 0;
-  while ((1 << L) < m) ++L;
-  return L;
-}
-
 tci_render_opts render_opts(const tc_context* c) {
   tci_render_opts o;
   o.start_level = c->start_level;
@@ -149,11 +110,185 @@ tci_render_opts render_opts(const tc_context* c) {
   o.xcd_remap = c->xcd_remap;
   o.refill_min = c->refill_min;
   o.refill_iters = c->refill_iters;
+  o.tile_order = c->tile_order;
   o.count = c->count_reads ? c->d_count : nullptr;
   return o;
 }
 
-}  // namespace
+tc_status validate_edits(tc_context* ctx, const tc_edit* edits, int32_t n,
+                         size_t* patch_bytes) {
+  if (n < 0 || n > 65536) return fail(ctx, TC_INVALID_ARG, "edits: bad n %d", n);
+  if (n > 0 && !edits) return fail(ctx, TC_INVALID_ARG, "edits: list is NULL");
+  size_t pb = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const tc_edit& e = edits[i];
+    if (e.kind == TC_EDIT_SET) {
+      if (e.w < 1 || e.h < 1 || e.w > TC_MAX_DIM || e.h > TC_MAX_DIM)
+        return fail(ctx, TC_INVALID_ARG, "edits: edit %d bad size", i);
+      if (!e.floor_top || !e.slab_bottom || !e.slab_top)
+        return fail(ctx, TC_INVALID_ARG, "edits: edit %d null patch", i);
+      int32_t bx, by;
+      if (!columns_valid(e.floor_top, e.slab_bottom, e.slab_top, e.w, e.h, e.w, &bx, &by))
+        return fail(ctx, TC_INVALID_ARG,
+                    "edits: edit %d patch cell (%d,%d) violates the column "
+                    "invariants", i, bx, by);
+      pb += (size_t)3 * e.w * e.h;
+    } else if (e.kind == TC_EDIT_CRATER) {
+      if (e.w < 1 || e.w > 4096 || e.h != e.w)
+        return fail(ctx, TC_INVALID_ARG, "edits: edit %d bad crater size", i);
+      if (e.depth < 0 || e.depth > 255)
+        return fail(ctx, TC_INVALID_ARG, "edits: edit %d bad crater depth", i);
+    } else {
+      return fail(ctx, TC_INVALID_ARG, "edits: edit %d bad kind %d", i, e.kind);
+    }
+    if ((int64_t)e.x0 + e.w > INT32_MAX || (int64_t)e.y0 + e.h > INT32_MAX ||
+        e.x0 < -(1 << 28) || e.y0 < -(1 << 28))
+      return fail(ctx, TC_INVALID_ARG, "edits: edit %d rectangle overflows", i);
+  }
+  *patch_bytes = pb;
+  return TC_OK;
+}
+
+void plan_edits(const tci_map& d, const tc_edit* edits, int32_t n,
+                size_t patch_bytes, char* host, EditPlan& p) {
+  const int32_t top = d.top;
+  p.n = n;
+  p.top = top;
+  p.off_edits = 0;
+  p.off_rects = (sizeof(tci_edit) * (size_t)n + 15) & ~(size_t)15;
+  p.off_patch = p.off_rects + sizeof(int32_t) * 4 * (size_t)n * (size_t)std::max(top, 1);
+  p.total = p.off_patch + patch_bytes;
+  p.nrect.assign(top + 1, 0);
+  p.rmw.assign(top + 1, 1);
+  p.rmh.assign(top + 1, 1);
+  p.max_w = p.max_h = 1;
+  tci_edit* he = host ? (tci_edit*)(host + p.off_edits) : nullptr;
+  int32_t* hr = host ? (int32_t*)(host + p.off_rects) : nullptr;
+  uint8_t* hp = host ? (uint8_t*)(host + p.off_patch) : nullptr;
+  size_t po = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const tc_edit& e = edits[i];
+    if (he) {
+      tci_edit& o = he[i];
+      o.kind = e.kind;
+      o.x0 = e.x0;
+      o.y0 = e.y0;
+      o.w = e.w;
+      o.h = e.h;
+      o.depth = e.depth;
+      o.data_off = (int64_t)po;
+    }
+    if (e.kind == TC_EDIT_SET) {
+      size_t m = (size_t)e.w * e.h;
+      if (hp) {
+        memcpy(hp + po, e.floor_top, m);
+        memcpy(hp + po + m, e.slab_bottom, m);
+        memcpy(hp + po + 2 * m, e.slab_top, m);
+      }
+      po += 3 * m;
+    }
+    int32_t x0 = std::max(e.x0, 0), y0 = std::max(e.y0, 0);
+    int32_t x1 = std::min(e.x0 + e.w, d.W), y1 = std::min(e.y0 + e.h, d.H);
+    if (x0 >= x1 || y0 >= y1) continue;
+    p.max_w = std::max(p.max_w, x1 - x0);
+    p.max_h = std::max(p.max_h, y1 - y0);
+    for (int32_t L = 1; L <= top; ++L) {
+      int32_t r[4] = {x0 >> L, y0 >> L, (x1 - 1) >> L, (y1 - 1) >> L};
+      if (hr) memcpy(hr + 4 * ((size_t)(L - 1) * n + p.nrect[L]), r, sizeof(r));
+      p.rmw[L] = std::max(p.rmw[L], r[2] - r[0] + 1);
+      p.rmh[L] = std::max(p.rmh[L], r[3] - r[1] + 1);
+      p.nrect[L]++;
+    }
+  }
+}
+
+hipError_t enqueue_edits(const tci_map& d, uint32_t* map, const char* dev,
+                         const EditPlan& p, hipStream_t s) {
+  hipError_t e = tci_launch_edits((const tci_edit*)(dev + p.off_edits), p.n,
+                                  (const uint8_t*)(dev + p.off_patch), map, d.lv[0],
+                                  d.W, d.H, p.max_w, p.max_h, s);
+  for (int32_t L = 1; L <= p.top && e == hipSuccess; ++L)
+    e = tci_launch_update_level(d, map, L,
+                                (const int32_t*)(dev + p.off_rects) + 4 * (size_t)(L - 1) * p.n,
+                                p.nrect[L], p.rmw[L], p.rmh[L], s);
+  return e;
+}
+
+tc_status plan_views(tc_context* ctx, const tc_view* views, int32_t n, ViewPlan& p) {
+  if (n < 1 || !views) return fail(ctx, TC_INVALID_ARG, "render: no views");
+  p.n = n;
+  p.views.resize(n);
+  p.prefix.resize((size_t)n + 1);
+  int64_t out = 0, pk = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const tc_view& v = views[i];
+    if (v.width < 1 || v.height < 1 || v.width > 16384 || v.height > 16384)
+      return fail(ctx, TC_INVALID_ARG, "render: view %d bad size %dx%d", i, v.width, v.height);
+    if (v.flags != 0) return fail(ctx, TC_INVALID_ARG, "render: view %d flags != 0", i);
+    for (int cx = 0; cx < 2; ++cx)
+      for (int cy = 0; cy < 2; ++cy) {
+        int64_t a = cx ? 2 * (int64_t)v.width - 1 : 1;
+        int64_t b = cy ? 2 * (int64_t)v.height - 1 : 1;
+        for (int c = 0; c < 3; ++c) {
+          int64_t O = (int64_t)v.o0[c] + a * v.o_px[c] + b * v.o_py[c];
+          int64_t D = (int64_t)v.d0[c] + a * v.d_px[c] + b * v.d_py[c];
+          if (O < INT32_MIN || O > INT32_MAX)
+            return fail(ctx, TC_INVALID_ARG, "render: view %d origin overflows int32", i);
+          if (D < -TC_MAX_DIR || D > TC_MAX_DIR)
+            return fail(ctx, TC_INVALID_ARG, "render: view %d |direction| > 2^23-1", i);
+        }
+      }
+    tci_view& o = p.views[i];
+    o.w = v.width;
+    o.h = v.height;
+    for (int c = 0; c < 3; ++c) {
+      o.o0[c] = v.o0[c]; o.opx[c] = v.o_px[c]; o.opy[c] = v.o_py[c];
+      o.d0[c] = v.d0[c]; o.dpx[c] = v.d_px[c]; o.dpy[c] = v.d_py[c];
+    }
+    o.tiles_x = (v.width + 7) >> 3;
+    o.out_base = out;
+    o.pkt_base = pk;
+    p.prefix[i] = pk;
+    out += (int64_t)v.width * v.height;
+    pk += (int64_t)o.tiles_x * ((v.height + 7) >> 3);
+  }
+  p.prefix[n] = pk;
+  if (out > ((int64_t)1 << 31))
+    return fail(ctx, TC_INVALID_ARG, "render: more than 2^31 rays");
+  p.rays = out;
+  p.npkt = pk;
+  p.off_views = 0;
+  p.off_prefix = (sizeof(tci_view) * (size_t)n + 15) & ~(size_t)15;
+  p.off_counter = (p.off_prefix + sizeof(int64_t) * ((size_t)n + 1) + 15) & ~(size_t)15;
+  p.total = p.off_counter + 64;
+  return TC_OK;
+}
+
+void write_views(const ViewPlan& p, char* host) {
+  memcpy(host + p.off_views, p.views.data(), sizeof(tci_view) * (size_t)p.n);
+  memcpy(host + p.off_prefix, p.prefix.data(), sizeof(int64_t) * ((size_t)p.n + 1));
+  memset(host + p.off_counter, 0, 64);
+}
+
+hipError_t enqueue_render(tc_context* ctx, const tci_map& d, const char* dev,
+                          const ViewPlan& p, void* out, hipStream_t s) {
+  tci_render_opts o = render_opts(ctx);
+  const tci_view* dv = (const tci_view*)(dev + p.off_views);
+  const int64_t* pre = (const int64_t*)(dev + p.off_prefix);
+  if (ctx->render_mode == 2) {
+    uint64_t* counter = (uint64_t*)(dev + p.off_counter);
+    hipError_t e = tci_launch_zero_u64(counter, 1, s);
+    int64_t blocks = (int64_t)ctx->num_cu * ctx->persist_waves / 4;
+    blocks = std::max<int64_t>(1, std::min<int64_t>(blocks, (p.npkt + 3) / 4));
+    if (e == hipSuccess)
+      e = tci_launch_render_persistent(d, dv, p.n, pre, p.npkt, out, counter,
+                                       (int32_t)blocks, o, s);
+    return e;
+  }
+  return tci_launch_render(d, dv, p.n, pre, p.npkt, out, ctx->render_mode == 1, o, s);
+}
+
+}  // namespace tci
 
 extern "C" {
 
@@ -195,7 +330,7 @@ void tc_destroy(tc_context* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
-  for (Slot& s : ctx->ring) {
+  for (tci::Slot& s : ctx->ring) {
     if (s.ev) (void)hipEventDestroy(s.ev);
     if (s.host) (void)hipHostFree(s.host);
     if (s.dev) (void)hipFree(s.dev);
@@ -216,6 +351,7 @@ tc_status tc_load_columns(tc_context* ctx, int32_t W, int32_t H,
   if (!ctx) return TC_INVALID_ARG;
   try {
     ctx->err.clear();
+    if (ctx->server) return fail(ctx, TC_INVALID_ARG, "tc_load_columns: a server owns the map");
     if (W < 1 || H < 1 || W > TC_MAX_DIM || H > TC_MAX_DIM ||
         (int64_t)W * H > TC_MAX_CELLS)
       return fail(ctx, TC_INVALID_ARG, "tc_load_columns: bad map size %dx%d", W, H);
@@ -277,6 +413,7 @@ tc_status tc_load_columns(tc_context* ctx, int32_t W, int32_t H,
       (void)hipFree(ctx->map);
     }
     ctx->map = map;
+    ctx->map_generation++;
     ctx->map_words = words;
     ctx->desc = d;
     ctx->W = W;
@@ -293,156 +430,28 @@ tc_status tc_apply_edit(tc_context* ctx, const tc_edit* edits, int32_t n,
   try {
     ctx->err.clear();
     if (!ctx->map) return fail(ctx, TC_NO_MAP, "tc_apply_edit: no map loaded");
-    if (n < 0 || n > 65536) return fail(ctx, TC_INVALID_ARG, "tc_apply_edit: bad n %d", n);
-    if (n == 0) return TC_OK;
-    if (!edits) return fail(ctx, TC_INVALID_ARG, "tc_apply_edit: edits is NULL");
+    if (ctx->server) return fail(ctx, TC_INVALID_ARG, "tc_apply_edit: a server owns the map");
     size_t patch_bytes = 0;
-    for (int32_t i = 0; i < n; ++i) {
-      const tc_edit& e = edits[i];
-      if (e.kind == TC_EDIT_SET) {
-        if (e.w < 1 || e.h < 1 || e.w > TC_MAX_DIM || e.h > TC_MAX_DIM)
-          return fail(ctx, TC_INVALID_ARG, "tc_apply_edit: edit %d bad size", i);
-        if (!e.floor_top || !e.slab_bottom || !e.slab_top)
-          return fail(ctx, TC_INVALID_ARG, "tc_apply_edit: edit %d null patch", i);
-        int32_t bx, by;
-        if (!columns_valid(e.floor_top, e.slab_bottom, e.slab_top, e.w, e.h, e.w, &bx, &by))
-          return fail(ctx, TC_INVALID_ARG,
-                      "tc_apply_edit: edit %d patch cell (%d,%d) violates the "
-                      "column invariants", i, bx, by);
-        patch_bytes += (size_t)3 * e.w * e.h;
-      } else if (e.kind == TC_EDIT_CRATER) {
-        if (e.w < 1 || e.w > 4096 || e.h != e.w)
-          return fail(ctx, TC_INVALID_ARG, "tc_apply_edit: edit %d bad crater size", i);
-        if (e.depth < 0 || e.depth > 255)
-          return fail(ctx, TC_INVALID_ARG, "tc_apply_edit: edit %d bad crater depth", i);
-      } else {
-        return fail(ctx, TC_INVALID_ARG, "tc_apply_edit: edit %d bad kind %d", i, e.kind);
-      }
-      if ((int64_t)e.x0 + e.w > INT32_MAX || (int64_t)e.y0 + e.h > INT32_MAX ||
-          e.x0 < -(1 << 28) || e.y0 < -(1 << 28))
-        return fail(ctx, TC_INVALID_ARG, "tc_apply_edit: edit %d rectangle overflows", i);
-    }
-    tc_status st = set_device(ctx);
+    tc_status st = tci::validate_edits(ctx, edits, n, &patch_bytes);
+    if (st) return st;
+    if (n == 0) return TC_OK;
+    st = set_device(ctx);
     if (st) return st;
     hipStream_t s = (hipStream_t)hip_stream;
-    const tci_map& d = ctx->desc;
-    const int32_t top = d.top;
-
-    // staging layout: [edits][rects level 1..top][patch bytes]
-    size_t off_edits = 0;
-    size_t off_rects = off_edits + sizeof(tci_edit) * (size_t)n;
-    off_rects = (off_rects + 15) & ~(size_t)15;
-    size_t rect_bytes = sizeof(int32_t) * 4 * (size_t)n * (size_t)std::max(top, 1);
-    size_t off_patch = off_rects + rect_bytes;
-    size_t total = off_patch + patch_bytes;
-    Slot* slot = nullptr;
-    st = acquire(ctx, total, &slot);
+    tci::EditPlan plan;
+    tci::plan_edits(ctx->desc, edits, n, patch_bytes, nullptr, plan);
+    tci::Slot* slot = nullptr;
+    st = tci::acquire(ctx, plan.total, &slot);
     if (st) return st;
-    char* h = (char*)slot->host;
-    tci_edit* he = (tci_edit*)(h + off_edits);
-    int32_t* hr = (int32_t*)(h + off_rects);
-    uint8_t* hp = (uint8_t*)(h + off_patch);
-    size_t po = 0;
-    int32_t max_w = 1, max_h = 1;
-    std::vector<int32_t> nrect(top + 1, 0), rmw(top + 1, 1), rmh(top + 1, 1);
-    for (int32_t i = 0; i < n; ++i) {
-      const tc_edit& e = edits[i];
-      tci_edit& o = he[i];
-      o.kind = e.kind;
-      o.x0 = e.x0;
-      o.y0 = e.y0;
-      o.w = e.w;
-      o.h = e.h;
-      o.depth = e.depth;
-      o.data_off = (int64_t)po;
-      if (e.kind == TC_EDIT_SET) {
-        size_t m = (size_t)e.w * e.h;
-        memcpy(hp + po, e.floor_top, m);
-        memcpy(hp + po + m, e.slab_bottom, m);
-        memcpy(hp + po + 2 * m, e.slab_top, m);
-        po += 3 * m;
-      }
-      int32_t x0 = std::max(e.x0, 0), y0 = std::max(e.y0, 0);
-      int32_t x1 = std::min(e.x0 + e.w, d.W), y1 = std::min(e.y0 + e.h, d.H);
-      if (x0 >= x1 || y0 >= y1) continue;
-      max_w = std::max(max_w, x1 - x0);
-      max_h = std::max(max_h, y1 - y0);
-      for (int32_t L = 1; L <= top; ++L) {
-        int32_t* r = hr + 4 * ((size_t)(L - 1) * n + nrect[L]);
-        r[0] = x0 >> L;
-        r[1] = y0 >> L;
-        r[2] = (x1 - 1) >> L;
-        r[3] = (y1 - 1) >> L;
-        rmw[L] = std::max(rmw[L], r[2] - r[0] + 1);
-        rmh[L] = std::max(rmh[L], r[3] - r[1] + 1);
-        nrect[L]++;
-      }
-    }
-    char* dv = (char*)slot->dev;
-    hipError_t e = hipMemcpyAsync(dv, h, total, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-      e = tci_launch_edits((const tci_edit*)(dv + off_edits), n,
-                           (const uint8_t*)(dv + off_patch), ctx->map, d.lv[0],
-                           d.W, d.H, max_w, max_h, s);
-    for (int32_t L = 1; L <= top && e == hipSuccess; ++L)
-      e = tci_launch_update_level(d, ctx->map, L,
-                                  (const int32_t*)(dv + off_rects) + 4 * (size_t)(L - 1) * n,
-                                  nrect[L], rmw[L], rmh[L], s);
-    st = release(ctx, slot, s);
+    tci::plan_edits(ctx->desc, edits, n, patch_bytes, (char*)slot->host, plan);
+    hipError_t e = hipMemcpyAsync(slot->dev, slot->host, plan.total, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = tci::enqueue_edits(ctx->desc, ctx->map, (const char*)slot->dev, plan, s);
+    st = tci::release(ctx, slot, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "tc_apply_edit");
     return st;
   } catch (...) {
     return fail(ctx, TC_OUT_OF_MEMORY, "tc_apply_edit: host allocation failed");
   }
-}
-
-// Validate views and fill the device view table; returns total rays.
-static tc_status prepare_views(tc_context* ctx, const tc_view* views, int32_t n,
-                               std::vector<tci_view>& dv,
-                               std::vector<int64_t>& prefix, int64_t* rays,
-                               int64_t* npkt) {
-  if (n < 1 || !views) return fail(ctx, TC_INVALID_ARG, "render: no views");
-  dv.resize(n);
-  prefix.resize((size_t)n + 1);
-  int64_t out = 0, pk = 0;
-  for (int32_t i = 0; i < n; ++i) {
-    const tc_view& v = views[i];
-    if (v.width < 1 || v.height < 1 || v.width > 16384 || v.height > 16384)
-      return fail(ctx, TC_INVALID_ARG, "render: view %d bad size %dx%d", i, v.width, v.height);
-    if (v.flags != 0) return fail(ctx, TC_INVALID_ARG, "render: view %d flags != 0", i);
-    for (int cx = 0; cx < 2; ++cx)
-      for (int cy = 0; cy < 2; ++cy) {
-        int64_t a = cx ? 2 * (int64_t)v.width - 1 : 1;
-        int64_t b = cy ? 2 * (int64_t)v.height - 1 : 1;
-        for (int c = 0; c < 3; ++c) {
-          int64_t O = (int64_t)v.o0[c] + a * v.o_px[c] + b * v.o_py[c];
-          int64_t D = (int64_t)v.d0[c] + a * v.d_px[c] + b * v.d_py[c];
-          if (O < INT32_MIN || O > INT32_MAX)
-            return fail(ctx, TC_INVALID_ARG, "render: view %d origin overflows int32", i);
-          if (D < -TC_MAX_DIR || D > TC_MAX_DIR)
-            return fail(ctx, TC_INVALID_ARG, "render: view %d |direction| > 2^23-1", i);
-        }
-      }
-    tci_view& o = dv[i];
-    o.w = v.width;
-    o.h = v.height;
-    for (int c = 0; c < 3; ++c) {
-      o.o0[c] = v.o0[c]; o.opx[c] = v.o_px[c]; o.opy[c] = v.o_py[c];
-      o.d0[c] = v.d0[c]; o.dpx[c] = v.d_px[c]; o.dpy[c] = v.d_py[c];
-    }
-    o.tiles_x = (v.width + 7) >> 3;
-    o.out_base = out;
-    o.pkt_base = pk;
-    prefix[i] = pk;
-    out += (int64_t)v.width * v.height;
-    pk += (int64_t)o.tiles_x * ((v.height + 7) >> 3);
-  }
-  prefix[n] = pk;
-  if (out > ((int64_t)1 << 31))
-    return fail(ctx, TC_INVALID_ARG, "render: more than 2^31 rays");
-  *rays = out;
-  *npkt = pk;
-  return TC_OK;
 }
 
 tc_status tc_render_views(tc_context* ctx, const tc_view* views, int32_t n,
@@ -451,45 +460,23 @@ tc_status tc_render_views(tc_context* ctx, const tc_view* views, int32_t n,
   try {
     ctx->err.clear();
     if (!ctx->map) return fail(ctx, TC_NO_MAP, "tc_render_views: no map loaded");
+    if (ctx->server) return fail(ctx, TC_INVALID_ARG, "tc_render_views: a server owns the map");
     if (!out_device) return fail(ctx, TC_INVALID_ARG, "tc_render_views: out is NULL");
-    std::vector<tci_view> dv;
-    std::vector<int64_t> prefix;
-    int64_t rays = 0, npkt = 0;
-    tc_status st = prepare_views(ctx, views, n, dv, prefix, &rays, &npkt);
+    tci::ViewPlan plan;
+    tc_status st = tci::plan_views(ctx, views, n, plan);
     if (st) return st;
     st = set_device(ctx);
     if (st) return st;
     hipStream_t s = (hipStream_t)hip_stream;
-    size_t off_views = 0;
-    size_t off_prefix = (sizeof(tci_view) * (size_t)n + 15) & ~(size_t)15;
-    size_t off_counter = (off_prefix + sizeof(int64_t) * ((size_t)n + 1) + 15) & ~(size_t)15;
-    size_t total = off_counter + 64;
-    Slot* slot = nullptr;
-    st = acquire(ctx, total, &slot);
+    tci::Slot* slot = nullptr;
+    st = tci::acquire(ctx, plan.total, &slot);
     if (st) return st;
-    char* h = (char*)slot->host;
-    memcpy(h + off_views, dv.data(), sizeof(tci_view) * (size_t)n);
-    memcpy(h + off_prefix, prefix.data(), sizeof(int64_t) * ((size_t)n + 1));
-    char* d = (char*)slot->dev;
-    hipError_t e = hipMemcpyAsync(d, h, off_counter, hipMemcpyHostToDevice, s);
-    tci_render_opts o = render_opts(ctx);
-    if (e == hipSuccess) {
-      if (ctx->render_mode == 2) {
-        uint64_t* counter = (uint64_t*)(d + off_counter);
-        e = tci_launch_zero_u64(counter, 1, s);
-        int64_t blocks = (int64_t)ctx->num_cu * ctx->persist_waves / 4;
-        blocks = std::max<int64_t>(1, std::min<int64_t>(blocks, (npkt + 3) / 4));
-        if (e == hipSuccess)
-          e = tci_launch_render_persistent(ctx->desc, (const tci_view*)(d + off_views), n,
-                                           (const int64_t*)(d + off_prefix), npkt,
-                                           out_device, counter, (int32_t)blocks, o, s);
-      } else {
-        e = tci_launch_render(ctx->desc, (const tci_view*)(d + off_views), n,
-                              (const int64_t*)(d + off_prefix), npkt, out_device,
-                              ctx->render_mode == 1, o, s);
-      }
-    }
-    tc_status rs = release(ctx, slot, s);
+    tci::write_views(plan, (char*)slot->host);
+    hipError_t e = hipMemcpyAsync(slot->dev, slot->host, plan.off_counter,
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = tci::enqueue_render(ctx, ctx->desc, (const char*)slot->dev, plan, out_device, s);
+    tc_status rs = tci::release(ctx, slot, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "tc_render_views");
     return rs;
   } catch (...) {
@@ -514,7 +501,7 @@ tc_status tc_set_option(tc_context* ctx, int32_t key, int64_t value) {
       ctx->max_level = (int32_t)value;
       return TC_OK;
     case TC_OPT_XCD_REMAP:
-      if (value < 0 || value > 1) break;
+      if (value < 0 || value > 4096) break;
       ctx->xcd_remap = (int32_t)value;
       return TC_OK;
     case TC_OPT_PERSIST_WAVES:
@@ -528,6 +515,10 @@ tc_status tc_set_option(tc_context* ctx, int32_t key, int64_t value) {
     case TC_OPT_REFILL_ITERS:
       if (value < 1 || value > 4096) break;
       ctx->refill_iters = (int32_t)value;
+      return TC_OK;
+    case TC_OPT_TILE_ORDER:
+      if (value < 0 || value > 1) break;
+      ctx->tile_order = (int32_t)value;
       return TC_OK;
     case TC_OPT_COUNT_READS:
       if (value < 0 || value > 1) break;
@@ -557,11 +548,11 @@ tc_status tc_get_option(const tc_context* ctx, int32_t key, int64_t* value) {
     case TC_OPT_REFILL_MIN: *value = ctx->refill_min; return TC_OK;
     case TC_OPT_REFILL_ITERS: *value = ctx->refill_iters; return TC_OK;
     case TC_OPT_COUNT_READS: *value = ctx->count_reads; return TC_OK;
+    case TC_OPT_TILE_ORDER: *value = ctx->tile_order; return TC_OK;
     default: return TC_INVALID_ARG;
   }
 }
 
-// Copy tile rows [ty0, ty1] of a level to the host.
 static tc_status read_level_rows(tc_context* ctx, int32_t L, int32_t ty0, int32_t ty1,
                                  std::vector<uint32_t>& buf, hipStream_t s) {
   const tci_level& l = ctx->desc.lv[L];

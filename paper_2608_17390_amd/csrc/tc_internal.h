@@ -58,6 +58,7 @@ struct tci_render_opts {
   int32_t xcd_remap;
   int32_t refill_min;
   int32_t refill_iters;
+  int32_t tile_order;          // 0: packets row-major in a view, 1: column-major
   unsigned long long* count;   // if set: add each ray's node/cell reads
 };
 

@@ -284,14 +284,21 @@ __device__ __forceinline__ int32_t walk_steps(const tci_map& m,
       ko = ex ? count_below(Kxe, s.Ky, r.ax) : count_below(Kye + 1, s.Kx, r.ay);
     const int32_t kx = ex ? km1 + 1 : ko;
     const int32_t ky = ex ? ko : km1 + 1;
-    if (kFlat) {
-      if (ex) { s.Kx += (int64_t)r.ay << 16; s.Zx += SZ; }
-      else    { s.Ky += (int64_t)r.ax << 16; s.Zy += SZ; }
+    // exit axis: one step past its exit crossing; other axis: ko steps
+    if (ex) {
+      s.Kx = Kxe + ((int64_t)r.ay << 16);
+      s.Zx = Ze + SZ;
+      if (!kFlat && ko) {
+        s.Ky += (int64_t)(mul48((uint32_t)ko, r.ax) << 16);
+        s.Zy += smul48(ko, r.Dz) << 16;
+      }
     } else {
-      s.Kx += (int64_t)(mul48((uint32_t)kx, r.ay) << 16);
-      s.Ky += (int64_t)(mul48((uint32_t)ky, r.ax) << 16);
-      s.Zx += smul48(kx, r.Dz) << 16;
-      s.Zy += smul48(ky, r.Dz) << 16;
+      s.Ky = Kye + ((int64_t)r.ax << 16);
+      s.Zy = Ze + SZ;
+      if (!kFlat && ko) {
+        s.Kx += (int64_t)(mul48((uint32_t)ko, r.ay) << 16);
+        s.Zx += smul48(ko, r.Dz) << 16;
+      }
     }
     const int32_t pcx = s.cx, pcy = s.cy;
     s.cx += r.Dx > 0 ? kx : -kx;
@@ -330,6 +337,24 @@ __device__ __forceinline__ int32_t find_view(const int64_t* pkt_prefix,
   return lo;
 }
 
+// Pixel of ray `k` (0..63, row-major in an 8x8 block) of packet `t` of a
+// view; packets run row-major (order 0) or column-major (order 1).
+__device__ __forceinline__ void packet_pixel(const tci_view& v, int64_t t,
+                                             int32_t k, int32_t order,
+                                             int32_t& px, int32_t& py) {
+  int32_t tx, ty;
+  if (order) {
+    const int32_t tiles_y = (v.h + 7) >> 3;
+    tx = (int32_t)(t / tiles_y);
+    ty = (int32_t)(t % tiles_y);
+  } else {
+    tx = (int32_t)(t % v.tiles_x);
+    ty = (int32_t)(t / v.tiles_x);
+  }
+  px = tx * 8 + (k & 7);
+  py = ty * 8 + (k >> 3);
+}
+
 __device__ __forceinline__ void store_hit(void* out, int64_t idx,
                                           uint32_t word, float depth) {
   uint2 h;
@@ -353,18 +378,22 @@ __global__ __launch_bounds__(256) void render_kernel(
   // XCD-aware order: consecutive hardware blocks go to different XCDs, so
   // hand each XCD a contiguous range of packets to share its L2.
   int64_t nb = gridDim.x, b = blockIdx.x;
-  if (o.xcd_remap) {
-    int64_t per = nb / 8;
-    if (b < per * 8) b = (b & 7) * per + (b >> 3);
+  if (o.xcd_remap > 0) {
+    // hardware block r of a group of 8G runs on XCD r % 8; give each XCD
+    // G consecutive logical blocks of the group
+    const int64_t G = o.xcd_remap, group = 8 * G;
+    if (b < (nb / group) * group) {
+      const int64_t g = b / group, r = b - g * group;
+      b = g * group + (r & 7) * G + (r >> 3);
+    }
   }
   const int32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t p = b * 4 + wave;
   if (p >= npkt) return;
   const int32_t vi = __builtin_amdgcn_readfirstlane(find_view(pkt_prefix, nviews, p));
   const tci_view& v = views[vi];
-  const int64_t t = p - v.pkt_base;
-  const int32_t px = (int32_t)(t % v.tiles_x) * 8 + (lane & 7);
-  const int32_t py = (int32_t)(t / v.tiles_x) * 8 + (lane >> 3);
+  int32_t px, py;
+  packet_pixel(v, p - v.pkt_base, lane, o.tile_order, px, py);
   if (px >= v.w || py >= v.h) return;
   ray_t r;
   pixel_ray(v, px, py, r);
@@ -433,9 +462,8 @@ __global__ __launch_bounds__(256) void render_persistent_kernel(
         if (mypkt >= 0 && mypkt < npkt && myray < 64) {
           const int32_t vi = find_view(pkt_prefix, nviews, mypkt);
           const tci_view& v = views[vi];
-          const int64_t t = mypkt - v.pkt_base;
-          const int32_t px = (int32_t)(t % v.tiles_x) * 8 + (myray & 7);
-          const int32_t py = (int32_t)(t / v.tiles_x) * 8 + (myray >> 3);
+          int32_t px, py;
+          packet_pixel(v, mypkt - v.pkt_base, myray, o.tile_order, px, py);
           if (px < v.w && py < v.h) {
             pixel_ray(v, px, py, r);
             out_idx = v.out_base + (int64_t)py * v.w + px;

@@ -1,0 +1,129 @@
+"""Captured frames (edits -> dirty pyramid update -> render in one HIP
+graph) and the autotuner, against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+tc = pytest.importorskip("paper_2608_17390_amd")
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from test_gpu_parity import assert_parity, load, gpu_render, MODES  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available()
+    c = tc.Context(0)
+    yield c
+    c.close()
+
+
+def _outbuf(views):
+    return torch.empty((synth.view_rays(views), 2), dtype=torch.int32, device="cuda")
+
+
+@pytest.mark.parametrize("mode", ["hier", "persistent"])
+def test_frame_replays_apply_edits_each_time(ctx, mode):
+    F, B, T = synth.make_map_from_config(1)
+    load(ctx, F, B, T)
+    ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, MODES[mode])
+    rng = np.random.default_rng(50)
+    views = synth.config_views(1, F, B) + [
+        synth.shadow_view(30, 40, 64, 35.0, 70.0),
+        synth.perspective_view(synth.eye_above_floor(F, B, 60.5, 200.5), 200, -20, 77, 45)]
+    edits = (synth.crater_list(51, 256, 256, 6, size=(8, 40), depth=(10, 60)) +
+             synth.random_set_patches(52, 256, 256, 3, max_size=20))
+    out = _outbuf(views)
+    frame = ctx.tc_frame_create(views, edits, out.data_ptr())
+    assert frame.rays == synth.view_rays(views)
+    Fk, Bk, Tk = F, B, T
+    for k in range(3):
+        frame.launch()
+        torch.cuda.synchronize()
+        wg, dg = tc.split_hits(out)
+        Fk, Bk, Tk = oracle.apply_edits(Fk, Bk, Tk, edits)
+        wo, do = oracle.render(Fk, Bk, Tk, views)
+        assert_parity(wg, dg, wo, do, "frame replay %d" % k)
+        # eager work between replays
+        junk = torch.ones(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert float(junk) == float(1 << 20)
+    g = ctx.tc_read_columns(0, 0, 256, 256)
+    assert np.array_equal(g[0], Fk) and np.array_equal(g[1], Bk)
+    levels = ctx.tc_pyramid_info()
+    for L in range(1, levels + 1):
+        assert np.array_equal(ctx.tc_read_pyramid(L), oracle.pyramid_level_fast(Fk, Bk, Tk, L))
+    frame.close()
+    ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, 0)
+
+
+def test_frame_without_edits_and_reload_invalidates(ctx):
+    F, B, T = synth.make_map_from_config(1)
+    load(ctx, F, B, T)
+    views = synth.config_views(1, F, B)
+    out = _outbuf(views)
+    frame = ctx.tc_frame_create(views, [], out.data_ptr())
+    for _ in range(4):
+        frame.launch()
+    torch.cuda.synchronize()
+    wo, do = oracle.render(F, B, T, views)
+    wg, dg = tc.split_hits(out)
+    assert_parity(wg, dg, wo, do, "frame no edits")
+    load(ctx, F, B, T)
+    with pytest.raises(tc.TCError) as e:
+        frame.launch()
+    assert e.value.status == tc.TC_INVALID_ARG
+    frame.close()
+
+
+def test_autotune_keeps_results(ctx):
+    F, B, T = synth.make_map_from_config(2)
+    load(ctx, F, B, T)
+    views = synth.config_views(2, F, B)
+    ref = gpu_render(ctx, views, "hier")
+    out = _outbuf(views)
+    best = ctx.tc_autotune(views, out.data_ptr(), reps=2)
+    assert best["tried"] >= 24 and best["ms"] > 0
+    assert best["render_mode"] in (0, 2)
+    assert ctx.tc_get_option(tc.TC_OPT_RENDER_MODE) == best["render_mode"]
+    out2 = tc.render(ctx, views)
+    torch.cuda.synchronize()
+    w, d = tc.split_hits(out2)
+    assert np.array_equal(w, ref[0]) and np.array_equal(d.view(np.uint32), ref[1].view(np.uint32))
+    ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, 0)
+    ctx.tc_set_option(tc.TC_OPT_START_LEVEL, 2)
+    ctx.tc_set_option(tc.TC_OPT_TILE_ORDER, 1)
+    ctx.tc_set_option(tc.TC_OPT_XCD_REMAP, 0)
+
+
+def test_c4_frame_sampled(ctx):
+    """Configuration 4: 64 views + 8 shadow passes + 16 craters, one graph
+    launch, checked on sampled pixels against the oracle's edited map."""
+    F, B, T = synth.make_map_from_config(4)
+    H, W = F.shape
+    load(ctx, F, B, T)
+    views = synth.config_views(4, F, B)
+    edits = synth.crater_list(synth.SEEDS[4]["edits"], W, H, 16, size=32)
+    out = _outbuf(views)
+    ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, 2)
+    frame = ctx.tc_frame_create(views, edits, out.data_ptr())
+    frame.launch()
+    torch.cuda.synchronize()
+    wg, dg = tc.split_hits(out)
+    F2, B2, T2 = oracle.apply_edits(F, B, T, edits)
+    va = synth.views_array(views)
+    base = np.concatenate([[0], np.cumsum(va["width"].astype(np.int64) * va["height"])])
+    rng = np.random.default_rng(45)
+    n = 30000
+    vi = rng.integers(0, len(views), n).astype(np.int32)
+    px = (rng.random(n) * va["width"][vi]).astype(np.int32)
+    py = (rng.random(n) * va["height"][vi]).astype(np.int32)
+    wo, do = oracle.cast_pixels(F2, B2, T2, views, vi, px, py)
+    idx = base[vi] + py.astype(np.int64) * va["width"][vi] + px
+    assert_parity(wg[idx], dg[idx], wo, do, "c4 frame")
+    frame.close()
+    ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, 0)

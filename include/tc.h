@@ -49,6 +49,7 @@ typedef int32_t tc_status;
 #define TC_NO_MAP (-3)
 #define TC_DEVICE_ERROR (-4)
 #define TC_OVER_BUDGET (-5)
+#define TC_TIMEOUT (-6)
 
 #define TC_S 65536                 /* fixed-point cells per unit */
 #define TC_MAX_DIM 16384           /* max W and H */
@@ -224,6 +225,60 @@ typedef struct tc_tune_result {
 tc_status tc_autotune(tc_context *ctx, const tc_view *views, int32_t n,
                       tc_hit *out_device, int32_t reps, void *hip_stream,
                       tc_tune_result *best);
+
+/* ---- request server -------------------------------------------------------
+ * Keeps the map resident and serves view and edit requests submitted from
+ * any thread (Section 2: edits are gameplay operations that must show up
+ * without a reload; Section 7: the paper's frames run one at a time).  A
+ * server thread admits requests strictly in submission order; a view is
+ * admitted once its hit buffer fits in a device pool of budget_bytes (the
+ * in-flight budget), and admitted views are launched together, up to
+ * max_batch_views per render, on one of `streams` streams, so work that
+ * arrives while other batches run overlaps them on the device.  A view sees
+ * exactly the edits submitted before it: the map is kept in two version
+ * buffers and an edit is applied to a copy of the newest version once no
+ * batch reads the other buffer.  While a server runs it owns the map:
+ * tc_load_columns, tc_apply_edit, tc_render_views and frames on the context
+ * fail with TC_INVALID_ARG, and the render knobs must not change.
+ * tc_server_stop drains all submitted work and leaves the newest map
+ * version in the context. */
+typedef struct tc_server tc_server;
+#define TC_SERVER_AUTO_RELEASE 1u /* free a view's hit buffer when it is done
+                                     (its result is discarded) */
+tc_status tc_server_start(tc_context *ctx, uint64_t budget_bytes,
+                          int32_t max_batch_views, int32_t streams,
+                          uint32_t flags, tc_server **out);
+/* Queue a view; *id identifies it.  TC_OVER_BUDGET if its hit buffer alone
+ * exceeds the budget; validation as for tc_render_views. */
+tc_status tc_server_submit_view(tc_server *s, const tc_view *view, uint64_t *id);
+/* Queue an edit list (applied in order, as tc_apply_edit); SET patches are
+ * copied before return. */
+tc_status tc_server_submit_edit(tc_server *s, const tc_edit *edits, int32_t n,
+                                uint64_t *id);
+/* State of a request: 0 queued, 1 on the device, 2 done; latency from
+ * submission to observed completion in seconds (-1 until done). */
+tc_status tc_server_poll(tc_server *s, uint64_t id, int32_t *state,
+                         double *latency_s);
+/* Block until the request is done (TC_OK) or timeout_s passes (TC_TIMEOUT). */
+tc_status tc_server_wait(tc_server *s, uint64_t id, double timeout_s);
+/* Device pointer to a finished view's hit records (width*height, rows
+ * top-down), valid until tc_server_release. */
+tc_status tc_server_result(tc_server *s, uint64_t id, const tc_hit **device_ptr,
+                           int64_t *records);
+/* Copy a finished view's hit records to host memory (`records` entries;
+ * must equal width*height).  Synchronous. */
+tc_status tc_server_read(tc_server *s, uint64_t id, tc_hit *host_dst,
+                         int64_t records);
+/* Forget a finished request and return its hit buffer to the pool. */
+tc_status tc_server_release(tc_server *s, uint64_t id);
+typedef struct tc_server_stats {
+  uint64_t batches, edits, views, rays;
+  uint64_t peak_bytes;   /* largest pool use seen */
+  uint64_t bytes_in_use;
+} tc_server_stats;
+tc_status tc_server_get_stats(tc_server *s, tc_server_stats *out);
+/* Finish every submitted request, stop the thread and free the server. */
+tc_status tc_server_stop(tc_server *s);
 
 /* ---- inspection (tests, checkpoints) ---------------------------------- */
 /* Copy the w x h rectangle at (x0, y0) of the current map into host arrays

@@ -4,10 +4,11 @@ The product is libtc.so (HIP kernels for gfx950 behind the C ABI of
 include/tc.h); this package holds its sources (csrc/), its build step
 (build.py) and a thin ctypes binding (_tc.py) with the same names.
 """
-from ._tc import (Context, Frame, TCError, tc_create, tc_view, tc_edit, render,
+from ._tc import (Context, Frame, Server, TCError, tc_create, tc_view, tc_edit, render,
                   split_hits, view_total_rays, load_library, LIB_PATH,
                   SIGNATURES, TC_OK, TC_INVALID_ARG, TC_OUT_OF_MEMORY,
-                  TC_NO_MAP, TC_DEVICE_ERROR, TC_OVER_BUDGET, TC_MISS,
+                  TC_NO_MAP, TC_DEVICE_ERROR, TC_OVER_BUDGET, TC_TIMEOUT,
+                  TC_SERVER_AUTO_RELEASE, TC_MISS,
                   TC_EDIT_SET, TC_EDIT_CRATER, TC_OPT_RENDER_MODE,
                   TC_OPT_START_LEVEL, TC_OPT_MAX_LEVEL, TC_OPT_XCD_REMAP,
                   TC_OPT_PERSIST_WAVES, TC_OPT_REFILL_MIN,

@@ -20,6 +20,8 @@ TC_OUT_OF_MEMORY = -2
 TC_NO_MAP = -3
 TC_DEVICE_ERROR = -4
 TC_OVER_BUDGET = -5
+TC_TIMEOUT = -6
+TC_SERVER_AUTO_RELEASE = 1
 TC_S = 65536
 TC_MISS = 0xFFFFFFFF
 TC_EDIT_SET = 1
@@ -36,7 +38,8 @@ TC_OPT_COUNT_READS = 8
 TC_OPT_TILE_ORDER = 9
 
 _STATUS = {0: "TC_OK", -1: "TC_INVALID_ARG", -2: "TC_OUT_OF_MEMORY",
-           -3: "TC_NO_MAP", -4: "TC_DEVICE_ERROR", -5: "TC_OVER_BUDGET"}
+           -3: "TC_NO_MAP", -4: "TC_DEVICE_ERROR", -5: "TC_OVER_BUDGET",
+           -6: "TC_TIMEOUT"}
 
 
 class tc_view(ctypes.Structure):
@@ -61,6 +64,12 @@ class tc_tune_result(ctypes.Structure):
                 ("persist_waves", ctypes.c_int32), ("refill_min", ctypes.c_int32),
                 ("refill_iters", ctypes.c_int32), ("ms", ctypes.c_float),
                 ("tried", ctypes.c_int32)]
+
+
+class tc_server_stats(ctypes.Structure):
+    _fields_ = [("batches", ctypes.c_uint64), ("edits", ctypes.c_uint64),
+                ("views", ctypes.c_uint64), ("rays", ctypes.c_uint64),
+                ("peak_bytes", ctypes.c_uint64), ("bytes_in_use", ctypes.c_uint64)]
 
 
 assert ctypes.sizeof(tc_view) == 84
@@ -88,6 +97,20 @@ SIGNATURES = [
     ("tc_frame_launch", _I32, [_P, _P]),
     ("tc_frame_rays", _I32, [_P, ctypes.POINTER(ctypes.c_int64)]),
     ("tc_frame_destroy", None, [_P]),
+    ("tc_server_start", _I32, [_P, ctypes.c_uint64, _I32, _I32, ctypes.c_uint32,
+                               ctypes.POINTER(_P)]),
+    ("tc_server_submit_view", _I32, [_P, ctypes.POINTER(tc_view), ctypes.POINTER(ctypes.c_uint64)]),
+    ("tc_server_submit_edit", _I32, [_P, ctypes.POINTER(tc_edit), _I32,
+                                     ctypes.POINTER(ctypes.c_uint64)]),
+    ("tc_server_poll", _I32, [_P, ctypes.c_uint64, ctypes.POINTER(_I32),
+                              ctypes.POINTER(ctypes.c_double)]),
+    ("tc_server_wait", _I32, [_P, ctypes.c_uint64, ctypes.c_double]),
+    ("tc_server_result", _I32, [_P, ctypes.c_uint64, ctypes.POINTER(_P),
+                                ctypes.POINTER(ctypes.c_int64)]),
+    ("tc_server_read", _I32, [_P, ctypes.c_uint64, _P, ctypes.c_int64]),
+    ("tc_server_release", _I32, [_P, ctypes.c_uint64]),
+    ("tc_server_get_stats", _I32, [_P, ctypes.POINTER(tc_server_stats)]),
+    ("tc_server_stop", _I32, [_P]),
     ("tc_autotune", _I32, [_P, ctypes.POINTER(tc_view), _I32, _P, _I32, _P,
                            ctypes.POINTER(tc_tune_result)]),
 ]
@@ -304,6 +327,9 @@ class Context:
         _check(self._h, st)
         return {f: getattr(r, f) for f, _ in tc_tune_result._fields_}
 
+    def tc_server_start(self, budget_bytes, max_batch_views=64, streams=4, flags=0):
+        return Server(self, budget_bytes, max_batch_views, streams, flags)
+
     def tc_map_bytes(self):
         v = ctypes.c_uint64()
         _check(self._h, load_library().tc_map_bytes(self._h, ctypes.byref(v)))
@@ -331,6 +357,68 @@ class Frame:
     def __del__(self):
         try:
             self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request server over a context's map."""
+
+    def __init__(self, ctx, budget_bytes, max_batch_views=64, streams=4, flags=0):
+        self._ctx = ctx
+        h = ctypes.c_void_p()
+        st = load_library().tc_server_start(ctx.handle, int(budget_bytes), int(max_batch_views),
+                                            int(streams), int(flags), ctypes.byref(h))
+        _check(ctx.handle, st)
+        self._h = h
+
+    def _chk(self, st):
+        _check(self._ctx.handle, st)
+
+    def tc_server_submit_view(self, view):
+        arr = _views_struct([view])
+        rid = ctypes.c_uint64()
+        self._chk(load_library().tc_server_submit_view(self._h, arr, ctypes.byref(rid)))
+        return rid.value
+
+    def tc_server_submit_edit(self, edits):
+        arr, keep = _edits_struct(list(edits))
+        rid = ctypes.c_uint64()
+        st = load_library().tc_server_submit_edit(self._h, arr, len(edits), ctypes.byref(rid))
+        del keep
+        self._chk(st)
+        return rid.value
+
+    def tc_server_poll(self, rid):
+        state, lat = ctypes.c_int32(), ctypes.c_double()
+        self._chk(load_library().tc_server_poll(self._h, rid, ctypes.byref(state),
+                                                ctypes.byref(lat)))
+        return state.value, lat.value
+
+    def tc_server_wait(self, rid, timeout_s=60.0):
+        self._chk(load_library().tc_server_wait(self._h, rid, float(timeout_s)))
+
+    def tc_server_read(self, rid, records):
+        out = np.empty((records, 2), np.uint32)
+        self._chk(load_library().tc_server_read(self._h, rid, out.ctypes.data, records))
+        return out[:, 0].copy(), out[:, 1].view(np.float32).copy()
+
+    def tc_server_release(self, rid):
+        self._chk(load_library().tc_server_release(self._h, rid))
+
+    def tc_server_get_stats(self):
+        st = tc_server_stats()
+        self._chk(load_library().tc_server_get_stats(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in tc_server_stats._fields_}
+
+    def tc_server_stop(self):
+        if self._h:
+            h, self._h = self._h, None
+            self._chk(load_library().tc_server_stop(h))
+
+    def __del__(self):
+        try:
+            self.tc_server_stop()
         except Exception:
             pass
 

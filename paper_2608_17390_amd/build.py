@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtc.so")
 INCLUDE = os.path.join(ROOT, "include")
-SOURCES = ["tc_map.hip", "tc_render.hip", "tc_api.cpp", "tc_frame.cpp"]
+SOURCES = ["tc_map.hip", "tc_render.hip", "tc_api.cpp", "tc_frame.cpp",
+           "tc_server.cpp"]
 ARCH = os.environ.get("TC_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

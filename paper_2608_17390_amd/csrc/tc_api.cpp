@@ -328,6 +328,7 @@ tc_status tc_create(int hip_device, tc_context** out) {
 
 void tc_destroy(tc_context* ctx) {
   if (!ctx) return;
+  if (ctx->server) (void)tc_server_stop((tc_server*)ctx->server);
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   for (tci::Slot& s : ctx->ring) {

@@ -1,0 +1,651 @@
+// Continuous-batching request server.
+//
+// The map and its pyramid stay resident; view and edit requests arrive
+// from any client thread and one server thread turns them into GPU work:
+//
+//  * admission: requests are taken strictly in submission order; a view is
+//    admitted when its hit buffer fits in the device pool (the in-flight
+//    budget), otherwise it and everything behind it wait for releases;
+//  * batching: admitted views are launched together as one render call on
+//    one of several streams, so batches that arrive while others run
+//    overlap on the device;
+//  * edits: the map lives in two version buffers.  A view renders the
+//    version holding exactly the edits submitted before it.  An edit is
+//    applied by copying the newest version into the other buffer -- once no
+//    batch still reads that buffer -- and editing it there, on a separate
+//    stream; batches of later views wait for that edit's event.  A view's
+//    result is therefore the same alone and in any mix.
+//
+// Section 2 of the paper: edits are gameplay operations whose results must
+// be visible without reloading; Section 7: its frames are submitted and
+// awaited one at a time, with nothing overlapping.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "tc_context.h"
+
+using tci::fail;
+using tci::hip_fail;
+
+namespace {
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+enum : int32_t { kQueued = 0, kInFlight = 1, kDone = 2 };
+
+struct Request {
+  uint64_t id = 0;
+  bool is_edit = false;
+  tc_view view{};
+  std::vector<tc_edit> edits;
+  std::vector<uint8_t> patch;
+  uint64_t epoch = 0;       // views: edits before it; edits: its number
+  size_t bytes = 0;
+  size_t pool_off = 0;
+  bool has_mem = false;
+  int32_t state = kQueued;
+  double t_submit = 0, t_done = 0;
+  int64_t rays = 0;
+};
+
+// First-fit allocator over [0, size) with 256-byte granules.
+class Pool {
+ public:
+  void reset(size_t size) {
+    free_.clear();
+    if (size) free_[0] = size;
+    used_ = 0;
+  }
+  bool alloc(size_t n, size_t* off) {
+    n = (n + 255) & ~(size_t)255;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= n) {
+        *off = it->first;
+        size_t rest = it->second - n, o = it->first + n;
+        free_.erase(it);
+        if (rest) free_[o] = rest;
+        used_ += n;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t n) {
+    n = (n + 255) & ~(size_t)255;
+    used_ -= n;
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t used() const { return used_; }
+
+ private:
+  std::map<size_t, size_t> free_;
+  size_t used_ = 0;
+};
+
+struct Batch {
+  std::vector<uint64_t> ids;
+  int version = 0;
+  hipEvent_t done = nullptr;
+  tci::Slot slot;
+  bool busy = false;
+  hipStream_t stream = nullptr;
+};
+
+}  // namespace
+
+struct tc_server {
+  tc_context* ctx = nullptr;
+  uint32_t flags = 0;
+  size_t budget = 0;
+  int32_t max_batch = 64;
+  char* pool_dev = nullptr;
+  Pool pool;
+  // map versions: buffer pointers, the epoch each holds, batches reading it
+  uint32_t* ver[2] = {nullptr, nullptr};
+  uint64_t ver_epoch[2] = {0, 0};
+  int ver_readers[2] = {0, 0};
+  int current = 0;
+  bool own_ver[2] = {false, false};
+  hipStream_t edit_stream = nullptr;
+  hipEvent_t edit_ev = nullptr;           // end of the newest edit
+  std::deque<std::pair<uint64_t, hipEvent_t>> edits_in_flight;
+  tci::Slot edit_slot;
+  std::vector<Batch> slots;
+  // request state (guarded by mu)
+  std::mutex mu;
+  std::condition_variable cv_done;
+  std::unordered_map<uint64_t, Request> reqs;
+  std::deque<uint64_t> incoming;
+  uint64_t next_id = 1;
+  uint64_t edits_submitted = 0;
+  // owned by the server thread
+  std::deque<uint64_t> fifo;
+  std::vector<uint64_t> admitted;
+  std::thread thread;
+  std::atomic<bool> stop{false};
+  std::atomic<int> error{0};
+  std::string err;
+  // statistics
+  std::atomic<uint64_t> st_batches{0}, st_edits{0}, st_views{0}, st_rays{0};
+  std::atomic<uint64_t> st_peak_bytes{0};
+};
+
+namespace {
+
+tci_map version_desc(const tc_server* s, int v) {
+  tci_map d = s->ctx->desc;
+  d.base = s->ver[v];
+  return d;
+}
+
+void set_error(tc_server* s, hipError_t e, const char* what) {
+  std::lock_guard<std::mutex> g(s->mu);
+  if (!s->error.load()) {
+    s->err = std::string(what) + ": " + hipGetErrorString(e);
+    s->error.store(1);
+  }
+  s->cv_done.notify_all();
+}
+
+void complete(tc_server* s, const std::vector<uint64_t>& ids, double t) {
+  std::lock_guard<std::mutex> g(s->mu);
+  for (uint64_t id : ids) {
+    auto it = s->reqs.find(id);
+    if (it == s->reqs.end()) continue;
+    Request& r = it->second;
+    r.state = kDone;
+    r.t_done = t;
+    if (!r.is_edit) {
+      s->st_views++;
+      s->st_rays += (uint64_t)r.rays;
+      if ((s->flags & TC_SERVER_AUTO_RELEASE) && r.has_mem) {
+        s->pool.release(r.pool_off, r.bytes);
+        r.has_mem = false;
+      }
+    }
+  }
+  s->cv_done.notify_all();
+}
+
+// Launch the admitted views as one batch; returns false if no stream slot
+// is free.
+bool launch_batch(tc_server* s) {
+  if (s->admitted.empty()) return true;
+  Batch* b = nullptr;
+  for (Batch& c : s->slots)
+    if (!c.busy) { b = &c; break; }
+  if (!b) return false;
+  tc_context* ctx = s->ctx;
+  std::vector<tc_view> views;
+  std::vector<size_t> offs;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    for (uint64_t id : s->admitted) {
+      Request& r = s->reqs[id];
+      views.push_back(r.view);
+      offs.push_back(r.pool_off);
+      r.state = kInFlight;
+    }
+  }
+  tci::ViewPlan plan;
+  if (tci::plan_views(ctx, views.data(), (int32_t)views.size(), plan) != TC_OK) {
+    set_error(s, hipErrorInvalidValue, "server: view validation");
+    return true;
+  }
+  for (size_t i = 0; i < views.size(); ++i) plan.views[i].out_base = (int64_t)(offs[i] / 8);
+  if (b->slot.cap < plan.total) {
+    if (b->slot.host) (void)hipHostFree(b->slot.host);
+    if (b->slot.dev) (void)hipFree(b->slot.dev);
+    b->slot.host = b->slot.dev = nullptr;
+    size_t cap = std::max<size_t>(plan.total, 64 << 10);
+    hipError_t e = hipHostMalloc(&b->slot.host, cap, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc(&b->slot.dev, cap);
+    if (e != hipSuccess) {
+      set_error(s, e, "server: staging allocation");
+      return true;
+    }
+    b->slot.cap = cap;
+  }
+  tci::write_views(plan, (char*)b->slot.host);
+  const int v = s->current;
+  hipError_t e = hipStreamWaitEvent(b->stream, s->edit_ev, 0);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->slot.dev, b->slot.host, plan.off_counter, hipMemcpyHostToDevice,
+                       b->stream);
+  if (e == hipSuccess)
+    e = tci::enqueue_render(ctx, version_desc(s, v), (const char*)b->slot.dev, plan,
+                            s->pool_dev, b->stream);
+  if (e == hipSuccess) e = hipEventRecord(b->done, b->stream);
+  if (e != hipSuccess) {
+    set_error(s, e, "server: render launch");
+    return true;
+  }
+  b->ids.swap(s->admitted);
+  s->admitted.clear();
+  b->version = v;
+  b->busy = true;
+  s->ver_readers[v]++;
+  s->st_batches++;
+  return true;
+}
+
+// Apply the edit request at the head of the queue, if the target version
+// buffer is free.  Returns true if it was applied.
+bool apply_edit(tc_server* s, uint64_t id) {
+  const int tgt = 1 - s->current;
+  if (s->ver_readers[tgt] > 0) return false;
+  tc_context* ctx = s->ctx;
+  Request* r;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    r = &s->reqs[id];
+    r->state = kInFlight;
+  }
+  // copy the newest version into the target, then edit the target
+  tci::EditPlan plan;
+  size_t patch_bytes = r->patch.size();
+  const tci_map d = version_desc(s, tgt);
+  tci::plan_edits(d, r->edits.data(), (int32_t)r->edits.size(), patch_bytes, nullptr, plan);
+  if (s->edit_slot.cap < plan.total) {
+    (void)hipStreamSynchronize(s->edit_stream);
+    if (s->edit_slot.host) (void)hipHostFree(s->edit_slot.host);
+    if (s->edit_slot.dev) (void)hipFree(s->edit_slot.dev);
+    s->edit_slot.host = s->edit_slot.dev = nullptr;
+    size_t cap = std::max<size_t>(plan.total, 64 << 10);
+    hipError_t e = hipHostMalloc(&s->edit_slot.host, cap, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc(&s->edit_slot.dev, cap);
+    if (e != hipSuccess) {
+      set_error(s, e, "server: edit staging");
+      return true;
+    }
+    s->edit_slot.cap = cap;
+  } else if (s->edit_slot.pending) {
+    // the previous edit's upload must be consumed before the buffer is reused
+    (void)hipEventSynchronize(s->edit_slot.ev);
+  }
+  tci::plan_edits(d, r->edits.data(), (int32_t)r->edits.size(), patch_bytes,
+                  (char*)s->edit_slot.host, plan);
+  hipError_t e = hipMemcpyAsync(s->ver[tgt], s->ver[s->current], ctx->map_words * 4,
+                                hipMemcpyDeviceToDevice, s->edit_stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->edit_slot.dev, s->edit_slot.host, plan.total,
+                       hipMemcpyHostToDevice, s->edit_stream);
+  if (e == hipSuccess)
+    e = tci::enqueue_edits(d, s->ver[tgt], (const char*)s->edit_slot.dev, plan, s->edit_stream);
+  hipEvent_t ev = nullptr;
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(ev, s->edit_stream);
+  if (e == hipSuccess) e = hipEventRecord(s->edit_ev, s->edit_stream);
+  if (e == hipSuccess) e = hipEventRecord(s->edit_slot.ev, s->edit_stream);
+  if (e != hipSuccess) {
+    set_error(s, e, "server: edit launch");
+    return true;
+  }
+  s->edit_slot.pending = true;
+  s->ver_epoch[tgt] = r->epoch;
+  s->current = tgt;
+  s->edits_in_flight.emplace_back(id, ev);
+  s->st_edits++;
+  return true;
+}
+
+void poll_completions(tc_server* s) {
+  for (Batch& b : s->slots) {
+    if (!b.busy) continue;
+    hipError_t q = hipEventQuery(b.done);
+    if (q == hipErrorNotReady) continue;
+    if (q != hipSuccess) {
+      set_error(s, q, "server: batch");
+      continue;
+    }
+    complete(s, b.ids, now_s());
+    b.ids.clear();
+    b.busy = false;
+    s->ver_readers[b.version]--;
+  }
+  while (!s->edits_in_flight.empty()) {
+    auto& f = s->edits_in_flight.front();
+    hipError_t q = hipEventQuery(f.second);
+    if (q == hipErrorNotReady) break;
+    (void)hipEventDestroy(f.second);
+    complete(s, {f.first}, now_s());
+    s->edits_in_flight.pop_front();
+  }
+}
+
+void server_loop(tc_server* s) {
+  (void)hipSetDevice(s->ctx->device);
+  while (true) {
+    {
+      std::lock_guard<std::mutex> g(s->mu);
+      while (!s->incoming.empty()) {
+        s->fifo.push_back(s->incoming.front());
+        s->incoming.pop_front();
+      }
+    }
+    poll_completions(s);
+    if (s->error.load()) break;
+    // admit in order
+    while (!s->fifo.empty()) {
+      const uint64_t id = s->fifo.front();
+      bool is_edit;
+      size_t bytes;
+      {
+        std::lock_guard<std::mutex> g(s->mu);
+        Request& r = s->reqs[id];
+        is_edit = r.is_edit;
+        bytes = r.bytes;
+      }
+      if (is_edit) {
+        if (!s->admitted.empty() && !launch_batch(s)) break;
+        if (!s->admitted.empty()) break;
+        if (!apply_edit(s, id)) break;
+        s->fifo.pop_front();
+        continue;
+      }
+      size_t off;
+      bool ok;
+      {
+        std::lock_guard<std::mutex> g(s->mu);
+        ok = s->pool.alloc(bytes, &off);
+        if (ok) {
+          Request& r = s->reqs[id];
+          r.pool_off = off;
+          r.has_mem = true;
+          uint64_t used = s->pool.used();
+          if (used > s->st_peak_bytes.load()) s->st_peak_bytes.store(used);
+        }
+      }
+      if (!ok) break;
+      s->admitted.push_back(id);
+      s->fifo.pop_front();
+      if ((int32_t)s->admitted.size() >= s->max_batch && !launch_batch(s)) break;
+    }
+    if (!s->admitted.empty()) launch_batch(s);
+    bool idle;
+    {
+      std::lock_guard<std::mutex> g(s->mu);
+      idle = s->fifo.empty() && s->incoming.empty() && s->admitted.empty();
+    }
+    bool busy = !s->edits_in_flight.empty();
+    for (Batch& b : s->slots) busy |= b.busy;
+    if (idle && !busy) {
+      if (s->stop.load()) break;
+      std::this_thread::sleep_for(std::chrono::microseconds(50));
+    } else {
+      std::this_thread::yield();
+    }
+  }
+  // drain the device before leaving
+  for (Batch& b : s->slots)
+    if (b.stream) (void)hipStreamSynchronize(b.stream);
+  if (s->edit_stream) (void)hipStreamSynchronize(s->edit_stream);
+  poll_completions(s);
+  std::lock_guard<std::mutex> g(s->mu);
+  s->cv_done.notify_all();
+}
+
+void server_free(tc_server* s) {
+  if (!s) return;
+  for (Batch& b : s->slots) {
+    if (b.stream) (void)hipStreamDestroy(b.stream);
+    if (b.done) (void)hipEventDestroy(b.done);
+    if (b.slot.host) (void)hipHostFree(b.slot.host);
+    if (b.slot.dev) (void)hipFree(b.slot.dev);
+  }
+  for (auto& f : s->edits_in_flight) (void)hipEventDestroy(f.second);
+  if (s->edit_slot.host) (void)hipHostFree(s->edit_slot.host);
+  if (s->edit_slot.dev) (void)hipFree(s->edit_slot.dev);
+  if (s->edit_slot.ev) (void)hipEventDestroy(s->edit_slot.ev);
+  if (s->edit_ev) (void)hipEventDestroy(s->edit_ev);
+  if (s->edit_stream) (void)hipStreamDestroy(s->edit_stream);
+  for (int v = 0; v < 2; ++v)
+    if (s->own_ver[v] && s->ver[v]) (void)hipFree(s->ver[v]);
+  if (s->pool_dev) (void)hipFree(s->pool_dev);
+  delete s;
+}
+
+}  // namespace
+
+extern "C" {
+
+tc_status tc_server_start(tc_context* ctx, uint64_t budget_bytes, int32_t max_batch_views,
+                          int32_t streams, uint32_t flags, tc_server** out) {
+  if (!ctx) return TC_INVALID_ARG;
+  if (!out) return fail(ctx, TC_INVALID_ARG, "tc_server_start: out is NULL");
+  *out = nullptr;
+  ctx->err.clear();
+  if (!ctx->map) return fail(ctx, TC_NO_MAP, "tc_server_start: no map loaded");
+  if (ctx->server) return fail(ctx, TC_INVALID_ARG, "tc_server_start: a server is running");
+  if (budget_bytes < 4096 || budget_bytes > ((uint64_t)1 << 40))
+    return fail(ctx, TC_INVALID_ARG, "tc_server_start: bad budget");
+  if (max_batch_views < 1 || max_batch_views > 4096 || streams < 1 || streams > 16)
+    return fail(ctx, TC_INVALID_ARG, "tc_server_start: bad batch or stream count");
+  if (flags & ~(uint32_t)TC_SERVER_AUTO_RELEASE)
+    return fail(ctx, TC_INVALID_ARG, "tc_server_start: unknown flags");
+  tc_status st = tci::set_device(ctx);
+  if (st) return st;
+  tc_server* s = new (std::nothrow) tc_server();
+  if (!s) return fail(ctx, TC_OUT_OF_MEMORY, "tc_server_start: host allocation");
+  s->ctx = ctx;
+  s->flags = flags;
+  s->budget = budget_bytes;
+  s->max_batch = max_batch_views;
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMalloc(&s->pool_dev, budget_bytes);
+  s->pool.reset(budget_bytes);
+  s->ver[0] = ctx->map;
+  if (e == hipSuccess) e = hipMalloc(&s->ver[1], ctx->map_words * 4);
+  s->own_ver[1] = e == hipSuccess;
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->edit_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->edit_ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->edit_slot.ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(s->edit_ev, s->edit_stream);
+  s->slots.resize(streams);
+  for (Batch& b : s->slots) {
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming);
+  }
+  if (e != hipSuccess) {
+    server_free(s);
+    return hip_fail(ctx, e, "tc_server_start");
+  }
+  try {
+    s->thread = std::thread(server_loop, s);
+  } catch (...) {
+    server_free(s);
+    return fail(ctx, TC_OUT_OF_MEMORY, "tc_server_start: cannot start the thread");
+  }
+  ctx->server = s;
+  *out = s;
+  return TC_OK;
+}
+
+tc_status tc_server_submit_view(tc_server* s, const tc_view* view, uint64_t* id) {
+  if (!s || !view || !id) return TC_INVALID_ARG;
+  tc_context* ctx = s->ctx;
+  tci::ViewPlan plan;
+  Request r;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    if (s->error.load()) return fail(ctx, TC_DEVICE_ERROR, "%s", s->err.c_str());
+    tc_status st = tci::plan_views(ctx, view, 1, plan);
+    if (st) return st;
+    r.bytes = (size_t)plan.rays * sizeof(tc_hit);
+    if (((r.bytes + 255) & ~(size_t)255) > s->budget)
+      return fail(ctx, TC_OVER_BUDGET, "tc_server_submit_view: view exceeds the budget");
+    r.id = s->next_id++;
+    r.view = *view;
+    r.rays = plan.rays;
+    r.epoch = s->edits_submitted;
+    r.t_submit = now_s();
+    *id = r.id;
+    s->incoming.push_back(r.id);
+    s->reqs.emplace(r.id, std::move(r));
+  }
+  return TC_OK;
+}
+
+tc_status tc_server_submit_edit(tc_server* s, const tc_edit* edits, int32_t n, uint64_t* id) {
+  if (!s || !id) return TC_INVALID_ARG;
+  tc_context* ctx = s->ctx;
+  size_t patch_bytes = 0;
+  std::lock_guard<std::mutex> g(s->mu);
+  if (s->error.load()) return fail(ctx, TC_DEVICE_ERROR, "%s", s->err.c_str());
+  tc_status st = tci::validate_edits(ctx, edits, n, &patch_bytes);
+  if (st) return st;
+  if (n < 1) return fail(ctx, TC_INVALID_ARG, "tc_server_submit_edit: no edits");
+  Request r;
+  r.is_edit = true;
+  r.edits.assign(edits, edits + n);
+  r.patch.resize(patch_bytes);
+  size_t po = 0;
+  for (tc_edit& e : r.edits) {
+    if (e.kind != TC_EDIT_SET) continue;
+    size_t m = (size_t)e.w * e.h;
+    memcpy(r.patch.data() + po, e.floor_top, m);
+    memcpy(r.patch.data() + po + m, e.slab_bottom, m);
+    memcpy(r.patch.data() + po + 2 * m, e.slab_top, m);
+    e.floor_top = r.patch.data() + po;
+    e.slab_bottom = r.patch.data() + po + m;
+    e.slab_top = r.patch.data() + po + 2 * m;
+    po += 3 * m;
+  }
+  r.id = s->next_id++;
+  r.epoch = ++s->edits_submitted;
+  r.t_submit = now_s();
+  *id = r.id;
+  s->incoming.push_back(r.id);
+  s->reqs.emplace(r.id, std::move(r));
+  return TC_OK;
+}
+
+tc_status tc_server_poll(tc_server* s, uint64_t id, int32_t* state, double* latency_s) {
+  if (!s || !state) return TC_INVALID_ARG;
+  std::lock_guard<std::mutex> g(s->mu);
+  auto it = s->reqs.find(id);
+  if (it == s->reqs.end()) return fail(s->ctx, TC_INVALID_ARG, "tc_server_poll: unknown id");
+  *state = it->second.state;
+  if (latency_s)
+    *latency_s = it->second.state == kDone ? it->second.t_done - it->second.t_submit : -1.0;
+  if (s->error.load()) return fail(s->ctx, TC_DEVICE_ERROR, "%s", s->err.c_str());
+  return TC_OK;
+}
+
+tc_status tc_server_wait(tc_server* s, uint64_t id, double timeout_s) {
+  if (!s) return TC_INVALID_ARG;
+  std::unique_lock<std::mutex> g(s->mu);
+  auto deadline = std::chrono::steady_clock::now() +
+                  std::chrono::microseconds((int64_t)(std::max(0.0, timeout_s) * 1e6));
+  while (true) {
+    auto it = s->reqs.find(id);
+    if (it == s->reqs.end()) return fail(s->ctx, TC_INVALID_ARG, "tc_server_wait: unknown id");
+    if (it->second.state == kDone) return TC_OK;
+    if (s->error.load()) return fail(s->ctx, TC_DEVICE_ERROR, "%s", s->err.c_str());
+    if (s->cv_done.wait_until(g, deadline) == std::cv_status::timeout) {
+      it = s->reqs.find(id);
+      if (it != s->reqs.end() && it->second.state == kDone) return TC_OK;
+      return TC_TIMEOUT;
+    }
+  }
+}
+
+tc_status tc_server_result(tc_server* s, uint64_t id, const tc_hit** device_ptr,
+                           int64_t* records) {
+  if (!s || !device_ptr || !records) return TC_INVALID_ARG;
+  std::lock_guard<std::mutex> g(s->mu);
+  auto it = s->reqs.find(id);
+  if (it == s->reqs.end() || it->second.is_edit)
+    return fail(s->ctx, TC_INVALID_ARG, "tc_server_result: unknown view id");
+  const Request& r = it->second;
+  if (r.state != kDone || !r.has_mem)
+    return fail(s->ctx, TC_INVALID_ARG, "tc_server_result: no result held");
+  *device_ptr = (const tc_hit*)(s->pool_dev + r.pool_off);
+  *records = r.rays;
+  return TC_OK;
+}
+
+tc_status tc_server_read(tc_server* s, uint64_t id, tc_hit* host_dst, int64_t records) {
+  if (!s || !host_dst) return TC_INVALID_ARG;
+  const tc_hit* src = nullptr;
+  int64_t n = 0;
+  tc_status st = tc_server_result(s, id, &src, &n);
+  if (st) return st;
+  if (records != n) return fail(s->ctx, TC_INVALID_ARG, "tc_server_read: size mismatch");
+  hipError_t e = hipSetDevice(s->ctx->device);
+  if (e == hipSuccess) e = hipMemcpy(host_dst, src, (size_t)n * sizeof(tc_hit), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(s->ctx, e, "tc_server_read");
+  return TC_OK;
+}
+
+tc_status tc_server_release(tc_server* s, uint64_t id) {
+  if (!s) return TC_INVALID_ARG;
+  std::lock_guard<std::mutex> g(s->mu);
+  auto it = s->reqs.find(id);
+  if (it == s->reqs.end()) return fail(s->ctx, TC_INVALID_ARG, "tc_server_release: unknown id");
+  if (it->second.state != kDone)
+    return fail(s->ctx, TC_INVALID_ARG, "tc_server_release: request not done");
+  if (it->second.has_mem) s->pool.release(it->second.pool_off, it->second.bytes);
+  s->reqs.erase(it);
+  return TC_OK;
+}
+
+tc_status tc_server_get_stats(tc_server* s, tc_server_stats* out) {
+  if (!s || !out) return TC_INVALID_ARG;
+  out->batches = s->st_batches.load();
+  out->edits = s->st_edits.load();
+  out->views = s->st_views.load();
+  out->rays = s->st_rays.load();
+  out->peak_bytes = s->st_peak_bytes.load();
+  std::lock_guard<std::mutex> g(s->mu);
+  out->bytes_in_use = s->pool.used();
+  return TC_OK;
+}
+
+tc_status tc_server_stop(tc_server* s) {
+  if (!s) return TC_INVALID_ARG;
+  tc_context* ctx = s->ctx;
+  s->stop.store(true);
+  if (s->thread.joinable()) s->thread.join();
+  tc_status st = TC_OK;
+  (void)hipSetDevice(ctx->device);
+  // the newest version becomes the context's map
+  if (s->current != 0) {
+    hipError_t e = hipMemcpy(ctx->map, s->ver[s->current], ctx->map_words * 4,
+                             hipMemcpyDeviceToDevice);
+    if (e != hipSuccess) st = hip_fail(ctx, e, "tc_server_stop");
+  }
+  if (s->error.load()) st = fail(ctx, TC_DEVICE_ERROR, "%s", s->err.c_str());
+  ctx->server = nullptr;
+  server_free(s);
+  return st;
+}
+
+}  // extern "C"

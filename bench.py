@@ -29,6 +29,38 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def traffic_from_profile(kernel_src, launches_key="render_c2"):
+    """HBM bytes per launch measured by rocprofv3 (FETCH_SIZE + WRITE_SIZE,
+    scaled by a plain copy's readings), if the committed profile was taken
+    on the current render source; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "%s_traffic.txt" % launches_key)
+    if not os.path.exists(path):
+        return None
+    try:
+        keys = {}
+        for line in open(path):
+            k, sep, v = line.partition(":")
+            if sep and k.strip() in ("render_source_sha256", "hbm_bytes_per_launch"):
+                keys[k.strip()] = v.strip()
+        sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+        if keys.get("render_source_sha256") != sha:
+            return None
+        return float(keys["hbm_bytes_per_launch"])
+    except (ValueError, KeyError, OSError):
+        return None
+
+
+def calib_copy(torch, mib=256, reps=3):
+    """A plain device-to-device copy of known size, for counter scaling."""
+    a = torch.empty(mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return mib << 20
+
+
 def time_renders(torch, ctx, tc, views, out, steps, warmup):
     """Per-step HIP event timings (ms) of tc_render_views on the current
     stream, plus the bracketed wall time of all timed steps."""
@@ -167,6 +199,70 @@ def c4_batched(torch, tc, synth, steps, warmup):
                         "grays_per_s": rays / (np.median(bms) * 1e-3) / 1e9}}
 
 
+def c5_served(torch, tc, synth, rates=(200, 500, 1000, 2000, 5000, 10000),
+              n_per_rate=1500):
+    """Configuration 5: Poisson request streams against the resident
+    2048x16384 map; 90% views (sizes and poses as configuration 4), 10%
+    craters of size 16-64; an 8 GiB in-flight hit-buffer budget.  Served:
+    continuous batching (up to 64 views per batch, 4 streams).  FIFO plain:
+    the same server with one view per batch on one stream.  Latency runs
+    from submission to observed completion."""
+    F, B, T = synth.make_map_from_config(5)
+    H, W = F.shape
+    seeds = synth.SEEDS[5]
+    ctx = tc.Context(0)
+    out = {"workload": "c5: 2048x16384 map resident, Poisson arrivals, 90% views "
+                       "(256^2..1920x1080) / 10% craters (16..64), 8 GiB in-flight budget",
+           "requests_per_rate": n_per_rate, "rates": {}}
+    for rate in rates:
+        rng = np.random.default_rng(seeds["views"] * 10 + rate)
+        arr = synth.poisson_arrivals(seeds["arrivals"] * 10 + rate, rate, n_per_rate)
+        reqs = []
+        for _ in range(n_per_rate):
+            if rng.random() < 0.1:
+                reqs.append(("edit", synth.crater_list(rng, W, H, 1, size=(16, 64))))
+            else:
+                reqs.append(("view", synth.request_view(rng, F, B)))
+        # C structures built before the timed submission loop
+        cs = [tc.view_struct(x) if k == "view" else tc.edits_struct(x) for k, x in reqs]
+        res = {}
+        for name, batch, streams in (("served", 64, 4), ("fifo_plain", 1, 1)):
+            ctx.tc_load_columns(F, B, T)
+            srv = ctx.tc_server_start(8 << 30, max_batch_views=batch, streams=streams,
+                                      flags=tc.TC_SERVER_AUTO_RELEASE)
+            ids = []
+            t0 = time.perf_counter()
+            late = 0.0
+            for (kind, x), c, t in zip(reqs, cs, arr):
+                while time.perf_counter() - t0 < t:
+                    pass
+                late = max(late, time.perf_counter() - t0 - t)
+                ids.append(srv.tc_server_submit_view(c) if kind == "view"
+                           else srv.tc_server_submit_edit(c))
+            for rid in ids:
+                srv.tc_server_wait(rid, 300.0)
+            t_end = time.perf_counter()
+            lat = []
+            rays = 0
+            for (kind, x), rid in zip(reqs, ids):
+                st, l = srv.tc_server_poll(rid)
+                if kind == "view":
+                    lat.append(l * 1e3)
+                    rays += int(x["width"]) * int(x["height"])
+            stats = srv.tc_server_get_stats()
+            srv.tc_server_stop()
+            res[name] = {"latency_ms_p50": float(np.percentile(lat, 50)),
+                         "latency_ms_p99": float(np.percentile(lat, 99)),
+                         "grays_per_s": rays / (t_end - t0) / 1e9,
+                         "batches": stats["batches"],
+                         "max_submit_lag_ms": late * 1e3,
+                         "peak_inflight_MiB": stats["peak_bytes"] / 2**20}
+            log("[bench] c5 rate %d %s: %s" % (rate, name, res[name]))
+        out["rates"][str(rate)] = res
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -176,8 +272,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--extra", action="store_true",
                     help="also time every render mode")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run a 256 MiB device copy (counter calibration)")
     ap.add_argument("--no-growth", action="store_true",
-                    help="skip the edit frame (c3) and batched frame (c4)")
+                    help="skip the edit frame (c3), batched frame (c4) and server (c5)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU; --gpus %d is not supported (the method "
@@ -190,6 +288,8 @@ def main():
     import synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calib_copy:
+        log("[bench] calibration copy of %d bytes" % calib_copy(torch))
     log("[bench] generating the 2048x2048 map")
     F, B, T = synth.make_map_from_config(2)
     views = synth.config_views(2, F, B)
@@ -232,7 +332,9 @@ def main():
                    "rays_per_frame": rays, "render_mode": args.mode,
                    "frame_ms_median": med, "frame_ms_p99": float(np.percentile(ms, 99))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": traffic_from_profile(os.path.join(
+                         ROOT, "paper_2608_17390_amd", "csrc", "tc_render.hip")),
                      "kernel": "render_kernel<false>" if args.mode == "hier" else args.mode,
                      "alg_bytes_per_launch": alg_bytes,
                      "kernel_ms_avg": avg},
@@ -249,6 +351,8 @@ def main():
         res["c3_frame"] = c3_frame(torch, tc, synth, 10, 2)
         log("[bench] c4 batched vs plain")
         res["c4_batched"] = c4_batched(torch, tc, synth, 10, 2)
+        log("[bench] c5 served vs FIFO plain")
+        res["c5_served"] = c5_served(torch, tc, synth)
     if not args.no_cpu:
         import oracle
         log("[bench] CPU oracle baseline")

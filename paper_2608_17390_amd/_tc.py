@@ -376,12 +376,21 @@ class Server:
         _check(self._ctx.handle, st)
 
     def tc_server_submit_view(self, view):
-        arr = _views_struct([view])
+        """view: a view record, or a prebuilt structure from view_struct()."""
+        arr = view if isinstance(view, ctypes.Array) else _views_struct([view])
         rid = ctypes.c_uint64()
         self._chk(load_library().tc_server_submit_view(self._h, arr, ctypes.byref(rid)))
         return rid.value
 
     def tc_server_submit_edit(self, edits):
+        """edits: a list of edit dicts, or a prebuilt (structure, keep) pair
+        from edits_struct()."""
+        if isinstance(edits, tuple):
+            arr, keep = edits
+            n = len(arr)
+            rid = ctypes.c_uint64()
+            self._chk(load_library().tc_server_submit_edit(self._h, arr, n, ctypes.byref(rid)))
+            return rid.value
         arr, keep = _edits_struct(list(edits))
         rid = ctypes.c_uint64()
         st = load_library().tc_server_submit_edit(self._h, arr, len(edits), ctypes.byref(rid))
@@ -421,6 +430,16 @@ class Server:
             self.tc_server_stop()
         except Exception:
             pass
+
+
+def view_struct(view):
+    """Prebuilt C view structure (for low-overhead repeated submission)."""
+    return _views_struct([view])
+
+
+def edits_struct(edits):
+    """Prebuilt C edit array plus the buffers it points into."""
+    return _edits_struct(list(edits))
 
 
 def tc_create(device=0):

@@ -181,7 +181,24 @@ tc_status tc_render_views(tc_context *ctx, const tc_view *views, int32_t n,
                                   and cells each ray reads to a context
                                   counter (diagnostic; default 0) */
 #define TC_OPT_TILE_ORDER 9    /* order of 8x8 pixel packets within a view:
-                                  0 row-major, 1 column-major (default 1) */
+                                  0 row-major, 1 column-major, 2 tile rows
+                                  sorted so the rows whose rays are closest
+                                  to horizontal (the longest walks) start
+                                  first (default 2) */
+#define TC_OPT_PRIORITY_BOOST 10 /* one-thread-per-pixel modes: a wave raises
+                                    its issue priority after this many,
+                                    twice and four times as many traversal
+                                    steps, so long walks do not trail the
+                                    launch (0: never; default 0) */
+#define TC_OPT_SPLIT_BUDGET 11   /* hierarchical mode: a ray still walking
+                                    after this many steps is finished by a
+                                    second pass that walks 64 runs of its
+                                    path in parallel, each from the exact
+                                    state the walk enters it with (0: no
+                                    second pass; default 128) */
+#define TC_OPT_SPLIT_QUEUE 12    /* most rays the second pass takes per call;
+                                    further long rays finish in the first
+                                    pass (default 131072) */
 tc_status tc_set_option(tc_context *ctx, int32_t key, int64_t value);
 tc_status tc_get_option(const tc_context *ctx, int32_t key, int64_t *value);
 

@@ -13,4 +13,5 @@ from ._tc import (Context, Frame, Server, TCError, tc_create, tc_view, tc_edit, 
                   TC_OPT_START_LEVEL, TC_OPT_MAX_LEVEL, TC_OPT_XCD_REMAP,
                   TC_OPT_PERSIST_WAVES, TC_OPT_REFILL_MIN,
                   TC_OPT_REFILL_ITERS, TC_OPT_COUNT_READS,
-                  TC_OPT_TILE_ORDER)
+                  TC_OPT_TILE_ORDER, TC_OPT_PRIORITY_BOOST, TC_OPT_SPLIT_BUDGET,
+                  TC_OPT_SPLIT_QUEUE)

@@ -36,6 +36,9 @@ TC_OPT_REFILL_MIN = 6
 TC_OPT_REFILL_ITERS = 7
 TC_OPT_COUNT_READS = 8
 TC_OPT_TILE_ORDER = 9
+TC_OPT_PRIORITY_BOOST = 10
+TC_OPT_SPLIT_BUDGET = 11
+TC_OPT_SPLIT_QUEUE = 12
 
 _STATUS = {0: "TC_OK", -1: "TC_INVALID_ARG", -2: "TC_OUT_OF_MEMORY",
            -3: "TC_NO_MAP", -4: "TC_DEVICE_ERROR", -5: "TC_OVER_BUDGET",

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -111,6 +112,12 @@ tci_render_opts render_opts(const tc_context* c) {
   o.refill_min = c->refill_min;
   o.refill_iters = c->refill_iters;
   o.tile_order = c->tile_order;
+  o.rows = nullptr;
+  o.boost = c->boost;
+  o.split_budget = 0;
+  o.qcap = 0;
+  o.queue = nullptr;
+  o.qcount = nullptr;
   o.count = c->count_reads ? c->d_count : nullptr;
   return o;
 }
@@ -248,6 +255,27 @@ tc_status plan_views(tc_context* ctx, const tc_view* views, int32_t n, ViewPlan&
     o.tiles_x = (v.width + 7) >> 3;
     o.out_base = out;
     o.pkt_base = pk;
+    o.rows_off = (int64_t)p.rows.size();
+    // tile rows ordered by how level the ray through the row's centre is:
+    // near-horizontal rays take the longest walks, so their packets start
+    // first and do not trail the launch
+    {
+      const int32_t ty_n = (v.height + 7) >> 3;
+      std::vector<std::pair<double, int32_t>> key((size_t)ty_n);
+      const int64_t a = v.width;  // 2 * (width / 2) + 1, rounded
+      for (int32_t ty = 0; ty < ty_n; ++ty) {
+        const int64_t b = 2 * (int64_t)std::min(ty * 8 + 4, v.height - 1) + 1;
+        const double dx = (double)v.d0[0] + (double)a * v.d_px[0] + (double)b * v.d_py[0];
+        const double dy = (double)v.d0[1] + (double)a * v.d_px[1] + (double)b * v.d_py[1];
+        const double dz = (double)v.d0[2] + (double)a * v.d_px[2] + (double)b * v.d_py[2];
+        const double hz = std::sqrt(dx * dx + dy * dy);
+        key[ty] = {hz > 0 ? std::fabs(dz) / hz : 1e30, ty};
+      }
+      std::stable_sort(key.begin(), key.end(),
+                       [](const std::pair<double, int32_t>& x,
+                          const std::pair<double, int32_t>& y) { return x.first < y.first; });
+      for (auto& k : key) p.rows.push_back(k.second);
+    }
     p.prefix[i] = pk;
     out += (int64_t)v.width * v.height;
     pk += (int64_t)o.tiles_x * ((v.height + 7) >> 3);
@@ -259,20 +287,27 @@ tc_status plan_views(tc_context* ctx, const tc_view* views, int32_t n, ViewPlan&
   p.npkt = pk;
   p.off_views = 0;
   p.off_prefix = (sizeof(tci_view) * (size_t)n + 15) & ~(size_t)15;
-  p.off_counter = (p.off_prefix + sizeof(int64_t) * ((size_t)n + 1) + 15) & ~(size_t)15;
-  p.total = p.off_counter + 64;
+  p.off_rows = (p.off_prefix + sizeof(int64_t) * ((size_t)n + 1) + 15) & ~(size_t)15;
+  p.off_counter = (p.off_rows + sizeof(int32_t) * p.rows.size() + 15) & ~(size_t)15;
+  // the split queue follows the counters (device only, never uploaded)
+  p.qcap = (ctx->render_mode == 0 && ctx->split_budget > 0)
+               ? (uint32_t)std::min<int64_t>(out, ctx->split_queue) : 0;
+  p.off_queue = p.off_counter + 64;
+  p.total = p.off_queue + sizeof(uint4) * (size_t)p.qcap;
   return TC_OK;
 }
 
 void write_views(const ViewPlan& p, char* host) {
   memcpy(host + p.off_views, p.views.data(), sizeof(tci_view) * (size_t)p.n);
   memcpy(host + p.off_prefix, p.prefix.data(), sizeof(int64_t) * ((size_t)p.n + 1));
+  memcpy(host + p.off_rows, p.rows.data(), sizeof(int32_t) * p.rows.size());
   memset(host + p.off_counter, 0, 64);
 }
 
 hipError_t enqueue_render(tc_context* ctx, const tci_map& d, const char* dev,
                           const ViewPlan& p, void* out, hipStream_t s) {
   tci_render_opts o = render_opts(ctx);
+  o.rows = (const int32_t*)(dev + p.off_rows);
   const tci_view* dv = (const tci_view*)(dev + p.off_views);
   const int64_t* pre = (const int64_t*)(dev + p.off_prefix);
   if (ctx->render_mode == 2) {
@@ -283,6 +318,20 @@ hipError_t enqueue_render(tc_context* ctx, const tci_map& d, const char* dev,
     if (e == hipSuccess)
       e = tci_launch_render_persistent(d, dv, p.n, pre, p.npkt, out, counter,
                                        (int32_t)blocks, o, s);
+    return e;
+  }
+  if (p.qcap > 0) {
+    uint64_t* counters = (uint64_t*)(dev + p.off_counter);
+    o.split_budget = ctx->split_budget;
+    o.qcap = p.qcap;
+    o.queue = (uint4*)(dev + p.off_queue);
+    o.qcount = (uint32_t*)(counters + 1);
+    hipError_t e = tci_launch_zero_u64(counters, 2, s);
+    if (e == hipSuccess)
+      e = tci_launch_render(d, dv, p.n, pre, p.npkt, out, 0, o, s);
+    const int32_t nb = (int32_t)std::max<int64_t>(
+        1, std::min<int64_t>(ctx->num_cu * 16, ((int64_t)p.qcap + 3) / 4));
+    if (e == hipSuccess) e = tci_launch_split(d, dv, o, out, nb, s);
     return e;
   }
   return tci_launch_render(d, dv, p.n, pre, p.npkt, out, ctx->render_mode == 1, o, s);
@@ -517,8 +566,20 @@ tc_status tc_set_option(tc_context* ctx, int32_t key, int64_t value) {
       if (value < 1 || value > 4096) break;
       ctx->refill_iters = (int32_t)value;
       return TC_OK;
+    case TC_OPT_SPLIT_BUDGET:
+      if (value < 0 || value > (1 << 20)) break;
+      ctx->split_budget = (int32_t)value;
+      return TC_OK;
+    case TC_OPT_SPLIT_QUEUE:
+      if (value < 1 || value > (1 << 26)) break;
+      ctx->split_queue = (int32_t)value;
+      return TC_OK;
+    case TC_OPT_PRIORITY_BOOST:
+      if (value < 0 || value > (1 << 20)) break;
+      ctx->boost = (int32_t)value;
+      return TC_OK;
     case TC_OPT_TILE_ORDER:
-      if (value < 0 || value > 1) break;
+      if (value < 0 || value > 2) break;
       ctx->tile_order = (int32_t)value;
       return TC_OK;
     case TC_OPT_COUNT_READS:
@@ -550,6 +611,9 @@ tc_status tc_get_option(const tc_context* ctx, int32_t key, int64_t* value) {
     case TC_OPT_REFILL_ITERS: *value = ctx->refill_iters; return TC_OK;
     case TC_OPT_COUNT_READS: *value = ctx->count_reads; return TC_OK;
     case TC_OPT_TILE_ORDER: *value = ctx->tile_order; return TC_OK;
+    case TC_OPT_PRIORITY_BOOST: *value = ctx->boost; return TC_OK;
+    case TC_OPT_SPLIT_BUDGET: *value = ctx->split_budget; return TC_OK;
+    case TC_OPT_SPLIT_QUEUE: *value = ctx->split_queue; return TC_OK;
     default: return TC_INVALID_ARG;
   }
 }

@@ -38,9 +38,12 @@ struct EditPlan {
 struct ViewPlan {
   int32_t n = 0;
   int64_t rays = 0, npkt = 0;
-  size_t off_views = 0, off_prefix = 0, off_counter = 0, total = 0;
+  size_t off_views = 0, off_prefix = 0, off_counter = 0, off_rows = 0, total = 0;
+  size_t off_queue = 0;
+  uint32_t qcap = 0;           // split queue capacity (0: no split pass)
   std::vector<tci_view> views;
   std::vector<int64_t> prefix;
+  std::vector<int32_t> rows;   // tile rows of every view, longest walks first
 };
 
 tc_status fail(tc_context* c, tc_status st, const char* fmt, ...);
@@ -90,7 +93,10 @@ struct tc_context {
   int32_t refill_min = 16;
   int32_t refill_iters = 16;
   int32_t count_reads = 0;
-  int32_t tile_order = 1;
+  int32_t tile_order = 2;
+  int32_t boost = 0;
+  int32_t split_budget = 128;
+  int32_t split_queue = 1 << 17;
   unsigned long long* d_count = nullptr;
   // a running server owns the map (tc_server.cpp)
   void* server = nullptr;

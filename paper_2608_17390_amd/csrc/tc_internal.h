@@ -40,6 +40,8 @@ struct tci_view {
   int32_t tiles_x;     // ceil(w / 8)
   int64_t out_base;    // first output record of the view
   int64_t pkt_base;    // first 8x8 packet of the view
+  int64_t rows_off;    // packet order 2: offset of the view's tile-row
+                       // permutation in the row table
 };
 
 // Device edit descriptor; SET data lives at data_off in the patch buffer
@@ -58,7 +60,17 @@ struct tci_render_opts {
   int32_t xcd_remap;
   int32_t refill_min;
   int32_t refill_iters;
-  int32_t tile_order;          // 0: packets row-major in a view, 1: column-major
+  int32_t tile_order;          // packets in a view: 0 row-major, 1 column-major,
+                               // 2 tile rows in the order of a row table
+  const int32_t* rows;         // row table of order 2
+  int32_t boost;               // iterations before a wave raises its priority
+                               // (0: never)
+  int32_t split_budget;        // hierarchical mode: steps before a ray is
+                               // handed to the split pass (0: never)
+  uint32_t qcap;               // capacity of the split queue
+  uint4* queue;                // split queue: (view, pixel index, first
+                               // dominant-axis cell line still to walk, 0)
+  uint32_t* qcount;            // split queue length
   unsigned long long* count;   // if set: add each ray's node/cell reads
 };
 
@@ -93,3 +105,8 @@ hipError_t tci_launch_render_persistent(const tci_map& m,
                                         const tci_render_opts& o,
                                         hipStream_t s);
 hipError_t tci_launch_zero_u64(uint64_t* p, int32_t n, hipStream_t s);
+// Second pass of a hierarchical render: walk every queued long ray as 64
+// segments in parallel, one wave per ray.
+hipError_t tci_launch_split(const tci_map& m, const tci_view* views,
+                            const tci_render_opts& o, void* out, int32_t nblocks,
+                            hipStream_t s);

@@ -43,7 +43,8 @@ constexpr int32_t kIterCap = 1 << 22;
 
 enum : int32_t { kTop = 1, kUnder = 2, kWmx = 3, kWpx = 4, kWmy = 5,
                  kWpy = 6, kInside = 7 };
-enum : int32_t { kWalking = 0, kHitCell = 1, kMissed = 2, kCapped = 3 };
+enum : int32_t { kWalking = 0, kHitCell = 1, kMissed = 2, kCapped = 3, kSegEnd = 4 };
+constexpr int32_t kAnchored = 8;
 
 struct lvl_t {
   uint32_t off;
@@ -65,28 +66,66 @@ __device__ __forceinline__ int64_t smul48(int32_t a, int32_t b) {
   asm("v_mul_hi_i32_i24 %0, %1, %2" : "=v"(hi) : "v"(a), "v"(b));
   return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
-// h * S * d for a height h <= 255 and d < 2^23
-__device__ __forceinline__ int64_t hS(uint32_t h, uint32_t d) {
-  return (int64_t)((uint64_t)__umul24(h, d) << 16);
-}
-
 struct ray_t {
   int64_t Ox, Oy, Oz;
   int32_t Dx, Dy, Dz;
   uint32_t ax, ay;
+  int32_t cx0, cy0;   // anchor cell: the start cell, or a segment's first cell
+  uint32_t rx, ry;    // residual flags of the x / y crossing heights
 };
 
+// Exact state of the cell walk, divided by S.  Every crossing moves its
+// key and height by a multiple of S, so the remainders modulo S are fixed
+// per axis: they fold into a tie offset of the x keys and a 0/1 flag of
+// the heights, and no comparison needs the low 16 bits.
+//   keys    the i-th x crossing has key KX0 + i*ay with
+//           KX0 = floor(nx*ay / S) + c, c = 1 iff (nx*ay mod S) > (ny*ax mod S),
+//           and the j-th y crossing KY0 + j*ax, KY0 = floor(ny*ax / S); an x
+//           crossing comes first iff its key is <= the y key (x first on
+//           ties), exactly as the times nx/ax and ny/ay compare.
+//   heights with Z = Oz*ax + nx*Dz (z * S * ax at the first x crossing),
+//           ZX0 = floor(Z / S) and rx = (Z mod S != 0), the i-th x crossing
+//           has height ZX0 + i*Dz and there
+//           z <= h  iff  height + rx <= h*ax,   z >= h  iff  height >= h*ax.
+//           Likewise for y.
+// The walk runs on the node grid of its current pyramid level L and keeps,
+// for the current node, the keys and heights of the crossings through its
+// far x and y faces: a step to the next node adds a << L to one of each,
+// a climb or a descent adds or removes half a node, and the child holding
+// the ray is the one on the near side of each middle crossing that happens
+// after the entry crossing.  The walk therefore enters exactly the cells
+// the flat walk enters, at the same keys.
 struct walk_t {
-  int32_t cx, cy;
-  int64_t Kx, Ky;     // keys of the next x / y crossing
-  int64_t Zx, Zy;     // scaled z at the next x / y crossing
-  int64_t Zin;        // scaled z at entry of the current cell
-  uint32_t Din;       // scale of Zin (1 at the origin, else ax or ay)
-  int32_t entry;      // face crossed on entry (kInside for the first cell)
+  int32_t ni, nj;     // node indices at level L
   int32_t L;          // current pyramid level
+  int64_t KXe, KYe;   // keys of the crossings through the far x / y faces
+  int64_t ZXe, ZYe;   // heights at those crossings
+  int64_t Kin;        // key of the entry crossing (unused while kInside)
+  int64_t Zin;        // height at entry of the current node
+  uint32_t Din;       // its scale: 1 at the origin, else ax or ay
+  uint32_t rin;       // its residual flag
+  int32_t entry;      // face crossed on entry (kInside before any crossing),
+                      // plus kAnchored until the first step: the walk then
+                      // sits in the anchor cell (r.cx0, r.cy0) and picks
+                      // children by it
   int32_t iters;
   int32_t reads;      // nodes and cells read from memory
 };
+
+// z <= h and z >= h for a height with floor part zq, flag r and scale d
+__device__ __forceinline__ bool z_le(int64_t zq, uint32_t r, uint32_t h, uint32_t d) {
+  return zq + (int64_t)r <= (int64_t)__umul24(h, d);
+}
+__device__ __forceinline__ bool z_ge(int64_t zq, uint32_t h, uint32_t d) {
+  return zq >= (int64_t)__umul24(h, d);
+}
+// a << L for an unsigned or signed 32-bit a as a 64-bit value
+__device__ __forceinline__ int64_t ushl(uint32_t a, int32_t L) {
+  return (int64_t)((uint64_t)a << L);
+}
+__device__ __forceinline__ int64_t sshl(int32_t a, int32_t L) {
+  return (int64_t)((uint64_t)(int64_t)a << L);
+}
 
 __device__ __forceinline__ void pixel_ray(const tci_view& v, int32_t px,
                                           int32_t py, ray_t& r) {
@@ -101,22 +140,36 @@ __device__ __forceinline__ void pixel_ray(const tci_view& v, int32_t px,
   r.ay = (uint32_t)(r.Dy < 0 ? -r.Dy : r.Dy);
 }
 
-__device__ __forceinline__ void walk_init(const ray_t& r, int32_t L0,
-                                          walk_t& s) {
-  s.cx = (int32_t)(r.Ox >> 16);
-  s.cy = (int32_t)(r.Oy >> 16);
-  int64_t nx = r.Dx > 0 ? ((int64_t)(s.cx + 1) << 16) - r.Ox
-                        : r.Ox - ((int64_t)s.cx << 16);
-  int64_t ny = r.Dy > 0 ? ((int64_t)(s.cy + 1) << 16) - r.Oy
-                        : r.Oy - ((int64_t)s.cy << 16);
-  s.Kx = r.Dx != 0 ? nx * (int64_t)r.ay : kNever;
-  s.Ky = r.Dy != 0 ? ny * (int64_t)r.ax : kNever;
-  s.Zx = r.Oz * (int64_t)r.ax + nx * (int64_t)r.Dz;
-  s.Zy = r.Oz * (int64_t)r.ay + ny * (int64_t)r.Dz;
-  s.Zin = r.Oz;
-  s.Din = 1;
-  s.entry = kInside;
+__device__ __forceinline__ void walk_init(ray_t& r, int32_t L0, walk_t& s) {
+  const int32_t cx = (int32_t)(r.Ox >> 16), cy = (int32_t)(r.Oy >> 16);
+  r.cx0 = cx;
+  r.cy0 = cy;
+  const int64_t nx = r.Dx > 0 ? ((int64_t)(cx + 1) << 16) - r.Ox
+                              : r.Ox - ((int64_t)cx << 16);
+  const int64_t ny = r.Dy > 0 ? ((int64_t)(cy + 1) << 16) - r.Oy
+                              : r.Oy - ((int64_t)cy << 16);
+  const int64_t kx = nx * (int64_t)r.ay, ky = ny * (int64_t)r.ax;
+  const int64_t tie = (kx & 0xFFFF) <= (ky & 0xFFFF) ? 0 : 1;
+  const int64_t zx = r.Oz * (int64_t)r.ax + nx * (int64_t)r.Dz;
+  const int64_t zy = r.Oz * (int64_t)r.ay + ny * (int64_t)r.Dz;
+  r.rx = (zx & 0xFFFF) != 0;
+  r.ry = (zy & 0xFFFF) != 0;
   s.L = L0;
+  s.ni = cx >> L0;
+  s.nj = cy >> L0;
+  // crossings before the far faces of the start node
+  const int32_t kxm1 = r.Dx > 0 ? ((s.ni + 1) << L0) - 1 - cx : cx - (s.ni << L0);
+  const int32_t kym1 = r.Dy > 0 ? ((s.nj + 1) << L0) - 1 - cy : cy - (s.nj << L0);
+  s.KXe = r.Dx == 0 ? kNever
+                    : (kx >> 16) + (r.Dy != 0 ? tie : 0) + (int64_t)kxm1 * r.ay;
+  s.KYe = r.Dy == 0 ? kNever : (ky >> 16) + (int64_t)kym1 * r.ax;
+  s.ZXe = (zx >> 16) + (int64_t)kxm1 * r.Dz;
+  s.ZYe = (zy >> 16) + (int64_t)kym1 * r.Dz;
+  s.Kin = 0;
+  s.Zin = r.Oz >> 16;
+  s.rin = (r.Oz & 0xFFFF) != 0;
+  s.Din = 1;
+  s.entry = kInside | kAnchored;
   s.iters = 0;
   s.reads = 0;
 }
@@ -134,28 +187,31 @@ __device__ __forceinline__ void set_hit(const ray_t& r, int32_t W, int32_t x,
                   : (float)(((double)tn / (double)td) * len / 65536.0);
 }
 
-// First hit inside the current cell (packed column v), given that the ray's
-// height range over the cell meets solid.
-__device__ __forceinline__ void resolve_hit(const ray_t& r, const walk_t& s,
+// First hit inside cell (x, y) (packed column v), entered with height zin
+// (scale din, flag rin) through face `entry`, given that the ray's height
+// range over the cell meets solid.
+__device__ __forceinline__ void resolve_hit(const ray_t& r, int32_t x, int32_t y,
+                                            int32_t entry, int64_t zin,
+                                            uint32_t din, uint32_t rin,
                                             int32_t W, uint32_t v,
                                             uint32_t& word, float& depth) {
   uint32_t F = v & 0xFF, B = (v >> 8) & 0xFF, T = (v >> 16) & 0xFF;
-  bool in_floor = s.Zin <= hS(F, s.Din);
-  bool in_slab = B != 0 && s.Zin >= hS(B, s.Din) && s.Zin <= hS(T, s.Din);
+  bool in_floor = z_le(zin, rin, F, din);
+  bool in_slab = B != 0 && z_ge(zin, B, din) && z_le(zin, rin, T, din);
   int32_t face, layer;
   int64_t tn, td;
   if (in_floor || in_slab) {
-    face = s.entry;
+    face = entry;
     layer = in_floor ? 0 : 1;
     switch (face) {
-      case kWmx: tn = ((int64_t)s.cx << 16) - r.Ox; td = r.ax; break;
-      case kWpx: tn = r.Ox - ((int64_t)(s.cx + 1) << 16); td = r.ax; break;
-      case kWmy: tn = ((int64_t)s.cy << 16) - r.Oy; td = r.ay; break;
-      case kWpy: tn = r.Oy - ((int64_t)(s.cy + 1) << 16); td = r.ay; break;
+      case kWmx: tn = ((int64_t)x << 16) - r.Ox; td = r.ax; break;
+      case kWpx: tn = r.Ox - ((int64_t)(x + 1) << 16); td = r.ax; break;
+      case kWmy: tn = ((int64_t)y << 16) - r.Oy; td = r.ay; break;
+      case kWpy: tn = r.Oy - ((int64_t)(y + 1) << 16); td = r.ay; break;
       default: tn = 0; td = 1; break;
     }
   } else if (r.Dz < 0) {
-    bool above = B != 0 && s.Zin > hS(T, s.Din);
+    bool above = B != 0 && !z_le(zin, rin, T, din);
     uint32_t tgt = above ? T : F;
     face = kTop;
     layer = above ? 1 : 0;
@@ -167,7 +223,7 @@ __device__ __forceinline__ void resolve_hit(const ray_t& r, const walk_t& s,
     tn = ((int64_t)B << 16) - r.Oz;
     td = r.Dz;
   }
-  set_hit(r, W, s.cx, s.cy, face, layer, tn, td, word, depth);
+  set_hit(r, W, x, y, face, layer, tn, td, word, depth);
 }
 
 // Hit record of a finished walk.
@@ -175,7 +231,7 @@ __device__ __forceinline__ void finish(const ray_t& r, const walk_t& s,
                                        int32_t W, int32_t state, uint32_t v,
                                        uint32_t& word, float& depth) {
   if (state == kHitCell) {
-    resolve_hit(r, s, W, v, word, depth);
+    resolve_hit(r, s.ni, s.nj, s.entry & 7, s.Zin, s.Din, s.rin, W, v, word, depth);
   } else if (state == kCapped) {
     word = kStuck;
     depth = __builtin_nanf("");
@@ -199,121 +255,209 @@ __device__ __forceinline__ void trace_vertical(const tci_map& m,
   uint32_t v = m.base[l.off + ((uint32_t)((cy >> 3) * l.tiles_x + (cx >> 3)) << 6) +
                       ((cy & 7) << 3) + (cx & 7)];
   uint32_t B = (v >> 8) & 0xFF, F = v & 0xFF, T = (v >> 16) & 0xFF;
-  walk_t s;
-  s.cx = cx; s.cy = cy; s.Zin = r.Oz; s.Din = 1; s.entry = kInside;
   bool in_floor = r.Oz <= ((int64_t)F << 16);
   bool in_slab = B != 0 && r.Oz >= ((int64_t)B << 16) && r.Oz <= ((int64_t)T << 16);
   if (in_floor || in_slab || r.Dz < 0 || (B != 0 && r.Oz < ((int64_t)B << 16)))
-    resolve_hit(r, s, m.W, v, word, depth);
-}
-
-// Number of terms K + j*(a<<16), j >= 0, strictly below E (E, K < 2^62;
-// the count is < 2^15 when E is a node exit).  Float estimate of the
-// quotient, then one exact correction.
-__device__ __forceinline__ int32_t count_below(int64_t E, int64_t K,
-                                               uint32_t a) {
-  if (E <= K) return 0;
-  const int64_t n = E - K - 1;             // count = floor(n / step) + 1
-  const int64_t step = (int64_t)a << 16;
-  const float nf = (float)(uint32_t)(n >> 32) * 4294967296.0f +
-                   (float)(uint32_t)n;
-  int32_t q = (int32_t)(nf * __builtin_amdgcn_rcpf((float)a * 65536.0f));
-  q = q < 0 ? 0 : q;
-  const int64_t p = (int64_t)(mul48((uint32_t)q, a) << 16);
-  q += (p > n) ? -1 : ((n - p >= step) ? 1 : 0);
-  return q + 1;
+    resolve_hit(r, cx, cy, kInside, r.Oz >> 16, 1, (r.Oz & 0xFFFF) != 0, m.W, v,
+                word, depth);
 }
 
 // Advance the walk by up to `budget` iterations.  Returns kWalking if the
 // budget ran out, else the final state; on kHitCell, `col` holds the
-// column of the current cell.
-template <bool kFlat>
-__device__ __forceinline__ int32_t walk_steps(const tci_map& m,
-                                              const lvl_t* lv, const ray_t& r,
-                                              walk_t& s, int32_t max_level,
-                                              int32_t budget, uint32_t& col) {
+// column of the current cell (s.ni, s.nj at level 0).
+// Number of terms K + j*a, j >= 0, strictly below E, for counts below 2^24
+// and E - K < 2^47: a float estimate of the quotient, then one exact
+// correction.
+__device__ __forceinline__ int32_t count_below(int64_t E, int64_t K, uint32_t a) {
+  if (E <= K) return 0;
+  const int64_t n = E - K - 1;             // count = floor(n / a) + 1
+  const float nf = (float)(uint32_t)(n >> 32) * 4294967296.0f + (float)(uint32_t)n;
+  int32_t q = (int32_t)(nf * __builtin_amdgcn_rcpf((float)a));
+  q = q < 0 ? 0 : q;
+  const int64_t p = (int64_t)mul48((uint32_t)q, a);
+  q += (p > n) ? -1 : ((n - p >= (int64_t)a) ? 1 : 0);
+  return q + 1;
+}
+
+// Walk state (at level 0) on entering cell line `start` of axis `axis`
+// (a column if 0, a row if 1) through the crossing the flat walk takes into
+// it: the crossing's key and height come from its index, the cell on the
+// other axis from the number of that axis's crossings that come first (x
+// first on ties).  If `start` is the start cell's line, the walk starts at
+// the origin.
+__device__ __forceinline__ void seg_init(ray_t& r, walk_t& s, int32_t axis,
+                                         int32_t start) {
+  walk_init(r, 0, s);   // level 0: far-face keys are the first crossings
+  if (axis == 0) {
+    const int32_t i = r.Dx > 0 ? start - r.cx0 - 1 : r.cx0 - start - 1;
+    if (i < 0) return;
+    const int64_t K = s.KXe + (int64_t)mul48((uint32_t)i, r.ay);
+    const int32_t c = count_below(K, s.KYe, r.ax);
+    s.Kin = K;
+    s.Zin = s.ZXe + smul48(i, r.Dz);
+    s.Din = r.ax;
+    s.rin = r.rx;
+    s.KXe = K + r.ay;
+    s.ZXe = s.Zin + r.Dz;
+    s.KYe += (int64_t)mul48((uint32_t)c, r.ax);
+    s.ZYe += smul48(c, r.Dz);
+    s.ni = start;
+    s.nj = r.cy0 + (r.Dy > 0 ? c : -c);
+    s.entry = (r.Dx > 0 ? kWmx : kWpx) | kAnchored;
+  } else {
+    const int32_t j = r.Dy > 0 ? start - r.cy0 - 1 : r.cy0 - start - 1;
+    if (j < 0) return;
+    const int64_t K = s.KYe + (int64_t)mul48((uint32_t)j, r.ax);
+    const int32_t c = count_below(K + 1, s.KXe, r.ay);
+    s.Kin = K;
+    s.Zin = s.ZYe + smul48(j, r.Dz);
+    s.Din = r.ay;
+    s.rin = r.ry;
+    s.KYe = K + r.ax;
+    s.ZYe = s.Zin + r.Dz;
+    s.KXe += (int64_t)mul48((uint32_t)c, r.ay);
+    s.ZXe += smul48(c, r.Dz);
+    s.nj = start;
+    s.ni = r.cx0 + (r.Dx > 0 ? c : -c);
+    s.entry = (r.Dy > 0 ? kWmy : kWpy) | kAnchored;
+  }
+  r.cx0 = s.ni;
+  r.cy0 = s.nj;
+}
+
+// Move a level-0 walk state up to the level-L node holding its cell: the
+// far faces of that node lie the remaining cells of the node further on.
+__device__ __forceinline__ void lift(const ray_t& r, walk_t& s, int32_t L) {
+  if (L <= 0) return;
+  const int32_t ni = s.ni >> L, nj = s.nj >> L;
+  const int32_t kx = r.Dx > 0 ? ((ni + 1) << L) - 1 - s.ni : s.ni - (ni << L);
+  const int32_t ky = r.Dy > 0 ? ((nj + 1) << L) - 1 - s.nj : s.nj - (nj << L);
+  s.KXe += (int64_t)mul48((uint32_t)kx, r.ay);
+  s.KYe += (int64_t)mul48((uint32_t)ky, r.ax);
+  s.ZXe += smul48(kx, r.Dz);
+  s.ZYe += smul48(ky, r.Dz);
+  s.ni = ni;
+  s.nj = nj;
+  s.L = L;
+}
+
+// With boost > 0 (wave-uniform loop only), a wave raises its instruction
+// issue priority after boost, 2*boost and 4*boost iterations: the few long
+// walks of a launch, which otherwise trail it, then win issue slots over
+// the many short ones sharing their SIMD.
+// With kSeg the walk also stops (kSegEnd) once its node lies wholly
+// outside the cell lines [seg_lo, seg_hi] of axis seg_axis (0 x, 1 y).
+template <bool kSeg = false>
+__device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
+                                              const ray_t& r, walk_t& s,
+                                              int32_t max_level, int32_t budget,
+                                              uint32_t& col, int32_t boost = 0,
+                                              int32_t seg_axis = 0,
+                                              int32_t seg_lo = 0, int32_t seg_hi = 0) {
   const bool desc = r.Dz < 0;
-  const int64_t SZ = (int64_t)r.Dz << 16;
+  const int32_t sx = r.Dx > 0 ? 1 : -1, sy = r.Dy > 0 ? 1 : -1;
+  const int32_t nearx = r.Dx > 0 ? 0 : 1, neary = r.Dy > 0 ? 0 : 1;
   for (int32_t it = 0; it < budget; ++it) {
+    if (boost > 0) {
+      if (it == boost) __builtin_amdgcn_s_setprio(1);
+      else if (it == 2 * boost) __builtin_amdgcn_s_setprio(2);
+      else if (it == 4 * boost) __builtin_amdgcn_s_setprio(3);
+    }
     if (++s.iters > kIterCap) return kCapped;
-    const int32_t L = kFlat ? 0 : s.L;
+    const int32_t L = s.L;
+    if (kSeg) {
+      const int32_t n = seg_axis == 0 ? s.ni : s.nj;
+      if ((n << L) > seg_hi || ((n + 1) << L) - 1 < seg_lo) return kSegEnd;
+    }
     const lvl_t l = lv[L];
-    const int32_t ni = s.cx >> L, nj = s.cy >> L;
-    const bool inmap = (uint32_t)ni < (uint32_t)l.w && (uint32_t)nj < (uint32_t)l.h;
+    const bool inmap = (uint32_t)s.ni < (uint32_t)l.w && (uint32_t)s.nj < (uint32_t)l.h;
     uint32_t v = 0;
     s.reads += inmap ? 1 : 0;
     if (inmap)
-      v = m.base[l.off + ((__umul24((uint32_t)nj >> 3, (uint32_t)l.tiles_x) +
-                           ((uint32_t)ni >> 3)) << 6) +
-                 ((nj & 7) << 3) + (ni & 7)];
-    // crossings before the node's far face on each axis
-    int32_t kxm1 = 0, kym1 = 0;
-    int64_t Kxe = s.Kx, Kye = s.Ky;
-    if (!kFlat) {
-      kxm1 = r.Dx > 0 ? ((ni + 1) << L) - 1 - s.cx : s.cx - (ni << L);
-      kym1 = r.Dy > 0 ? ((nj + 1) << L) - 1 - s.cy : s.cy - (nj << L);
-      Kxe += (int64_t)(mul48((uint32_t)kxm1, r.ay) << 16);
-      Kye += (int64_t)(mul48((uint32_t)kym1, r.ax) << 16);
-    }
-    const bool ex = Kxe <= Kye;               // leave through an x face
-    const int32_t km1 = ex ? kxm1 : kym1;
-    int64_t Ze = ex ? s.Zx : s.Zy;
-    if (!kFlat) Ze += smul48(km1, r.Dz) << 16;
+      v = m.base[l.off + ((__umul24((uint32_t)s.nj >> 3, (uint32_t)l.tiles_x) +
+                           ((uint32_t)s.ni >> 3)) << 6) +
+                 ((s.nj & 7) << 3) + (s.ni & 7)];
+    const bool ex = s.KXe <= s.KYe;           // leave through an x face
+    const int64_t Ze = ex ? s.ZXe : s.ZYe;
     const uint32_t De = ex ? r.ax : r.ay;
+    const uint32_t re = ex ? r.rx : r.ry;
     bool occ = false;
     if (inmap) {
-      const int64_t Zlo = desc ? Ze : s.Zin;
+      const int64_t lo = (desc ? Ze : s.Zin) + (int64_t)(desc ? re : s.rin);
       const uint32_t Dlo = desc ? De : s.Din;
-      const int64_t Zhi = desc ? s.Zin : Ze;
+      const int64_t hi = desc ? s.Zin : Ze;
       const uint32_t Dhi = desc ? s.Din : De;
       const uint32_t a = v & 0xFF, b = (v >> 8) & 0xFF, c = (v >> 16) & 0xFF;
-      occ = (Zlo <= hS(a, Dlo)) || ((Zlo <= hS(c, Dlo)) && (Zhi >= hS(b, Dhi)));
+      occ = (lo <= (int64_t)__umul24(a, Dlo)) ||
+            ((lo <= (int64_t)__umul24(c, Dlo)) && (hi >= (int64_t)__umul24(b, Dhi)));
     }
     if (occ) {
       if (L == 0) {
         col = v;
         return kHitCell;
       }
-      s.L = L - 1;
+      // descend into the child holding the ray after the entry crossing
+      const int32_t Lc = L - 1;
+      const int64_t midx = s.KXe - ushl(r.ay, Lc), midy = s.KYe - ushl(r.ax, Lc);
+      int32_t bx, by;
+      const bool anchored = (s.entry & kAnchored) != 0;
+      if (r.Dx == 0 || anchored) bx = (r.cx0 >> Lc) & 1;
+      else if (s.entry == kWmx || s.entry == kWpx) bx = nearx;
+      else bx = (midx <= s.Kin) ? 1 - nearx : nearx;
+      if (r.Dy == 0 || anchored) by = (r.cy0 >> Lc) & 1;
+      else if (s.entry == kWmy || s.entry == kWpy) by = neary;
+      else by = (midy < s.Kin) ? 1 - neary : neary;
+      if (bx == nearx) {
+        s.KXe = midx;
+        s.ZXe -= sshl(r.Dz, Lc);
+      }
+      if (by == neary) {
+        s.KYe = midy;
+        s.ZYe -= sshl(r.Dz, Lc);
+      }
+      s.ni = 2 * s.ni + bx;
+      s.nj = 2 * s.nj + by;
+      s.L = Lc;
       continue;
     }
-    // jump to the node exit: km1 + 1 crossings on the exit axis and, on
-    // the other axis, those strictly before it (x first on ties)
-    int32_t ko = 0;
-    if (!kFlat && L > 0)
-      ko = ex ? count_below(Kxe, s.Ky, r.ax) : count_below(Kye + 1, s.Kx, r.ay);
-    const int32_t kx = ex ? km1 + 1 : ko;
-    const int32_t ky = ex ? ko : km1 + 1;
-    // exit axis: one step past its exit crossing; other axis: ko steps
+    // step to the next node of this level through the exit face
+    const int32_t pi = s.ni, pj = s.nj;
     if (ex) {
-      s.Kx = Kxe + ((int64_t)r.ay << 16);
-      s.Zx = Ze + SZ;
-      if (!kFlat && ko) {
-        s.Ky += (int64_t)(mul48((uint32_t)ko, r.ax) << 16);
-        s.Zy += smul48(ko, r.Dz) << 16;
-      }
+      s.Kin = s.KXe;
+      s.KXe += ushl(r.ay, L);
+      s.ZXe += sshl(r.Dz, L);
+      s.ni += sx;
+      s.entry = r.Dx > 0 ? kWmx : kWpx;
     } else {
-      s.Ky = Kye + ((int64_t)r.ax << 16);
-      s.Zy = Ze + SZ;
-      if (!kFlat && ko) {
-        s.Kx += (int64_t)(mul48((uint32_t)ko, r.ay) << 16);
-        s.Zx += smul48(ko, r.Dz) << 16;
-      }
+      s.Kin = s.KYe;
+      s.KYe += ushl(r.ax, L);
+      s.ZYe += sshl(r.Dz, L);
+      s.nj += sy;
+      s.entry = r.Dy > 0 ? kWmy : kWpy;
     }
-    const int32_t pcx = s.cx, pcy = s.cy;
-    s.cx += r.Dx > 0 ? kx : -kx;
-    s.cy += r.Dy > 0 ? ky : -ky;
     s.Zin = Ze;
     s.Din = De;
-    s.entry = ex ? (r.Dx > 0 ? kWmx : kWpx) : (r.Dy > 0 ? kWmy : kWpy);
+    s.rin = re;
     // the ray cannot come back into the map, or is above all solid
-    const bool away = (s.cx < 0 && r.Dx <= 0) || (s.cx >= m.W && r.Dx >= 0) ||
-                      (s.cy < 0 && r.Dy <= 0) || (s.cy >= m.H && r.Dy >= 0);
-    const bool above = r.Dz >= 0 && s.Zin > hS(255, s.Din);
+    const bool away = (s.ni < 0 && r.Dx <= 0) || (s.ni >= l.w && r.Dx >= 0) ||
+                      (s.nj < 0 && r.Dy <= 0) || (s.nj >= l.h && r.Dy >= 0);
+    const bool above = r.Dz >= 0 && !z_le(s.Zin, s.rin, 255, s.Din);
     if (away || above) return kMissed;
-    // go up one level when the jump left the parent node
-    if (!kFlat && L < max_level && (((pcx ^ s.cx) | (pcy ^ s.cy)) >> (L + 1)) != 0)
+    // go up one level when the step entered a new parent node; the new node
+    // is then the near half of its parent along the exit axis
+    if (L < max_level && (((pi ^ s.ni) | (pj ^ s.nj)) >> 1) != 0) {
+      if (ex || (s.ni & 1) == nearx) {
+        s.KXe += ushl(r.ay, L);
+        s.ZXe += sshl(r.Dz, L);
+      }
+      if (!ex || (s.nj & 1) == neary) {
+        s.KYe += ushl(r.ax, L);
+        s.ZYe += sshl(r.Dz, L);
+      }
+      s.ni >>= 1;
+      s.nj >>= 1;
       s.L = L + 1;
+    }
   }
   return kWalking;
 }
@@ -341,9 +485,13 @@ __device__ __forceinline__ int32_t find_view(const int64_t* pkt_prefix,
 // view; packets run row-major (order 0) or column-major (order 1).
 __device__ __forceinline__ void packet_pixel(const tci_view& v, int64_t t,
                                              int32_t k, int32_t order,
+                                             const int32_t* rows,
                                              int32_t& px, int32_t& py) {
   int32_t tx, ty;
-  if (order) {
+  if (order == 2) {
+    tx = (int32_t)(t % v.tiles_x);
+    ty = rows[v.rows_off + t / v.tiles_x];
+  } else if (order == 1) {
     const int32_t tiles_y = (v.h + 7) >> 3;
     tx = (int32_t)(t / tiles_y);
     ty = (int32_t)(t % tiles_y);
@@ -393,7 +541,7 @@ __global__ __launch_bounds__(256) void render_kernel(
   const int32_t vi = __builtin_amdgcn_readfirstlane(find_view(pkt_prefix, nviews, p));
   const tci_view& v = views[vi];
   int32_t px, py;
-  packet_pixel(v, p - v.pkt_base, lane, o.tile_order, px, py);
+  packet_pixel(v, p - v.pkt_base, lane, o.tile_order, o.rows, px, py);
   if (px >= v.w || py >= v.h) return;
   ray_t r;
   pixel_ray(v, px, py, r);
@@ -406,13 +554,123 @@ __global__ __launch_bounds__(256) void render_kernel(
     const int32_t top = kFlat ? 0 : m.top;
     walk_init(r, kFlat ? 0 : clamp_level(o.start_level, top), s);
     uint32_t col = 0;
-    const int32_t st = walk_steps<kFlat>(m, lv, r, s,
-                                         kFlat ? 0 : clamp_level(o.max_level, top),
-                                         kIterCap + 1, col);
+    const int32_t Lmax = kFlat ? 0 : clamp_level(o.max_level, top);
+    const int32_t boost = __builtin_amdgcn_readfirstlane(o.boost);
+    bool split = !kFlat && o.split_budget > 0 && o.qcap > 0;
+    int32_t st;
+    for (;;) {
+      st = walk_steps(m, lv, r, s, Lmax, split ? o.split_budget : kIterCap + 1, col, boost);
+      if (!split) break;
+      split = false;
+      // long walks go to the split pass, as many as the queue holds
+      const uint64_t want = __ballot(st == kWalking);
+      if (!want) break;
+      const uint64_t act = __ballot(1);
+      const int32_t leader = __ffsll((unsigned long long)act) - 1;
+      uint32_t base = 0;
+      if (lane == leader) base = atomicAdd(o.qcount, (uint32_t)__popcll(want));
+      base = __shfl(base, leader);
+      if (st != kWalking) break;
+      const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+          (uint32_t)(want >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)want, 0));
+      if (base + rank < o.qcap) {
+        // the walk has reached the current node: the second pass need only
+        // split the path from the node's near line on the dominant axis
+        const bool ax_x = r.ax >= r.ay;
+        const int32_t n = ax_x ? s.ni : s.nj, c0 = ax_x ? r.cx0 : r.cy0;
+        const bool fwd = (ax_x ? r.Dx : r.Dy) > 0;
+        const int32_t near = fwd ? (n << s.L) : ((n + 1) << s.L) - 1;
+        const int32_t from = fwd ? max(near, c0) : min(near, c0);
+        o.queue[base + rank] = make_uint4((uint32_t)vi, (uint32_t)(py * v.w + px),
+                                          (uint32_t)from, 0u);
+        if (o.count) atomicAdd(o.count, (unsigned long long)s.reads);
+        return;
+      }
+    }
     finish(r, s, m.W, st, col, word, depth);
     if (o.count) atomicAdd(o.count, (unsigned long long)s.reads);
   }
   store_hit(out, v.out_base + (int64_t)py * v.w + px, word, depth);
+}
+
+// Dominant-axis cell line where the ray leaves the map's columns, or rises
+// above every height, estimated in double precision (only the sizes of the
+// split segments depend on it).
+__device__ __forceinline__ int32_t exit_line(const ray_t& r, const tci_map& m,
+                                             int32_t axis) {
+  const double S = 65536.0;
+  double t = 1e300;
+  if (r.Dx > 0) t = fmin(t, ((double)m.W * S - (double)r.Ox) / r.Dx);
+  if (r.Dx < 0) t = fmin(t, (double)r.Ox / -(double)r.Dx);
+  if (r.Dy > 0) t = fmin(t, ((double)m.H * S - (double)r.Oy) / r.Dy);
+  if (r.Dy < 0) t = fmin(t, (double)r.Oy / -(double)r.Dy);
+  if (r.Dz > 0) t = fmin(t, (256.0 * S - (double)r.Oz) / r.Dz);
+  t = fmax(t, 0.0);
+  const double c = axis == 0 ? ((double)r.Ox + t * r.Dx) / S : ((double)r.Oy + t * r.Dy) / S;
+  const double lim = axis == 0 ? (double)m.W : (double)m.H;
+  return (int32_t)floor(fmin(fmax(c, -1.0), lim));
+}
+
+// Split pass: one wave per queued ray; lane k walks the k-th of 64 runs of
+// dominant-axis cell lines (the last run is open-ended), each from the
+// exact state in which the flat walk enters it.  The first lane with a hit
+// holds the ray's first hit.  Waves stride over the queue and leave when
+// it is exhausted.
+__global__ __launch_bounds__(256) void split_kernel(tci_map m,
+                                                    const tci_view* __restrict__ views,
+                                                    void* out, tci_render_opts o) {
+  __shared__ lvl_t lv[TCI_MAX_LEVELS];
+  load_levels(m, lv);
+  const int32_t lane = threadIdx.x & 63;
+  const uint32_t n = min(*o.qcount, o.qcap);
+  const int32_t Lmax = clamp_level(o.max_level, m.top);
+  for (uint32_t e = blockIdx.x * 4 + (threadIdx.x >> 6); e < n; e += gridDim.x * 4) {
+    const uint4 q = o.queue[e];
+    const tci_view& v = views[q.x];
+    const int32_t px = (int32_t)(q.y % (uint32_t)v.w), py = (int32_t)(q.y / (uint32_t)v.w);
+    ray_t r;
+    pixel_ray(v, px, py, r);
+    const int32_t axis = r.ax >= r.ay ? 0 : 1;
+    const int32_t c0 = (int32_t)q.z;   // first line still to walk
+    const int32_t dir = (axis == 0 ? r.Dx : r.Dy) > 0 ? 1 : -1;
+    const int32_t last = exit_line(r, m, axis);
+    const int64_t N = max((int64_t)1, (int64_t)(last - c0) * dir + 1);
+    const int32_t b0 = c0 + dir * (int32_t)(((int64_t)lane * N) >> 6);
+    const int32_t b1 = c0 + dir * (int32_t)(((int64_t)(lane + 1) * N) >> 6);
+    int32_t lo = INT32_MIN, hi = INT32_MAX;
+    if (lane < 63) {
+      if (dir > 0) hi = b1 - 1; else lo = b1 + 1;
+    }
+    walk_t s;
+    uint32_t col = 0;
+    int32_t st = kSegEnd;
+    if (lane == 63 || b0 != b1) {
+      seg_init(r, s, axis, b0);
+      lift(r, s, clamp_level(o.start_level, Lmax));
+      st = kWalking;
+    }
+    // walk in chunks; once some segment holds a hit, the segments after it
+    // cannot matter and stop
+    for (;;) {
+      const uint64_t hit_now = __ballot(st == kHitCell || st == kCapped);
+      const int32_t first = hit_now ? __ffsll((unsigned long long)hit_now) - 1 : 64;
+      if (st == kWalking && lane > first) st = kSegEnd;
+      if (!__ballot(st == kWalking)) break;
+      if (st == kWalking)
+        st = walk_steps<true>(m, lv, r, s, Lmax, 16, col, 0, axis, lo, hi);
+    }
+    if (o.count && (lane == 63 || b0 != b1)) atomicAdd(o.count, (unsigned long long)s.reads);
+    const uint64_t hits = __ballot(st == kHitCell || st == kCapped);
+    const int64_t idx = v.out_base + q.y;
+    if (hits == 0) {
+      if (lane == 0) store_hit(out, idx, kMiss, __builtin_inff());
+    } else if (lane == __ffsll((unsigned long long)hits) - 1) {
+      uint32_t word;
+      float depth;
+      finish(r, s, m.W, st, col, word, depth);
+      store_hit(out, idx, word, depth);
+    }
+  }
 }
 
 // Persistent waves.  Each wave keeps 64 rays in flight; when at least
@@ -463,7 +721,7 @@ __global__ __launch_bounds__(256) void render_persistent_kernel(
           const int32_t vi = find_view(pkt_prefix, nviews, mypkt);
           const tci_view& v = views[vi];
           int32_t px, py;
-          packet_pixel(v, mypkt - v.pkt_base, myray, o.tile_order, px, py);
+          packet_pixel(v, mypkt - v.pkt_base, myray, o.tile_order, o.rows, px, py);
           if (px < v.w && py < v.h) {
             pixel_ray(v, px, py, r);
             out_idx = v.out_base + (int64_t)py * v.w + px;
@@ -489,7 +747,7 @@ __global__ __launch_bounds__(256) void render_persistent_kernel(
     if (drained && __ballot(active) == 0) break;
     int32_t st = kWalking;
     uint32_t col = 0;
-    if (active) st = walk_steps<false>(m, lv, r, s, Lmax, iters, col);
+    if (active) st = walk_steps(m, lv, r, s, Lmax, iters, col);
     if (st != kWalking) {
       uint32_t word;
       float depth;
@@ -516,6 +774,13 @@ hipError_t tci_launch_render(const tci_map& m, const tci_view* views,
     hipLaunchKernelGGL(render_kernel<false>, dim3((uint32_t)blocks),
                        dim3(256), 0, s, m, views, nviews, pkt_prefix, npkt,
                        out, o);
+  return hipGetLastError();
+}
+
+hipError_t tci_launch_split(const tci_map& m, const tci_view* views,
+                            const tci_render_opts& o, void* out, int32_t nblocks,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(split_kernel, dim3(nblocks), dim3(256), 0, s, m, views, out, o);
   return hipGetLastError();
 }
 

@@ -96,7 +96,7 @@ def test_autotune_keeps_results(ctx):
     assert np.array_equal(w, ref[0]) and np.array_equal(d.view(np.uint32), ref[1].view(np.uint32))
     ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, 0)
     ctx.tc_set_option(tc.TC_OPT_START_LEVEL, 2)
-    ctx.tc_set_option(tc.TC_OPT_TILE_ORDER, 1)
+    ctx.tc_set_option(tc.TC_OPT_TILE_ORDER, 2)
     ctx.tc_set_option(tc.TC_OPT_XCD_REMAP, 0)
 
 

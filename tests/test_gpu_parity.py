@@ -151,6 +151,80 @@ def test_level_options_do_not_change_results(ctx):
     ctx.tc_set_option(tc.TC_OPT_PERSIST_WAVES, 16)
 
 
+def test_packet_orders_and_xcd_groups(ctx):
+    """Every packet order and XCD grouping gives the same bytes."""
+    F, B, T = synth.make_map_from_config(1)
+    load(ctx, F, B, T)
+    rng = np.random.default_rng(12)
+    views = _random_views(rng, F, B, 12, [(77, 53), (130, 9), (8, 300), (64, 64)])
+    wo, do = oracle.render(F, B, T, views)
+    for order in (0, 1, 2):
+        for remap in (0, 3):
+            ctx.tc_set_option(tc.TC_OPT_TILE_ORDER, order)
+            ctx.tc_set_option(tc.TC_OPT_XCD_REMAP, remap)
+            for mode in MODES:
+                wg, dg = gpu_render(ctx, views, mode)
+                assert_parity(wg, dg, wo, do, "order %d remap %d %s" % (order, remap, mode))
+    ctx.tc_set_option(tc.TC_OPT_TILE_ORDER, 2)
+    ctx.tc_set_option(tc.TC_OPT_XCD_REMAP, 0)
+
+
+@pytest.mark.parametrize("budget,queue", [(1, 1 << 20), (5, 1 << 20), (1, 7), (30, 1000)])
+def test_split_pass(ctx, budget, queue):
+    """Rays still walking after `budget` steps are finished by 64 parallel
+    segment walks; a tiny budget sends nearly every ray there, a tiny queue
+    leaves the overflow to the first pass.  Results must not change."""
+    F, B, T = synth.make_map_from_config(1)
+    load(ctx, F, B, T)
+    rng = np.random.default_rng(13)
+    views = synth.config_views(1, F, B) + _random_views(
+        rng, F, B, 9, [(77, 53), (8, 9), (130, 64)])
+    wo, do = oracle.render(F, B, T, views)
+    ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, budget)
+    ctx.tc_set_option(tc.TC_OPT_SPLIT_QUEUE, queue)
+    try:
+        for order, start in ((0, 0), (2, 2), (2, 5)):
+            ctx.tc_set_option(tc.TC_OPT_TILE_ORDER, order)
+            ctx.tc_set_option(tc.TC_OPT_START_LEVEL, start)
+            wg, dg = gpu_render(ctx, views, "hier")
+            assert_parity(wg, dg, wo, do, "split budget %d queue %d start %d" % (
+                budget, queue, start))
+    finally:
+        ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 128)
+        ctx.tc_set_option(tc.TC_OPT_SPLIT_QUEUE, 1 << 17)
+        ctx.tc_set_option(tc.TC_OPT_TILE_ORDER, 2)
+        ctx.tc_set_option(tc.TC_OPT_START_LEVEL, 2)
+
+
+def test_split_pass_edge_rays_and_large_map(ctx):
+    """Split walks on rays from outside the map, along cell edges and over
+    the 2048x2048 map's long horizon rays."""
+    F, B, T = synth.make_map(61, 45, 3, dual=0.35, period=16)
+    load(ctx, F, B, T)
+    views = [
+        synth.ortho_view((0, -5 * S, 40 * S), (S, 0, 0), (0, S // 4, 0), (0, 3, -1), 62, 60),
+        synth.ortho_view((-5 * S, 0, 80 * S), (0, S, 0), (0, 0, S // 2), (5, 0, -2), 46, 70),
+        synth.ortho_view((0, 0, 60 * S), (S, 0, 0), (0, S, 0), (1, 1, -1), 61, 45),
+        synth.perspective_view((-500.0, -300.0, 90.0), 45, -3, 64, 48),
+        synth.perspective_view((30.5, 22.5, 400.0), 10, -89.9, 50, 50),
+    ]
+    wo, do = oracle.render(F, B, T, views)
+    ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 2)
+    try:
+        wg, dg = gpu_render(ctx, views, "hier")
+        assert_parity(wg, dg, wo, do, "split edge")
+        F, B, T = synth.make_map_from_config(2)
+        load(ctx, F, B, T)
+        v = synth.config_views(2, F, B)
+        wo, do = oracle.render(F, B, T, v)
+        for budget in (8, 96):
+            ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, budget)
+            wg, dg = gpu_render(ctx, v, "hier")
+            assert_parity(wg, dg, wo, do, "split c2 budget %d" % budget)
+    finally:
+        ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 128)
+
+
 def test_straight_down_closed_form_large_map(ctx):
     """Straight-down orthographic image over the whole 2048x16384 map: each
     hit is the column's topmost solid, face top, depth 256 - height."""

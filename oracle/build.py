@@ -5,13 +5,16 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "oracle.c")
+SOURCES = [SRC, os.path.join(HERE, "march.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 
 def build(verbose=False):
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-pthread",
-           "-Wall", "-Wextra", "-o", tmp, SRC, "-lm"]
+    # no floating-point contraction: the sampled march is defined one IEEE
+    # single operation at a time
+    cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fPIC", "-shared",
+           "-pthread", "-Wall", "-Wextra", "-o", tmp] + SOURCES + ["-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -4,7 +4,7 @@ import os
 
 import numpy as np
 
-from .build import LIB, SRC, build
+from .build import LIB, SOURCES, build
 
 _lib = None
 
@@ -20,7 +20,8 @@ MISS = 0xFFFFFFFF
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < max(
+                os.path.getmtime(f) for f in SOURCES):
             build()
         L = ctypes.CDLL(LIB)
         p = ctypes.c_void_p
@@ -38,6 +39,17 @@ def lib():
         L.or_cast_pixels.restype = None
         L.or_cast_pixels.argtypes = [ctypes.c_int32, ctypes.c_int32, p, p, p,
                                      p, p, p, p, ctypes.c_int64, p, p]
+        f32, i32, i64 = ctypes.c_float, ctypes.c_int32, ctypes.c_int64
+        L.om_march_rows.restype = i64
+        L.om_march_rows.argtypes = [i32, i32, p, p, p, p, ctypes.c_int, i32, i32,
+                                    i32, f32, ctypes.c_int, ctypes.c_int, p, p,
+                                    ctypes.c_int, p]
+        L.om_march_list.restype = None
+        L.om_march_list.argtypes = [i32, i32, p, p, p, p, p, i64, f32,
+                                    ctypes.c_int, ctypes.c_int, p, p]
+        L.om_march_pixels.restype = None
+        L.om_march_pixels.argtypes = [i32, i32, p, p, p, p, p, p, p, i64, f32,
+                                      ctypes.c_int, ctypes.c_int, p, p]
         _lib = L
     return _lib
 
@@ -125,6 +137,68 @@ def cast_pixels(F, B, T, views, vi, px, py):
     depth = np.empty(n, np.float64)
     lib().or_cast_pixels(W, H, _ptr(F), _ptr(B), _ptr(T), _ptr(v), _ptr(vi),
                          _ptr(px), _ptr(py), n, _ptr(word), _ptr(depth))
+    return word, depth
+
+
+def _march_args(far, steps, bisect):
+    if not (far > 0 and 1 <= steps and 0 <= bisect):
+        raise ValueError("march needs far > 0, steps >= 1, bisect >= 0")
+    return float(np.float32(far)), int(steps), int(bisect)
+
+
+def march(F, B, T, views, far=600.0, steps=128, bisect=4, threads=None,
+          rows=None, with_reads=False):
+    """Sampled march (Section 3.1 RAYMARCH, single precision) of every pixel
+    of every view.  Returns (word uint32[n], depth float32[n]) and, with
+    with_reads, the number of in-map samples tested."""
+    F, B, T = _map(F, B, T)
+    v = _views(views)
+    H, W = F.shape
+    r0, r1, st = rows if rows is not None else (0, 1 << 30, 1)
+    n = 0
+    for x in v:
+        hh = min(int(x["height"]), r1)
+        n += int(x["width"]) * len(range(r0, hh, st)) if hh > r0 else 0
+    word = np.empty(n, np.uint32)
+    depth = np.empty(n, np.float32)
+    reads = ctypes.c_int64(0)
+    th = threads if threads else (os.cpu_count() or 1)
+    got = lib().om_march_rows(W, H, _ptr(F), _ptr(B), _ptr(T), _ptr(v), len(v),
+                              r0, r1, st, *_march_args(far, steps, bisect),
+                              _ptr(word), _ptr(depth), th, ctypes.byref(reads))
+    if got != n:
+        raise RuntimeError("oracle march failed")
+    return (word, depth, reads.value) if with_reads else (word, depth)
+
+
+def march_rays(F, B, T, O, D, far=600.0, steps=128, bisect=4):
+    """Sampled march of explicit rays: O, D int64 arrays of shape (n, 3)."""
+    F, B, T = _map(F, B, T)
+    H, W = F.shape
+    O = np.ascontiguousarray(O, np.int64).reshape(-1, 3)
+    D = np.ascontiguousarray(D, np.int64).reshape(-1, 3)
+    n = O.shape[0]
+    word = np.empty(n, np.uint32)
+    depth = np.empty(n, np.float32)
+    lib().om_march_list(W, H, _ptr(F), _ptr(B), _ptr(T), _ptr(O), _ptr(D), n,
+                        *_march_args(far, steps, bisect), _ptr(word), _ptr(depth))
+    return word, depth
+
+
+def march_pixels(F, B, T, views, vi, px, py, far=600.0, steps=128, bisect=4):
+    """Sampled march of selected pixels (view index, column, row)."""
+    F, B, T = _map(F, B, T)
+    H, W = F.shape
+    v = _views(views)
+    vi = np.ascontiguousarray(vi, np.int32)
+    px = np.ascontiguousarray(px, np.int32)
+    py = np.ascontiguousarray(py, np.int32)
+    n = vi.size
+    word = np.empty(n, np.uint32)
+    depth = np.empty(n, np.float32)
+    lib().om_march_pixels(W, H, _ptr(F), _ptr(B), _ptr(T), _ptr(v), _ptr(vi),
+                          _ptr(px), _ptr(py), n, *_march_args(far, steps, bisect),
+                          _ptr(word), _ptr(depth))
     return word, depth
 
 

@@ -22,7 +22,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-MODES = {"hier": 0, "flat": 1, "persistent": 2}
+MODES = {"hier": 0, "flat": 1, "persistent": 2, "march": 3}
+KERNEL_NAMES = {"hier": "render_kernel<false> + split_kernel (one traversal)",
+                "flat": "render_kernel<true>", "persistent": "render_persistent_kernel",
+                "march": "march_kernel"}
+PROTOCOL_SEED = 6000      # poses of the twelve protocol views
 
 
 def log(*a):
@@ -80,6 +84,19 @@ def time_renders(torch, ctx, tc, views, out, steps, warmup):
     return ms, wall
 
 
+def kernel_times(torch, ctx, tc, views, out, steps):
+    """(traversal kernel ms, split pass ms) of each of `steps` renders,
+    from the HIP events the library records around its kernels."""
+    ctx.tc_set_option(tc.TC_OPT_KERNEL_TIMING, 1)
+    rows = []
+    for _ in range(steps):
+        ctx.tc_render_views(views, out.data_ptr())
+        rows.append(ctx.tc_read_kernel_times())
+    ctx.tc_set_option(tc.TC_OPT_KERNEL_TIMING, 0)
+    torch.cuda.synchronize()
+    return np.array(rows, dtype=np.float64)
+
+
 def cpu_baseline(oracle, F, B, T, views, rays_per_frame, budget_s=12.0):
     """The CPU oracle on the host cores, on repeated renders of the same
     view until about budget_s seconds of wall time have passed."""
@@ -130,6 +147,79 @@ def c3_frame(torch, tc, synth, steps, warmup):
             "rays_per_frame": rays, "frame_ms_median": float(np.median(ms)),
             "frame_ms_p99": float(np.percentile(ms, 99)),
             "grays_per_s": rays / (np.median(ms) * 1e-3) / 1e9}
+
+
+def march_protocol(torch, tc, synth, steps, warmup):
+    """The sampled march of Section 3.1 at the paper's setting (128 samples,
+    4 halvings, far 600) on the views of its measurement protocol (Section
+    4.3: twelve 1280x800 views, three per pitch 0, -30, -60, -90 degrees)
+    over the 2048x16384 map.  Per view: march and exact render times, and
+    the quality metrics of Section 4.2 of the march against the exact cast
+    (a hit beyond the far limit counts as background), averaged per pitch
+    as the paper reports them."""
+    from paper_2608_17390_amd import metrics
+    F, B, T = synth.make_map_from_config(3)
+    views, pitches = synth.pitch_views(F, B, PROTOCOL_SEED)
+    ctx = tc.Context(0)
+    ctx.tc_load_columns(F, B, T)
+    n = 1280 * 800
+    outs = {m: [torch.empty((n, 2), dtype=torch.int32, device="cuda") for _ in views]
+            for m in ("march", "hier")}
+    times = {}
+    kern = {}
+    for m in ("march", "hier"):
+        ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, MODES[m])
+        per_view = []
+        kv = []
+        for v, out in zip(views, outs[m]):
+            ms, _ = time_renders(torch, ctx, tc, [v], out, steps, warmup)
+            per_view.append(float(np.median(ms)))
+            kv.append(kernel_times(torch, ctx, tc, [v], out, steps).sum(axis=1).mean())
+        times[m] = per_view
+        kern[m] = kv
+    # algorithmic bytes of the march: 8 B per hit record + 4 B per column
+    # sample read over the map (the library's own count)
+    ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, MODES["march"])
+    ctx.tc_set_option(tc.TC_OPT_COUNT_READS, 1)
+    ctx.tc_read_counters()
+    for v, out in zip(views, outs["march"]):
+        ctx.tc_render_views([v], out.data_ptr())
+    samples = ctx.tc_read_counters()
+    ctx.tc_set_option(tc.TC_OPT_COUNT_READS, 0)
+    torch.cuda.synchronize()
+    q = []
+    for k, v in enumerate(views):
+        wm, dm = tc.split_hits(outs["march"][k])
+        we, de = tc.split_hits(outs["hier"][k])
+        q.append(metrics.quality(wm, dm, we, de, 1280, 800, far=600.0))
+    per_pitch = {}
+    for p in sorted(set(pitches), reverse=True):
+        ks = [k for k, pk in enumerate(pitches) if pk == p]
+        per_pitch[str(p)] = {
+            "march_ms": float(np.mean([times["march"][k] for k in ks])),
+            "exact_ms": float(np.mean([times["hier"][k] for k in ks])),
+            "see_through_pct": 100 * float(np.mean([q[k]["see_through"] for k in ks])),
+            "covers_sky_pct": 100 * float(np.mean([q[k]["covers_sky"] for k in ks])),
+            "coherence_pct": 100 * float(np.mean([q[k]["coherence"] for k in ks])),
+            "depth_err_median": float(np.mean([q[k]["depth_err_median"] for k in ks])),
+            "depth_err_p95": float(np.mean([q[k]["depth_err_p95"] for k in ks])),
+        }
+    alg = 8 * n * len(views) + 4 * samples
+    kms = float(np.sum(kern["march"]))
+    ctx.close()
+    return {"workload": "protocol: 2048x16384 map, twelve 1280x800 views (3 per pitch "
+                        "0/-30/-60/-90), march 128 samples + 4 halvings, far 600",
+            "march_ms_per_view": float(np.mean(times["march"])),
+            "exact_ms_per_view": float(np.mean(times["hier"])),
+            "march_grays_per_s": n / (np.mean(times["march"]) * 1e-3) / 1e9,
+            "exact_grays_per_s": n / (np.mean(times["hier"]) * 1e-3) / 1e9,
+            "samples_per_ray": samples / (n * len(views)),
+            "march_roofline": {"bound": "hbm", "achieved": alg / (kms * 1e-3) / 1e9,
+                               "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                               "frac": alg / (kms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                               "alg_bytes_per_view": alg / len(views),
+                               "kernel_ms_per_view": kms / len(views)},
+            "per_pitch": per_pitch}
 
 
 def c4_batched(torch, tc, synth, steps, warmup):
@@ -274,6 +364,8 @@ def main():
                     help="also time every render mode")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a 256 MiB device copy (counter calibration)")
+    ap.add_argument("--no-march", action="store_true",
+                    help="skip the sampled-march leg (protocol views)")
     ap.add_argument("--no-growth", action="store_true",
                     help="skip the edit frame (c3), batched frame (c4) and server (c5)")
     args = ap.parse_args()
@@ -300,11 +392,16 @@ def main():
     out = torch.empty((rays, 2), dtype=torch.int32, device="cuda")
     ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, MODES[args.mode])
 
-    # algorithmic bytes: node/cell reads counted by the library itself
+    # algorithmic bytes: node/cell reads of the one-pass exact walk (split
+    # pass off, so speculative segment walks are not counted), counted by
+    # the library itself
+    budget = ctx.tc_get_option(tc.TC_OPT_SPLIT_BUDGET)
+    ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 0)
     ctx.tc_set_option(tc.TC_OPT_COUNT_READS, 1)
     ctx.tc_render_views(views, out.data_ptr())
     reads = ctx.tc_read_counters()
     ctx.tc_set_option(tc.TC_OPT_COUNT_READS, 0)
+    ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, budget)
     alg_bytes = 8 * rays + 4 * reads
     log("[bench] %d rays, %d node/cell reads (%.1f per ray)" % (rays, reads, reads / rays))
 
@@ -312,8 +409,11 @@ def main():
     ms, wall = time_renders(torch, ctx, tc, views, out, args.steps, args.warmup)
     ms_per_step = wall * 1e3 / args.steps
     med = float(np.median(ms))
-    avg = float(ms.mean())
-    achieved = alg_bytes / (avg * 1e-3) / 1e9
+    # the traversal kernels alone, timed by HIP events the library records
+    # on the render stream around each kernel, over as many renders again
+    kern = kernel_times(torch, ctx, tc, views, out, args.steps)
+    kavg = float(kern.sum(axis=1).mean())
+    achieved = alg_bytes / (kavg * 1e-3) / 1e9
     res = {
         "metric": "Grays/s and ms/frame @1920x1080 eye-level; batched vs plain p99 latency",
         "value": rays / (ms_per_step * 1e-3) / 1e9,
@@ -335,9 +435,12 @@ def main():
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                      "traffic": traffic_from_profile(os.path.join(
                          ROOT, "paper_2608_17390_amd", "csrc", "tc_render.hip")),
-                     "kernel": "render_kernel<false>" if args.mode == "hier" else args.mode,
+                     "kernel": KERNEL_NAMES[args.mode],
                      "alg_bytes_per_launch": alg_bytes,
-                     "kernel_ms_avg": avg},
+                     "kernel_ms_avg": kavg,
+                     "traversal_ms_avg": float(kern[:, 0].mean()),
+                     "split_pass_ms_avg": float(kern[:, 1].mean()),
+                     "render_call_ms_avg": float(ms.mean())},
     }
     if args.extra:
         modes = {}
@@ -346,6 +449,9 @@ def main():
             mm, _ = time_renders(torch, ctx, tc, views, out, 10, 2)
             modes[m] = float(np.median(mm))
         res["mode_ms_median"] = modes
+    if not args.no_march:
+        log("[bench] sampled march on the protocol views")
+        res["march_protocol"] = march_protocol(torch, tc, synth, 10, 2)
     if not args.no_growth:
         log("[bench] c3 edit frame")
         res["c3_frame"] = c3_frame(torch, tc, synth, 10, 2)

@@ -163,7 +163,9 @@ tc_status tc_render_views(tc_context *ctx, const tc_view *views, int32_t n,
 /* ---- options ---------------------------------------------------------- */
 /* Tuning knobs of the render path.  Each takes effect for later calls. */
 #define TC_OPT_RENDER_MODE 1   /* 0 hierarchical (default), 1 flat walk,
-                                  2 persistent packet queue */
+                                  2 persistent packet queue (all three
+                                  exact and bit-identical); 3 the sampled
+                                  march below */
 #define TC_OPT_START_LEVEL 2   /* pyramid level a ray starts at (default 2);
                                   clamped to the top level */
 #define TC_OPT_MAX_LEVEL 3     /* highest level a ray ascends to (default
@@ -199,6 +201,32 @@ tc_status tc_render_views(tc_context *ctx, const tc_view *views, int32_t n,
 #define TC_OPT_SPLIT_QUEUE 12    /* most rays the second pass takes per call;
                                     further long rays finish in the first
                                     pass (default 131072) */
+/* Render mode 3 is the paper's sampled ray march (Section 3.1, RAYMARCH),
+ * not an exact cast.  Per pixel the segment from the eye ends at the far
+ * limit (TC_OPT_MARCH_FAR world units along the ray) or where the ray
+ * reaches z = 0, whichever is first; TC_OPT_MARCH_STEPS points spaced
+ * uniformly inside it are tested in order with the SOLID predicate; the
+ * first solid one and the one before it (or the eye) are refined by
+ * TC_OPT_MARCH_BISECT halvings and the solid end is the hit.  The end point
+ * is never tested, so a ray with no solid sample is a miss.  All arithmetic
+ * is IEEE single precision, one rounding per operation:
+ *   o = (float)O * 2^-16, d = (float)D, len = sqrt((dx*dx + dy*dy) + dz*dz),
+ *   t_end = far / len, then min(t_end, -oz / dz) if dz < 0,
+ *   dt = t_end / (steps + 1), sample i at t = (float)i * dt,
+ *   point = o + t * d, midpoint (ta + tb) * 0.5, depth = tb * len,
+ * so results are reproducible bit for bit.  A hit word holds the column of
+ * the final point, face 0 (TC_FACE_SAMPLED) and the layer whose interval
+ * holds it.  A sample can step over a feature thinner than its spacing:
+ * that is the method's quality/cost trade-off (Section 3.1). */
+#define TC_FACE_SAMPLED 0
+#define TC_OPT_MARCH_STEPS 14    /* forward samples, 1..65536 (default 128) */
+#define TC_OPT_MARCH_BISECT 15   /* bisection steps, 0..64 (default 4) */
+#define TC_OPT_MARCH_FAR 16      /* far limit in world units, 1..2^20
+                                    (default 600, Section 5) */
+#define TC_OPT_KERNEL_TIMING 13  /* 1: tc_render_views records HIP events on
+                                    its stream around each render kernel,
+                                    read back by tc_read_kernel_times
+                                    (diagnostic; default 0) */
 tc_status tc_set_option(tc_context *ctx, int32_t key, int64_t value);
 tc_status tc_get_option(const tc_context *ctx, int32_t key, int64_t *value);
 
@@ -322,6 +350,14 @@ tc_status tc_read_pyramid(tc_context *ctx, int32_t level, uint32_t *out,
  * pyramid nodes and cells read by all rays rendered since the last reset.
  * Synchronises `hip_stream`.  0 if counting was never enabled. */
 tc_status tc_read_counters(tc_context *ctx, uint64_t *reads, void *hip_stream);
+
+/* Durations in milliseconds of the kernels of the most recent
+ * tc_render_views call made with TC_OPT_KERNEL_TIMING on, measured with HIP
+ * events recorded on that call's stream: ms[0] the traversal kernel (any
+ * render mode), ms[1] the split pass (0 when it did not run).  `ms` holds 2
+ * floats.  Waits for those events.  TC_INVALID_ARG if no timed call was
+ * made since timing was switched on. */
+tc_status tc_read_kernel_times(tc_context *ctx, float *ms);
 
 /* Device bytes held by the map: packed columns plus every pyramid level. */
 tc_status tc_map_bytes(const tc_context *ctx, uint64_t *bytes);

@@ -14,4 +14,6 @@ from ._tc import (Context, Frame, Server, TCError, tc_create, tc_view, tc_edit, 
                   TC_OPT_PERSIST_WAVES, TC_OPT_REFILL_MIN,
                   TC_OPT_REFILL_ITERS, TC_OPT_COUNT_READS,
                   TC_OPT_TILE_ORDER, TC_OPT_PRIORITY_BOOST, TC_OPT_SPLIT_BUDGET,
-                  TC_OPT_SPLIT_QUEUE)
+                  TC_OPT_SPLIT_QUEUE, TC_OPT_KERNEL_TIMING,
+                  TC_OPT_MARCH_STEPS, TC_OPT_MARCH_BISECT, TC_OPT_MARCH_FAR,
+                  TC_FACE_SAMPLED)

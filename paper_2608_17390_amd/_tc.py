@@ -39,6 +39,11 @@ TC_OPT_TILE_ORDER = 9
 TC_OPT_PRIORITY_BOOST = 10
 TC_OPT_SPLIT_BUDGET = 11
 TC_OPT_SPLIT_QUEUE = 12
+TC_OPT_KERNEL_TIMING = 13
+TC_OPT_MARCH_STEPS = 14
+TC_OPT_MARCH_BISECT = 15
+TC_OPT_MARCH_FAR = 16
+TC_FACE_SAMPLED = 0
 
 _STATUS = {0: "TC_OK", -1: "TC_INVALID_ARG", -2: "TC_OUT_OF_MEMORY",
            -3: "TC_NO_MAP", -4: "TC_DEVICE_ERROR", -5: "TC_OVER_BUDGET",
@@ -94,6 +99,7 @@ SIGNATURES = [
     ("tc_pyramid_dims", _I32, [_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     ("tc_read_pyramid", _I32, [_P, _I32, _P, _P]),
     ("tc_read_counters", _I32, [_P, ctypes.POINTER(ctypes.c_uint64), _P]),
+    ("tc_read_kernel_times", _I32, [_P, ctypes.POINTER(ctypes.c_float)]),
     ("tc_map_bytes", _I32, [_P, ctypes.POINTER(ctypes.c_uint64)]),
     ("tc_frame_create", _I32, [_P, ctypes.POINTER(tc_view), _I32, ctypes.POINTER(tc_edit),
                                _I32, _P, _P, ctypes.POINTER(_P)]),
@@ -308,6 +314,12 @@ class Context:
         _check(self._h, load_library().tc_read_counters(self._h, ctypes.byref(v),
                                                         _stream_handle(stream)))
         return v.value
+
+    def tc_read_kernel_times(self):
+        """(traversal kernel ms, split pass ms) of the last timed render."""
+        ms = (ctypes.c_float * 2)()
+        _check(self._h, load_library().tc_read_kernel_times(self._h, ms))
+        return float(ms[0]), float(ms[1])
 
     def tc_frame_create(self, views, edits, out_ptr, stream=None):
         varr = _views_struct(views)

@@ -16,8 +16,11 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtc.so")
 INCLUDE = os.path.join(ROOT, "include")
-SOURCES = ["tc_map.hip", "tc_render.hip", "tc_api.cpp", "tc_frame.cpp",
-           "tc_server.cpp"]
+SOURCES = ["tc_map.hip", "tc_render.hip", "tc_march.hip", "tc_api.cpp",
+           "tc_frame.cpp", "tc_server.cpp"]
+# per-source flags: the sampled march is defined one IEEE single operation
+# at a time, so nothing may be fused into a multiply-add
+EXTRA = {"tc_march.hip": ["-ffp-contract=off"]}
 ARCH = os.environ.get("TC_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -39,8 +42,8 @@ def build(verbose=False, jobs=None):
     for src in SOURCES:
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
         objs.append(obj)
-        cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src),
-                                 "-o", obj]
+        cmd = [HIPCC] + FLAGS + EXTRA.get(src, []) + [
+            "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append(subprocess.Popen(cmd))

@@ -119,6 +119,9 @@ tci_render_opts render_opts(const tc_context* c) {
   o.queue = nullptr;
   o.qcount = nullptr;
   o.count = c->count_reads ? c->d_count : nullptr;
+  o.march_far = (float)c->march_far;
+  o.march_steps = c->march_steps;
+  o.march_bisect = c->march_bisect;
   return o;
 }
 
@@ -305,19 +308,30 @@ void write_views(const ViewPlan& p, char* host) {
 }
 
 hipError_t enqueue_render(tc_context* ctx, const tci_map& d, const char* dev,
-                          const ViewPlan& p, void* out, hipStream_t s) {
+                          const ViewPlan& p, void* out, hipStream_t s,
+                          hipEvent_t* kev, bool* split_ran) {
   tci_render_opts o = render_opts(ctx);
   o.rows = (const int32_t*)(dev + p.off_rows);
   const tci_view* dv = (const tci_view*)(dev + p.off_views);
   const int64_t* pre = (const int64_t*)(dev + p.off_prefix);
+  auto mark = [&](int i) { return kev ? hipEventRecord(kev[i], s) : hipSuccess; };
+  if (split_ran) *split_ran = false;
+  if (ctx->render_mode == 3) {
+    hipError_t e = mark(0);
+    if (e == hipSuccess) e = tci_launch_march(d, dv, p.n, pre, p.npkt, out, o, s);
+    if (e == hipSuccess) e = mark(1);
+    return e;
+  }
   if (ctx->render_mode == 2) {
     uint64_t* counter = (uint64_t*)(dev + p.off_counter);
     hipError_t e = tci_launch_zero_u64(counter, 1, s);
     int64_t blocks = (int64_t)ctx->num_cu * ctx->persist_waves / 4;
     blocks = std::max<int64_t>(1, std::min<int64_t>(blocks, (p.npkt + 3) / 4));
+    if (e == hipSuccess) e = mark(0);
     if (e == hipSuccess)
       e = tci_launch_render_persistent(d, dv, p.n, pre, p.npkt, out, counter,
                                        (int32_t)blocks, o, s);
+    if (e == hipSuccess) e = mark(1);
     return e;
   }
   if (p.qcap > 0) {
@@ -327,14 +341,22 @@ hipError_t enqueue_render(tc_context* ctx, const tci_map& d, const char* dev,
     o.queue = (uint4*)(dev + p.off_queue);
     o.qcount = (uint32_t*)(counters + 1);
     hipError_t e = tci_launch_zero_u64(counters, 2, s);
+    if (e == hipSuccess) e = mark(0);
     if (e == hipSuccess)
       e = tci_launch_render(d, dv, p.n, pre, p.npkt, out, 0, o, s);
+    if (e == hipSuccess) e = mark(1);
     const int32_t nb = (int32_t)std::max<int64_t>(
         1, std::min<int64_t>(ctx->num_cu * 16, ((int64_t)p.qcap + 3) / 4));
     if (e == hipSuccess) e = tci_launch_split(d, dv, o, out, nb, s);
+    if (e == hipSuccess) e = mark(2);
+    if (split_ran) *split_ran = true;
     return e;
   }
-  return tci_launch_render(d, dv, p.n, pre, p.npkt, out, ctx->render_mode == 1, o, s);
+  hipError_t e = mark(0);
+  if (e == hipSuccess)
+    e = tci_launch_render(d, dv, p.n, pre, p.npkt, out, ctx->render_mode == 1, o, s);
+  if (e == hipSuccess) e = mark(1);
+  return e;
 }
 
 }  // namespace tci
@@ -387,6 +409,8 @@ void tc_destroy(tc_context* ctx) {
   }
   if (ctx->map) (void)hipFree(ctx->map);
   if (ctx->d_count) (void)hipFree(ctx->d_count);
+  for (hipEvent_t& e : ctx->kev)
+    if (e) (void)hipEventDestroy(e);
   delete ctx;
 }
 
@@ -518,14 +542,26 @@ tc_status tc_render_views(tc_context* ctx, const tc_view* views, int32_t n,
     st = set_device(ctx);
     if (st) return st;
     hipStream_t s = (hipStream_t)hip_stream;
+    hipEvent_t* kev = nullptr;
+    if (ctx->kernel_timing) {
+      for (hipEvent_t& ev : ctx->kev)
+        if (!ev) TC_HIP(hipEventCreate(&ev), "hipEventCreate");
+      kev = ctx->kev;
+    }
     tci::Slot* slot = nullptr;
     st = tci::acquire(ctx, plan.total, &slot);
     if (st) return st;
     tci::write_views(plan, (char*)slot->host);
     hipError_t e = hipMemcpyAsync(slot->dev, slot->host, plan.off_counter,
                                   hipMemcpyHostToDevice, s);
+    bool split_ran = false;
     if (e == hipSuccess)
-      e = tci::enqueue_render(ctx, ctx->desc, (const char*)slot->dev, plan, out_device, s);
+      e = tci::enqueue_render(ctx, ctx->desc, (const char*)slot->dev, plan, out_device, s,
+                              kev, &split_ran);
+    if (kev) {
+      ctx->kev_valid = e == hipSuccess;
+      ctx->kev_split = split_ran;
+    }
     tc_status rs = tci::release(ctx, slot, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "tc_render_views");
     return rs;
@@ -539,7 +575,7 @@ tc_status tc_set_option(tc_context* ctx, int32_t key, int64_t value) {
   ctx->err.clear();
   switch (key) {
     case TC_OPT_RENDER_MODE:
-      if (value < 0 || value > 2) break;
+      if (value < 0 || value > 3) break;
       ctx->render_mode = (int32_t)value;
       return TC_OK;
     case TC_OPT_START_LEVEL:
@@ -573,6 +609,23 @@ tc_status tc_set_option(tc_context* ctx, int32_t key, int64_t value) {
     case TC_OPT_SPLIT_QUEUE:
       if (value < 1 || value > (1 << 26)) break;
       ctx->split_queue = (int32_t)value;
+      return TC_OK;
+    case TC_OPT_MARCH_STEPS:
+      if (value < 1 || value > 65536) break;
+      ctx->march_steps = (int32_t)value;
+      return TC_OK;
+    case TC_OPT_MARCH_BISECT:
+      if (value < 0 || value > 64) break;
+      ctx->march_bisect = (int32_t)value;
+      return TC_OK;
+    case TC_OPT_MARCH_FAR:
+      if (value < 1 || value > (1 << 20)) break;
+      ctx->march_far = (int32_t)value;
+      return TC_OK;
+    case TC_OPT_KERNEL_TIMING:
+      if (value < 0 || value > 1) break;
+      ctx->kernel_timing = (int32_t)value;
+      ctx->kev_valid = false;
       return TC_OK;
     case TC_OPT_PRIORITY_BOOST:
       if (value < 0 || value > (1 << 20)) break;
@@ -614,6 +667,10 @@ tc_status tc_get_option(const tc_context* ctx, int32_t key, int64_t* value) {
     case TC_OPT_PRIORITY_BOOST: *value = ctx->boost; return TC_OK;
     case TC_OPT_SPLIT_BUDGET: *value = ctx->split_budget; return TC_OK;
     case TC_OPT_SPLIT_QUEUE: *value = ctx->split_queue; return TC_OK;
+    case TC_OPT_KERNEL_TIMING: *value = ctx->kernel_timing; return TC_OK;
+    case TC_OPT_MARCH_STEPS: *value = ctx->march_steps; return TC_OK;
+    case TC_OPT_MARCH_BISECT: *value = ctx->march_bisect; return TC_OK;
+    case TC_OPT_MARCH_FAR: *value = ctx->march_far; return TC_OK;
     default: return TC_INVALID_ARG;
   }
 }
@@ -717,6 +774,23 @@ tc_status tc_read_counters(tc_context* ctx, uint64_t* reads, void* hip_stream) {
   TC_HIP(hipMemsetAsync(ctx->d_count, 0, sizeof(v), s), "hipMemsetAsync(counter)");
   TC_HIP(hipStreamSynchronize(s), "hipStreamSynchronize(counter)");
   *reads = v;
+  return TC_OK;
+}
+
+tc_status tc_read_kernel_times(tc_context* ctx, float* ms) {
+  if (!ctx) return TC_INVALID_ARG;
+  ctx->err.clear();
+  if (!ms) return fail(ctx, TC_INVALID_ARG, "tc_read_kernel_times: ms is NULL");
+  if (!ctx->kev_valid)
+    return fail(ctx, TC_INVALID_ARG, "tc_read_kernel_times: no timed render since timing was enabled");
+  tc_status st = set_device(ctx);
+  if (st) return st;
+  const int last = ctx->kev_split ? 2 : 1;
+  TC_HIP(hipEventSynchronize(ctx->kev[last]), "hipEventSynchronize");
+  TC_HIP(hipEventElapsedTime(&ms[0], ctx->kev[0], ctx->kev[1]), "hipEventElapsedTime");
+  ms[1] = 0.0f;
+  if (ctx->kev_split)
+    TC_HIP(hipEventElapsedTime(&ms[1], ctx->kev[1], ctx->kev[2]), "hipEventElapsedTime");
   return TC_OK;
 }
 

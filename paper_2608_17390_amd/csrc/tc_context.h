@@ -64,8 +64,11 @@ hipError_t enqueue_edits(const tci_map& d, uint32_t* map, const char* dev,
 tc_status plan_views(tc_context* ctx, const tc_view* views, int32_t n,
                      ViewPlan& plan);
 void write_views(const ViewPlan& plan, char* host);
+// `kev`, if given, receives event records before the traversal kernel,
+// after it and after the split pass (the last only when that pass runs).
 hipError_t enqueue_render(tc_context* ctx, const tci_map& d, const char* dev,
-                          const ViewPlan& plan, void* out, hipStream_t s);
+                          const ViewPlan& plan, void* out, hipStream_t s,
+                          hipEvent_t* kev = nullptr, bool* split_ran = nullptr);
 
 tci_render_opts render_opts(const tc_context* c);
 
@@ -97,7 +100,14 @@ struct tc_context {
   int32_t boost = 0;
   int32_t split_budget = 128;
   int32_t split_queue = 1 << 17;
+  int32_t march_steps = 128;
+  int32_t march_bisect = 4;
+  int32_t march_far = 600;
   unsigned long long* d_count = nullptr;
+  // TC_OPT_KERNEL_TIMING: events of the last timed render call
+  int32_t kernel_timing = 0;
+  hipEvent_t kev[3] = {nullptr, nullptr, nullptr};
+  bool kev_valid = false, kev_split = false;
   // a running server owns the map (tc_server.cpp)
   void* server = nullptr;
 };

@@ -164,6 +164,8 @@ tc_status tc_autotune(tc_context* ctx, const tc_view* views, int32_t n,
   try {
     ctx->err.clear();
     if (!ctx->map) return fail(ctx, TC_NO_MAP, "tc_autotune: no map loaded");
+    if (ctx->render_mode == 3)
+      return fail(ctx, TC_INVALID_ARG, "tc_autotune: tunes the exact render modes only");
     hipStream_t s = (hipStream_t)hip_stream;
     std::vector<Knobs> cand;
     const Knobs cur = read_knobs(ctx);

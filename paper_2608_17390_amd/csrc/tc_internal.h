@@ -72,6 +72,9 @@ struct tci_render_opts {
                                // dominant-axis cell line still to walk, 0)
   uint32_t* qcount;            // split queue length
   unsigned long long* count;   // if set: add each ray's node/cell reads
+  float march_far;             // sampled march: far limit along each ray
+  int32_t march_steps;         // sampled march: forward samples
+  int32_t march_bisect;        // sampled march: bisection steps
 };
 
 // ---- launchers (return hipError_t of the launch) -------------------------
@@ -105,6 +108,11 @@ hipError_t tci_launch_render_persistent(const tci_map& m,
                                         const tci_render_opts& o,
                                         hipStream_t s);
 hipError_t tci_launch_zero_u64(uint64_t* p, int32_t n, hipStream_t s);
+// Render: the sampled march (RAYMARCH), one thread per pixel.
+hipError_t tci_launch_march(const tci_map& m, const tci_view* views,
+                            int32_t nviews, const int64_t* pkt_prefix,
+                            int64_t npkt, void* out, const tci_render_opts& o,
+                            hipStream_t s);
 // Second pass of a hierarchical render: walk every queued long ray as 64
 // segments in parallel, one wave per ray.
 hipError_t tci_launch_split(const tci_map& m, const tci_view* views,

@@ -15,7 +15,7 @@ from .configs import CONFIGS, SEEDS, config
 from .maps import make_map, make_map_from_config, pack_columns_check
 from .views import (S, MAX_DIR, VIEW_DTYPE, perspective_view, ortho_view,
                     shadow_view, views_array, config_views, view_rays,
-                    batched_views, request_view, eye_above_floor)
+                    batched_views, request_view, eye_above_floor, pitch_views)
 from .edits import crater_list, random_set_patches, EDIT_CRATER, EDIT_SET
 from .arrivals import poisson_arrivals
 
@@ -23,7 +23,7 @@ __all__ = [
     "CONFIGS", "SEEDS", "config", "make_map", "make_map_from_config",
     "pack_columns_check", "S", "MAX_DIR", "VIEW_DTYPE", "perspective_view",
     "ortho_view", "shadow_view", "views_array", "config_views", "view_rays",
-    "batched_views", "request_view", "eye_above_floor",
+    "batched_views", "request_view", "eye_above_floor", "pitch_views",
     "crater_list", "random_set_patches", "EDIT_CRATER", "EDIT_SET",
     "poisson_arrivals",
 ]

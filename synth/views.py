@@ -178,6 +178,22 @@ def request_view(rng, F, B):
     return v[0]
 
 
+def pitch_views(F, B, seed, width=1280, height=800, pitches=(0, -30, -60, -90),
+                per_pitch=3, dz=40.0):
+    """Views of the paper's measurement protocol (Section 4.3): per_pitch
+    random poses at each pitch, width x height, each eye dz units above a
+    single-layer column.  Returns (views, pitch of each view)."""
+    rng = np.random.default_rng(seed)
+    H, W = F.shape
+    views, tags = [], []
+    for pitch in pitches:
+        for _ in range(per_pitch):
+            eye = eye_above_floor(F, B, rng.uniform(0, W), rng.uniform(0, H), dz=dz)
+            views.append(perspective_view(eye, rng.uniform(0, 360), pitch, width, height))
+            tags.append(pitch)
+    return views, tags
+
+
 def config_views(k, F, B):
     """The fixed views of configurations 1-4 (list of VIEW_DTYPE scalars)."""
     from .configs import config as _config

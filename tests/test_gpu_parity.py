@@ -112,6 +112,33 @@ def test_c2_full_image(ctx, mode):
     assert_parity(wg, dg, wo, do, "c2 " + mode)
 
 
+def test_kernel_timing_leaves_results_unchanged(ctx):
+    """TC_OPT_KERNEL_TIMING records events around the kernels: results are
+    the same bytes, times are positive, the split pass time is 0 when that
+    pass is off, and reading before any timed render is an error."""
+    F, B, T = synth.make_map_from_config(2)
+    load(ctx, F, B, T)
+    views = synth.config_views(2, F, B)
+    ref = gpu_render(ctx, views, "hier")
+    ctx.tc_set_option(tc.TC_OPT_KERNEL_TIMING, 1)
+    with pytest.raises(tc.TCError) as e:
+        ctx.tc_read_kernel_times()
+    assert e.value.status == tc.TC_INVALID_ARG
+    try:
+        for mode, budget in (("hier", 128), ("hier", 0), ("flat", 128), ("persistent", 128)):
+            ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, budget)
+            w, d = gpu_render(ctx, views, mode)
+            assert np.array_equal(w, ref[0]), mode
+            assert np.array_equal(d.view(np.uint32), ref[1].view(np.uint32)), mode
+            t0, t1 = ctx.tc_read_kernel_times()
+            assert t0 > 0
+            assert (t1 > 0) == (mode == "hier" and budget > 0), (mode, budget, t1)
+    finally:
+        ctx.tc_set_option(tc.TC_OPT_KERNEL_TIMING, 0)
+        ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 128)
+        ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, 0)
+
+
 def test_modes_identical_bytes(ctx):
     F, B, T = synth.make_map_from_config(2)
     load(ctx, F, B, T)

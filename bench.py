@@ -294,7 +294,7 @@ def c5_served(torch, tc, synth, rates=(200, 500, 1000, 2000, 5000, 10000),
     """Configuration 5: Poisson request streams against the resident
     2048x16384 map; 90% views (sizes and poses as configuration 4), 10%
     craters of size 16-64; an 8 GiB in-flight hit-buffer budget.  Served:
-    continuous batching (up to 64 views per batch, 4 streams).  FIFO plain:
+    continuous batching (up to 8 views per batch, 2 streams).  FIFO plain:
     the same server with one view per batch on one stream.  Latency runs
     from submission to observed completion."""
     F, B, T = synth.make_map_from_config(5)
@@ -316,7 +316,7 @@ def c5_served(torch, tc, synth, rates=(200, 500, 1000, 2000, 5000, 10000),
         # C structures built before the timed submission loop
         cs = [tc.view_struct(x) if k == "view" else tc.edits_struct(x) for k, x in reqs]
         res = {}
-        for name, batch, streams in (("served", 64, 4), ("fifo_plain", 1, 1)):
+        for name, batch, streams in (("served", 8, 2), ("fifo_plain", 1, 1)):
             ctx.tc_load_columns(F, B, T)
             srv = ctx.tc_server_start(8 << 30, max_batch_views=batch, streams=streams,
                                       flags=tc.TC_SERVER_AUTO_RELEASE)

@@ -279,10 +279,13 @@ tc_status tc_autotune(tc_context *ctx, const tc_view *views, int32_t n,
  * admitted once its hit buffer fits in a device pool of budget_bytes (the
  * in-flight budget), and admitted views are launched together, up to
  * max_batch_views per render, on one of `streams` streams, so work that
- * arrives while other batches run overlaps them on the device.  A view sees
- * exactly the edits submitted before it: the map is kept in two version
- * buffers and an edit is applied to a copy of the newest version once no
- * batch reads the other buffer.  While a server runs it owns the map:
+ * arrives while other batches run overlaps them on the device.  Batches use
+ * the context's render mode and knobs, with the split pass of the
+ * hierarchical mode off.  A view sees exactly the edits submitted before
+ * it: the map is kept in two version buffers, and an edit is applied to the
+ * buffer not holding the newest version, once no batch reads it, after that
+ * buffer replays the previous edit; starting a server copies the map once
+ * into the second buffer.  While a server runs it owns the map:
  * tc_load_columns, tc_apply_edit, tc_render_views and frames on the context
  * fail with TC_INVALID_ARG, and the render knobs must not change.
  * tc_server_stop drains all submitted work and leaves the newest map

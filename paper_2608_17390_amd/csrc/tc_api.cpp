@@ -224,7 +224,8 @@ hipError_t enqueue_edits(const tci_map& d, uint32_t* map, const char* dev,
   return e;
 }
 
-tc_status plan_views(tc_context* ctx, const tc_view* views, int32_t n, ViewPlan& p) {
+tc_status plan_views(tc_context* ctx, const tc_view* views, int32_t n, ViewPlan& p,
+                     bool allow_split) {
   if (n < 1 || !views) return fail(ctx, TC_INVALID_ARG, "render: no views");
   p.n = n;
   p.views.resize(n);
@@ -293,7 +294,7 @@ tc_status plan_views(tc_context* ctx, const tc_view* views, int32_t n, ViewPlan&
   p.off_rows = (p.off_prefix + sizeof(int64_t) * ((size_t)n + 1) + 15) & ~(size_t)15;
   p.off_counter = (p.off_rows + sizeof(int32_t) * p.rows.size() + 15) & ~(size_t)15;
   // the split queue follows the counters (device only, never uploaded)
-  p.qcap = (ctx->render_mode == 0 && ctx->split_budget > 0)
+  p.qcap = (allow_split && ctx->render_mode == 0 && ctx->split_budget > 0)
                ? (uint32_t)std::min<int64_t>(out, ctx->split_queue) : 0;
   p.off_queue = p.off_counter + 64;
   p.total = p.off_queue + sizeof(uint4) * (size_t)p.qcap;
@@ -309,7 +310,7 @@ void write_views(const ViewPlan& p, char* host) {
 
 hipError_t enqueue_render(tc_context* ctx, const tci_map& d, const char* dev,
                           const ViewPlan& p, void* out, hipStream_t s,
-                          hipEvent_t* kev, bool* split_ran) {
+                          hipEvent_t* kev, bool* split_ran, bool counters_zeroed) {
   tci_render_opts o = render_opts(ctx);
   o.rows = (const int32_t*)(dev + p.off_rows);
   const tci_view* dv = (const tci_view*)(dev + p.off_views);
@@ -324,7 +325,7 @@ hipError_t enqueue_render(tc_context* ctx, const tci_map& d, const char* dev,
   }
   if (ctx->render_mode == 2) {
     uint64_t* counter = (uint64_t*)(dev + p.off_counter);
-    hipError_t e = tci_launch_zero_u64(counter, 1, s);
+    hipError_t e = counters_zeroed ? hipSuccess : tci_launch_zero_u64(counter, 1, s);
     int64_t blocks = (int64_t)ctx->num_cu * ctx->persist_waves / 4;
     blocks = std::max<int64_t>(1, std::min<int64_t>(blocks, (p.npkt + 3) / 4));
     if (e == hipSuccess) e = mark(0);
@@ -340,7 +341,7 @@ hipError_t enqueue_render(tc_context* ctx, const tci_map& d, const char* dev,
     o.qcap = p.qcap;
     o.queue = (uint4*)(dev + p.off_queue);
     o.qcount = (uint32_t*)(counters + 1);
-    hipError_t e = tci_launch_zero_u64(counters, 2, s);
+    hipError_t e = counters_zeroed ? hipSuccess : tci_launch_zero_u64(counters, 2, s);
     if (e == hipSuccess) e = mark(0);
     if (e == hipSuccess)
       e = tci_launch_render(d, dv, p.n, pre, p.npkt, out, 0, o, s);
@@ -552,12 +553,13 @@ tc_status tc_render_views(tc_context* ctx, const tc_view* views, int32_t n,
     st = tci::acquire(ctx, plan.total, &slot);
     if (st) return st;
     tci::write_views(plan, (char*)slot->host);
-    hipError_t e = hipMemcpyAsync(slot->dev, slot->host, plan.off_counter,
+    // tables and zeroed queue counters in one upload
+    hipError_t e = hipMemcpyAsync(slot->dev, slot->host, plan.off_queue,
                                   hipMemcpyHostToDevice, s);
     bool split_ran = false;
     if (e == hipSuccess)
       e = tci::enqueue_render(ctx, ctx->desc, (const char*)slot->dev, plan, out_device, s,
-                              kev, &split_ran);
+                              kev, &split_ran, true);
     if (kev) {
       ctx->kev_valid = e == hipSuccess;
       ctx->kev_split = split_ran;

@@ -61,14 +61,20 @@ void plan_edits(const tci_map& d, const tc_edit* edits, int32_t n,
 hipError_t enqueue_edits(const tci_map& d, uint32_t* map, const char* dev,
                          const EditPlan& plan, hipStream_t s);
 
+// With allow_split false the plan has no split queue (qcap 0), whatever
+// the context's split budget.
 tc_status plan_views(tc_context* ctx, const tc_view* views, int32_t n,
-                     ViewPlan& plan);
+                     ViewPlan& plan, bool allow_split = true);
 void write_views(const ViewPlan& plan, char* host);
 // `kev`, if given, receives event records before the traversal kernel,
 // after it and after the split pass (the last only when that pass runs).
+// With counters_zeroed the queue counters at plan.off_counter were uploaded
+// as zeros with the tables (bytes [0, plan.off_queue)), so no kernel clears
+// them; a captured frame, which replays, clears them itself.
 hipError_t enqueue_render(tc_context* ctx, const tci_map& d, const char* dev,
                           const ViewPlan& plan, void* out, hipStream_t s,
-                          hipEvent_t* kev = nullptr, bool* split_ran = nullptr);
+                          hipEvent_t* kev = nullptr, bool* split_ran = nullptr,
+                          bool counters_zeroed = false);
 
 tci_render_opts render_opts(const tc_context* c);
 

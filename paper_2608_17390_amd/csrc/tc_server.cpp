@@ -10,11 +10,18 @@
 //    one of several streams, so batches that arrive while others run
 //    overlap on the device;
 //  * edits: the map lives in two version buffers.  A view renders the
-//    version holding exactly the edits submitted before it.  An edit is
-//    applied by copying the newest version into the other buffer -- once no
-//    batch still reads that buffer -- and editing it there, on a separate
-//    stream; batches of later views wait for that edit's event.  A view's
-//    result is therefore the same alone and in any mix.
+//    version holding exactly the edits submitted before it.  Edit k goes
+//    into the buffer that does not hold the newest version -- once no batch
+//    still reads it -- after that buffer has caught up by replaying edit
+//    k - 1 (it holds every edit before that one), on a separate stream;
+//    batches of later views wait for that stream's event.  Every edit is
+//    thus applied twice, once per buffer, and no map is ever copied.  A
+//    view's result is the same alone and in any mix.
+//  * batches run the render mode and options of the context, except that
+//    the split pass of the hierarchical mode is off;
+//  * wake-up: submissions signal the server thread, which sleeps only when
+//    nothing is queued or in flight, and polls completions while work is
+//    on the device.
 //
 // Section 2 of the paper: edits are gameplay operations whose results must
 // be visible without reloading; Section 7: its frames are submitted and
@@ -109,6 +116,14 @@ class Pool {
   size_t used_ = 0;
 };
 
+// An uploaded edit list, kept until both version buffers hold it.
+struct EditUpload {
+  tci::EditPlan plan;
+  tci::Slot slot;
+  uint64_t epoch = 0;
+  bool valid = false;
+};
+
 struct Batch {
   std::vector<uint64_t> ids;
   int version = 0;
@@ -136,11 +151,13 @@ struct tc_server {
   hipStream_t edit_stream = nullptr;
   hipEvent_t edit_ev = nullptr;           // end of the newest edit
   std::deque<std::pair<uint64_t, hipEvent_t>> edits_in_flight;
-  tci::Slot edit_slot;
+  EditUpload uploads[2];                   // the newest edit and the one before
+  uint64_t edits_applied = 0;
   std::vector<Batch> slots;
   // request state (guarded by mu)
   std::mutex mu;
   std::condition_variable cv_done;
+  std::condition_variable cv_work;         // signalled on submission and stop
   std::unordered_map<uint64_t, Request> reqs;
   std::deque<uint64_t> incoming;
   uint64_t next_id = 1;
@@ -214,8 +231,10 @@ bool launch_batch(tc_server* s) {
       r.state = kInFlight;
     }
   }
+  // batches run without the split pass: under concurrent requests its
+  // second launch costs more latency than the long walks it shortens
   tci::ViewPlan plan;
-  if (tci::plan_views(ctx, views.data(), (int32_t)views.size(), plan) != TC_OK) {
+  if (tci::plan_views(ctx, views.data(), (int32_t)views.size(), plan, false) != TC_OK) {
     set_error(s, hipErrorInvalidValue, "server: view validation");
     return true;
   }
@@ -237,11 +256,11 @@ bool launch_batch(tc_server* s) {
   const int v = s->current;
   hipError_t e = hipStreamWaitEvent(b->stream, s->edit_ev, 0);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(b->slot.dev, b->slot.host, plan.off_counter, hipMemcpyHostToDevice,
+    e = hipMemcpyAsync(b->slot.dev, b->slot.host, plan.off_queue, hipMemcpyHostToDevice,
                        b->stream);
   if (e == hipSuccess)
     e = tci::enqueue_render(ctx, version_desc(s, v), (const char*)b->slot.dev, plan,
-                            s->pool_dev, b->stream);
+                            s->pool_dev, b->stream, nullptr, nullptr, true);
   if (e == hipSuccess) e = hipEventRecord(b->done, b->stream);
   if (e != hipSuccess) {
     set_error(s, e, "server: render launch");
@@ -257,58 +276,74 @@ bool launch_batch(tc_server* s) {
 }
 
 // Apply the edit request at the head of the queue, if the target version
-// buffer is free.  Returns true if it was applied.
+// buffer is free.  Returns true if it was applied (or failed for good).
 bool apply_edit(tc_server* s, uint64_t id) {
   const int tgt = 1 - s->current;
   if (s->ver_readers[tgt] > 0) return false;
-  tc_context* ctx = s->ctx;
   Request* r;
   {
     std::lock_guard<std::mutex> g(s->mu);
     r = &s->reqs[id];
     r->state = kInFlight;
   }
-  // copy the newest version into the target, then edit the target
-  tci::EditPlan plan;
-  size_t patch_bytes = r->patch.size();
   const tci_map d = version_desc(s, tgt);
-  tci::plan_edits(d, r->edits.data(), (int32_t)r->edits.size(), patch_bytes, nullptr, plan);
-  if (s->edit_slot.cap < plan.total) {
-    (void)hipStreamSynchronize(s->edit_stream);
-    if (s->edit_slot.host) (void)hipHostFree(s->edit_slot.host);
-    if (s->edit_slot.dev) (void)hipFree(s->edit_slot.dev);
-    s->edit_slot.host = s->edit_slot.dev = nullptr;
-    size_t cap = std::max<size_t>(plan.total, 64 << 10);
-    hipError_t e = hipHostMalloc(&s->edit_slot.host, cap, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipMalloc(&s->edit_slot.dev, cap);
-    if (e != hipSuccess) {
-      set_error(s, e, "server: edit staging");
+  // the target holds every edit but the newest applied one: replay it
+  hipError_t e = hipSuccess;
+  if (s->ver_epoch[tgt] != s->ver_epoch[s->current]) {
+    const EditUpload& prev = s->uploads[(s->edits_applied - 1) & 1];
+    if (!prev.valid || prev.epoch != s->ver_epoch[s->current]) {
+      set_error(s, hipErrorInvalidValue, "server: edit log out of step");
       return true;
     }
-    s->edit_slot.cap = cap;
-  } else if (s->edit_slot.pending) {
-    // the previous edit's upload must be consumed before the buffer is reused
-    (void)hipEventSynchronize(s->edit_slot.ev);
+    e = tci::enqueue_edits(d, s->ver[tgt], (const char*)prev.slot.dev, prev.plan,
+                           s->edit_stream);
+  }
+  // upload the new edit list into the other log slot; its previous content
+  // (the edit before the replayed one) is in both buffers already
+  EditUpload& u = s->uploads[s->edits_applied & 1];
+  size_t patch_bytes = r->patch.size();
+  tci::plan_edits(d, r->edits.data(), (int32_t)r->edits.size(), patch_bytes, nullptr, u.plan);
+  if (u.slot.pending) {
+    // the host buffer is rewritten only after its last upload was consumed
+    (void)hipEventSynchronize(u.slot.ev);
+    u.slot.pending = false;
+  }
+  if (u.slot.cap < u.plan.total) {
+    (void)hipStreamSynchronize(s->edit_stream);
+    if (u.slot.host) (void)hipHostFree(u.slot.host);
+    if (u.slot.dev) (void)hipFree(u.slot.dev);
+    u.slot.host = u.slot.dev = nullptr;
+    u.slot.cap = 0;
+    size_t cap = std::max<size_t>(u.plan.total, 64 << 10);
+    hipError_t ea = hipHostMalloc(&u.slot.host, cap, hipHostMallocDefault);
+    if (ea == hipSuccess) ea = hipMalloc(&u.slot.dev, cap);
+    if (ea != hipSuccess) {
+      set_error(s, ea, "server: edit staging");
+      return true;
+    }
+    u.slot.cap = cap;
   }
   tci::plan_edits(d, r->edits.data(), (int32_t)r->edits.size(), patch_bytes,
-                  (char*)s->edit_slot.host, plan);
-  hipError_t e = hipMemcpyAsync(s->ver[tgt], s->ver[s->current], ctx->map_words * 4,
-                                hipMemcpyDeviceToDevice, s->edit_stream);
+                  (char*)u.slot.host, u.plan);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(s->edit_slot.dev, s->edit_slot.host, plan.total,
-                       hipMemcpyHostToDevice, s->edit_stream);
+    e = hipMemcpyAsync(u.slot.dev, u.slot.host, u.plan.total, hipMemcpyHostToDevice,
+                       s->edit_stream);
+  if (e == hipSuccess) e = hipEventRecord(u.slot.ev, s->edit_stream);
+  if (e == hipSuccess) u.slot.pending = true;
   if (e == hipSuccess)
-    e = tci::enqueue_edits(d, s->ver[tgt], (const char*)s->edit_slot.dev, plan, s->edit_stream);
+    e = tci::enqueue_edits(d, s->ver[tgt], (const char*)u.slot.dev, u.plan, s->edit_stream);
   hipEvent_t ev = nullptr;
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventRecord(ev, s->edit_stream);
   if (e == hipSuccess) e = hipEventRecord(s->edit_ev, s->edit_stream);
-  if (e == hipSuccess) e = hipEventRecord(s->edit_slot.ev, s->edit_stream);
   if (e != hipSuccess) {
+    if (ev) (void)hipEventDestroy(ev);
     set_error(s, e, "server: edit launch");
     return true;
   }
-  s->edit_slot.pending = true;
+  u.epoch = r->epoch;
+  u.valid = true;
+  s->edits_applied++;
   s->ver_epoch[tgt] = r->epoch;
   s->current = tgt;
   s->edits_in_flight.emplace_back(id, ev);
@@ -398,7 +433,11 @@ void server_loop(tc_server* s) {
     for (Batch& b : s->slots) busy |= b.busy;
     if (idle && !busy) {
       if (s->stop.load()) break;
-      std::this_thread::sleep_for(std::chrono::microseconds(50));
+      // sleep until a submission or stop (the timeout only bounds a missed
+      // signal)
+      std::unique_lock<std::mutex> g(s->mu);
+      s->cv_work.wait_for(g, std::chrono::milliseconds(2),
+                          [s] { return !s->incoming.empty() || s->stop.load(); });
     } else {
       std::this_thread::yield();
     }
@@ -421,9 +460,11 @@ void server_free(tc_server* s) {
     if (b.slot.dev) (void)hipFree(b.slot.dev);
   }
   for (auto& f : s->edits_in_flight) (void)hipEventDestroy(f.second);
-  if (s->edit_slot.host) (void)hipHostFree(s->edit_slot.host);
-  if (s->edit_slot.dev) (void)hipFree(s->edit_slot.dev);
-  if (s->edit_slot.ev) (void)hipEventDestroy(s->edit_slot.ev);
+  for (EditUpload& u : s->uploads) {
+    if (u.slot.host) (void)hipHostFree(u.slot.host);
+    if (u.slot.dev) (void)hipFree(u.slot.dev);
+    if (u.slot.ev) (void)hipEventDestroy(u.slot.ev);
+  }
   if (s->edit_ev) (void)hipEventDestroy(s->edit_ev);
   if (s->edit_stream) (void)hipStreamDestroy(s->edit_stream);
   for (int v = 0; v < 2; ++v)
@@ -466,7 +507,12 @@ tc_status tc_server_start(tc_context* ctx, uint64_t budget_bytes, int32_t max_ba
   s->own_ver[1] = e == hipSuccess;
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->edit_stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&s->edit_ev, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->edit_slot.ev, hipEventDisableTiming);
+  for (EditUpload& u : s->uploads)
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&u.slot.ev, hipEventDisableTiming);
+  // both version buffers start as the loaded map
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->ver[1], s->ver[0], ctx->map_words * 4, hipMemcpyDeviceToDevice,
+                       s->edit_stream);
   if (e == hipSuccess) e = hipEventRecord(s->edit_ev, s->edit_stream);
   s->slots.resize(streams);
   for (Batch& b : s->slots) {
@@ -510,6 +556,7 @@ tc_status tc_server_submit_view(tc_server* s, const tc_view* view, uint64_t* id)
     s->incoming.push_back(r.id);
     s->reqs.emplace(r.id, std::move(r));
   }
+  s->cv_work.notify_one();
   return TC_OK;
 }
 
@@ -544,6 +591,7 @@ tc_status tc_server_submit_edit(tc_server* s, const tc_edit* edits, int32_t n, u
   *id = r.id;
   s->incoming.push_back(r.id);
   s->reqs.emplace(r.id, std::move(r));
+  s->cv_work.notify_one();
   return TC_OK;
 }
 
@@ -632,7 +680,11 @@ tc_status tc_server_get_stats(tc_server* s, tc_server_stats* out) {
 tc_status tc_server_stop(tc_server* s) {
   if (!s) return TC_INVALID_ARG;
   tc_context* ctx = s->ctx;
-  s->stop.store(true);
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->stop.store(true);
+  }
+  s->cv_work.notify_all();
   if (s->thread.joinable()) s->thread.join();
   tc_status st = TC_OK;
   (void)hipSetDevice(ctx->device);

@@ -96,6 +96,40 @@ def test_mixed_stream_matches_epochs(ctx, mode, batch, streams):
                               oracle.pyramid_level_fast(final[0], final[1], final[2], L))
 
 
+def test_back_to_back_edits_replay(ctx):
+    """Runs of edits with no view between them, then views, then more
+    edits: each version buffer catches up by replaying the edit it missed,
+    so every view still equals the oracle at its epoch."""
+    F, B, T = synth.make_map_from_config(1)
+    load(ctx, F, B, T)
+    rng = np.random.default_rng(77)
+    reqs = []
+    for k in range(5):
+        for _ in range(int(rng.integers(1, 5))):
+            reqs.append(("edit", synth.crater_list(rng, 256, 256, int(rng.integers(1, 3)),
+                                                   size=(8, 40), depth=(10, 80))
+                         if rng.random() < 0.6 else synth.random_set_patches(rng, 256, 256, 2,
+                                                                              max_size=24)))
+        for _ in range(int(rng.integers(1, 4))):
+            eye = synth.eye_above_floor(F, B, rng.uniform(0, 256), rng.uniform(0, 256), dz=12.0)
+            reqs.append(("view", synth.perspective_view(eye, rng.uniform(0, 360), -25, 48, 32)))
+    exp, final = _expected(F, B, T, reqs)
+    srv = ctx.tc_server_start(64 << 20, max_batch_views=4, streams=2)
+    ids = [srv.tc_server_submit_view(x) if k == "view" else srv.tc_server_submit_edit(x)
+           for k, x in reqs]
+    for rid in ids:
+        srv.tc_server_wait(rid, 60.0)
+    for i, (kind, x) in enumerate(reqs):
+        if kind == "view":
+            wg, dg = srv.tc_server_read(ids[i], 48 * 32)
+            assert_parity(wg, dg, exp[i][0], exp[i][1], "view %d" % i)
+            srv.tc_server_release(ids[i])
+    srv.tc_server_stop()
+    g = ctx.tc_read_columns(0, 0, 256, 256)
+    assert np.array_equal(g[0], final[0]) and np.array_equal(g[1], final[1])
+    assert np.array_equal(g[2], final[2])
+
+
 def test_budget_admission_and_release(ctx):
     """With a budget of three large views, a burst of 20 is admitted as the
     client releases finished results; the pool never exceeds the budget."""

@@ -33,10 +33,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def traffic_from_profile(kernel_src, launches_key="render_c2"):
+def traffic_from_profile(kernel_srcs, launches_key="render_c2"):
     """HBM bytes per launch measured by rocprofv3 (FETCH_SIZE + WRITE_SIZE,
     scaled by a plain copy's readings), if the committed profile was taken
-    on the current render source; else None."""
+    on the current render sources (sha256 over the files in order); else
+    None."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "%s_traffic.txt" % launches_key)
     if not os.path.exists(path):
@@ -47,7 +48,10 @@ def traffic_from_profile(kernel_src, launches_key="render_c2"):
             k, sep, v = line.partition(":")
             if sep and k.strip() in ("render_source_sha256", "hbm_bytes_per_launch"):
                 keys[k.strip()] = v.strip()
-        sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+        h = hashlib.sha256()
+        for f in kernel_srcs:
+            h.update(open(f, "rb").read())
+        sha = h.hexdigest()
         if keys.get("render_source_sha256") != sha:
             return None
         return float(keys["hbm_bytes_per_launch"])
@@ -433,8 +437,9 @@ def main():
                    "frame_ms_median": med, "frame_ms_p99": float(np.percentile(ms, 99))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-                     "traffic": traffic_from_profile(os.path.join(
-                         ROOT, "paper_2608_17390_amd", "csrc", "tc_render.hip")),
+                     "traffic": traffic_from_profile(
+                         [os.path.join(ROOT, "paper_2608_17390_amd", "csrc", f)
+                          for f in ("tc_walk.h", "tc_render.hip")]),
                      "kernel": KERNEL_NAMES[args.mode],
                      "alg_bytes_per_launch": alg_bytes,
                      "kernel_ms_avg": kavg,

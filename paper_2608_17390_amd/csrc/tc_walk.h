@@ -1,0 +1,520 @@
+// The exact cell walk, shared by the render kernels and the shading pass.
+//
+// Each pixel's ray walks the exact cell sequence of a 2D digital
+// differential analyser over the map (the exact limit of the paper's
+// per-pixel march, Section 3.1, with the cell-boundary convention fixed:
+// start in floor(O / S), closed per-cell parameter intervals, x before y on
+// simultaneous crossings).  A cell is hit when the ray's height range over
+// its interval meets the column's solid set (z <= F, or B <= z <= T when
+// B > 0: the SOLID predicate of Section 3.1).
+//
+// Acceleration: the walk runs at pyramid level L (a node = 2^L x 2^L
+// cells).  The same interval test against a node's (fmax, smin, smax)
+// decides whether the ray may meet solid inside the node before leaving
+// it; if not, the ray jumps to the node exit in one step -- the skip of the
+// paper's hierarchical voxel march (Section 3.2), on a 2D per-layer min/max
+// pyramid instead of a 3D occupancy grid.  The jump reproduces the flat
+// walk exactly: it advances the x and y crossing counters by the number of
+// crossings the flat walk would take, so the state after a skip equals the
+// flat walk's state on entering the same cell.
+//
+// Arithmetic.  With |Dx|, |Dy| = ax, ay and nx, ny the distances (in S
+// units) to the next x and y boundaries:
+//   crossing keys  Kx = nx * ay,  Ky = ny * ax   (time * ax * ay); the next
+//                  crossing is x iff Kx <= Ky;
+//   heights        Zx = Oz * ax + nx * Dz  is z (S units) at the next x
+//                  crossing scaled by ax, likewise Zy; z <= h*S at that
+//                  crossing iff Zx <= h * S * ax.
+// All quantities fit in int64 for |O| < 2^31 and |D| < 2^23; products of a
+// height (8 bits) or a crossing count (< 2^24) with a direction component
+// (< 2^23) are 24-bit multiplies.  Depth is computed once per ray in double
+// and rounded to float.
+#pragma once
+
+#include "tc_internal.h"
+
+namespace {
+
+constexpr uint32_t kMiss = 0xFFFFFFFFu;
+constexpr uint32_t kStuck = 0xFFFFFFFEu;   // iteration cap reached (never
+                                           // expected; guards against hangs)
+// Key of a crossing that never happens (axis with zero direction).  Real
+// keys stay below 2^58 and a node adds at most 2^54, so no sum overflows.
+constexpr int64_t kNever = (int64_t)1 << 62;
+constexpr int32_t kIterCap = 1 << 22;
+
+enum : int32_t { kTop = 1, kUnder = 2, kWmx = 3, kWpx = 4, kWmy = 5,
+                 kWpy = 6, kInside = 7 };
+enum : int32_t { kWalking = 0, kHitCell = 1, kMissed = 2, kCapped = 3, kSegEnd = 4 };
+constexpr int32_t kAnchored = 8;
+
+struct lvl_t {
+  uint32_t off;
+  int32_t w, h, tiles_x;
+};
+
+// a * b for a < 2^24, b < 2^24 as a 48-bit product: two full-rate 24-bit
+// multiplies instead of a quarter-rate 64-bit one.
+__device__ __forceinline__ uint64_t mul48(uint32_t a, uint32_t b) {
+  uint32_t lo, hi;
+  asm("v_mul_u32_u24 %0, %1, %2" : "=v"(lo) : "v"(a), "v"(b));
+  asm("v_mul_hi_u32_u24 %0, %1, %2" : "=v"(hi) : "v"(a), "v"(b));
+  return ((uint64_t)hi << 32) | lo;
+}
+// a * b for 0 <= a < 2^23 and |b| < 2^23, signed 48-bit product.
+__device__ __forceinline__ int64_t smul48(int32_t a, int32_t b) {
+  int32_t lo, hi;
+  asm("v_mul_i32_i24 %0, %1, %2" : "=v"(lo) : "v"(a), "v"(b));
+  asm("v_mul_hi_i32_i24 %0, %1, %2" : "=v"(hi) : "v"(a), "v"(b));
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+struct ray_t {
+  int64_t Ox, Oy, Oz;
+  int32_t Dx, Dy, Dz;
+  uint32_t ax, ay;
+  int32_t cx0, cy0;   // anchor cell: the start cell, or a segment's first cell
+  uint32_t rx, ry;    // residual flags of the x / y crossing heights
+};
+
+// Exact state of the cell walk, divided by S.  Every crossing moves its
+// key and height by a multiple of S, so the remainders modulo S are fixed
+// per axis: they fold into a tie offset of the x keys and a 0/1 flag of
+// the heights, and no comparison needs the low 16 bits.
+//   keys    the i-th x crossing has key KX0 + i*ay with
+//           KX0 = floor(nx*ay / S) + c, c = 1 iff (nx*ay mod S) > (ny*ax mod S),
+//           and the j-th y crossing KY0 + j*ax, KY0 = floor(ny*ax / S); an x
+//           crossing comes first iff its key is <= the y key (x first on
+//           ties), exactly as the times nx/ax and ny/ay compare.
+//   heights with Z = Oz*ax + nx*Dz (z * S * ax at the first x crossing),
+//           ZX0 = floor(Z / S) and rx = (Z mod S != 0), the i-th x crossing
+//           has height ZX0 + i*Dz and there
+//           z <= h  iff  height + rx <= h*ax,   z >= h  iff  height >= h*ax.
+//           Likewise for y.
+// The walk runs on the node grid of its current pyramid level L and keeps,
+// for the current node, the keys and heights of the crossings through its
+// far x and y faces: a step to the next node adds a << L to one of each,
+// a climb or a descent adds or removes half a node, and the child holding
+// the ray is the one on the near side of each middle crossing that happens
+// after the entry crossing.  The walk therefore enters exactly the cells
+// the flat walk enters, at the same keys.
+struct walk_t {
+  int32_t ni, nj;     // node indices at level L
+  int32_t L;          // current pyramid level
+  int64_t KXe, KYe;   // keys of the crossings through the far x / y faces
+  int64_t ZXe, ZYe;   // heights at those crossings
+  int64_t Kin;        // key of the entry crossing (unused while kInside)
+  int64_t Zin;        // height at entry of the current node
+  uint32_t Din;       // its scale: 1 at the origin, else ax or ay
+  uint32_t rin;       // its residual flag
+  int32_t entry;      // face crossed on entry (kInside before any crossing),
+                      // plus kAnchored until the first step: the walk then
+                      // sits in the anchor cell (r.cx0, r.cy0) and picks
+                      // children by it
+  int32_t iters;
+  int32_t reads;      // nodes and cells read from memory
+};
+
+// z <= h and z >= h for a height with floor part zq, flag r and scale d
+__device__ __forceinline__ bool z_le(int64_t zq, uint32_t r, uint32_t h, uint32_t d) {
+  return zq + (int64_t)r <= (int64_t)__umul24(h, d);
+}
+__device__ __forceinline__ bool z_ge(int64_t zq, uint32_t h, uint32_t d) {
+  return zq >= (int64_t)__umul24(h, d);
+}
+// a << L for an unsigned or signed 32-bit a as a 64-bit value
+__device__ __forceinline__ int64_t ushl(uint32_t a, int32_t L) {
+  return (int64_t)((uint64_t)a << L);
+}
+__device__ __forceinline__ int64_t sshl(int32_t a, int32_t L) {
+  return (int64_t)((uint64_t)(int64_t)a << L);
+}
+
+__device__ __forceinline__ void pixel_ray(const tci_view& v, int32_t px,
+                                          int32_t py, ray_t& r) {
+  int64_t a = 2 * (int64_t)px + 1, b = 2 * (int64_t)py + 1;
+  r.Ox = (int64_t)v.o0[0] + a * v.opx[0] + b * v.opy[0];
+  r.Oy = (int64_t)v.o0[1] + a * v.opx[1] + b * v.opy[1];
+  r.Oz = (int64_t)v.o0[2] + a * v.opx[2] + b * v.opy[2];
+  r.Dx = (int32_t)((int64_t)v.d0[0] + a * v.dpx[0] + b * v.dpy[0]);
+  r.Dy = (int32_t)((int64_t)v.d0[1] + a * v.dpx[1] + b * v.dpy[1]);
+  r.Dz = (int32_t)((int64_t)v.d0[2] + a * v.dpx[2] + b * v.dpy[2]);
+  r.ax = (uint32_t)(r.Dx < 0 ? -r.Dx : r.Dx);
+  r.ay = (uint32_t)(r.Dy < 0 ? -r.Dy : r.Dy);
+}
+
+__device__ __forceinline__ void walk_init(ray_t& r, int32_t L0, walk_t& s) {
+  const int32_t cx = (int32_t)(r.Ox >> 16), cy = (int32_t)(r.Oy >> 16);
+  r.cx0 = cx;
+  r.cy0 = cy;
+  const int64_t nx = r.Dx > 0 ? ((int64_t)(cx + 1) << 16) - r.Ox
+                              : r.Ox - ((int64_t)cx << 16);
+  const int64_t ny = r.Dy > 0 ? ((int64_t)(cy + 1) << 16) - r.Oy
+                              : r.Oy - ((int64_t)cy << 16);
+  const int64_t kx = nx * (int64_t)r.ay, ky = ny * (int64_t)r.ax;
+  const int64_t tie = (kx & 0xFFFF) <= (ky & 0xFFFF) ? 0 : 1;
+  const int64_t zx = r.Oz * (int64_t)r.ax + nx * (int64_t)r.Dz;
+  const int64_t zy = r.Oz * (int64_t)r.ay + ny * (int64_t)r.Dz;
+  r.rx = (zx & 0xFFFF) != 0;
+  r.ry = (zy & 0xFFFF) != 0;
+  s.L = L0;
+  s.ni = cx >> L0;
+  s.nj = cy >> L0;
+  // crossings before the far faces of the start node
+  const int32_t kxm1 = r.Dx > 0 ? ((s.ni + 1) << L0) - 1 - cx : cx - (s.ni << L0);
+  const int32_t kym1 = r.Dy > 0 ? ((s.nj + 1) << L0) - 1 - cy : cy - (s.nj << L0);
+  s.KXe = r.Dx == 0 ? kNever
+                    : (kx >> 16) + (r.Dy != 0 ? tie : 0) + (int64_t)kxm1 * r.ay;
+  s.KYe = r.Dy == 0 ? kNever : (ky >> 16) + (int64_t)kym1 * r.ax;
+  s.ZXe = (zx >> 16) + (int64_t)kxm1 * r.Dz;
+  s.ZYe = (zy >> 16) + (int64_t)kym1 * r.Dz;
+  s.Kin = 0;
+  s.Zin = r.Oz >> 16;
+  s.rin = (r.Oz & 0xFFFF) != 0;
+  s.Din = 1;
+  s.entry = kInside | kAnchored;
+  s.iters = 0;
+  s.reads = 0;
+}
+
+__device__ __forceinline__ void set_hit(const ray_t& r, int32_t W, int32_t x,
+                                        int32_t y, int32_t face,
+                                        int32_t layer, int64_t tn,
+                                        int64_t td, uint32_t& word,
+                                        float& depth) {
+  word = (uint32_t)(y * W + x) | ((uint32_t)face << 27) |
+         ((uint32_t)layer << 30);
+  double len = sqrt((double)r.Dx * r.Dx + (double)r.Dy * r.Dy +
+                    (double)r.Dz * r.Dz);
+  depth = tn == 0 ? 0.0f
+                  : (float)(((double)tn / (double)td) * len / 65536.0);
+}
+
+// First hit inside cell (x, y) (packed column v), entered with height zin
+// (scale din, flag rin) through face `entry`, given that the ray's height
+// range over the cell meets solid.
+__device__ __forceinline__ void resolve_hit(const ray_t& r, int32_t x, int32_t y,
+                                            int32_t entry, int64_t zin,
+                                            uint32_t din, uint32_t rin,
+                                            int32_t W, uint32_t v,
+                                            uint32_t& word, float& depth) {
+  uint32_t F = v & 0xFF, B = (v >> 8) & 0xFF, T = (v >> 16) & 0xFF;
+  bool in_floor = z_le(zin, rin, F, din);
+  bool in_slab = B != 0 && z_ge(zin, B, din) && z_le(zin, rin, T, din);
+  int32_t face, layer;
+  int64_t tn, td;
+  if (in_floor || in_slab) {
+    face = entry;
+    layer = in_floor ? 0 : 1;
+    switch (face) {
+      case kWmx: tn = ((int64_t)x << 16) - r.Ox; td = r.ax; break;
+      case kWpx: tn = r.Ox - ((int64_t)(x + 1) << 16); td = r.ax; break;
+      case kWmy: tn = ((int64_t)y << 16) - r.Oy; td = r.ay; break;
+      case kWpy: tn = r.Oy - ((int64_t)(y + 1) << 16); td = r.ay; break;
+      default: tn = 0; td = 1; break;
+    }
+  } else if (r.Dz < 0) {
+    bool above = B != 0 && !z_le(zin, rin, T, din);
+    uint32_t tgt = above ? T : F;
+    face = kTop;
+    layer = above ? 1 : 0;
+    tn = r.Oz - ((int64_t)tgt << 16);
+    td = -(int64_t)r.Dz;
+  } else {
+    face = kUnder;
+    layer = 1;
+    tn = ((int64_t)B << 16) - r.Oz;
+    td = r.Dz;
+  }
+  set_hit(r, W, x, y, face, layer, tn, td, word, depth);
+}
+
+// Hit record of a finished walk.
+__device__ __forceinline__ void finish(const ray_t& r, const walk_t& s,
+                                       int32_t W, int32_t state, uint32_t v,
+                                       uint32_t& word, float& depth) {
+  if (state == kHitCell) {
+    resolve_hit(r, s.ni, s.nj, s.entry & 7, s.Zin, s.Din, s.rin, W, v, word, depth);
+  } else if (state == kCapped) {
+    word = kStuck;
+    depth = __builtin_nanf("");
+  } else {
+    word = kMiss;
+    depth = __builtin_inff();
+  }
+}
+
+// Vertical ray (Dx = Dy = 0): only the start column can be met.
+__device__ __forceinline__ void trace_vertical(const tci_map& m,
+                                               const lvl_t* lv,
+                                               const ray_t& r, uint32_t& word,
+                                               float& depth) {
+  word = kMiss;
+  depth = __builtin_inff();
+  if (r.Dz == 0) return;
+  int32_t cx = (int32_t)(r.Ox >> 16), cy = (int32_t)(r.Oy >> 16);
+  if ((uint32_t)cx >= (uint32_t)m.W || (uint32_t)cy >= (uint32_t)m.H) return;
+  const lvl_t l = lv[0];
+  uint32_t v = m.base[l.off + ((uint32_t)((cy >> 3) * l.tiles_x + (cx >> 3)) << 6) +
+                      ((cy & 7) << 3) + (cx & 7)];
+  uint32_t B = (v >> 8) & 0xFF, F = v & 0xFF, T = (v >> 16) & 0xFF;
+  bool in_floor = r.Oz <= ((int64_t)F << 16);
+  bool in_slab = B != 0 && r.Oz >= ((int64_t)B << 16) && r.Oz <= ((int64_t)T << 16);
+  if (in_floor || in_slab || r.Dz < 0 || (B != 0 && r.Oz < ((int64_t)B << 16)))
+    resolve_hit(r, cx, cy, kInside, r.Oz >> 16, 1, (r.Oz & 0xFFFF) != 0, m.W, v,
+                word, depth);
+}
+
+// Advance the walk by up to `budget` iterations.  Returns kWalking if the
+// budget ran out, else the final state; on kHitCell, `col` holds the
+// column of the current cell (s.ni, s.nj at level 0).
+// Number of terms K + j*a, j >= 0, strictly below E, for counts below 2^24
+// and E - K < 2^47: a float estimate of the quotient, then one exact
+// correction.
+__device__ __forceinline__ int32_t count_below(int64_t E, int64_t K, uint32_t a) {
+  if (E <= K) return 0;
+  const int64_t n = E - K - 1;             // count = floor(n / a) + 1
+  const float nf = (float)(uint32_t)(n >> 32) * 4294967296.0f + (float)(uint32_t)n;
+  int32_t q = (int32_t)(nf * __builtin_amdgcn_rcpf((float)a));
+  q = q < 0 ? 0 : q;
+  const int64_t p = (int64_t)mul48((uint32_t)q, a);
+  q += (p > n) ? -1 : ((n - p >= (int64_t)a) ? 1 : 0);
+  return q + 1;
+}
+
+// Walk state (at level 0) on entering cell line `start` of axis `axis`
+// (a column if 0, a row if 1) through the crossing the flat walk takes into
+// it: the crossing's key and height come from its index, the cell on the
+// other axis from the number of that axis's crossings that come first (x
+// first on ties).  If `start` is the start cell's line, the walk starts at
+// the origin.
+__device__ __forceinline__ void seg_init(ray_t& r, walk_t& s, int32_t axis,
+                                         int32_t start) {
+  walk_init(r, 0, s);   // level 0: far-face keys are the first crossings
+  if (axis == 0) {
+    const int32_t i = r.Dx > 0 ? start - r.cx0 - 1 : r.cx0 - start - 1;
+    if (i < 0) return;
+    const int64_t K = s.KXe + (int64_t)mul48((uint32_t)i, r.ay);
+    const int32_t c = count_below(K, s.KYe, r.ax);
+    s.Kin = K;
+    s.Zin = s.ZXe + smul48(i, r.Dz);
+    s.Din = r.ax;
+    s.rin = r.rx;
+    s.KXe = K + r.ay;
+    s.ZXe = s.Zin + r.Dz;
+    s.KYe += (int64_t)mul48((uint32_t)c, r.ax);
+    s.ZYe += smul48(c, r.Dz);
+    s.ni = start;
+    s.nj = r.cy0 + (r.Dy > 0 ? c : -c);
+    s.entry = (r.Dx > 0 ? kWmx : kWpx) | kAnchored;
+  } else {
+    const int32_t j = r.Dy > 0 ? start - r.cy0 - 1 : r.cy0 - start - 1;
+    if (j < 0) return;
+    const int64_t K = s.KYe + (int64_t)mul48((uint32_t)j, r.ax);
+    const int32_t c = count_below(K + 1, s.KXe, r.ay);
+    s.Kin = K;
+    s.Zin = s.ZYe + smul48(j, r.Dz);
+    s.Din = r.ay;
+    s.rin = r.ry;
+    s.KYe = K + r.ax;
+    s.ZYe = s.Zin + r.Dz;
+    s.KXe += (int64_t)mul48((uint32_t)c, r.ay);
+    s.ZXe += smul48(c, r.Dz);
+    s.nj = start;
+    s.ni = r.cx0 + (r.Dx > 0 ? c : -c);
+    s.entry = (r.Dy > 0 ? kWmy : kWpy) | kAnchored;
+  }
+  r.cx0 = s.ni;
+  r.cy0 = s.nj;
+}
+
+// Move a level-0 walk state up to the level-L node holding its cell: the
+// far faces of that node lie the remaining cells of the node further on.
+__device__ __forceinline__ void lift(const ray_t& r, walk_t& s, int32_t L) {
+  if (L <= 0) return;
+  const int32_t ni = s.ni >> L, nj = s.nj >> L;
+  const int32_t kx = r.Dx > 0 ? ((ni + 1) << L) - 1 - s.ni : s.ni - (ni << L);
+  const int32_t ky = r.Dy > 0 ? ((nj + 1) << L) - 1 - s.nj : s.nj - (nj << L);
+  s.KXe += (int64_t)mul48((uint32_t)kx, r.ay);
+  s.KYe += (int64_t)mul48((uint32_t)ky, r.ax);
+  s.ZXe += smul48(kx, r.Dz);
+  s.ZYe += smul48(ky, r.Dz);
+  s.ni = ni;
+  s.nj = nj;
+  s.L = L;
+}
+
+// With boost > 0 (wave-uniform loop only), a wave raises its instruction
+// issue priority after boost, 2*boost and 4*boost iterations: the few long
+// walks of a launch, which otherwise trail it, then win issue slots over
+// the many short ones sharing their SIMD.
+// With kSeg the walk also stops (kSegEnd) once its node lies wholly
+// outside the cell lines [seg_lo, seg_hi] of axis seg_axis (0 x, 1 y).
+template <bool kSeg = false>
+__device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
+                                              const ray_t& r, walk_t& s,
+                                              int32_t max_level, int32_t budget,
+                                              uint32_t& col, int32_t boost = 0,
+                                              int32_t seg_axis = 0,
+                                              int32_t seg_lo = 0, int32_t seg_hi = 0) {
+  const bool desc = r.Dz < 0;
+  const int32_t sx = r.Dx > 0 ? 1 : -1, sy = r.Dy > 0 ? 1 : -1;
+  const int32_t nearx = r.Dx > 0 ? 0 : 1, neary = r.Dy > 0 ? 0 : 1;
+  for (int32_t it = 0; it < budget; ++it) {
+    if (boost > 0) {
+      if (it == boost) __builtin_amdgcn_s_setprio(1);
+      else if (it == 2 * boost) __builtin_amdgcn_s_setprio(2);
+      else if (it == 4 * boost) __builtin_amdgcn_s_setprio(3);
+    }
+    if (++s.iters > kIterCap) return kCapped;
+    const int32_t L = s.L;
+    if (kSeg) {
+      const int32_t n = seg_axis == 0 ? s.ni : s.nj;
+      if ((n << L) > seg_hi || ((n + 1) << L) - 1 < seg_lo) return kSegEnd;
+    }
+    const lvl_t l = lv[L];
+    const bool inmap = (uint32_t)s.ni < (uint32_t)l.w && (uint32_t)s.nj < (uint32_t)l.h;
+    uint32_t v = 0;
+    s.reads += inmap ? 1 : 0;
+    if (inmap)
+      v = m.base[l.off + ((__umul24((uint32_t)s.nj >> 3, (uint32_t)l.tiles_x) +
+                           ((uint32_t)s.ni >> 3)) << 6) +
+                 ((s.nj & 7) << 3) + (s.ni & 7)];
+    const bool ex = s.KXe <= s.KYe;           // leave through an x face
+    const int64_t Ze = ex ? s.ZXe : s.ZYe;
+    const uint32_t De = ex ? r.ax : r.ay;
+    const uint32_t re = ex ? r.rx : r.ry;
+    bool occ = false;
+    if (inmap) {
+      const int64_t lo = (desc ? Ze : s.Zin) + (int64_t)(desc ? re : s.rin);
+      const uint32_t Dlo = desc ? De : s.Din;
+      const int64_t hi = desc ? s.Zin : Ze;
+      const uint32_t Dhi = desc ? s.Din : De;
+      const uint32_t a = v & 0xFF, b = (v >> 8) & 0xFF, c = (v >> 16) & 0xFF;
+      occ = (lo <= (int64_t)__umul24(a, Dlo)) ||
+            ((lo <= (int64_t)__umul24(c, Dlo)) && (hi >= (int64_t)__umul24(b, Dhi)));
+    }
+    if (occ) {
+      if (L == 0) {
+        col = v;
+        return kHitCell;
+      }
+      // descend into the child holding the ray after the entry crossing
+      const int32_t Lc = L - 1;
+      const int64_t midx = s.KXe - ushl(r.ay, Lc), midy = s.KYe - ushl(r.ax, Lc);
+      int32_t bx, by;
+      const bool anchored = (s.entry & kAnchored) != 0;
+      if (r.Dx == 0 || anchored) bx = (r.cx0 >> Lc) & 1;
+      else if (s.entry == kWmx || s.entry == kWpx) bx = nearx;
+      else bx = (midx <= s.Kin) ? 1 - nearx : nearx;
+      if (r.Dy == 0 || anchored) by = (r.cy0 >> Lc) & 1;
+      else if (s.entry == kWmy || s.entry == kWpy) by = neary;
+      else by = (midy < s.Kin) ? 1 - neary : neary;
+      if (bx == nearx) {
+        s.KXe = midx;
+        s.ZXe -= sshl(r.Dz, Lc);
+      }
+      if (by == neary) {
+        s.KYe = midy;
+        s.ZYe -= sshl(r.Dz, Lc);
+      }
+      s.ni = 2 * s.ni + bx;
+      s.nj = 2 * s.nj + by;
+      s.L = Lc;
+      continue;
+    }
+    // step to the next node of this level through the exit face
+    const int32_t pi = s.ni, pj = s.nj;
+    if (ex) {
+      s.Kin = s.KXe;
+      s.KXe += ushl(r.ay, L);
+      s.ZXe += sshl(r.Dz, L);
+      s.ni += sx;
+      s.entry = r.Dx > 0 ? kWmx : kWpx;
+    } else {
+      s.Kin = s.KYe;
+      s.KYe += ushl(r.ax, L);
+      s.ZYe += sshl(r.Dz, L);
+      s.nj += sy;
+      s.entry = r.Dy > 0 ? kWmy : kWpy;
+    }
+    s.Zin = Ze;
+    s.Din = De;
+    s.rin = re;
+    // the ray cannot come back into the map, or is above all solid
+    const bool away = (s.ni < 0 && r.Dx <= 0) || (s.ni >= l.w && r.Dx >= 0) ||
+                      (s.nj < 0 && r.Dy <= 0) || (s.nj >= l.h && r.Dy >= 0);
+    const bool above = r.Dz >= 0 && !z_le(s.Zin, s.rin, 255, s.Din);
+    if (away || above) return kMissed;
+    // go up one level when the step entered a new parent node; the new node
+    // is then the near half of its parent along the exit axis
+    if (L < max_level && (((pi ^ s.ni) | (pj ^ s.nj)) >> 1) != 0) {
+      if (ex || (s.ni & 1) == nearx) {
+        s.KXe += ushl(r.ay, L);
+        s.ZXe += sshl(r.Dz, L);
+      }
+      if (!ex || (s.nj & 1) == neary) {
+        s.KYe += ushl(r.ax, L);
+        s.ZYe += sshl(r.Dz, L);
+      }
+      s.ni >>= 1;
+      s.nj >>= 1;
+      s.L = L + 1;
+    }
+  }
+  return kWalking;
+}
+
+__device__ __forceinline__ void load_levels(const tci_map& m, lvl_t* lv) {
+  if (threadIdx.x < TCI_MAX_LEVELS) {
+    const tci_level& l = m.lv[threadIdx.x];
+    lv[threadIdx.x] = lvl_t{l.off, l.w, l.h, l.tiles_x};
+  }
+  __syncthreads();
+}
+
+// View containing packet p: largest v with pkt_prefix[v] <= p.
+__device__ __forceinline__ int32_t find_view(const int64_t* pkt_prefix,
+                                             int32_t nviews, int64_t p) {
+  int32_t lo = 0, hi = nviews - 1;
+  while (lo < hi) {
+    int32_t mid = (lo + hi + 1) >> 1;
+    if (pkt_prefix[mid] <= p) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Pixel of ray `k` (0..63, row-major in an 8x8 block) of packet `t` of a
+// view; packets run row-major (order 0) or column-major (order 1).
+__device__ __forceinline__ void packet_pixel(const tci_view& v, int64_t t,
+                                             int32_t k, int32_t order,
+                                             const int32_t* rows,
+                                             int32_t& px, int32_t& py) {
+  int32_t tx, ty;
+  if (order == 2) {
+    tx = (int32_t)(t % v.tiles_x);
+    ty = rows[v.rows_off + t / v.tiles_x];
+  } else if (order == 1) {
+    const int32_t tiles_y = (v.h + 7) >> 3;
+    tx = (int32_t)(t / tiles_y);
+    ty = (int32_t)(t % tiles_y);
+  } else {
+    tx = (int32_t)(t % v.tiles_x);
+    ty = (int32_t)(t / v.tiles_x);
+  }
+  px = tx * 8 + (k & 7);
+  py = ty * 8 + (k >> 3);
+}
+
+__device__ __forceinline__ void store_hit(void* out, int64_t idx,
+                                          uint32_t word, float depth) {
+  uint2 h;
+  h.x = word;
+  h.y = __float_as_uint(depth);
+  reinterpret_cast<uint2*>(out)[idx] = h;
+}
+
+__device__ __forceinline__ int32_t clamp_level(int32_t v, int32_t top) {
+  return v < 0 ? 0 : (v > top ? top : v);
+}
+
+}  // namespace

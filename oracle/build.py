@@ -5,7 +5,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "oracle.c")
-SOURCES = [SRC, os.path.join(HERE, "march.c")]
+SOURCES = [SRC, os.path.join(HERE, "march.c"), os.path.join(HERE, "shade.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

@@ -50,6 +50,10 @@ def lib():
         L.om_march_pixels.restype = None
         L.om_march_pixels.argtypes = [i32, i32, p, p, p, p, p, p, p, i64, f32,
                                       ctypes.c_int, ctypes.c_int, p, p]
+        L.os_shade_views.restype = i64
+        L.os_shade_views.argtypes = [i32, i32, p, p, p, p, ctypes.c_int, p, p, p]
+        L.os_shade_pixels.restype = i64
+        L.os_shade_pixels.argtypes = [i32, i32, p, p, p, p, p, p, p, i64, p, p, p]
         _lib = L
     return _lib
 
@@ -200,6 +204,63 @@ def march_pixels(F, B, T, views, vi, px, py, far=600.0, steps=128, bisect=4):
                           _ptr(px), _ptr(py), n, *_march_args(far, steps, bisect),
                           _ptr(word), _ptr(depth))
     return word, depth
+
+
+SHADE_DT = np.dtype([("light", "<i4", 3), ("ambient", "<f4"), ("cave_ambient", "<f4"),
+                     ("fog_far", "<f4"), ("sky_rgba", "<u4"), ("fog_rgba", "<u4")])
+
+
+def _shade_params(light, ambient, cave_ambient, fog_far, sky_rgba, fog_rgba):
+    p = np.zeros(1, SHADE_DT)
+    p["light"] = np.asarray(light, np.int64)
+    p["ambient"] = ambient
+    p["cave_ambient"] = cave_ambient
+    p["fog_far"] = fog_far
+    p["sky_rgba"] = sky_rgba
+    p["fog_rgba"] = fog_rgba
+    return p
+
+
+def shade(F, B, T, views, light, palette, ambient=0.3, cave_ambient=0.12,
+          fog_far=600.0, sky_rgba=0xFFEBCE87, fog_rgba=0xFFD2C8B4):
+    """Shaded RGBA (uint32 R | G<<8 | B<<16 | A<<24) of every pixel of every
+    view: exact hit, shadow ray along `light` (integer direction toward the
+    light), palette (512 uint32: floor by height, then slab top by
+    height), gradient normal, ambient / cave ambient, linear fog."""
+    F, B, T = _map(F, B, T)
+    v = _views(views)
+    H, W = F.shape
+    pal = np.ascontiguousarray(palette, np.uint32)
+    assert pal.size == 512
+    prm = _shade_params(light, ambient, cave_ambient, fog_far, sky_rgba, fog_rgba)
+    n = int((v["width"].astype(np.int64) * v["height"]).sum())
+    out = np.empty(n, np.uint32)
+    err = lib().os_shade_views(W, H, _ptr(F), _ptr(B), _ptr(T), _ptr(v), len(v),
+                               _ptr(prm), _ptr(pal), _ptr(out))
+    if err:
+        raise RuntimeError("shading oracle: %d face times disagree with the cast" % err)
+    return out
+
+
+def shade_pixels(F, B, T, views, vi, px, py, light, palette, ambient=0.3,
+                 cave_ambient=0.12, fog_far=600.0, sky_rgba=0xFFEBCE87,
+                 fog_rgba=0xFFD2C8B4):
+    """shade() of selected pixels (view index, column, row)."""
+    F, B, T = _map(F, B, T)
+    H, W = F.shape
+    v = _views(views)
+    vi = np.ascontiguousarray(vi, np.int32)
+    px = np.ascontiguousarray(px, np.int32)
+    py = np.ascontiguousarray(py, np.int32)
+    pal = np.ascontiguousarray(palette, np.uint32)
+    prm = _shade_params(light, ambient, cave_ambient, fog_far, sky_rgba, fog_rgba)
+    out = np.empty(vi.size, np.uint32)
+    err = lib().os_shade_pixels(W, H, _ptr(F), _ptr(B), _ptr(T), _ptr(v), _ptr(vi),
+                                _ptr(px), _ptr(py), vi.size, _ptr(prm), _ptr(pal),
+                                _ptr(out))
+    if err:
+        raise RuntimeError("shading oracle: %d face times disagree with the cast" % err)
+    return out
 
 
 def decode(word):

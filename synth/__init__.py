@@ -18,6 +18,7 @@ from .views import (S, MAX_DIR, VIEW_DTYPE, perspective_view, ortho_view,
                     batched_views, request_view, eye_above_floor, pitch_views)
 from .edits import crater_list, random_set_patches, EDIT_CRATER, EDIT_SET
 from .arrivals import poisson_arrivals
+from .palette import default_palette, rgba
 
 __all__ = [
     "CONFIGS", "SEEDS", "config", "make_map", "make_map_from_config",
@@ -25,5 +26,5 @@ __all__ = [
     "ortho_view", "shadow_view", "views_array", "config_views", "view_rays",
     "batched_views", "request_view", "eye_above_floor", "pitch_views",
     "crater_list", "random_set_patches", "EDIT_CRATER", "EDIT_SET",
-    "poisson_arrivals",
+    "poisson_arrivals", "default_palette", "rgba",
 ]

@@ -199,7 +199,9 @@ def config_views(k, F, B):
     from .configs import config as _config
     c = _config(k)
     if k == 1:
-        return [perspective_view(eye_above_floor(F, B, 128.5, 128.5), 0, 0,
+        # eye-level across the map from its west side (an eye at the centre
+        # sits in a pit and sees only its walls)
+        return [perspective_view(eye_above_floor(F, B, 32.5, 128.5), 0, 0,
                                  320, 240)]
     if k == 2:
         return [perspective_view(eye_above_floor(F, B, 1024.5, 32.5), 0, 0,

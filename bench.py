@@ -157,10 +157,11 @@ def march_protocol(torch, tc, synth, steps, warmup):
     """The sampled march of Section 3.1 at the paper's setting (128 samples,
     4 halvings, far 600) on the views of its measurement protocol (Section
     4.3: twelve 1280x800 views, three per pitch 0, -30, -60, -90 degrees)
-    over the 2048x16384 map.  Per view: march and exact render times, and
-    the quality metrics of Section 4.2 of the march against the exact cast
-    (a hit beyond the far limit counts as background), averaged per pitch
-    as the paper reports them."""
+    over the 2048x16384 map.  Per view: march and exact render times, the
+    time of a complete shaded frame (exact render + shading pass with a
+    shadow ray per lit pixel), and the quality metrics of Section 4.2 of the
+    march against the exact cast (a hit beyond the far limit counts as
+    background), averaged per pitch as the paper reports them."""
     from paper_2608_17390_amd import metrics
     F, B, T = synth.make_map_from_config(3)
     views, pitches = synth.pitch_views(F, B, PROTOCOL_SEED)
@@ -181,6 +182,29 @@ def march_protocol(torch, tc, synth, steps, warmup):
             kv.append(kernel_times(torch, ctx, tc, [v], out, steps).sum(axis=1).mean())
         times[m] = per_view
         kern[m] = kv
+    # a complete frame: exact render then the shading pass (shadow ray per
+    # lit pixel, palette, gradient normal, fog), as the paper's frames shade
+    # every method the same way
+    pal = synth.default_palette()
+    light = (1 << 16, 2 << 16, 2 << 16)
+    rgba = torch.empty(n, dtype=torch.int32, device="cuda")
+    ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, MODES["hier"])
+    shaded = []
+    for v, out in zip(views, outs["hier"]):
+        for _ in range(warmup):
+            ctx.tc_render_views([v], out.data_ptr())
+            ctx.tc_shade_views([v], out.data_ptr(), light, pal, rgba.data_ptr())
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        for a0, b0 in ev:
+            a0.record()
+            ctx.tc_render_views([v], out.data_ptr())
+            ctx.tc_shade_views([v], out.data_ptr(), light, pal, rgba.data_ptr())
+            b0.record()
+        torch.cuda.synchronize()
+        shaded.append(float(np.median([a0.elapsed_time(b0) for a0, b0 in ev])))
+    times["shaded"] = shaded
     # algorithmic bytes of the march: 8 B per hit record + 4 B per column
     # sample read over the map (the library's own count)
     ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, MODES["march"])
@@ -202,6 +226,7 @@ def march_protocol(torch, tc, synth, steps, warmup):
         per_pitch[str(p)] = {
             "march_ms": float(np.mean([times["march"][k] for k in ks])),
             "exact_ms": float(np.mean([times["hier"][k] for k in ks])),
+            "exact_shaded_frame_ms": float(np.mean([times["shaded"][k] for k in ks])),
             "see_through_pct": 100 * float(np.mean([q[k]["see_through"] for k in ks])),
             "covers_sky_pct": 100 * float(np.mean([q[k]["covers_sky"] for k in ks])),
             "coherence_pct": 100 * float(np.mean([q[k]["coherence"] for k in ks])),
@@ -215,6 +240,7 @@ def march_protocol(torch, tc, synth, steps, warmup):
                         "0/-30/-60/-90), march 128 samples + 4 halvings, far 600",
             "march_ms_per_view": float(np.mean(times["march"])),
             "exact_ms_per_view": float(np.mean(times["hier"])),
+            "exact_shaded_frame_ms": float(np.mean(times["shaded"])),
             "march_grays_per_s": n / (np.mean(times["march"]) * 1e-3) / 1e9,
             "exact_grays_per_s": n / (np.mean(times["hier"]) * 1e-3) / 1e9,
             "samples_per_ray": samples / (n * len(views)),

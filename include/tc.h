@@ -160,6 +160,63 @@ tc_status tc_apply_edit(tc_context *ctx, const tc_edit *edits, int32_t n,
 tc_status tc_render_views(tc_context *ctx, const tc_view *views, int32_t n,
                           tc_hit *out_device, void *hip_stream);
 
+/* ---- shading ------------------------------------------------------------
+ * The shared shading stage of the paper's methods (Section 3: one palette,
+ * diffuse lighting with a height-field gradient normal, a shadow term and
+ * fog; Section 3.5: cave ambient), applied to the hit records of an exact
+ * render.  The paper gives no formulas; this is the library's definition.
+ * Per pixel, with the ray (O, D) of its view and its hit record:
+ *   miss        sky_rgba (also for a record naming no map cell, face 0,
+ *               or a face the ray cannot have crossed)
+ *   hit         cell (x, y), face, layer; column (F, B, T); h = T on the
+ *               slab layer, else F
+ *   time        t = tn / td by face: top (Oz - h S) / -Dz; underside
+ *               (B S - Oz) / Dz; wall facing -X (x S - Ox) / Dx, facing +X
+ *               (Ox - (x+1) S) / -Dx, and likewise in y; inside 0 / 1
+ *   distance    q * len * 2^-16, q = (float)((double)tn / (double)td),
+ *               len = sqrtf(((float)Dx*Dx + (float)Dy*Dy) + (float)Dz*Dz)
+ *   normal      top face: n = (-gx, -gy, 1) / sqrtf((gx*gx + gy*gy) + 1),
+ *               gx = (float)(s(x+1, y) - s(x-1, y)) * 0.5, gy likewise, over
+ *               the hit layer's surface s (floor: F; slab: T where the
+ *               column has a slab, else the hit column's T), neighbours
+ *               clamped to the map; underside (0, 0, -1); walls their
+ *               outward axis; inside (0, 0, 1)
+ *   light       l = L / sqrtf(((float)Lx*Lx + (float)Ly*Ly) + (float)Lz*Lz);
+ *               lambert = (nx*lx + ny*ly) + nz*lz
+ *   shadow      if lambert > 0 and not inside: an exact ray from
+ *               P = O + floor(tn * D / td) (fixed point, per component),
+ *               moved one unit (2^-16 cell) out through the hit face, along
+ *               L; lit iff it meets nothing
+ *   intensity   I = fminf(a + (lit ? lambert : 0), 1), a = cave_ambient for
+ *               a floor hit on a column with a slab, else ambient
+ *   colour      per channel c = (float)albedo * I, albedo =
+ *               palette[layer * 256 + h]; f = fminf(distance / fog_far, 1);
+ *               c = c + ((float)fog - c) * f; byte (uint8)(c + 0.5); alpha 255
+ * Single precision, one IEEE operation at a time in this order, no fused
+ * multiply-add: the output is reproducible bit for bit. */
+typedef struct tc_shade_params {
+  int32_t light[3];        /* integer direction toward the light, |c| <=
+                              TC_MAX_DIR, not all 0 */
+  float ambient;           /* 0..1 */
+  float cave_ambient;      /* 0..1 */
+  float fog_far;           /* > 0: distance of complete fog */
+  uint32_t sky_rgba;       /* R | G << 8 | B << 16 | A << 24 */
+  uint32_t fog_rgba;
+  const uint32_t *palette; /* host, 512 RGBA entries: floor top at height h,
+                              then slab top at height h; copied */
+} tc_shade_params;
+
+/* Shade n views whose hit records (tc_render_views of the same views on the
+ * current map, in any exact render mode) are in hits_device, into
+ * rgba_device (one uint32 per pixel, same order), owned by the caller.
+ * The shadow rays use the exact walk and the context's render knobs.
+ * Errors: as tc_render_views for the views; TC_INVALID_ARG for null
+ * pointers, a zero or too long light direction, fog_far <= 0 or not
+ * finite, ambient terms outside 0..1. */
+tc_status tc_shade_views(tc_context *ctx, const tc_view *views, int32_t n,
+                         const tc_hit *hits_device, const tc_shade_params *params,
+                         uint32_t *rgba_device, void *hip_stream);
+
 /* ---- options ---------------------------------------------------------- */
 /* Tuning knobs of the render path.  Each takes effect for later calls. */
 #define TC_OPT_RENDER_MODE 1   /* 0 hierarchical (default), 1 flat walk,

@@ -74,6 +74,13 @@ class tc_tune_result(ctypes.Structure):
                 ("tried", ctypes.c_int32)]
 
 
+class tc_shade_params(ctypes.Structure):
+    _fields_ = [("light", ctypes.c_int32 * 3), ("ambient", ctypes.c_float),
+                ("cave_ambient", ctypes.c_float), ("fog_far", ctypes.c_float),
+                ("sky_rgba", ctypes.c_uint32), ("fog_rgba", ctypes.c_uint32),
+                ("palette", ctypes.c_void_p)]
+
+
 class tc_server_stats(ctypes.Structure):
     _fields_ = [("batches", ctypes.c_uint64), ("edits", ctypes.c_uint64),
                 ("views", ctypes.c_uint64), ("rays", ctypes.c_uint64),
@@ -92,6 +99,8 @@ SIGNATURES = [
     ("tc_load_columns", _I32, [_P, _I32, _I32, _P, _P, _P, ctypes.c_size_t, _P]),
     ("tc_apply_edit", _I32, [_P, ctypes.POINTER(tc_edit), _I32, _P]),
     ("tc_render_views", _I32, [_P, ctypes.POINTER(tc_view), _I32, _P, _P]),
+    ("tc_shade_views", _I32, [_P, ctypes.POINTER(tc_view), _I32, _P,
+                              ctypes.POINTER(tc_shade_params), _P, _P]),
     ("tc_set_option", _I32, [_P, _I32, ctypes.c_int64]),
     ("tc_get_option", _I32, [_P, _I32, ctypes.POINTER(ctypes.c_int64)]),
     ("tc_read_columns", _I32, [_P, _I32, _I32, _I32, _I32, _P, _P, _P, _P]),
@@ -270,6 +279,28 @@ class Context:
         st = load_library().tc_render_views(self._h, arr, len(arr),
                                             ctypes.c_void_p(int(out_ptr)),
                                             _stream_handle(stream))
+        _check(self._h, st)
+
+    def tc_shade_views(self, views, hits_ptr, light, palette, out_ptr, ambient=0.3,
+                       cave_ambient=0.12, fog_far=600.0, sky_rgba=0xFFEBCE87,
+                       fog_rgba=0xFFD2C8B4, stream=None):
+        """Shade the hit records at hits_ptr (device) of `views` into
+        out_ptr (device, one uint32 RGBA per pixel); `palette` is 512
+        uint32 on the host."""
+        arr = _views_struct(views)
+        pal = np.ascontiguousarray(palette, np.uint32)
+        if pal.size != 512:
+            raise ValueError("palette needs 512 entries")
+        p = tc_shade_params()
+        for c in range(3):
+            p.light[c] = int(light[c])
+        p.ambient, p.cave_ambient, p.fog_far = ambient, cave_ambient, fog_far
+        p.sky_rgba, p.fog_rgba = sky_rgba, fog_rgba
+        p.palette = pal.ctypes.data
+        st = load_library().tc_shade_views(self._h, arr, len(arr),
+                                           ctypes.c_void_p(int(hits_ptr)), ctypes.byref(p),
+                                           ctypes.c_void_p(int(out_ptr)),
+                                           _stream_handle(stream))
         _check(self._h, st)
 
     def tc_set_option(self, key, value):

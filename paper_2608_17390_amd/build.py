@@ -16,11 +16,11 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtc.so")
 INCLUDE = os.path.join(ROOT, "include")
-SOURCES = ["tc_map.hip", "tc_render.hip", "tc_march.hip", "tc_api.cpp",
+SOURCES = ["tc_map.hip", "tc_render.hip", "tc_march.hip", "tc_shade.hip", "tc_api.cpp",
            "tc_frame.cpp", "tc_server.cpp"]
-# per-source flags: the sampled march is defined one IEEE single operation
-# at a time, so nothing may be fused into a multiply-add
-EXTRA = {"tc_march.hip": ["-ffp-contract=off"]}
+# per-source flags: the sampled march and the shading pass are defined one
+# IEEE single operation at a time, so nothing may be fused into a multiply-add
+EXTRA = {"tc_march.hip": ["-ffp-contract=off"], "tc_shade.hip": ["-ffp-contract=off"]}
 ARCH = os.environ.get("TC_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -572,6 +572,66 @@ tc_status tc_render_views(tc_context* ctx, const tc_view* views, int32_t n,
   }
 }
 
+tc_status tc_shade_views(tc_context* ctx, const tc_view* views, int32_t n,
+                         const tc_hit* hits_device, const tc_shade_params* params,
+                         uint32_t* rgba_device, void* hip_stream) {
+  if (!ctx) return TC_INVALID_ARG;
+  try {
+    ctx->err.clear();
+    if (!ctx->map) return fail(ctx, TC_NO_MAP, "tc_shade_views: no map loaded");
+    if (ctx->server) return fail(ctx, TC_INVALID_ARG, "tc_shade_views: a server owns the map");
+    if (!hits_device || !rgba_device || !params || !params->palette)
+      return fail(ctx, TC_INVALID_ARG, "tc_shade_views: null pointer");
+    const tc_shade_params& p = *params;
+    bool any = false;
+    for (int c = 0; c < 3; ++c) {
+      if (p.light[c] < -TC_MAX_DIR || p.light[c] > TC_MAX_DIR)
+        return fail(ctx, TC_INVALID_ARG, "tc_shade_views: light component out of range");
+      any |= p.light[c] != 0;
+    }
+    if (!any) return fail(ctx, TC_INVALID_ARG, "tc_shade_views: zero light direction");
+    if (!(p.fog_far > 0.0f) || !std::isfinite(p.fog_far))
+      return fail(ctx, TC_INVALID_ARG, "tc_shade_views: bad fog_far");
+    if (!(p.ambient >= 0.0f && p.ambient <= 1.0f) ||
+        !(p.cave_ambient >= 0.0f && p.cave_ambient <= 1.0f))
+      return fail(ctx, TC_INVALID_ARG, "tc_shade_views: ambient outside 0..1");
+    tci::ViewPlan plan;
+    tc_status st = tci::plan_views(ctx, views, n, plan, false);
+    if (st) return st;
+    st = set_device(ctx);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const size_t off_pal = (plan.off_queue + 255) & ~(size_t)255;
+    const size_t total = off_pal + 512 * sizeof(uint32_t);
+    tci::Slot* slot = nullptr;
+    st = tci::acquire(ctx, total, &slot);
+    if (st) return st;
+    tci::write_views(plan, (char*)slot->host);
+    memcpy((char*)slot->host + off_pal, p.palette, 512 * sizeof(uint32_t));
+    const char* dev = (const char*)slot->dev;
+    hipError_t e = hipMemcpyAsync(slot->dev, slot->host, total, hipMemcpyHostToDevice, s);
+    tci_shade sh;
+    for (int c = 0; c < 3; ++c) sh.light[c] = p.light[c];
+    sh.ambient = p.ambient;
+    sh.cave_ambient = p.cave_ambient;
+    sh.fog_far = p.fog_far;
+    sh.sky_rgba = p.sky_rgba;
+    sh.fog_rgba = p.fog_rgba;
+    sh.palette = (const uint32_t*)(dev + off_pal);
+    tci_render_opts o = tci::render_opts(ctx);
+    o.rows = (const int32_t*)(dev + plan.off_rows);
+    if (e == hipSuccess)
+      e = tci_launch_shade(ctx->desc, (const tci_view*)(dev + plan.off_views), plan.n,
+                           (const int64_t*)(dev + plan.off_prefix), plan.npkt, hits_device,
+                           rgba_device, sh, o, s);
+    tc_status rs = tci::release(ctx, slot, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "tc_shade_views");
+    return rs;
+  } catch (...) {
+    return fail(ctx, TC_OUT_OF_MEMORY, "tc_shade_views: host allocation failed");
+  }
+}
+
 tc_status tc_set_option(tc_context* ctx, int32_t key, int64_t value) {
   if (!ctx) return TC_INVALID_ARG;
   ctx->err.clear();

@@ -77,6 +77,14 @@ struct tci_render_opts {
   int32_t march_bisect;        // sampled march: bisection steps
 };
 
+// Shading parameters (the device copy of tc_shade_params).
+struct tci_shade {
+  int32_t light[3];            // integer direction toward the light
+  float ambient, cave_ambient, fog_far;
+  uint32_t sky_rgba, fog_rgba;
+  const uint32_t* palette;     // 512 RGBA entries in device memory
+};
+
 // ---- launchers (return hipError_t of the launch) -------------------------
 hipError_t tci_launch_repack(const uint8_t* planes, int32_t W, int32_t H,
                              uint32_t* base, tci_level l0, hipStream_t s);
@@ -108,6 +116,11 @@ hipError_t tci_launch_render_persistent(const tci_map& m,
                                         const tci_render_opts& o,
                                         hipStream_t s);
 hipError_t tci_launch_zero_u64(uint64_t* p, int32_t n, hipStream_t s);
+// Shade: per pixel, the colour of its hit record (with a shadow ray).
+hipError_t tci_launch_shade(const tci_map& m, const tci_view* views, int32_t nviews,
+                            const int64_t* pkt_prefix, int64_t npkt, const void* hits,
+                            uint32_t* rgba, const tci_shade& sh, const tci_render_opts& o,
+                            hipStream_t s);
 // Render: the sampled march (RAYMARCH), one thread per pixel.
 hipError_t tci_launch_march(const tci_map& m, const tci_view* views,
                             int32_t nviews, const int64_t* pkt_prefix,

@@ -205,6 +205,28 @@ def march_protocol(torch, tc, synth, steps, warmup):
         torch.cuda.synchronize()
         shaded.append(float(np.median([a0.elapsed_time(b0) for a0, b0 in ev])))
     times["shaded"] = shaded
+    # the shading kernel alone: HIP events the library records around it,
+    # and its algorithmic bytes (8 B hit record in, 4 B colour out, 4 B per
+    # column, gradient neighbour and shadow-ray node or cell read)
+    ctx.tc_set_option(tc.TC_OPT_KERNEL_TIMING, 1)
+    shade_k = []
+    for v, out in zip(views, outs["hier"]):
+        ctx.tc_render_views([v], out.data_ptr())
+        for _ in range(steps):
+            ctx.tc_shade_views([v], out.data_ptr(), light, pal, rgba.data_ptr())
+            shade_k.append(ctx.tc_read_kernel_times()[0])
+    ctx.tc_set_option(tc.TC_OPT_KERNEL_TIMING, 0)
+    ctx.tc_set_option(tc.TC_OPT_COUNT_READS, 1)
+    ctx.tc_read_counters()
+    for v, out in zip(views, outs["hier"]):
+        ctx.tc_render_views([v], out.data_ptr())
+    ctx.tc_read_counters()
+    for v, out in zip(views, outs["hier"]):
+        ctx.tc_shade_views([v], out.data_ptr(), light, pal, rgba.data_ptr())
+    shade_reads = ctx.tc_read_counters()
+    ctx.tc_set_option(tc.TC_OPT_COUNT_READS, 0)
+    shade_alg = (12 * n * len(views) + 4 * shade_reads) / len(views)
+    shade_ms = float(np.mean(shade_k))
     # algorithmic bytes of the march: 8 B per hit record + 4 B per column
     # sample read over the map (the library's own count)
     ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, MODES["march"])
@@ -249,6 +271,12 @@ def march_protocol(torch, tc, synth, steps, warmup):
                                "frac": alg / (kms * 1e-3) / 1e9 / PEAK_HBM_GBS,
                                "alg_bytes_per_view": alg / len(views),
                                "kernel_ms_per_view": kms / len(views)},
+            "shade_roofline": {"bound": "hbm", "achieved": shade_alg / (shade_ms * 1e-3) / 1e9,
+                               "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                               "frac": shade_alg / (shade_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                               "alg_bytes_per_view": shade_alg,
+                               "kernel_ms_per_view": shade_ms,
+                               "reads_per_pixel": shade_reads / (n * len(views))},
             "per_pitch": per_pitch}
 
 

@@ -280,10 +280,11 @@ tc_status tc_shade_views(tc_context *ctx, const tc_view *views, int32_t n,
 #define TC_OPT_MARCH_BISECT 15   /* bisection steps, 0..64 (default 4) */
 #define TC_OPT_MARCH_FAR 16      /* far limit in world units, 1..2^20
                                     (default 600, Section 5) */
-#define TC_OPT_KERNEL_TIMING 13  /* 1: tc_render_views records HIP events on
-                                    its stream around each render kernel,
-                                    read back by tc_read_kernel_times
-                                    (diagnostic; default 0) */
+#define TC_OPT_KERNEL_TIMING 13  /* 1: tc_render_views and tc_shade_views
+                                    record HIP events on their stream around
+                                    each kernel, read back by
+                                    tc_read_kernel_times (diagnostic;
+                                    default 0) */
 tc_status tc_set_option(tc_context *ctx, int32_t key, int64_t value);
 tc_status tc_get_option(const tc_context *ctx, int32_t key, int64_t *value);
 
@@ -407,14 +408,17 @@ tc_status tc_read_pyramid(tc_context *ctx, int32_t level, uint32_t *out,
                           void *hip_stream);
 
 /* Read and reset the counter of TC_OPT_COUNT_READS: the number of
- * pyramid nodes and cells read by all rays rendered since the last reset.
+ * pyramid nodes and cells read by all rays rendered since the last reset
+ * (the shading pass adds its hit columns, gradient neighbours and the
+ * nodes and cells of its shadow rays).
  * Synchronises `hip_stream`.  0 if counting was never enabled. */
 tc_status tc_read_counters(tc_context *ctx, uint64_t *reads, void *hip_stream);
 
 /* Durations in milliseconds of the kernels of the most recent
- * tc_render_views call made with TC_OPT_KERNEL_TIMING on, measured with HIP
- * events recorded on that call's stream: ms[0] the traversal kernel (any
- * render mode), ms[1] the split pass (0 when it did not run).  `ms` holds 2
+ * tc_render_views or tc_shade_views call made with TC_OPT_KERNEL_TIMING on,
+ * measured with HIP events recorded on that call's stream: ms[0] the
+ * traversal kernel (any render mode) or the shading kernel, ms[1] the split
+ * pass (0 when it did not run).  `ms` holds 2
  * floats.  Waits for those events.  TC_INVALID_ARG if no timed call was
  * made since timing was switched on. */
 tc_status tc_read_kernel_times(tc_context *ctx, float *ms);

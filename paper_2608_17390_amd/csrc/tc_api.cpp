@@ -620,10 +620,22 @@ tc_status tc_shade_views(tc_context* ctx, const tc_view* views, int32_t n,
     sh.palette = (const uint32_t*)(dev + off_pal);
     tci_render_opts o = tci::render_opts(ctx);
     o.rows = (const int32_t*)(dev + plan.off_rows);
+    hipEvent_t* kev = nullptr;
+    if (ctx->kernel_timing) {
+      for (hipEvent_t& ev : ctx->kev)
+        if (!ev && e == hipSuccess) e = hipEventCreate(&ev);
+      kev = ctx->kev;
+    }
+    if (e == hipSuccess && kev) e = hipEventRecord(kev[0], s);
     if (e == hipSuccess)
       e = tci_launch_shade(ctx->desc, (const tci_view*)(dev + plan.off_views), plan.n,
                            (const int64_t*)(dev + plan.off_prefix), plan.npkt, hits_device,
                            rgba_device, sh, o, s);
+    if (e == hipSuccess && kev) e = hipEventRecord(kev[1], s);
+    if (kev) {
+      ctx->kev_valid = e == hipSuccess;
+      ctx->kev_split = false;
+    }
     tc_status rs = tci::release(ctx, slot, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "tc_shade_views");
     return rs;

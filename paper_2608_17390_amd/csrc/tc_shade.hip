@@ -54,9 +54,11 @@ __device__ __forceinline__ int64_t floordiv(int64_t a, int64_t b) {  // b > 0
   return q;
 }
 
-// Does a ray from P along L meet any solid?
+// Does a ray from P along L meet any solid?  `reads` gains the nodes and
+// cells the walk read.
 __device__ __forceinline__ bool occluded(const tci_map& m, const lvl_t* lv, const int64_t P[3],
-                                         const int32_t L[3], int32_t L0, int32_t Lmax) {
+                                         const int32_t L[3], int32_t L0, int32_t Lmax,
+                                         int32_t& reads) {
   ray_t s;
   s.Ox = P[0];
   s.Oy = P[1];
@@ -70,12 +72,14 @@ __device__ __forceinline__ bool occluded(const tci_map& m, const lvl_t* lv, cons
     uint32_t w;
     float d;
     trace_vertical(m, lv, s, w, d);
+    reads += 1;
     return w != kMiss;
   }
   walk_t st;
   walk_init(s, L0, st);
   uint32_t col = 0;
   const int32_t res = walk_steps(m, lv, s, st, Lmax, kIterCap + 1, col);
+  reads += st.reads;
   return res == kHitCell || res == kCapped;
 }
 
@@ -104,6 +108,7 @@ __global__ __launch_bounds__(256) void shade_kernel(
     rgba[idx] = sh.sky_rgba;
     return;
   }
+  int32_t reads = 1;   // the hit column
   ray_t r;
   pixel_ray(v, px, py, r);
   const int64_t O[3] = {r.Ox, r.Oy, r.Oz};
@@ -138,6 +143,7 @@ __global__ __launch_bounds__(256) void shade_kernel(
   const float dist = q * len * (1.0f / 65536.0f);
   float n0, n1, n2;
   if (face == kTop) {
+    reads += 4;        // the four neighbouring columns
     const float gx = (float)(surf(sm, x + 1, y, layer, T) - surf(sm, x - 1, y, layer, T)) * 0.5f;
     const float gy = (float)(surf(sm, x, y + 1, layer, T) - surf(sm, x, y - 1, layer, T)) * 0.5f;
     const float nl = sqrtf((gx * gx + gy * gy) + 1.0f);
@@ -169,7 +175,7 @@ __global__ __launch_bounds__(256) void shade_kernel(
       P[cc] = O[cc] + floordiv(tn * (int64_t)D[cc], td) + nudge[cc];
     const int32_t top = m.top;
     lit = !occluded(m, lv, P, sh.light, clamp_level(o.start_level, top),
-                    clamp_level(o.max_level, top));
+                    clamp_level(o.max_level, top), reads);
   }
   const float amb = (layer == 0 && B > 0) ? sh.cave_ambient : sh.ambient;
   const float I = fminf(amb + (lit ? lambert : 0.0f), 1.0f);
@@ -185,6 +191,7 @@ __global__ __launch_bounds__(256) void shade_kernel(
     out |= (uint32_t)(val + 0.5f) << (8 * cc);
   }
   rgba[idx] = out;
+  if (o.count) atomicAdd(o.count, (unsigned long long)reads);
 }
 
 }  // namespace

@@ -117,6 +117,29 @@ def test_protocol_views_sampled(ctx):
     assert_same(g[idx], o, "protocol")
 
 
+def test_kernel_timing_and_read_count(ctx):
+    F, B, T = synth.make_map_from_config(1)
+    load(ctx, F, B, T)
+    views = synth.config_views(1, F, B)
+    pal = synth.default_palette()
+    hits = tc.render(ctx, views)
+    out = torch.empty(synth.view_rays(views), dtype=torch.int32, device="cuda")
+    ctx.tc_set_option(tc.TC_OPT_KERNEL_TIMING, 1)
+    ctx.tc_set_option(tc.TC_OPT_COUNT_READS, 1)
+    try:
+        ctx.tc_read_counters()
+        ctx.tc_shade_views(views, hits.data_ptr(), LIGHTS[1], pal, out.data_ptr())
+        t0, t1 = ctx.tc_read_kernel_times()
+        reads = ctx.tc_read_counters()
+    finally:
+        ctx.tc_set_option(tc.TC_OPT_KERNEL_TIMING, 0)
+        ctx.tc_set_option(tc.TC_OPT_COUNT_READS, 0)
+    assert t0 > 0 and t1 == 0
+    w, _ = tc.split_hits(hits)
+    nhit = int(np.sum(w != oracle.MISS))
+    assert nhit <= reads <= 64 * nhit
+
+
 def test_errors(ctx):
     F, B, T = synth.make_map_from_config(1)
     load(ctx, F, B, T)

@@ -220,9 +220,9 @@ tc_status tc_shade_views(tc_context *ctx, const tc_view *views, int32_t n,
 /* ---- options ---------------------------------------------------------- */
 /* Tuning knobs of the render path.  Each takes effect for later calls. */
 #define TC_OPT_RENDER_MODE 1   /* 0 hierarchical (default), 1 flat walk,
-                                  2 persistent packet queue (all three
-                                  exact and bit-identical); 3 the sampled
-                                  march below */
+                                  2 persistent packet queue, 4 hierarchical
+                                  with occupancy masks (all four exact and
+                                  bit-identical); 3 the sampled march below */
 #define TC_OPT_START_LEVEL 2   /* pyramid level a ray starts at (default 2);
                                   clamped to the top level */
 #define TC_OPT_MAX_LEVEL 3     /* highest level a ray ascends to (default
@@ -406,6 +406,16 @@ tc_status tc_pyramid_dims(const tc_context *ctx, int32_t level, int32_t *w,
  * max T of two-layer cells (0 if none).  Synchronises `hip_stream`. */
 tc_status tc_read_pyramid(tc_context *ctx, int32_t level, uint32_t *out,
                           void *hip_stream);
+
+/* Copy the occupancy masks of pyramid level `level` (1..levels) to `out`,
+ * row-major, dims as tc_pyramid_dims.  Bit k of a node's mask is set iff
+ * the slab interval [B, T] of some column of its 2^L x 2^L block meets the
+ * closed height band [4k, 4k + 4] (Section 3.2: a conservative occupancy
+ * hierarchy whose levels are unions of their children).  Render mode 4
+ * skips a node whose slabs the ray passes between.  Synchronises
+ * `hip_stream`. */
+tc_status tc_read_occupancy(tc_context *ctx, int32_t level, uint64_t *out,
+                            void *hip_stream);
 
 /* Read and reset the counter of TC_OPT_COUNT_READS: the number of
  * pyramid nodes and cells read by all rays rendered since the last reset

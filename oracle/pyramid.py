@@ -47,3 +47,24 @@ def pyramid_level_fast(F, B, T, L):
     smin = b.min(axis=(1, 3)).astype(np.uint32)
     smax = t.max(axis=(1, 3)).astype(np.uint32)
     return fmax | (smin << 8) | (smax << 16)
+
+
+def occupancy_level(F, B, T, L):
+    """Occupancy masks of level L >= 1 (uint64, row-major [y][x]): bit k of a
+    node is set iff some two-layer column of its 2^L x 2^L block has a slab
+    [B, T] meeting the closed height band [4k, 4k + 4], i.e. B <= 4k + 4 and
+    T >= 4k.  The union over the block follows the occupancy hierarchy of
+    Section 3.2 (each level the union of its children)."""
+    H, W = F.shape
+    n = 1 << L
+    HL = (H + n - 1) // n
+    WL = (W + n - 1) // n
+    b = B.astype(np.int64)
+    t = T.astype(np.int64)
+    cell = np.zeros((H, W), np.uint64)
+    for k in range(64):
+        meets = (b > 0) & (b <= 4 * k + 4) & (t >= 4 * k)
+        cell |= meets.astype(np.uint64) << np.uint64(k)
+    pad = ((0, HL * n - H), (0, WL * n - W))
+    c = np.pad(cell, pad, constant_values=0).reshape(HL, n, WL, n)
+    return np.bitwise_or.reduce(np.bitwise_or.reduce(c, axis=3), axis=1)

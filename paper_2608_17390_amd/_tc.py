@@ -107,6 +107,7 @@ SIGNATURES = [
     ("tc_pyramid_info", _I32, [_P, ctypes.POINTER(_I32)]),
     ("tc_pyramid_dims", _I32, [_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     ("tc_read_pyramid", _I32, [_P, _I32, _P, _P]),
+    ("tc_read_occupancy", _I32, [_P, _I32, _P, _P]),
     ("tc_read_counters", _I32, [_P, ctypes.POINTER(ctypes.c_uint64), _P]),
     ("tc_read_kernel_times", _I32, [_P, ctypes.POINTER(ctypes.c_float)]),
     ("tc_map_bytes", _I32, [_P, ctypes.POINTER(ctypes.c_uint64)]),
@@ -331,6 +332,14 @@ class Context:
         _check(self._h, load_library().tc_pyramid_dims(self._h, level, ctypes.byref(w),
                                                        ctypes.byref(h)))
         return w.value, h.value
+
+    def tc_read_occupancy(self, level, stream=None):
+        w, h = self.tc_pyramid_dims(level)
+        out = np.empty((h, w), np.uint64)
+        st = load_library().tc_read_occupancy(self._h, level, out.ctypes.data,
+                                              _stream_handle(stream))
+        _check(self._h, st)
+        return out
 
     def tc_read_pyramid(self, level, stream=None):
         w, h = self.tc_pyramid_dims(level)

@@ -355,7 +355,8 @@ hipError_t enqueue_render(tc_context* ctx, const tci_map& d, const char* dev,
   }
   hipError_t e = mark(0);
   if (e == hipSuccess)
-    e = tci_launch_render(d, dv, p.n, pre, p.npkt, out, ctx->render_mode == 1, o, s);
+    e = tci_launch_render(d, dv, p.n, pre, p.npkt, out,
+                          ctx->render_mode == 1 ? 1 : (ctx->render_mode == 4 ? 2 : 0), o, s);
   if (e == hipSuccess) e = mark(1);
   return e;
 }
@@ -460,6 +461,15 @@ tc_status tc_load_columns(tc_context* ctx, int32_t W, int32_t H,
       l.tiles_x = (l.w + 7) >> 3;
       l.off = (uint32_t)words;
       words += (size_t)l.tiles_x * ((l.h + 7) >> 3) * 64;
+    }
+    // occupancy masks of levels 1..top after the pyramid, 2 words a node
+    for (int32_t L = 0; L < TCI_MAX_LEVELS; ++L) {
+      tci_level& k = d.mk[L];
+      k = tci_level{0, 0, 0, 0};
+      if (L < 1 || L > d.top) continue;
+      k = d.lv[L];
+      k.off = (uint32_t)words;
+      words += (size_t)k.tiles_x * ((k.h + 7) >> 3) * 128;
     }
     uint32_t* map = nullptr;
     uint8_t* planes = nullptr;
@@ -649,7 +659,7 @@ tc_status tc_set_option(tc_context* ctx, int32_t key, int64_t value) {
   ctx->err.clear();
   switch (key) {
     case TC_OPT_RENDER_MODE:
-      if (value < 0 || value > 3) break;
+      if (value < 0 || value > 4) break;
       ctx->render_mode = (int32_t)value;
       return TC_OK;
     case TC_OPT_START_LEVEL:
@@ -830,6 +840,34 @@ tc_status tc_read_pyramid(tc_context* ctx, int32_t level, uint32_t* out, void* h
     return TC_OK;
   } catch (...) {
     return fail(ctx, TC_OUT_OF_MEMORY, "tc_read_pyramid: host allocation failed");
+  }
+}
+
+tc_status tc_read_occupancy(tc_context* ctx, int32_t level, uint64_t* out, void* hip_stream) {
+  if (!ctx) return TC_INVALID_ARG;
+  try {
+    ctx->err.clear();
+    if (!ctx->map) return fail(ctx, TC_NO_MAP, "tc_read_occupancy: no map loaded");
+    if (level < 1 || level > ctx->desc.top || !out)
+      return fail(ctx, TC_INVALID_ARG, "tc_read_occupancy: bad level %d", level);
+    tc_status st = set_device(ctx);
+    if (st) return st;
+    tci_level k = ctx->desc.mk[level];
+    const size_t words = (size_t)k.tiles_x * ((k.h + 7) >> 3) * 128;
+    std::vector<uint32_t> buf(words);
+    hipStream_t s = (hipStream_t)hip_stream;
+    TC_HIP(hipMemcpyAsync(buf.data(), ctx->map + k.off, words * 4, hipMemcpyDeviceToHost, s),
+           "hipMemcpyAsync(read)");
+    TC_HIP(hipStreamSynchronize(s), "hipStreamSynchronize(read)");
+    k.off = 0;
+    for (int32_t j = 0; j < k.h; ++j)
+      for (int32_t i = 0; i < k.w; ++i) {
+        const uint32_t w = tci_mask_index(k, i, j);
+        out[(size_t)j * k.w + i] = (uint64_t)buf[w] | ((uint64_t)buf[w + 1] << 32);
+      }
+    return TC_OK;
+  } catch (...) {
+    return fail(ctx, TC_OUT_OF_MEMORY, "tc_read_occupancy: host allocation failed");
   }
 }
 

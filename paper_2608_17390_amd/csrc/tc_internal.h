@@ -18,9 +18,16 @@ struct tci_level {
   int32_t tiles_x;   // ceil(w / 8)
 };
 
+// Occupancy masks: for every pyramid node of levels 1..top, 64 bits over
+// height, bit k set iff the slab interval [B, T] of some column of the node
+// meets the closed band [4k, 4k + 4].  They refine the node's slab test:
+// a ray whose height range over the node meets no set band passes between
+// the slabs.  Stored in the same allocation after the pyramid, tiled 8 x 8
+// like the levels, two 32-bit words (low, high) per node.
 struct tci_map {
   const uint32_t* base;           // all levels, one allocation
   tci_level lv[TCI_MAX_LEVELS];
+  tci_level mk[TCI_MAX_LEVELS];   // occupancy mask levels 1..top (off in words)
   int32_t W, H;
   int32_t top;                    // highest stored level (0 if none)
 };
@@ -29,6 +36,13 @@ __host__ __device__ inline uint32_t tci_tile_index(const tci_level& L,
                                                    int32_t i, int32_t j) {
   return L.off + ((uint32_t)((j >> 3) * L.tiles_x + (i >> 3)) << 6) +
          (uint32_t)((j & 7) << 3) + (uint32_t)(i & 7);
+}
+
+// Word index of the low word of node (i, j)'s occupancy mask.
+__host__ __device__ inline uint32_t tci_mask_index(const tci_level& M,
+                                                   int32_t i, int32_t j) {
+  return M.off + ((uint32_t)((j >> 3) * M.tiles_x + (i >> 3)) << 7) +
+         ((((uint32_t)(j & 7) << 3) + (uint32_t)(i & 7)) << 1);
 }
 
 // Device copy of a view plus the first ray index of the view and the
@@ -102,7 +116,9 @@ hipError_t tci_launch_update_level(const tci_map& m, uint32_t* base,
                                    int32_t nrect, int32_t max_w,
                                    int32_t max_h, hipStream_t s);
 
-// Render: views on the device, one thread per pixel.
+// Render: views on the device, one thread per pixel.  flat: 0 the
+// hierarchical walk, 1 the flat walk, 2 the hierarchical walk with the
+// occupancy masks.
 hipError_t tci_launch_render(const tci_map& m, const tci_view* views,
                              int32_t nviews, const int64_t* pkt_prefix,
                              int64_t npkt, void* out, int32_t flat,

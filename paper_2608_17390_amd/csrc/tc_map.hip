@@ -8,6 +8,11 @@
 // A ray whose height range over the node's time span stays above fmax and
 // either above smax or below smin cannot meet solid in the block.
 //
+// Beside each node, a 64-bit occupancy mask over height (bit k: a slab of
+// the block meets the band [4k, 4k + 4]) is the union of its children's,
+// as the paper's occupancy pyramid takes the union of its children
+// (Section 3.2); it is built and updated with the node.
+//
 // Edits follow Section 2 (a dirty rectangle with new heights and slab
 // metadata) and Section 4.4 (the dig crater).  Only the nodes above the
 // edited rectangles are recomputed, from the same 2x2 reduction as the full
@@ -70,6 +75,45 @@ __global__ void repack_kernel(const uint8_t* __restrict__ planes, int32_t W,
   base[l0.off + k] = v;
 }
 
+// Occupancy bands of one column's slab [B, T]: bits (B + 3) / 4 - 1 ..
+// T / 4, the bands [4k, 4k + 4] that meet it (none without a slab).
+__device__ inline uint64_t cell_mask(uint32_t c) {
+  const uint32_t B = (c >> 8) & 0xFF, T = (c >> 16) & 0xFF;
+  if (!B) return 0;
+  const uint32_t lo = (B + 3) / 4 - 1, hi = T / 4;
+  return (~0ull >> (63 - hi)) & (~0ull << lo);
+}
+
+// Occupancy mask of node (i, j) of level L: the union of its children's.
+__device__ inline uint64_t reduce_mask(const tci_map& m, const uint32_t* base,
+                                       int32_t L, int32_t i, int32_t j) {
+  const tci_level& c = m.lv[L - 1];
+  uint64_t acc = 0;
+  #pragma unroll
+  for (int dj = 0; dj < 2; ++dj) {
+    #pragma unroll
+    for (int di = 0; di < 2; ++di) {
+      int32_t ci = 2 * i + di, cj = 2 * j + dj;
+      if (ci < c.w && cj < c.h) {
+        if (L == 1) {
+          acc |= cell_mask(base[tci_tile_index(c, ci, cj)]);
+        } else {
+          const uint32_t k = tci_mask_index(m.mk[L - 1], ci, cj);
+          acc |= (uint64_t)base[k] | ((uint64_t)base[k + 1] << 32);
+        }
+      }
+    }
+  }
+  return acc;
+}
+
+__device__ inline void store_mask(const tci_map& m, uint32_t* base, int32_t L,
+                                  int32_t i, int32_t j, uint64_t v) {
+  const uint32_t k = tci_mask_index(m.mk[L], i, j);
+  base[k] = (uint32_t)v;
+  base[k + 1] = (uint32_t)(v >> 32);
+}
+
 __global__ void build_level_kernel(tci_map m, uint32_t* __restrict__ base,
                                    int32_t L) {
   const tci_level& l = m.lv[L];
@@ -80,8 +124,13 @@ __global__ void build_level_kernel(tci_map m, uint32_t* __restrict__ base,
   int32_t i = (tile % l.tiles_x) * 8 + (e & 7);
   int32_t j = (tile / l.tiles_x) * 8 + (e >> 3);
   uint32_t v = 0;
-  if (i < l.w && j < l.h) v = reduce_node(m, base, L, i, j);
+  uint64_t mask = 0;
+  if (i < l.w && j < l.h) {
+    v = reduce_node(m, base, L, i, j);
+    mask = reduce_mask(m, base, L, i, j);
+  }
   base[l.off + k] = v;
+  store_mask(m, base, L, i, j, mask);
 }
 
 __device__ inline bool covers(const tci_edit& e, int32_t x, int32_t y) {
@@ -154,6 +203,7 @@ __global__ void update_level_kernel(tci_map m, uint32_t* __restrict__ base,
        k += (int64_t)gridDim.y * blockDim.x) {
     int32_t i = x0 + (int32_t)(k % rw), j = y0 + (int32_t)(k / rw);
     base[tci_tile_index(l, i, j)] = reduce_node(m, base, L, i, j);
+    store_mask(m, base, L, i, j, reduce_mask(m, base, L, i, j));
   }
 }
 

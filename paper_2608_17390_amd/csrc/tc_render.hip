@@ -8,13 +8,16 @@
 namespace {
 
 // One thread per pixel; a wave casts one 8x8 pixel packet.
-template <bool kFlat>
+// kOcc: node tests also consult the occupancy masks (render mode 4).
+template <bool kFlat, bool kOcc = false>
 __global__ __launch_bounds__(256) void render_kernel(
     tci_map m, const tci_view* __restrict__ views, int32_t nviews,
     const int64_t* __restrict__ pkt_prefix, int64_t npkt, void* out,
     tci_render_opts o) {
   __shared__ lvl_t lv[TCI_MAX_LEVELS];
-  load_levels(m, lv);
+  __shared__ uint32_t moff[kOcc ? TCI_MAX_LEVELS : 1];
+  if constexpr (kOcc) load_levels_occ(m, lv, moff);
+  else load_levels(m, lv);
   // XCD-aware order: consecutive hardware blocks go to different XCDs, so
   // hand each XCD a contiguous range of packets to share its L2.
   int64_t nb = gridDim.x, b = blockIdx.x;
@@ -51,7 +54,8 @@ __global__ __launch_bounds__(256) void render_kernel(
     bool split = !kFlat && o.split_budget > 0 && o.qcap > 0;
     int32_t st;
     for (;;) {
-      st = walk_steps(m, lv, r, s, Lmax, split ? o.split_budget : kIterCap + 1, col, boost);
+      st = walk_steps<false, kOcc>(m, lv, r, s, Lmax, split ? o.split_budget : kIterCap + 1,
+                                   col, boost, 0, 0, 0, moff);
       if (!split) break;
       split = false;
       // long walks go to the split pass, as many as the queue holds
@@ -259,8 +263,11 @@ hipError_t tci_launch_render(const tci_map& m, const tci_view* views,
                              const tci_render_opts& o, hipStream_t s) {
   int64_t blocks = (npkt + 3) / 4;
   if (blocks < 1) return hipSuccess;
-  if (flat)
+  if (flat == 1)
     hipLaunchKernelGGL(render_kernel<true>, dim3((uint32_t)blocks), dim3(256),
+                       0, s, m, views, nviews, pkt_prefix, npkt, out, o);
+  else if (flat == 2)
+    hipLaunchKernelGGL((render_kernel<false, true>), dim3((uint32_t)blocks), dim3(256),
                        0, s, m, views, nviews, pkt_prefix, npkt, out, o);
   else
     hipLaunchKernelGGL(render_kernel<false>, dim3((uint32_t)blocks),

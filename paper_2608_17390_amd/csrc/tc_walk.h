@@ -349,13 +349,19 @@ __device__ __forceinline__ void lift(const ray_t& r, walk_t& s, int32_t L) {
 // the many short ones sharing their SIMD.
 // With kSeg the walk also stops (kSegEnd) once its node lies wholly
 // outside the cell lines [seg_lo, seg_hi] of axis seg_axis (0 x, 1 y).
-template <bool kSeg = false>
+// With kOcc, a node that only the slab test keeps is also tested against
+// its occupancy mask (moff: the mask levels' word offsets, in LDS): the
+// ray's height range over the node, widened by two units to cover the
+// rounding of its float estimate, must meet an occupied band, or the ray
+// passes between the node's slabs and the node is skipped.
+template <bool kSeg = false, bool kOcc = false>
 __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
                                               const ray_t& r, walk_t& s,
                                               int32_t max_level, int32_t budget,
                                               uint32_t& col, int32_t boost = 0,
                                               int32_t seg_axis = 0,
-                                              int32_t seg_lo = 0, int32_t seg_hi = 0) {
+                                              int32_t seg_lo = 0, int32_t seg_hi = 0,
+                                              const uint32_t* moff = nullptr) {
   const bool desc = r.Dz < 0;
   const int32_t sx = r.Dx > 0 ? 1 : -1, sy = r.Dy > 0 ? 1 : -1;
   const int32_t nearx = r.Dx > 0 ? 0 : 1, neary = r.Dy > 0 ? 0 : 1;
@@ -392,6 +398,23 @@ __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
       const uint32_t a = v & 0xFF, b = (v >> 8) & 0xFF, c = (v >> 16) & 0xFF;
       occ = (lo <= (int64_t)__umul24(a, Dlo)) ||
             ((lo <= (int64_t)__umul24(c, Dlo)) && (hi >= (int64_t)__umul24(b, Dhi)));
+      if constexpr (kOcc) {
+        if (occ && L > 0 && !(lo <= (int64_t)__umul24(a, Dlo))) {
+          const uint32_t mi = moff[L] +
+                              ((__umul24((uint32_t)s.nj >> 3, (uint32_t)l.tiles_x) +
+                                ((uint32_t)s.ni >> 3)) << 7) +
+                              ((((uint32_t)(s.nj & 7) << 3) + (uint32_t)(s.ni & 7)) << 1);
+          const uint2 mw = *reinterpret_cast<const uint2*>(m.base + mi);
+          const uint64_t mask = (uint64_t)mw.x | ((uint64_t)mw.y << 32);
+          s.reads += 2;
+          const float zl = (float)lo / (float)Dlo - 2.0f;
+          const float zh = (float)hi / (float)Dhi + 2.0f;
+          const int32_t kl = min(max((int32_t)floorf(zl * 0.25f), 0), 63);
+          const int32_t kh = min(max((int32_t)floorf(zh * 0.25f), 0), 63);
+          const uint64_t range = (~0ull >> (63 - kh)) & (~0ull << kl);
+          occ = (mask & range) != 0;
+        }
+      }
     }
     if (occ) {
       if (L == 0) {
@@ -468,6 +491,16 @@ __device__ __forceinline__ void load_levels(const tci_map& m, lvl_t* lv) {
   if (threadIdx.x < TCI_MAX_LEVELS) {
     const tci_level& l = m.lv[threadIdx.x];
     lv[threadIdx.x] = lvl_t{l.off, l.w, l.h, l.tiles_x};
+  }
+  __syncthreads();
+}
+
+// Level table plus the occupancy mask levels' word offsets.
+__device__ __forceinline__ void load_levels_occ(const tci_map& m, lvl_t* lv, uint32_t* moff) {
+  if (threadIdx.x < TCI_MAX_LEVELS) {
+    const tci_level& l = m.lv[threadIdx.x];
+    lv[threadIdx.x] = lvl_t{l.off, l.w, l.h, l.tiles_x};
+    moff[threadIdx.x] = m.mk[threadIdx.x].off;
   }
   __syncthreads();
 }

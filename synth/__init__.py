@@ -12,7 +12,7 @@ same shape, the same two-interval column encoding and a comparable share of
 double-level cells.
 """
 from .configs import CONFIGS, SEEDS, config
-from .maps import make_map, make_map_from_config, pack_columns_check
+from .maps import make_map, make_map_from_config, pack_columns_check, cave_map
 from .views import (S, MAX_DIR, VIEW_DTYPE, perspective_view, ortho_view,
                     shadow_view, views_array, config_views, view_rays,
                     batched_views, request_view, eye_above_floor, pitch_views)
@@ -21,7 +21,7 @@ from .arrivals import poisson_arrivals
 from .palette import default_palette, rgba
 
 __all__ = [
-    "CONFIGS", "SEEDS", "config", "make_map", "make_map_from_config",
+    "CONFIGS", "SEEDS", "config", "make_map", "make_map_from_config", "cave_map",
     "pack_columns_check", "S", "MAX_DIR", "VIEW_DTYPE", "perspective_view",
     "ortho_view", "shadow_view", "views_array", "config_views", "view_rays",
     "batched_views", "request_view", "eye_above_floor", "pitch_views",

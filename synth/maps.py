@@ -172,6 +172,13 @@ def make_map(W, H, seed, dual=0.2, period=64, cliffs="steps", n_cliffs=6,
     return F, B, T
 
 
+def cave_map(seed, W, H, dual=0.5):
+    """A cave-heavy map: half the cells two-layer, in blobs whose slabs sit
+    at heights set by their own surroundings, so one pyramid node often
+    holds slabs at several heights with air between them."""
+    return make_map(W, H, seed, dual=dual, period=64, cliffs="steps", n_cliffs=8)
+
+
 _MAP_CACHE = {}
 
 

@@ -15,7 +15,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 S = 65536
-MODES = {"hier": 0, "flat": 1, "persistent": 2}
+MODES = {"hier": 0, "flat": 1, "persistent": 2, "occupancy": 4}
 DEPTH_RTOL = 1e-5
 
 
@@ -102,7 +102,7 @@ def test_ragged_multi_view_batch(ctx, mode):
     assert_parity(wg, dg, wo, do, "ragged " + mode)
 
 
-@pytest.mark.parametrize("mode", ["hier", "persistent"])
+@pytest.mark.parametrize("mode", ["hier", "persistent", "occupancy"])
 def test_c2_full_image(ctx, mode):
     F, B, T = synth.make_map_from_config(2)
     views = synth.config_views(2, F, B)
@@ -137,6 +137,28 @@ def test_kernel_timing_leaves_results_unchanged(ctx):
         ctx.tc_set_option(tc.TC_OPT_KERNEL_TIMING, 0)
         ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 128)
         ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, 0)
+
+
+def test_occupancy_mode_on_a_cave_heavy_map(ctx):
+    """Half the cells two-layer, with slabs at scattered heights (the case
+    the occupancy masks are for): the masks match their definition and the
+    occupancy mode is bit-identical to the oracle on eye-level, cave and
+    oblique views."""
+    F, B, T = synth.cave_map(97, 512, 512)
+    load(ctx, F, B, T)
+    for L in range(1, ctx.tc_pyramid_info() + 1):
+        assert np.array_equal(ctx.tc_read_occupancy(L), oracle.occupancy_level(F, B, T, L)), L
+    rng = np.random.default_rng(98)
+    views = _random_views(rng, F, B, 8, [(96, 64), (64, 48)])
+    ys, xs = np.nonzero((B > 0) & (B.astype(int) - F.astype(int) > 6))
+    for k in rng.choice(ys.size, 6, replace=False):
+        x, y = int(xs[k]), int(ys[k])
+        views.append(synth.perspective_view((x + 0.5, y + 0.5, (int(F[y, x]) + int(B[y, x])) / 2),
+                                            rng.uniform(0, 360), rng.uniform(-30, 10), 48, 32))
+    wo, do = oracle.render(F, B, T, views)
+    for mode in ("occupancy", "hier"):
+        wg, dg = gpu_render(ctx, views, mode)
+        assert_parity(wg, dg, wo, do, "cave map " + mode)
 
 
 def test_modes_identical_bytes(ctx):
@@ -333,6 +355,7 @@ def test_pyramid_matches_definition(ctx, shape):
     assert (1 << levels) >= max(W, H) > (1 << (levels - 1)) or max(W, H) == 1
     for L in range(1, levels + 1):
         assert np.array_equal(ctx.tc_read_pyramid(L), oracle.pyramid_level_fast(F, B, T, L)), L
+        assert np.array_equal(ctx.tc_read_occupancy(L), oracle.occupancy_level(F, B, T, L)), L
     f2, b2, t2 = ctx.tc_read_columns(0, 0, W, H)
     assert np.array_equal(f2, F) and np.array_equal(b2, B) and np.array_equal(t2, T)
 
@@ -349,10 +372,13 @@ def _edited_checks(ctx, F, B, T, edits, views, sample_rows=None):
     assert np.array_equal(g[0], F2) and np.array_equal(g[1], B2) and np.array_equal(g[2], T2)
     levels = ctx.tc_pyramid_info()
     pyr_edit = [ctx.tc_read_pyramid(L) for L in range(1, levels + 1)]
-    res_edit = {m: gpu_render(ctx, views, m) for m in ("hier", "persistent")}
+    occ_edit = [ctx.tc_read_occupancy(L) for L in range(1, levels + 1)]
+    res_edit = {m: gpu_render(ctx, views, m) for m in ("hier", "persistent", "occupancy")}
     load(ctx, F2, B2, T2)
     for L in range(1, levels + 1):
         assert np.array_equal(ctx.tc_read_pyramid(L), pyr_edit[L - 1]), L
+        assert np.array_equal(ctx.tc_read_occupancy(L), occ_edit[L - 1]), L
+        assert np.array_equal(occ_edit[L - 1], oracle.occupancy_level(F2, B2, T2, L)), L
     w_fresh, d_fresh = gpu_render(ctx, views, "hier")
     for m, (w, d) in res_edit.items():
         assert np.array_equal(w, w_fresh), m

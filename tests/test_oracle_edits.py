@@ -72,6 +72,38 @@ def test_pyramid_hand_case():
     assert p3[0, 0] == node(10, 9, 40)
 
 
+def test_occupancy_hand_case():
+    """Slabs [20, 25], [30, 31], [9, 40] as in the pyramid hand case: the
+    bands [4k, 4k+4] they meet are k = 4..6 ([20,25]: 16-20 touches 20,
+    20-24, 24-28), k = 7 ([30,31]: 28-32), k = 2..10 ([9,40]: 8-12 .. 40-44
+    touches 40).  A slab whose bottom sits on a band edge meets both
+    neighbours: [8, 8] sets k = 1 and 2."""
+    F = np.array([[1, 2, 3, 4, 5],
+                  [6, 7, 8, 9, 10],
+                  [0, 0, 0, 0, 0]], np.uint8)
+    B = np.zeros_like(F)
+    T = np.zeros_like(F)
+    B[0, 1], T[0, 1] = 20, 25
+    B[1, 4], T[1, 4] = 30, 31
+    B[2, 2], T[2, 2] = 9, 40
+    bits = lambda ks: sum(1 << k for k in ks)
+    m1 = oracle.occupancy_level(F, B, T, 1)
+    assert m1.shape == (2, 3) and m1.dtype == np.uint64
+    assert int(m1[0, 0]) == bits(range(4, 7))
+    assert int(m1[0, 1]) == 0
+    assert int(m1[0, 2]) == bits([7])
+    assert int(m1[1, 1]) == bits(range(2, 11))
+    assert int(m1[1, 0]) == 0 and int(m1[1, 2]) == 0
+    m2 = oracle.occupancy_level(F, B, T, 2)
+    assert int(m2[0, 0]) == bits(range(2, 11))
+    assert int(m2[0, 1]) == bits([7])
+    m3 = oracle.occupancy_level(F, B, T, 3)
+    assert int(m3[0, 0]) == bits(range(2, 11))
+    one = np.zeros((1, 1), np.uint8)
+    assert int(oracle.occupancy_level(one, one + 8, one + 8, 1)[0, 0]) == bits([1, 2])
+    assert int(oracle.occupancy_level(one, one + 1, one + 255, 1)[0, 0]) == (1 << 64) - 1
+
+
 def test_pyramid_two_definitions_agree():
     for seed, (W, H) in enumerate([(37, 23), (64, 64), (5, 130), (1, 1)]):
         F, B, T = synth.make_map(W, H, 500 + seed, dual=0.3, period=8)

@@ -280,6 +280,46 @@ def march_protocol(torch, tc, synth, steps, warmup):
             "per_pitch": per_pitch}
 
 
+CAVE_SEED = 6002          # the cave-heavy comparison map
+
+
+def occupancy_compare(torch, tc, synth, steps, warmup):
+    """The 2D min/max pyramid (render mode 0, with and without its split
+    pass) against the same walk with occupancy masks (mode 4): frame time
+    and node/cell reads per ray, on a cave-heavy 2048x2048 map (half the
+    cells two-layer) and on the headline 2048x2048 map."""
+    out = {}
+    cases = {"cave": synth.cave_map(CAVE_SEED, 2048, 2048),
+             "c2": synth.make_map_from_config(2)}
+    for name, (F, B, T) in cases.items():
+        ctx = tc.Context(0)
+        ctx.tc_load_columns(F, B, T)
+        views = ([synth.perspective_view(synth.eye_above_floor(F, B, 1024.5, 32.5), 0, 0, 1920, 1080),
+                  synth.perspective_view((1024.5, 600.5, 330.0), 0, -40, 1920, 1080)]
+                 if name == "cave" else synth.config_views(2, F, B))
+        rays = synth.view_rays(views)
+        buf = torch.empty((rays, 2), dtype=torch.int32, device="cuda")
+        res = {}
+        for label, mode, budget in (("pyramid_split", 0, 128), ("pyramid", 0, 0),
+                                    ("occupancy", 4, 0)):
+            ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, mode)
+            ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, budget)
+            ms, _ = time_renders(torch, ctx, tc, views, buf, steps, warmup)
+            ctx.tc_set_option(tc.TC_OPT_COUNT_READS, 1)
+            ctx.tc_read_counters()
+            ctx.tc_render_views(views, buf.data_ptr())
+            reads = ctx.tc_read_counters()
+            ctx.tc_set_option(tc.TC_OPT_COUNT_READS, 0)
+            res[label] = {"frame_ms_median": float(np.median(ms)),
+                          "grays_per_s": rays / (np.median(ms) * 1e-3) / 1e9,
+                          "reads_per_ray": reads / rays}
+        ctx.close()
+        out[name] = res
+    out["workload"] = ("2048x2048 cave-heavy map (50% two-layer), a 1920x1080 eye-level and "
+                       "a 1920x1080 oblique view; and the c2 headline view")
+    return out
+
+
 def c4_batched(torch, tc, synth, steps, warmup):
     """Configuration 4: 64 views of uneven sizes + 8 shadow passes + 16
     craters.  Plain: tc_apply_edit then one tc_render_views per view,
@@ -511,6 +551,9 @@ def main():
     if not args.no_march:
         log("[bench] sampled march on the protocol views")
         res["march_protocol"] = march_protocol(torch, tc, synth, 10, 2)
+    if not args.no_march:
+        log("[bench] 2D pyramid vs occupancy masks")
+        res["occupancy_compare"] = occupancy_compare(torch, tc, synth, 10, 2)
     if not args.no_growth:
         log("[bench] c3 edit frame")
         res["c3_frame"] = c3_frame(torch, tc, synth, 10, 2)

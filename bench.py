@@ -22,10 +22,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-MODES = {"hier": 0, "flat": 1, "persistent": 2, "march": 3}
-KERNEL_NAMES = {"hier": "render_kernel<false> + split_kernel (one traversal)",
-                "flat": "render_kernel<true>", "persistent": "render_persistent_kernel",
-                "march": "march_kernel"}
+MODES = {"hier": 0, "flat": 1, "persistent": 2, "march": 3, "occupancy": 4}
+KERNEL_NAMES = {"hier": "render_hier_kernel + split_kernel (one traversal)",
+                "flat": "render_flat_kernel", "persistent": "render_persistent_kernel",
+                "march": "march_kernel", "occupancy": "render_occ_kernel"}
 PROTOCOL_SEED = 6000      # poses of the twelve protocol views
 
 
@@ -454,8 +454,8 @@ def c5_served(torch, tc, synth, rates=(200, 500, 1000, 2000, 5000, 10000),
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--mode", default="hier", choices=list(MODES))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--extra", action="store_true",

@@ -9,11 +9,11 @@ namespace {
 
 // One thread per pixel; a wave casts one 8x8 pixel packet.
 // kOcc: node tests also consult the occupancy masks (render mode 4).
-template <bool kFlat, bool kOcc = false>
-__global__ __launch_bounds__(256) void render_kernel(
-    tci_map m, const tci_view* __restrict__ views, int32_t nviews,
+template <bool kFlat, bool kOcc>
+__device__ __forceinline__ void render_body(
+    const tci_map& m, const tci_view* __restrict__ views, int32_t nviews,
     const int64_t* __restrict__ pkt_prefix, int64_t npkt, void* out,
-    tci_render_opts o) {
+    const tci_render_opts& o) {
   __shared__ lvl_t lv[TCI_MAX_LEVELS];
   __shared__ uint32_t moff[kOcc ? TCI_MAX_LEVELS : 1];
   if constexpr (kOcc) load_levels_occ(m, lv, moff);
@@ -54,8 +54,11 @@ __global__ __launch_bounds__(256) void render_kernel(
     bool split = !kFlat && o.split_budget > 0 && o.qcap > 0;
     int32_t st;
     for (;;) {
-      st = walk_steps<false, kOcc>(m, lv, r, s, Lmax, split ? o.split_budget : kIterCap + 1,
-                                   col, boost, 0, 0, 0, moff);
+      // the budget bounds the walk: at most the split budget, then (or
+      // without a split pass) kIterCap + 1 iterations
+      st = walk_steps<false, kOcc, false>(m, lv, r, s, Lmax,
+                                          split ? o.split_budget : kIterCap + 1, col, boost,
+                                          0, 0, 0, moff, o.count != nullptr);
       if (!split) break;
       split = false;
       // long walks go to the split pass, as many as the queue holds
@@ -73,7 +76,11 @@ __global__ __launch_bounds__(256) void render_kernel(
         // the walk has reached the current node: the second pass need only
         // split the path from the node's near line on the dominant axis
         const bool ax_x = r.ax >= r.ay;
-        const int32_t n = ax_x ? s.ni : s.nj, c0 = ax_x ? r.cx0 : r.cy0;
+        // the start cell's line, selected here: selected before the walk it
+        // would hold one more register through it
+        int32_t cx = r.cx0, cy = r.cy0;
+        asm volatile("" : "+v"(cx), "+v"(cy));
+        const int32_t n = ax_x ? s.ni : s.nj, c0 = ax_x ? cx : cy;
         const bool fwd = (ax_x ? r.Dx : r.Dy) > 0;
         const int32_t near = fwd ? (n << s.L) : ((n + 1) << s.L) - 1;
         const int32_t from = fwd ? max(near, c0) : min(near, c0);
@@ -83,10 +90,39 @@ __global__ __launch_bounds__(256) void render_kernel(
         return;
       }
     }
+    if (st == kWalking) st = kCapped;   // the whole budget ran out (never expected)
+    // the origin is needed again only here: recompute it from the view
+    // rather than keep it in registers through the walk
+    pixel_ray(v, px, py, r);
     finish(r, s, m.W, st, col, word, depth);
     if (o.count) atomicAdd(o.count, (unsigned long long)s.reads);
   }
   store_hit(out, v.out_base + (int64_t)py * v.w + px, word, depth);
+}
+
+// The three one-thread-per-pixel kernels.  The hierarchical one is asked
+// for 7 waves per SIMD (at most 72 VGPRs): it is bound by instruction issue,
+// and the extra wave hides more of the walk's load latency; the only value
+// the limit moves to scratch is used once, at split-pass enqueue.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8)))
+void render_hier_kernel(tci_map m, const tci_view* __restrict__ views, int32_t nviews,
+                        const int64_t* __restrict__ pkt_prefix, int64_t npkt, void* out,
+                        tci_render_opts o) {
+  render_body<false, false>(m, views, nviews, pkt_prefix, npkt, out, o);
+}
+
+__global__ __launch_bounds__(256)
+void render_flat_kernel(tci_map m, const tci_view* __restrict__ views, int32_t nviews,
+                        const int64_t* __restrict__ pkt_prefix, int64_t npkt, void* out,
+                        tci_render_opts o) {
+  render_body<true, false>(m, views, nviews, pkt_prefix, npkt, out, o);
+}
+
+__global__ __launch_bounds__(256)
+void render_occ_kernel(tci_map m, const tci_view* __restrict__ views, int32_t nviews,
+                       const int64_t* __restrict__ pkt_prefix, int64_t npkt, void* out,
+                       tci_render_opts o) {
+  render_body<false, true>(m, views, nviews, pkt_prefix, npkt, out, o);
 }
 
 // Dominant-axis cell line where the ray leaves the map's columns, or rises
@@ -264,13 +300,13 @@ hipError_t tci_launch_render(const tci_map& m, const tci_view* views,
   int64_t blocks = (npkt + 3) / 4;
   if (blocks < 1) return hipSuccess;
   if (flat == 1)
-    hipLaunchKernelGGL(render_kernel<true>, dim3((uint32_t)blocks), dim3(256),
+    hipLaunchKernelGGL(render_flat_kernel, dim3((uint32_t)blocks), dim3(256),
                        0, s, m, views, nviews, pkt_prefix, npkt, out, o);
   else if (flat == 2)
-    hipLaunchKernelGGL((render_kernel<false, true>), dim3((uint32_t)blocks), dim3(256),
+    hipLaunchKernelGGL(render_occ_kernel, dim3((uint32_t)blocks), dim3(256),
                        0, s, m, views, nviews, pkt_prefix, npkt, out, o);
   else
-    hipLaunchKernelGGL(render_kernel<false>, dim3((uint32_t)blocks),
+    hipLaunchKernelGGL(render_hier_kernel, dim3((uint32_t)blocks),
                        dim3(256), 0, s, m, views, nviews, pkt_prefix, npkt,
                        out, o);
   return hipGetLastError();

@@ -349,19 +349,24 @@ __device__ __forceinline__ void lift(const ray_t& r, walk_t& s, int32_t L) {
 // the many short ones sharing their SIMD.
 // With kSeg the walk also stops (kSegEnd) once its node lies wholly
 // outside the cell lines [seg_lo, seg_hi] of axis seg_axis (0 x, 1 y).
+// With kCap every call counts the walk's iterations in s.iters and stops
+// (kCapped) past kIterCap, a guard for callers that resume a walk without
+// bound; a caller whose budget already bounds the walk passes false.  With
+// count false, s.reads is left alone.
 // With kOcc, a node that only the slab test keeps is also tested against
 // its occupancy mask (moff: the mask levels' word offsets, in LDS): the
 // ray's height range over the node, widened by two units to cover the
 // rounding of its float estimate, must meet an occupied band, or the ray
 // passes between the node's slabs and the node is skipped.
-template <bool kSeg = false, bool kOcc = false>
+template <bool kSeg = false, bool kOcc = false, bool kCap = true>
 __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
                                               const ray_t& r, walk_t& s,
                                               int32_t max_level, int32_t budget,
                                               uint32_t& col, int32_t boost = 0,
                                               int32_t seg_axis = 0,
                                               int32_t seg_lo = 0, int32_t seg_hi = 0,
-                                              const uint32_t* moff = nullptr) {
+                                              const uint32_t* moff = nullptr,
+                                              bool count = true) {
   const bool desc = r.Dz < 0;
   const int32_t sx = r.Dx > 0 ? 1 : -1, sy = r.Dy > 0 ? 1 : -1;
   const int32_t nearx = r.Dx > 0 ? 0 : 1, neary = r.Dy > 0 ? 0 : 1;
@@ -371,7 +376,9 @@ __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
       else if (it == 2 * boost) __builtin_amdgcn_s_setprio(2);
       else if (it == 4 * boost) __builtin_amdgcn_s_setprio(3);
     }
-    if (++s.iters > kIterCap) return kCapped;
+    if constexpr (kCap) {
+      if (++s.iters > kIterCap) return kCapped;
+    }
     const int32_t L = s.L;
     if (kSeg) {
       const int32_t n = seg_axis == 0 ? s.ni : s.nj;
@@ -380,7 +387,7 @@ __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
     const lvl_t l = lv[L];
     const bool inmap = (uint32_t)s.ni < (uint32_t)l.w && (uint32_t)s.nj < (uint32_t)l.h;
     uint32_t v = 0;
-    s.reads += inmap ? 1 : 0;
+    if (count) s.reads += inmap ? 1 : 0;
     if (inmap)
       v = m.base[l.off + ((__umul24((uint32_t)s.nj >> 3, (uint32_t)l.tiles_x) +
                            ((uint32_t)s.ni >> 3)) << 6) +
@@ -406,7 +413,7 @@ __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
                               ((((uint32_t)(s.nj & 7) << 3) + (uint32_t)(s.ni & 7)) << 1);
           const uint2 mw = *reinterpret_cast<const uint2*>(m.base + mi);
           const uint64_t mask = (uint64_t)mw.x | ((uint64_t)mw.y << 32);
-          s.reads += 2;
+          if (count) s.reads += 2;
           const float zl = (float)lo / (float)Dlo - 2.0f;
           const float zh = (float)hi / (float)Dhi + 2.0f;
           const int32_t kl = min(max((int32_t)floorf(zl * 0.25f), 0), 63);

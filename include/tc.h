@@ -313,8 +313,9 @@ void tc_frame_destroy(tc_frame *frame);
 /* ---- autotuning ----------------------------------------------------------- */
 /* Time tc_render_views on these views (reps timed calls per setting, median)
  * over a grid of the render knobs -- traversal mode, start level, packet
- * order, XCD grouping, and the persistent queue's waves per CU, refill
- * threshold and refill interval -- then keep the fastest setting on the
+ * order, XCD grouping, split budget (0 or 128), and the persistent queue's
+ * waves per CU, refill threshold and refill interval -- then keep the
+ * fastest setting on the
  * context and report it.  Results are those of tc_render_views for every
  * setting (bit-identical); only the time differs.  Synchronises
  * hip_stream.  The paper picks each method's knob by a sweep on a fixed
@@ -324,6 +325,7 @@ typedef struct tc_tune_result {
   int32_t persist_waves, refill_min, refill_iters;
   float ms;      /* median time per call of the chosen setting */
   int32_t tried; /* settings timed */
+  int32_t split_budget;
 } tc_tune_result;
 tc_status tc_autotune(tc_context *ctx, const tc_view *views, int32_t n,
                       tc_hit *out_device, int32_t reps, void *hip_stream,

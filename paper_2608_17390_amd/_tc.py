@@ -71,7 +71,7 @@ class tc_tune_result(ctypes.Structure):
                 ("tile_order", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
                 ("persist_waves", ctypes.c_int32), ("refill_min", ctypes.c_int32),
                 ("refill_iters", ctypes.c_int32), ("ms", ctypes.c_float),
-                ("tried", ctypes.c_int32)]
+                ("tried", ctypes.c_int32), ("split_budget", ctypes.c_int32)]
 
 
 class tc_shade_params(ctypes.Structure):

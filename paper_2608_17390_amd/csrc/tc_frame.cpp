@@ -42,7 +42,7 @@ void frame_free(tc_frame* f) {
 }
 
 struct Knobs {
-  int32_t mode, start, order, remap, waves, rmin, riters;
+  int32_t mode, start, order, remap, waves, rmin, riters, split;
 };
 
 void apply_knobs(tc_context* c, const Knobs& k) {
@@ -53,11 +53,12 @@ void apply_knobs(tc_context* c, const Knobs& k) {
   c->persist_waves = k.waves;
   c->refill_min = k.rmin;
   c->refill_iters = k.riters;
+  c->split_budget = k.split;
 }
 
 Knobs read_knobs(const tc_context* c) {
   return Knobs{c->render_mode, c->start_level, c->tile_order, c->xcd_remap,
-               c->persist_waves, c->refill_min, c->refill_iters};
+               c->persist_waves, c->refill_min, c->refill_iters, c->split_budget};
 }
 
 }  // namespace
@@ -169,10 +170,11 @@ tc_status tc_autotune(tc_context* ctx, const tc_view* views, int32_t n,
     hipStream_t s = (hipStream_t)hip_stream;
     std::vector<Knobs> cand;
     const Knobs cur = read_knobs(ctx);
-    for (int32_t order : {0, 1, 2})
-      for (int32_t remap : {0, 2, 8})
-        for (int32_t start : {1, 2, 3, 4})
-          cand.push_back(Knobs{0, start, order, remap, cur.waves, cur.rmin, cur.riters});
+    for (int32_t split : {0, 128})
+      for (int32_t order : {0, 1, 2})
+        for (int32_t remap : {0, 2, 8})
+          for (int32_t start : {1, 2, 3, 4})
+            cand.push_back(Knobs{0, start, order, remap, cur.waves, cur.rmin, cur.riters, split});
     std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
     for (auto& e : ev) TC_HIP(hipEventCreate(&e), "hipEventCreate");
     auto time_knobs = [&](const Knobs& k, float* med) -> tc_status {
@@ -209,7 +211,7 @@ tc_status tc_autotune(tc_context* ctx, const tc_view* views, int32_t n,
       for (int32_t rmin : {8, 16, 32})
         for (int32_t riters : {16, 64}) {
           if (st) break;
-          Knobs k{2, bk.start, bk.order, bk.remap, waves, rmin, riters};
+          Knobs k{2, bk.start, bk.order, bk.remap, waves, rmin, riters, bk.split};
           float m;
           st = time_knobs(k, &m);
           if (st) break;
@@ -229,6 +231,7 @@ tc_status tc_autotune(tc_context* ctx, const tc_view* views, int32_t n,
     best->persist_waves = bk.waves;
     best->refill_min = bk.rmin;
     best->refill_iters = bk.riters;
+    best->split_budget = bk.split;
     best->ms = bms;
     best->tried = tried;
     return TC_OK;

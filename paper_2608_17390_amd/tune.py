@@ -8,7 +8,7 @@ from . import _tc
 OPTS = {"render_mode": _tc.TC_OPT_RENDER_MODE, "start_level": _tc.TC_OPT_START_LEVEL,
         "tile_order": _tc.TC_OPT_TILE_ORDER, "xcd_remap": _tc.TC_OPT_XCD_REMAP,
         "persist_waves": _tc.TC_OPT_PERSIST_WAVES, "refill_min": _tc.TC_OPT_REFILL_MIN,
-        "refill_iters": _tc.TC_OPT_REFILL_ITERS}
+        "refill_iters": _tc.TC_OPT_REFILL_ITERS, "split_budget": _tc.TC_OPT_SPLIT_BUDGET}
 
 
 def default_cache_path():
@@ -35,7 +35,7 @@ def autotune(ctx, views, out_ptr, workload, cache_path=None, reps=5, force=False
             cache = json.load(open(path))
         except ValueError:
             cache = {}
-    if key in cache and not force:
+    if key in cache and not force and all(k in cache[key] for k in OPTS):
         knobs = cache[key]
         for k, opt in OPTS.items():
             ctx.tc_set_option(opt, knobs[k])

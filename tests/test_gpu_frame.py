@@ -87,8 +87,10 @@ def test_autotune_keeps_results(ctx):
     ref = gpu_render(ctx, views, "hier")
     out = _outbuf(views)
     best = ctx.tc_autotune(views, out.data_ptr(), reps=2)
-    assert best["tried"] >= 24 and best["ms"] > 0
+    assert best["tried"] >= 72 and best["ms"] > 0
     assert best["render_mode"] in (0, 2)
+    assert best["split_budget"] in (0, 128)
+    assert ctx.tc_get_option(tc.TC_OPT_SPLIT_BUDGET) == best["split_budget"]
     assert ctx.tc_get_option(tc.TC_OPT_RENDER_MODE) == best["render_mode"]
     out2 = tc.render(ctx, views)
     torch.cuda.synchronize()
@@ -98,6 +100,7 @@ def test_autotune_keeps_results(ctx):
     ctx.tc_set_option(tc.TC_OPT_START_LEVEL, 2)
     ctx.tc_set_option(tc.TC_OPT_TILE_ORDER, 2)
     ctx.tc_set_option(tc.TC_OPT_XCD_REMAP, 0)
+    ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 128)
 
 
 def test_c4_frame_sampled(ctx):

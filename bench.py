@@ -70,20 +70,26 @@ def calib_copy(torch, mib=256, reps=3):
 
 
 def time_renders(torch, ctx, tc, views, out, steps, warmup):
-    """Per-step HIP event timings (ms) of tc_render_views on the current
-    stream, plus the bracketed wall time of all timed steps."""
+    """The timed region: `steps` back-to-back tc_render_views calls on the
+    current stream, bracketed by synchronisations (wall time); then as many
+    again with HIP events around each call (per-step ms, for the median and
+    p99).  Views are converted to C structures once, outside both."""
+    vs = tc.views_struct(views)
     for _ in range(warmup):
-        ctx.tc_render_views(views, out.data_ptr())
+        ctx.tc_render_views(vs, out.data_ptr())
     torch.cuda.synchronize()
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     t0 = time.perf_counter()
-    for k in range(steps):
-        starts[k].record()
-        ctx.tc_render_views(views, out.data_ptr())
-        ends[k].record()
+    for _ in range(steps):
+        ctx.tc_render_views(vs, out.data_ptr())
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    for k in range(steps):
+        starts[k].record()
+        ctx.tc_render_views(vs, out.data_ptr())
+        ends[k].record()
+    torch.cuda.synchronize()
     ms = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
     return ms, wall
 
@@ -93,8 +99,9 @@ def kernel_times(torch, ctx, tc, views, out, steps):
     from the HIP events the library records around its kernels."""
     ctx.tc_set_option(tc.TC_OPT_KERNEL_TIMING, 1)
     rows = []
+    vs = tc.views_struct(views)
     for _ in range(steps):
-        ctx.tc_render_views(views, out.data_ptr())
+        ctx.tc_render_views(vs, out.data_ptr())
         rows.append(ctx.tc_read_kernel_times())
     ctx.tc_set_option(tc.TC_OPT_KERNEL_TIMING, 0)
     torch.cuda.synchronize()

@@ -5,7 +5,7 @@ include/tc.h); this package holds its sources (csrc/), its build step
 (build.py) and a thin ctypes binding (_tc.py) with the same names.
 """
 from ._tc import (Context, Frame, Server, TCError, tc_create, tc_view, tc_edit, render,
-                  split_hits, view_total_rays, view_struct, edits_struct, load_library, LIB_PATH,
+                  split_hits, view_total_rays, view_struct, views_struct, edits_struct, load_library, LIB_PATH,
                   SIGNATURES, TC_OK, TC_INVALID_ARG, TC_OUT_OF_MEMORY,
                   TC_NO_MAP, TC_DEVICE_ERROR, TC_OVER_BUDGET, TC_TIMEOUT,
                   TC_SERVER_AUTO_RELEASE, TC_MISS,

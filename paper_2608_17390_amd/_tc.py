@@ -185,10 +185,24 @@ def _stream_handle(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+# numpy layout of tc_view (84 bytes, the field order of the C struct)
+_VIEW_NP = np.dtype([("width", "<i4"), ("height", "<i4"), ("o0", "<i4", 3),
+                     ("o_px", "<i4", 3), ("o_py", "<i4", 3), ("d0", "<i4", 3),
+                     ("d_px", "<i4", 3), ("d_py", "<i4", 3), ("flags", "<u4")])
+
+
 def _views_struct(views):
-    from numpy.lib import recfunctions  # noqa: F401
+    """ctypes array of tc_view: an existing one as is, a numpy structured
+    array (or list of records) with the tc_view fields copied in one go."""
+    if isinstance(views, ctypes.Array) and views._type_ is tc_view:
+        return views
     a = np.asarray(views)
     a = a.reshape(-1)
+    if a.dtype.names is not None and set(a.dtype.names) == set(_VIEW_NP.names):
+        b = np.zeros(len(a), _VIEW_NP)
+        for f in _VIEW_NP.names:
+            b[f] = a[f]
+        return (tc_view * len(b)).from_buffer_copy(b.tobytes())
     arr = (tc_view * len(a))()
     for i, v in enumerate(a):
         t = arr[i]
@@ -490,6 +504,11 @@ class Server:
 def view_struct(view):
     """Prebuilt C view structure (for low-overhead repeated submission)."""
     return _views_struct([view])
+
+
+def views_struct(views):
+    """Prebuilt C array of several views, accepted wherever views are."""
+    return _views_struct(views)
 
 
 def edits_struct(edits):

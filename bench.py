@@ -123,9 +123,15 @@ def cpu_baseline(oracle, F, B, T, views, rays_per_frame, budget_s=12.0):
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
+    # one thread, on every 8th row of the same view (about 4 s)
+    t1 = time.perf_counter()
+    w, _ = oracle.render(F, B, T, views, threads=1, rows=(0, 1 << 30, 8))
+    dt1 = time.perf_counter() - t1
     return {"value": done * rays_per_frame / dt / 1e9, "unit": "Grays/s",
             "cores": cores, "kind": "oracle",
-            "sample": "%d full renders of the 1920x1080 headline view (%.1f s)" % (done, dt)}
+            "sample": "%d full renders of the 1920x1080 headline view (%.1f s)" % (done, dt),
+            "single_thread_value": w.size / dt1 / 1e9,
+            "single_thread_sample": "every 8th row of the same view on one thread (%.1f s)" % dt1}
 
 
 def c3_frame(torch, tc, synth, steps, warmup):

@@ -3,6 +3,7 @@ declares (no GPU needed, no compute calls)."""
 import ctypes
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -57,3 +58,22 @@ def test_create_fails_cleanly_without_device():
     st = tc.load_library().tc_create(0, ctypes.byref(h))
     assert st == tc.TC_DEVICE_ERROR
     assert tc.load_library().tc_last_error(None)
+
+
+def build_c_consumer(out_path):
+    """Compile tests/c/consumer.c, a plain C99 program that uses the library
+    through include/tc.h only, against the in-tree libtc.so."""
+    libdir = os.path.dirname(tc.LIB_PATH)
+    cmd = ["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-D__HIP_PLATFORM_AMD__",
+           "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "include"), "-o", out_path,
+           os.path.join(ROOT, "tests", "c", "consumer.c"), "-L" + libdir, "-ltc",
+           "-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath," + libdir, "-Wl,-rpath,/opt/rocm/lib"]
+    subprocess.run(cmd, check=True, capture_output=True, timeout=120)
+    return out_path
+
+
+def test_header_is_plain_c_and_links(tmp_path):
+    """The header compiles as C99 with warnings as errors, and a C program
+    links against the library."""
+    exe = build_c_consumer(str(tmp_path / "consumer"))
+    assert os.path.exists(exe)

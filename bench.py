@@ -546,7 +546,7 @@ def main():
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                      "traffic": traffic_from_profile(
                          [os.path.join(ROOT, "paper_2608_17390_amd", "csrc", f)
-                          for f in ("tc_walk.h", "tc_render.hip")]),
+                          for f in ("tc_walk.h", "tc_beam.h", "tc_packet.h", "tc_render.hip")]),
                      "kernel": KERNEL_NAMES[args.mode],
                      "alg_bytes_per_launch": alg_bytes,
                      "kernel_ms_avg": kavg,

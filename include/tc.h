@@ -258,6 +258,18 @@ tc_status tc_shade_views(tc_context *ctx, const tc_view *views, int32_t n,
 #define TC_OPT_SPLIT_QUEUE 12    /* most rays the second pass takes per call;
                                     further long rays finish in the first
                                     pass (default 131072) */
+#define TC_OPT_BEAM_PASSES 17    /* render modes 0 and 4: before walking, the
+                                    64 rays of each 8x8 pixel packet find a
+                                    common start parameter t such that none
+                                    of them meets solid in [0, t], by testing
+                                    bounding boxes of the packet's ray bundle
+                                    over 64 intervals at a time against the
+                                    min/max pyramid, at most this many times
+                                    (Section 3.2's skip of empty space, for a
+                                    bundle); each ray then walks exactly from
+                                    the last cell line it enters before t, so
+                                    results are unchanged (0: rays start at
+                                    the eye; 0..64, default 4) */
 /* Render mode 3 is the paper's sampled ray march (Section 3.1, RAYMARCH),
  * not an exact cast.  Per pixel the segment from the eye ends at the far
  * limit (TC_OPT_MARCH_FAR world units along the ray) or where the ray
@@ -314,7 +326,8 @@ void tc_frame_destroy(tc_frame *frame);
 /* Time tc_render_views on these views (reps timed calls per setting, median)
  * over a grid of the render knobs -- traversal mode, start level, packet
  * order, XCD grouping, split budget (0 or 128), and the persistent queue's
- * waves per CU, refill threshold and refill interval -- then keep the
+ * waves per CU, refill threshold and refill interval, then the packet beam
+ * passes (0, 2, 4 or 8) of the best one-thread-per-pixel setting -- then keep the
  * fastest setting on the
  * context and report it.  Results are those of tc_render_views for every
  * setting (bit-identical); only the time differs.  Synchronises
@@ -326,6 +339,7 @@ typedef struct tc_tune_result {
   float ms;      /* median time per call of the chosen setting */
   int32_t tried; /* settings timed */
   int32_t split_budget;
+  int32_t beam_passes;
 } tc_tune_result;
 tc_status tc_autotune(tc_context *ctx, const tc_view *views, int32_t n,
                       tc_hit *out_device, int32_t reps, void *hip_stream,

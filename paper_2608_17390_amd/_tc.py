@@ -23,7 +23,17 @@ TC_OVER_BUDGET = -5
 TC_TIMEOUT = -6
 TC_SERVER_AUTO_RELEASE = 1
 TC_S = 65536
+TC_MAX_DIM = 16384
+TC_MAX_CELLS = 1 << 27
+TC_MAX_DIR = (1 << 23) - 1
 TC_MISS = 0xFFFFFFFF
+TC_FACE_TOP = 1
+TC_FACE_UNDER = 2
+TC_FACE_WMX = 3
+TC_FACE_WPX = 4
+TC_FACE_WMY = 5
+TC_FACE_WPY = 6
+TC_FACE_INSIDE = 7
 TC_EDIT_SET = 1
 TC_EDIT_CRATER = 2
 
@@ -43,6 +53,7 @@ TC_OPT_KERNEL_TIMING = 13
 TC_OPT_MARCH_STEPS = 14
 TC_OPT_MARCH_BISECT = 15
 TC_OPT_MARCH_FAR = 16
+TC_OPT_BEAM_PASSES = 17
 TC_FACE_SAMPLED = 0
 
 _STATUS = {0: "TC_OK", -1: "TC_INVALID_ARG", -2: "TC_OUT_OF_MEMORY",
@@ -71,7 +82,8 @@ class tc_tune_result(ctypes.Structure):
                 ("tile_order", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
                 ("persist_waves", ctypes.c_int32), ("refill_min", ctypes.c_int32),
                 ("refill_iters", ctypes.c_int32), ("ms", ctypes.c_float),
-                ("tried", ctypes.c_int32), ("split_budget", ctypes.c_int32)]
+                ("tried", ctypes.c_int32), ("split_budget", ctypes.c_int32),
+                ("beam_passes", ctypes.c_int32)]
 
 
 class tc_shade_params(ctypes.Structure):

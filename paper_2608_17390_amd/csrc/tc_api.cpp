@@ -115,6 +115,7 @@ tci_render_opts render_opts(const tc_context* c) {
   o.rows = nullptr;
   o.boost = c->boost;
   o.split_budget = 0;
+  o.beam_passes = c->beam_passes;
   o.qcap = 0;
   o.queue = nullptr;
   o.qcount = nullptr;
@@ -690,6 +691,10 @@ tc_status tc_set_option(tc_context* ctx, int32_t key, int64_t value) {
       if (value < 0 || value > (1 << 20)) break;
       ctx->split_budget = (int32_t)value;
       return TC_OK;
+    case TC_OPT_BEAM_PASSES:
+      if (value < 0 || value > 64) break;
+      ctx->beam_passes = (int32_t)value;
+      return TC_OK;
     case TC_OPT_SPLIT_QUEUE:
       if (value < 1 || value > (1 << 26)) break;
       ctx->split_queue = (int32_t)value;
@@ -751,6 +756,7 @@ tc_status tc_get_option(const tc_context* ctx, int32_t key, int64_t* value) {
     case TC_OPT_PRIORITY_BOOST: *value = ctx->boost; return TC_OK;
     case TC_OPT_SPLIT_BUDGET: *value = ctx->split_budget; return TC_OK;
     case TC_OPT_SPLIT_QUEUE: *value = ctx->split_queue; return TC_OK;
+    case TC_OPT_BEAM_PASSES: *value = ctx->beam_passes; return TC_OK;
     case TC_OPT_KERNEL_TIMING: *value = ctx->kernel_timing; return TC_OK;
     case TC_OPT_MARCH_STEPS: *value = ctx->march_steps; return TC_OK;
     case TC_OPT_MARCH_BISECT: *value = ctx->march_bisect; return TC_OK;

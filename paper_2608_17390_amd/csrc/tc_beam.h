@@ -1,0 +1,172 @@
+// Packet beam: a conservative common start for the rays of one 8 x 8 pixel
+// packet (one wave), so that each ray's exact walk begins where solid can
+// first be near instead of at the eye.
+//
+// A packet's rays are P(a, b, t) = O(a, b) + t D(a, b) with O and D affine in
+// the pixel coordinates a = 2 px + 1, b = 2 py + 1.  At a fixed t each
+// coordinate is therefore affine in (a, b): over the packet's pixel
+// rectangle it lies within
+//   centre(t) +- (ha |dO/da + t dD/da| + hb |dO/db + t dD/db|)
+// (ha, hb the half-spans of a and b), and for t >= 0 the extent is at most
+// e0 + t e1 with e0 = ha |dO/da| + hb |dO/db|, e1 = ha |dD/da| + hb |dD/db|.
+// Both bounds are then linear in t, so over a parameter interval [t0, t1]
+// their extremes are at its ends.  The box they give, widened by a margin
+// that covers the single-precision rounding, is tested against the
+// min/max pyramid: at the level whose nodes are wider than the box it
+// overlaps at most 2 x 2 nodes, and if its height range lies above every
+// node's fmax and outside every node's [smin, smax], no ray of the packet
+// meets solid during [t0, t1] (the node test of the walk, applied to a
+// bundle of rays; Section 3.2's skip of empty space).
+//
+// The 64 lanes test 64 consecutive intervals at once, of geometrically
+// growing length, starting at the current start; the start moves to the
+// first interval that could not be cleared and the search repeats from
+// there with short intervals, at most `passes` times.  Each ray then begins
+// its walk on the last cell line of its dominant axis that it enters no
+// later than that start, in the exact state the full walk would enter it
+// with (seg_init), so every hit record is unchanged.
+#pragma once
+
+#include "tc_walk.h"
+
+namespace {
+
+constexpr float kBeamFirst = 0.5f;           // first interval: cells along the centre ray
+constexpr float kBeamGrowth = 0.125f;        // each interval 1/8 longer than the last
+constexpr float kBeamLog2Growth = 0.169925f; // log2(1 + kBeamGrowth)
+
+// Could solid lie in the box [lox, hix] x [loy, hiy] x [loz, hiz] (cells,
+// height units)?  Reads at most four nodes, counted in `reads`.
+__device__ __forceinline__ bool beam_box_solid(const tci_map& m, const lvl_t* lv, float lox,
+                                               float hix, float loy, float hiy, float loz,
+                                               float hiz, int32_t& reads) {
+  if (loz > 255.0f) return false;               // above every height
+  const float ext = fmaxf(hix - lox, hiy - loy);
+  if (!(ext < 65536.0f)) return true;           // no claim for huge or NaN boxes
+  // 2^L > ext: the box overlaps at most two nodes per axis at level L
+  int32_t L = ext < 1.0f ? 0 : __builtin_amdgcn_frexp_expf(ext);
+  L = min(L, m.top);
+  const float lim = 1048576.0f;
+  const int32_t x0 = (int32_t)floorf(fminf(fmaxf(lox, -lim), lim)) >> L;
+  const int32_t x1 = (int32_t)floorf(fminf(fmaxf(hix, -lim), lim)) >> L;
+  const int32_t y0 = (int32_t)floorf(fminf(fmaxf(loy, -lim), lim)) >> L;
+  const int32_t y1 = (int32_t)floorf(fminf(fmaxf(hiy, -lim), lim)) >> L;
+  if (x1 - x0 > 1 || y1 - y0 > 1) return true;  // wider than the top level's nodes
+  const lvl_t l = lv[L];
+  const int32_t i0 = max(x0, 0), i1 = min(x1, l.w - 1);
+  const int32_t j0 = max(y0, 0), j1 = min(y1, l.h - 1);
+  if (i0 > i1 || j0 > j1) return false;         // beside the map: air
+  const tci_level tl{l.off, l.w, l.h, l.tiles_x};
+  const uint32_t w00 = m.base[tci_tile_index(tl, i0, j0)];
+  const uint32_t w10 = m.base[tci_tile_index(tl, i1, j0)];
+  const uint32_t w01 = m.base[tci_tile_index(tl, i0, j1)];
+  const uint32_t w11 = m.base[tci_tile_index(tl, i1, j1)];
+  reads += 1 + (i1 != i0) + (j1 != j0) + (i1 != i0 && j1 != j0);
+  const uint32_t fmax = max(max(w00 & 0xFF, w10 & 0xFF), max(w01 & 0xFF, w11 & 0xFF));
+  const uint32_t smin = min(min((w00 >> 8) & 0xFF, (w10 >> 8) & 0xFF),
+                            min((w01 >> 8) & 0xFF, (w11 >> 8) & 0xFF));
+  const uint32_t smax = max(max((w00 >> 16) & 0xFF, (w10 >> 16) & 0xFF),
+                            max((w01 >> 16) & 0xFF, (w11 >> 16) & 0xFF));
+  // a column with no slab has smin = smax = 0, which the floor test covers
+  return loz <= (float)fmax || (loz <= (float)smax && hiz >= (float)smin);
+}
+
+// Parameter t >= 0 such that no ray of the packet whose tile is (tx, ty)
+// meets solid during [0, t].  Called by all 64 lanes of the wave together
+// (it uses ballots); `reads` gains the nodes this lane read.
+__device__ __forceinline__ float beam_start(const tci_map& m, const lvl_t* lv, const tci_view& v,
+                                            int32_t tx, int32_t ty, int32_t passes,
+                                            int32_t lane, int32_t& reads) {
+  const int32_t px0 = tx * 8, py0 = ty * 8;
+  const int32_t px1 = min(px0 + 7, v.w - 1), py1 = min(py0 + 7, v.h - 1);
+  // centre and half-spans of a and b over the packet's pixels
+  const int64_t ac = px0 + px1 + 1, bc = py0 + py1 + 1;
+  const float ha = (float)(px1 - px0), hb = (float)(py1 - py0);
+  const float inv = 1.0f / 65536.0f;
+  // per coordinate, the bundle lies within lo(t) = A + t B, hi(t) = A' + t B'
+  // for t >= 0: the centre ray oc + t dc plus or minus the extent bound
+  // ha |opx + t dpx| + hb |opy + t dpy| <= e0 + t e1 (all over S); both
+  // bounds are linear, so their extremes over an interval are at its ends
+  float A[3], Bv[3], Ah[3], Bh[3], len2 = 0.0f;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    // the centre ray in exact integers first: the view's corner rays fit
+    // in 32 bits, the centre lies between them
+    const float oc = (float)((int64_t)v.o0[c] + ac * v.opx[c] + bc * v.opy[c]) * inv;
+    const float dc = (float)((int64_t)v.d0[c] + ac * v.dpx[c] + bc * v.dpy[c]) * inv;
+    const float e0 = (ha * fabsf((float)v.opx[c]) + hb * fabsf((float)v.opy[c])) * inv;
+    const float e1 = (ha * fabsf((float)v.dpx[c]) + hb * fabsf((float)v.dpy[c])) * inv;
+    A[c] = oc - e0;
+    Bv[c] = dc - e1;
+    Ah[c] = oc + e0;
+    Bh[c] = dc + e1;
+    len2 += dc * dc;
+  }
+  const float len = sqrtf(len2);
+  if (!(len > 0.0f)) return 0.0f;
+  const float u = kBeamFirst / len;
+  // lane k covers [ta + u g(k), ta + u g(k + 1)], g(k) = ((1 + r)^k - 1) / r;
+  // lane k's end and lane k + 1's start are the same float (same inputs,
+  // same operations), so the intervals leave no gap
+  const float g0 = (exp2f((float)lane * kBeamLog2Growth) - 1.0f) * (1.0f / kBeamGrowth);
+  const float g1 = (exp2f((float)(lane + 1) * kBeamLog2Growth) - 1.0f) * (1.0f / kBeamGrowth);
+  float ta = 0.0f;
+  for (int32_t pass = 0; pass < passes; ++pass) {
+    const float t0 = fmaf(u, g0, ta), t1 = fmaf(u, g1, ta);
+    float lo[3], hi[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float l = fminf(fmaf(t0, Bv[c], A[c]), fmaf(t1, Bv[c], A[c]));
+      const float h = fmaxf(fmaf(t0, Bh[c], Ah[c]), fmaf(t1, Bh[c], Ah[c]));
+      // rounding of the view's values, the bounds and their images: a few
+      // units in the last place of values below 2^16, plus an absolute
+      // sixteenth of a cell
+      const float mg = fmaf(fabsf(l) + fabsf(h), 0x1p-18f, 0.0625f);
+      lo[c] = l - mg;
+      hi[c] = h + mg;
+    }
+    const bool solid =
+        beam_box_solid(m, lv, lo[0], hi[0], lo[1], hi[1], lo[2], hi[2], reads);
+    const uint64_t bad = __ballot(solid);
+    if (bad & 1ull) break;                         // no progress
+    const int32_t k = bad ? __ffsll((unsigned long long)bad) - 1 : 63;
+    const float next = bad ? t0 : t1;
+    ta = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(next), k));
+  }
+  return ta;
+}
+
+// Walk state of ray r at the last cell line of its dominant axis that it
+// enters no later than parameter t (beam_start: no solid lies on the ray up
+// to t, nor within the boxes' margin beyond it), at level 0: such a ray is
+// close to solid, where coarse nodes would only be descended again; at the
+// origin and level L0 if that line is the start cell's.  The line comes from O + t D in
+// double precision: t, D and O are exact there and the one rounding of the
+// fma moves the entry by less than 2^-20 S units, far inside the margin.
+__device__ __forceinline__ void start_walk(ray_t& r, walk_t& s, float t, int32_t L0,
+                                           int32_t W, int32_t H) {
+  if (t > 0.0f) {
+    const bool ax_x = r.ax >= r.ay;
+    const int64_t O = ax_x ? r.Ox : r.Oy;
+    const int32_t D = ax_x ? r.Dx : r.Dy;
+    const int32_t n = ax_x ? W : H;
+    const int32_t c0 = (int32_t)(O >> 16);
+    const double q = fma((double)t, (double)D, (double)O) * (1.0 / 65536.0);
+    int32_t c;
+    bool ahead;
+    if (D > 0) {        // line c is entered at x = c: the largest c <= q
+      c = (int32_t)floor(fmax(fmin(q, (double)n), -1048576.0));
+      ahead = c > c0;
+    } else {            // line c is entered at x = c + 1: the smallest c >= q - 1
+      c = (int32_t)ceil(fmin(fmax(q, 0.0), 1048576.0)) - 1;
+      ahead = c < c0;
+    }
+    if (ahead) {
+      seg_init(r, s, ax_x ? 0 : 1, c);
+      return;
+    }
+  }
+  walk_init(r, L0, s);
+}
+
+}  // namespace

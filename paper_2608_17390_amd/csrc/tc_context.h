@@ -105,6 +105,7 @@ struct tc_context {
   int32_t tile_order = 2;
   int32_t boost = 0;
   int32_t split_budget = 128;
+  int32_t beam_passes = 4;
   int32_t split_queue = 1 << 17;
   int32_t march_steps = 128;
   int32_t march_bisect = 4;

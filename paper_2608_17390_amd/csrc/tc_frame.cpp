@@ -42,7 +42,7 @@ void frame_free(tc_frame* f) {
 }
 
 struct Knobs {
-  int32_t mode, start, order, remap, waves, rmin, riters, split;
+  int32_t mode, start, order, remap, waves, rmin, riters, split, beam;
 };
 
 void apply_knobs(tc_context* c, const Knobs& k) {
@@ -54,11 +54,13 @@ void apply_knobs(tc_context* c, const Knobs& k) {
   c->refill_min = k.rmin;
   c->refill_iters = k.riters;
   c->split_budget = k.split;
+  c->beam_passes = k.beam;
 }
 
 Knobs read_knobs(const tc_context* c) {
   return Knobs{c->render_mode, c->start_level, c->tile_order, c->xcd_remap,
-               c->persist_waves, c->refill_min, c->refill_iters, c->split_budget};
+               c->persist_waves, c->refill_min, c->refill_iters, c->split_budget,
+               c->beam_passes};
 }
 
 }  // namespace
@@ -174,7 +176,8 @@ tc_status tc_autotune(tc_context* ctx, const tc_view* views, int32_t n,
       for (int32_t order : {0, 1, 2})
         for (int32_t remap : {0, 2, 8})
           for (int32_t start : {1, 2, 3, 4})
-            cand.push_back(Knobs{0, start, order, remap, cur.waves, cur.rmin, cur.riters, split});
+            cand.push_back(Knobs{0, start, order, remap, cur.waves, cur.rmin, cur.riters, split,
+                                 cur.beam});
     std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
     for (auto& e : ev) TC_HIP(hipEventCreate(&e), "hipEventCreate");
     auto time_knobs = [&](const Knobs& k, float* med) -> tc_status {
@@ -211,13 +214,26 @@ tc_status tc_autotune(tc_context* ctx, const tc_view* views, int32_t n,
       for (int32_t rmin : {8, 16, 32})
         for (int32_t riters : {16, 64}) {
           if (st) break;
-          Knobs k{2, bk.start, bk.order, bk.remap, waves, rmin, riters, bk.split};
+          Knobs k{2, bk.start, bk.order, bk.remap, waves, rmin, riters, bk.split, bk.beam};
           float m;
           st = time_knobs(k, &m);
           if (st) break;
           ++tried;
           if (m < bms) { bms = m; bk = k; }
         }
+    // the packet beam start of the one-thread-per-pixel modes, around the
+    // best setting
+    if (!st && bk.mode == 0)
+      for (int32_t beam : {0, 2, 4, 8}) {
+        if (beam == bk.beam) continue;
+        Knobs k = bk;
+        k.beam = beam;
+        float m;
+        st = time_knobs(k, &m);
+        if (st) break;
+        ++tried;
+        if (m < bms) { bms = m; bk = k; }
+      }
     for (auto& e : ev) (void)hipEventDestroy(e);
     if (st) {
       apply_knobs(ctx, cur);
@@ -232,6 +248,7 @@ tc_status tc_autotune(tc_context* ctx, const tc_view* views, int32_t n,
     best->refill_min = bk.rmin;
     best->refill_iters = bk.riters;
     best->split_budget = bk.split;
+    best->beam_passes = bk.beam;
     best->ms = bms;
     best->tried = tried;
     return TC_OK;

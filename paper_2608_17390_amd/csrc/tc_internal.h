@@ -81,6 +81,8 @@ struct tci_render_opts {
                                // (0: never)
   int32_t split_budget;        // hierarchical mode: steps before a ray is
                                // handed to the split pass (0: never)
+  int32_t beam_passes;         // hierarchical modes: search passes of the
+                               // packet beam start (0: rays start at the eye)
   uint32_t qcap;               // capacity of the split queue
   uint4* queue;                // split queue: (view, pixel index, first
                                // dominant-axis cell line still to walk, 0)

@@ -17,25 +17,33 @@ __device__ __forceinline__ int32_t find_view(const int64_t* pkt_prefix,
   return lo;
 }
 
-// Pixel of ray `k` (0..63, row-major in an 8x8 block) of packet `t` of a
-// view; packets run row-major (order 0), column-major (order 1) or by the
-// view's tile-row table (order 2).
+// Tile (8x8 pixel block) of packet `t` of a view; packets run row-major
+// (order 0), column-major (order 1) or by the view's tile-row table (order
+// 2).  A view holds fewer than 2^22 packets, so 32-bit arithmetic suffices.
+__device__ __forceinline__ void packet_tile(const tci_view& v, int64_t t64,
+                                            int32_t order, const int32_t* rows,
+                                            int32_t& tx, int32_t& ty) {
+  const uint32_t t = (uint32_t)t64;
+  if (order == 2) {
+    tx = (int32_t)(t % (uint32_t)v.tiles_x);
+    ty = rows[v.rows_off + t / (uint32_t)v.tiles_x];
+  } else if (order == 1) {
+    const uint32_t tiles_y = (uint32_t)(v.h + 7) >> 3;
+    tx = (int32_t)(t / tiles_y);
+    ty = (int32_t)(t % tiles_y);
+  } else {
+    tx = (int32_t)(t % (uint32_t)v.tiles_x);
+    ty = (int32_t)(t / (uint32_t)v.tiles_x);
+  }
+}
+
+// Pixel of ray `k` (0..63, row-major in the 8x8 block) of packet `t`.
 __device__ __forceinline__ void packet_pixel(const tci_view& v, int64_t t,
                                              int32_t k, int32_t order,
                                              const int32_t* rows,
                                              int32_t& px, int32_t& py) {
   int32_t tx, ty;
-  if (order == 2) {
-    tx = (int32_t)(t % v.tiles_x);
-    ty = rows[v.rows_off + t / v.tiles_x];
-  } else if (order == 1) {
-    const int32_t tiles_y = (v.h + 7) >> 3;
-    tx = (int32_t)(t / tiles_y);
-    ty = (int32_t)(t % tiles_y);
-  } else {
-    tx = (int32_t)(t % v.tiles_x);
-    ty = (int32_t)(t / v.tiles_x);
-  }
+  packet_tile(v, t, order, rows, tx, ty);
   px = tx * 8 + (k & 7);
   py = ty * 8 + (k >> 3);
 }

@@ -3,7 +3,8 @@
 // walk itself (tc_walk.h) is the exact cell sequence of a 2D digital
 // differential analyser over the map, accelerated by the per-layer min/max
 // pyramid (Section 3.1 SOLID and RAYMARCH, Section 3.2 skip-to-exit).
-#include "tc_walk.h"
+#include "tc_beam.h"
+#include "tc_packet.h"
 
 namespace {
 
@@ -18,36 +19,42 @@ __device__ __forceinline__ void render_body(
   __shared__ uint32_t moff[kOcc ? TCI_MAX_LEVELS : 1];
   if constexpr (kOcc) load_levels_occ(m, lv, moff);
   else load_levels(m, lv);
-  // XCD-aware order: consecutive hardware blocks go to different XCDs, so
-  // hand each XCD a contiguous range of packets to share its L2.
-  int64_t nb = gridDim.x, b = blockIdx.x;
-  if (o.xcd_remap > 0) {
-    // hardware block r of a group of 8G runs on XCD r % 8; give each XCD
-    // G consecutive logical blocks of the group
-    const int64_t G = o.xcd_remap, group = 8 * G;
-    if (b < (nb / group) * group) {
-      const int64_t g = b / group, r = b - g * group;
-      b = g * group + (r & 7) * G + (r >> 3);
-    }
-  }
-  const int32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // XCD-aware order: hand each XCD a contiguous range of packets to share
+  // its L2
+  const int64_t b = tcp::xcd_block(blockIdx.x, gridDim.x, o.xcd_remap);
+  // the packet is the wave's: keep its index, view and tile in scalar
+  // registers
+  const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int64_t p = b * 4 + wave;
   if (p >= npkt) return;
-  const int32_t vi = __builtin_amdgcn_readfirstlane(find_view(pkt_prefix, nviews, p));
+  const int32_t vi = __builtin_amdgcn_readfirstlane(tcp::find_view(pkt_prefix, nviews, p));
   const tci_view& v = views[vi];
-  int32_t px, py;
-  packet_pixel(v, p - v.pkt_base, lane, o.tile_order, o.rows, px, py);
-  if (px >= v.w || py >= v.h) return;
+  int32_t tx, ty;
+  tcp::packet_tile(v, p - v.pkt_base, o.tile_order, o.rows, tx, ty);
+  tx = __builtin_amdgcn_readfirstlane(tx);
+  ty = __builtin_amdgcn_readfirstlane(ty);
+  const int32_t px = tx * 8 + (lane & 7), py = ty * 8 + (lane >> 3);
+  // the packet's common start (all 64 lanes take part)
+  float t_start = 0.0f;
+  int32_t beam_reads = 0;
+  if (!kFlat && o.beam_passes > 0)
+    t_start = beam_start(m, lv, v, tx, ty, o.beam_passes, lane, beam_reads);
+  if (px >= v.w || py >= v.h) {
+    if (o.count && beam_reads) atomicAdd(o.count, (unsigned long long)beam_reads);
+    return;
+  }
   ray_t r;
   pixel_ray(v, px, py, r);
   uint32_t word;
   float depth;
   if (r.Dx == 0 && r.Dy == 0) {
     trace_vertical(m, lv, r, word, depth);
+    if (o.count && beam_reads) atomicAdd(o.count, (unsigned long long)beam_reads);
   } else {
     walk_t s;
     const int32_t top = kFlat ? 0 : m.top;
-    walk_init(r, kFlat ? 0 : clamp_level(o.start_level, top), s);
+    start_walk(r, s, t_start, kFlat ? 0 : clamp_level(o.start_level, top), m.W, m.H);
+    s.reads = beam_reads;
     uint32_t col = 0;
     const int32_t Lmax = kFlat ? 0 : clamp_level(o.max_level, top);
     const int32_t boost = __builtin_amdgcn_readfirstlane(o.boost);
@@ -97,7 +104,7 @@ __device__ __forceinline__ void render_body(
     finish(r, s, m.W, st, col, word, depth);
     if (o.count) atomicAdd(o.count, (unsigned long long)s.reads);
   }
-  store_hit(out, v.out_base + (int64_t)py * v.w + px, word, depth);
+  tcp::store_hit(out, v.out_base + (int64_t)py * v.w + px, word, depth);
 }
 
 // The three one-thread-per-pixel kernels.  The hierarchical one is asked
@@ -195,12 +202,12 @@ __global__ __launch_bounds__(256) void split_kernel(tci_map m,
     const uint64_t hits = __ballot(st == kHitCell || st == kCapped);
     const int64_t idx = v.out_base + q.y;
     if (hits == 0) {
-      if (lane == 0) store_hit(out, idx, kMiss, __builtin_inff());
+      if (lane == 0) tcp::store_hit(out, idx, kMiss, __builtin_inff());
     } else if (lane == __ffsll((unsigned long long)hits) - 1) {
       uint32_t word;
       float depth;
       finish(r, s, m.W, st, col, word, depth);
-      store_hit(out, idx, word, depth);
+      tcp::store_hit(out, idx, word, depth);
     }
   }
 }
@@ -250,10 +257,10 @@ __global__ __launch_bounds__(256) void render_persistent_kernel(
         if (rank < remaining) { mypkt = pkt; myray = taken + rank; }
         else { mypkt = next; myray = rank - remaining; }
         if (mypkt >= 0 && mypkt < npkt && myray < 64) {
-          const int32_t vi = find_view(pkt_prefix, nviews, mypkt);
+          const int32_t vi = tcp::find_view(pkt_prefix, nviews, mypkt);
           const tci_view& v = views[vi];
           int32_t px, py;
-          packet_pixel(v, mypkt - v.pkt_base, myray, o.tile_order, o.rows, px, py);
+          tcp::packet_pixel(v, mypkt - v.pkt_base, myray, o.tile_order, o.rows, px, py);
           if (px < v.w && py < v.h) {
             pixel_ray(v, px, py, r);
             out_idx = v.out_base + (int64_t)py * v.w + px;
@@ -261,7 +268,7 @@ __global__ __launch_bounds__(256) void render_persistent_kernel(
               uint32_t word;
               float depth;
               trace_vertical(m, lv, r, word, depth);
-              store_hit(out, out_idx, word, depth);
+              tcp::store_hit(out, out_idx, word, depth);
             } else {
               walk_init(r, L0, s);
               active = true;
@@ -284,7 +291,7 @@ __global__ __launch_bounds__(256) void render_persistent_kernel(
       uint32_t word;
       float depth;
       finish(r, s, m.W, st, col, word, depth);
-      store_hit(out, out_idx, word, depth);
+      tcp::store_hit(out, out_idx, word, depth);
       if (o.count) atomicAdd(o.count, (unsigned long long)s.reads);
       active = false;
     }

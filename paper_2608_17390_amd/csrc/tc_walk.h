@@ -146,16 +146,21 @@ __device__ __forceinline__ void walk_init(ray_t& r, int32_t L0, walk_t& s) {
   const int32_t cx = (int32_t)(r.Ox >> 16), cy = (int32_t)(r.Oy >> 16);
   r.cx0 = cx;
   r.cy0 = cy;
-  const int64_t nx = r.Dx > 0 ? ((int64_t)(cx + 1) << 16) - r.Ox
-                              : r.Ox - ((int64_t)cx << 16);
-  const int64_t ny = r.Dy > 0 ? ((int64_t)(cy + 1) << 16) - r.Oy
-                              : r.Oy - ((int64_t)cy << 16);
-  const int64_t kx = nx * (int64_t)r.ay, ky = ny * (int64_t)r.ax;
-  const int64_t tie = (kx & 0xFFFF) <= (ky & 0xFFFF) ? 0 : 1;
-  const int64_t zx = r.Oz * (int64_t)r.ax + nx * (int64_t)r.Dz;
-  const int64_t zy = r.Oz * (int64_t)r.ay + ny * (int64_t)r.Dz;
-  r.rx = (zx & 0xFFFF) != 0;
-  r.ry = (zy & 0xFFFF) != 0;
+  // distances to the first boundaries, 0..2^16 (S units)
+  const uint32_t fx = (uint32_t)r.Ox & 0xFFFF, fy = (uint32_t)r.Oy & 0xFFFF;
+  const uint32_t nx = r.Dx > 0 ? 65536u - fx : fx;
+  const uint32_t ny = r.Dy > 0 ? 65536u - fy : fy;
+  const int64_t kx = (int64_t)mul48(nx, r.ay), ky = (int64_t)mul48(ny, r.ax);
+  const int64_t tie = ((uint32_t)kx & 0xFFFF) <= ((uint32_t)ky & 0xFFFF) ? 0 : 1;
+  // Z = Oz * a + n * Dz with Oz = zh * S + zl (|Oz| < 2^31, so |zh| < 2^15):
+  // floor(Z / S) = zh * a + floor(w / S) and Z mod S = w mod S for
+  // w = zl * a + n * Dz
+  const int32_t zh = (int32_t)(r.Oz >> 16);
+  const uint32_t zl = (uint32_t)r.Oz & 0xFFFF;
+  const int64_t wx = (int64_t)mul48(zl, r.ax) + smul48((int32_t)nx, r.Dz);
+  const int64_t wy = (int64_t)mul48(zl, r.ay) + smul48((int32_t)ny, r.Dz);
+  r.rx = ((uint32_t)wx & 0xFFFF) != 0;
+  r.ry = ((uint32_t)wy & 0xFFFF) != 0;
   s.L = L0;
   s.ni = cx >> L0;
   s.nj = cy >> L0;
@@ -163,10 +168,10 @@ __device__ __forceinline__ void walk_init(ray_t& r, int32_t L0, walk_t& s) {
   const int32_t kxm1 = r.Dx > 0 ? ((s.ni + 1) << L0) - 1 - cx : cx - (s.ni << L0);
   const int32_t kym1 = r.Dy > 0 ? ((s.nj + 1) << L0) - 1 - cy : cy - (s.nj << L0);
   s.KXe = r.Dx == 0 ? kNever
-                    : (kx >> 16) + (r.Dy != 0 ? tie : 0) + (int64_t)kxm1 * r.ay;
-  s.KYe = r.Dy == 0 ? kNever : (ky >> 16) + (int64_t)kym1 * r.ax;
-  s.ZXe = (zx >> 16) + (int64_t)kxm1 * r.Dz;
-  s.ZYe = (zy >> 16) + (int64_t)kym1 * r.Dz;
+                    : (kx >> 16) + (r.Dy != 0 ? tie : 0) + (int64_t)mul48((uint32_t)kxm1, r.ay);
+  s.KYe = r.Dy == 0 ? kNever : (ky >> 16) + (int64_t)mul48((uint32_t)kym1, r.ax);
+  s.ZXe = smul48((int32_t)r.ax, zh) + (wx >> 16) + smul48(kxm1, r.Dz);
+  s.ZYe = smul48((int32_t)r.ay, zh) + (wy >> 16) + smul48(kym1, r.Dz);
   s.Kin = 0;
   s.Zin = r.Oz >> 16;
   s.rin = (r.Oz & 0xFFFF) != 0;
@@ -510,47 +515,6 @@ __device__ __forceinline__ void load_levels_occ(const tci_map& m, lvl_t* lv, uin
     moff[threadIdx.x] = m.mk[threadIdx.x].off;
   }
   __syncthreads();
-}
-
-// View containing packet p: largest v with pkt_prefix[v] <= p.
-__device__ __forceinline__ int32_t find_view(const int64_t* pkt_prefix,
-                                             int32_t nviews, int64_t p) {
-  int32_t lo = 0, hi = nviews - 1;
-  while (lo < hi) {
-    int32_t mid = (lo + hi + 1) >> 1;
-    if (pkt_prefix[mid] <= p) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
-// Pixel of ray `k` (0..63, row-major in an 8x8 block) of packet `t` of a
-// view; packets run row-major (order 0) or column-major (order 1).
-__device__ __forceinline__ void packet_pixel(const tci_view& v, int64_t t,
-                                             int32_t k, int32_t order,
-                                             const int32_t* rows,
-                                             int32_t& px, int32_t& py) {
-  int32_t tx, ty;
-  if (order == 2) {
-    tx = (int32_t)(t % v.tiles_x);
-    ty = rows[v.rows_off + t / v.tiles_x];
-  } else if (order == 1) {
-    const int32_t tiles_y = (v.h + 7) >> 3;
-    tx = (int32_t)(t / tiles_y);
-    ty = (int32_t)(t % tiles_y);
-  } else {
-    tx = (int32_t)(t % v.tiles_x);
-    ty = (int32_t)(t / v.tiles_x);
-  }
-  px = tx * 8 + (k & 7);
-  py = ty * 8 + (k >> 3);
-}
-
-__device__ __forceinline__ void store_hit(void* out, int64_t idx,
-                                          uint32_t word, float depth) {
-  uint2 h;
-  h.x = word;
-  h.y = __float_as_uint(depth);
-  reinterpret_cast<uint2*>(out)[idx] = h;
 }
 
 __device__ __forceinline__ int32_t clamp_level(int32_t v, int32_t top) {

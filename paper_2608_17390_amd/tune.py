@@ -8,7 +8,8 @@ from . import _tc
 OPTS = {"render_mode": _tc.TC_OPT_RENDER_MODE, "start_level": _tc.TC_OPT_START_LEVEL,
         "tile_order": _tc.TC_OPT_TILE_ORDER, "xcd_remap": _tc.TC_OPT_XCD_REMAP,
         "persist_waves": _tc.TC_OPT_PERSIST_WAVES, "refill_min": _tc.TC_OPT_REFILL_MIN,
-        "refill_iters": _tc.TC_OPT_REFILL_ITERS, "split_budget": _tc.TC_OPT_SPLIT_BUDGET}
+        "refill_iters": _tc.TC_OPT_REFILL_ITERS, "split_budget": _tc.TC_OPT_SPLIT_BUDGET,
+        "beam_passes": _tc.TC_OPT_BEAM_PASSES}
 
 
 def default_cache_path():

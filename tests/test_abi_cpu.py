@@ -36,6 +36,21 @@ def test_binding_covers_every_declared_symbol():
     assert set(_declared_functions()) <= bound
 
 
+def test_binding_constants_match_the_header():
+    """Every integer #define of the header (options, status codes, edit
+    kinds, faces) is exported by the package with the same value."""
+    src = open(os.path.join(ROOT, "include", "tc.h")).read()
+    defs = re.findall(r"^#define\s+(TC_[A-Z0-9_]+)\s+([^/\n]+?)\s*(?:/\*.*)?$", src, flags=re.M)
+    checked = 0
+    for name, expr in defs:
+        expr = re.sub(r"\b(0x[0-9A-Fa-f]+|\d+)[uU]\b", r"\1", expr)
+        if not re.fullmatch(r"[0-9xA-Fa-f()<>\-+ ]+", expr):
+            continue
+        assert getattr(tc, name, None) == eval(expr), name
+        checked += 1
+    assert checked >= 40
+
+
 def test_struct_layouts():
     assert ctypes.sizeof(tc.tc_view) == 84
     assert ctypes.sizeof(tc.tc_edit) == 6 * 4 + 3 * 8

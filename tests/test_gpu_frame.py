@@ -30,7 +30,8 @@ def _outbuf(views):
 def test_frame_replays_apply_edits_each_time(ctx, mode):
     F, B, T = synth.make_map_from_config(1)
     load(ctx, F, B, T)
-    ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, MODES[mode])
+    ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, MODES[mode][0])
+    ctx.tc_set_option(tc.TC_OPT_BEAM_PASSES, MODES[mode][1])
     rng = np.random.default_rng(50)
     views = synth.config_views(1, F, B) + [
         synth.shadow_view(30, 40, 64, 35.0, 70.0),
@@ -59,6 +60,7 @@ def test_frame_replays_apply_edits_each_time(ctx, mode):
         assert np.array_equal(ctx.tc_read_pyramid(L), oracle.pyramid_level_fast(Fk, Bk, Tk, L))
     frame.close()
     ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, 0)
+    ctx.tc_set_option(tc.TC_OPT_BEAM_PASSES, 4)
 
 
 def test_frame_without_edits_and_reload_invalidates(ctx):
@@ -91,6 +93,8 @@ def test_autotune_keeps_results(ctx):
     assert best["render_mode"] in (0, 2)
     assert best["split_budget"] in (0, 128)
     assert ctx.tc_get_option(tc.TC_OPT_SPLIT_BUDGET) == best["split_budget"]
+    assert best["beam_passes"] in (0, 2, 4, 8)
+    assert ctx.tc_get_option(tc.TC_OPT_BEAM_PASSES) == best["beam_passes"]
     assert ctx.tc_get_option(tc.TC_OPT_RENDER_MODE) == best["render_mode"]
     out2 = tc.render(ctx, views)
     torch.cuda.synchronize()

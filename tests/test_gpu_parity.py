@@ -15,7 +15,10 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 S = 65536
-MODES = {"hier": 0, "flat": 1, "persistent": 2, "occupancy": 4}
+# (render mode, packet beam passes): the hierarchical modes run with the
+# beam start (the default) and without it
+MODES = {"hier": (0, 4), "hier_nobeam": (0, 0), "flat": (1, 0), "persistent": (2, 0),
+         "occupancy": (4, 4)}
 DEPTH_RTOL = 1e-5
 
 
@@ -28,9 +31,11 @@ def ctx():
 
 
 def gpu_render(ctx, views, mode="hier"):
-    ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, MODES[mode])
+    ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, MODES[mode][0])
+    ctx.tc_set_option(tc.TC_OPT_BEAM_PASSES, MODES[mode][1])
     out = tc.render(ctx, views)
     torch.cuda.synchronize()
+    ctx.tc_set_option(tc.TC_OPT_BEAM_PASSES, 4)
     return tc.split_hits(out)
 
 

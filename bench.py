@@ -479,6 +479,9 @@ def main():
                     help="skip the sampled-march leg (protocol views)")
     ap.add_argument("--no-growth", action="store_true",
                     help="skip the edit frame (c3), batched frame (c4) and server (c5)")
+    ap.add_argument("--beam-passes", type=int, default=None,
+                    help="packet beam passes of the headline render (default: the "
+                         "library's)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU; --gpus %d is not supported (the method "
@@ -502,6 +505,9 @@ def main():
     torch.cuda.synchronize()
     out = torch.empty((rays, 2), dtype=torch.int32, device="cuda")
     ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, MODES[args.mode])
+    if args.beam_passes is not None:
+        ctx.tc_set_option(tc.TC_OPT_BEAM_PASSES, args.beam_passes)
+    beam = ctx.tc_get_option(tc.TC_OPT_BEAM_PASSES)
 
     # algorithmic bytes: node/cell reads of the one-pass exact walk (split
     # pass off, so speculative segment walks are not counted), counted by
@@ -540,7 +546,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "c2: 2048x2048 two-layer map (30% two-layer cells, "
                                "40-unit cliffs), one 1920x1080 eye-level horizon view",
-                   "rays_per_frame": rays, "render_mode": args.mode,
+                   "rays_per_frame": rays, "render_mode": args.mode, "beam_passes": beam,
                    "frame_ms_median": med, "frame_ms_p99": float(np.percentile(ms, 99))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,

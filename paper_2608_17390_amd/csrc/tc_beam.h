@@ -56,11 +56,13 @@ __device__ __forceinline__ bool beam_box_solid(const tci_map& m, const lvl_t* lv
   const int32_t i0 = max(x0, 0), i1 = min(x1, l.w - 1);
   const int32_t j0 = max(y0, 0), j1 = min(y1, l.h - 1);
   if (i0 > i1 || j0 > j1) return false;         // beside the map: air
-  const tci_level tl{l.off, l.w, l.h, l.tiles_x};
-  const uint32_t w00 = m.base[tci_tile_index(tl, i0, j0)];
-  const uint32_t w10 = m.base[tci_tile_index(tl, i1, j0)];
-  const uint32_t w01 = m.base[tci_tile_index(tl, i0, j1)];
-  const uint32_t w11 = m.base[tci_tile_index(tl, i1, j1)];
+  // tiled index (tci_tile_index) with 24-bit multiplies: tile rows and
+  // tiles per row are below 2^11
+  auto at = [&](int32_t i, int32_t j) {
+    return m.base[l.off + ((__umul24((uint32_t)j >> 3, (uint32_t)l.tiles_x) + ((uint32_t)i >> 3))
+                           << 6) + (((uint32_t)j & 7) << 3) + ((uint32_t)i & 7)];
+  };
+  const uint32_t w00 = at(i0, j0), w10 = at(i1, j0), w01 = at(i0, j1), w11 = at(i1, j1);
   reads += 1 + (i1 != i0) + (j1 != j0) + (i1 != i0 && j1 != j0);
   const uint32_t fmax = max(max(w00 & 0xFF, w10 & 0xFF), max(w01 & 0xFF, w11 & 0xFF));
   const uint32_t smin = min(min((w00 >> 8) & 0xFF, (w10 >> 8) & 0xFF),

@@ -59,13 +59,21 @@ __device__ __forceinline__ void render_body(
     const int32_t Lmax = kFlat ? 0 : clamp_level(o.max_level, top);
     const int32_t boost = __builtin_amdgcn_readfirstlane(o.boost);
     bool split = !kFlat && o.split_budget > 0 && o.qcap > 0;
+    // the walk runs a loop specialised to the sign of the ray's vertical
+    // direction (a packet's rays mostly share it; a wave holding both signs
+    // runs the two loops one after the other)
+    const bool down = r.Dz < 0;
     int32_t st;
     for (;;) {
       // the budget bounds the walk: at most the split budget, then (or
       // without a split pass) kIterCap + 1 iterations
-      st = walk_steps<false, kOcc, false>(m, lv, r, s, Lmax,
-                                          split ? o.split_budget : kIterCap + 1, col, boost,
-                                          0, 0, 0, moff, o.count != nullptr);
+      const int32_t budget = split ? o.split_budget : kIterCap + 1;
+      if (down)
+        st = walk_steps<false, kOcc, false, 1>(m, lv, r, s, Lmax, budget, col, boost, 0, 0, 0,
+                                               moff, o.count != nullptr);
+      else
+        st = walk_steps<false, kOcc, false, 2>(m, lv, r, s, Lmax, budget, col, boost, 0, 0, 0,
+                                               moff, o.count != nullptr);
       if (!split) break;
       split = false;
       // long walks go to the split pass, as many as the queue holds
@@ -99,8 +107,12 @@ __device__ __forceinline__ void render_body(
     }
     if (st == kWalking) st = kCapped;   // the whole budget ran out (never expected)
     // the origin is needed again only here: recompute it from the view
-    // rather than keep it in registers through the walk
-    pixel_ray(v, px, py, r);
+    // rather than keep it in registers through the walk (the empty asm
+    // hides that the pixel is unchanged, so the first computation is not
+    // reused)
+    int32_t qx = px, qy = py;
+    asm volatile("" : "+v"(qx), "+v"(qy));
+    pixel_ray(v, qx, qy, r);
     finish(r, s, m.W, st, col, word, depth);
     if (o.count) atomicAdd(o.count, (unsigned long long)s.reads);
   }

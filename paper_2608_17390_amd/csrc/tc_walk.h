@@ -363,7 +363,10 @@ __device__ __forceinline__ void lift(const ray_t& r, walk_t& s, int32_t L) {
 // ray's height range over the node, widened by two units to cover the
 // rounding of its float estimate, must meet an occupied band, or the ray
 // passes between the node's slabs and the node is skipped.
-template <bool kSeg = false, bool kOcc = false, bool kCap = true>
+// kDir fixes the sign of the ray's vertical direction for callers that know
+// it for every lane of the wave (1: Dz < 0, 2: Dz >= 0; 0: read it per ray),
+// so the loop carries no per-lane selects on it.
+template <bool kSeg = false, bool kOcc = false, bool kCap = true, int kDir = 0>
 __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
                                               const ray_t& r, walk_t& s,
                                               int32_t max_level, int32_t budget,
@@ -372,7 +375,7 @@ __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
                                               int32_t seg_lo = 0, int32_t seg_hi = 0,
                                               const uint32_t* moff = nullptr,
                                               bool count = true) {
-  const bool desc = r.Dz < 0;
+  const bool desc = kDir == 1 ? true : (kDir == 2 ? false : r.Dz < 0);
   const int32_t sx = r.Dx > 0 ? 1 : -1, sy = r.Dy > 0 ? 1 : -1;
   const int32_t nearx = r.Dx > 0 ? 0 : 1, neary = r.Dy > 0 ? 0 : 1;
   for (int32_t it = 0; it < budget; ++it) {
@@ -478,7 +481,7 @@ __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
     // the ray cannot come back into the map, or is above all solid
     const bool away = (s.ni < 0 && r.Dx <= 0) || (s.ni >= l.w && r.Dx >= 0) ||
                       (s.nj < 0 && r.Dy <= 0) || (s.nj >= l.h && r.Dy >= 0);
-    const bool above = r.Dz >= 0 && !z_le(s.Zin, s.rin, 255, s.Din);
+    const bool above = !desc && !z_le(s.Zin, s.rin, 255, s.Din);
     if (away || above) return kMissed;
     // go up one level when the step entered a new parent node; the new node
     // is then the near half of its parent along the exit axis

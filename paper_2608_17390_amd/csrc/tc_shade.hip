@@ -55,7 +55,9 @@ __device__ __forceinline__ int64_t floordiv(int64_t a, int64_t b) {  // b > 0
 }
 
 // Does a ray from P along L meet any solid?  `reads` gains the nodes and
-// cells the walk read.
+// cells the walk read.  kDir: the sign of L[2] (1 negative, 2 otherwise),
+// the walk loop's specialisation.
+template <int kDir>
 __device__ __forceinline__ bool occluded(const tci_map& m, const lvl_t* lv, const int64_t P[3],
                                          const int32_t L[3], int32_t L0, int32_t Lmax,
                                          int32_t& reads) {
@@ -78,11 +80,14 @@ __device__ __forceinline__ bool occluded(const tci_map& m, const lvl_t* lv, cons
   walk_t st;
   walk_init(s, L0, st);
   uint32_t col = 0;
-  const int32_t res = walk_steps(m, lv, s, st, Lmax, kIterCap + 1, col);
+  const int32_t res = walk_steps<false, false, true, kDir>(m, lv, s, st, Lmax, kIterCap + 1, col);
   reads += st.reads;
   return res == kHitCell || res == kCapped;
 }
 
+// One kernel per sign of the light's vertical direction: every shadow ray
+// of a launch shares it, so the walk loop is specialised to it.
+template <int kDir>
 __global__ __launch_bounds__(256) void shade_kernel(
     tci_map m, const tci_view* __restrict__ views, int32_t nviews,
     const int64_t* __restrict__ pkt_prefix, int64_t npkt, const uint2* __restrict__ hits,
@@ -174,7 +179,7 @@ __global__ __launch_bounds__(256) void shade_kernel(
     for (int cc = 0; cc < 3; ++cc)
       P[cc] = O[cc] + floordiv(tn * (int64_t)D[cc], td) + nudge[cc];
     const int32_t top = m.top;
-    lit = !occluded(m, lv, P, sh.light, clamp_level(o.start_level, top),
+    lit = !occluded<kDir>(m, lv, P, sh.light, clamp_level(o.start_level, top),
                     clamp_level(o.max_level, top), reads);
   }
   const float amb = (layer == 0 && B > 0) ? sh.cave_ambient : sh.ambient;
@@ -202,7 +207,11 @@ hipError_t tci_launch_shade(const tci_map& m, const tci_view* views, int32_t nvi
                             hipStream_t s) {
   int64_t blocks = (npkt + 3) / 4;
   if (blocks < 1) return hipSuccess;
-  hipLaunchKernelGGL(shade_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, m, views, nviews,
-                     pkt_prefix, npkt, (const uint2*)hits, rgba, sh, o);
+  if (sh.light[2] < 0)
+    hipLaunchKernelGGL(shade_kernel<1>, dim3((uint32_t)blocks), dim3(256), 0, s, m, views,
+                       nviews, pkt_prefix, npkt, (const uint2*)hits, rgba, sh, o);
+  else
+    hipLaunchKernelGGL(shade_kernel<2>, dim3((uint32_t)blocks), dim3(256), 0, s, m, views,
+                       nviews, pkt_prefix, npkt, (const uint2*)hits, rgba, sh, o);
   return hipGetLastError();
 }

@@ -258,6 +258,12 @@ tc_status tc_shade_views(tc_context *ctx, const tc_view *views, int32_t n,
 #define TC_OPT_SPLIT_QUEUE 12    /* most rays the second pass takes per call;
                                     further long rays finish in the first
                                     pass (default 131072) */
+#define TC_OPT_SPLIT_WAVES 18    /* waves of one block the second pass gives
+                                    each long ray: its remaining path is cut
+                                    into 64 runs per wave, each walked by one
+                                    lane from the exact state the walk enters
+                                    it with; the earliest run with a hit gives
+                                    the record (1, 2 or 4; default 4) */
 #define TC_OPT_BEAM_PASSES 17    /* render modes 0 and 4: before walking, the
                                     64 rays of each 8x8 pixel packet find a
                                     common start parameter t such that none

@@ -54,6 +54,7 @@ TC_OPT_MARCH_STEPS = 14
 TC_OPT_MARCH_BISECT = 15
 TC_OPT_MARCH_FAR = 16
 TC_OPT_BEAM_PASSES = 17
+TC_OPT_SPLIT_WAVES = 18
 TC_FACE_SAMPLED = 0
 
 _STATUS = {0: "TC_OK", -1: "TC_INVALID_ARG", -2: "TC_OUT_OF_MEMORY",

@@ -119,6 +119,7 @@ tci_render_opts render_opts(const tc_context* c) {
   o.qcap = 0;
   o.queue = nullptr;
   o.qcount = nullptr;
+  o.split_waves = 1;
   o.count = c->count_reads ? c->d_count : nullptr;
   o.march_far = (float)c->march_far;
   o.march_steps = c->march_steps;
@@ -298,6 +299,7 @@ tc_status plan_views(tc_context* ctx, const tc_view* views, int32_t n, ViewPlan&
   p.qcap = (allow_split && ctx->render_mode == 0 && ctx->split_budget > 0)
                ? (uint32_t)std::min<int64_t>(out, ctx->split_queue) : 0;
   p.off_queue = p.off_counter + 64;
+  p.qwaves = ctx->split_waves;
   p.total = p.off_queue + sizeof(uint4) * (size_t)p.qcap;
   return TC_OK;
 }
@@ -342,13 +344,15 @@ hipError_t enqueue_render(tc_context* ctx, const tci_map& d, const char* dev,
     o.qcap = p.qcap;
     o.queue = (uint4*)(dev + p.off_queue);
     o.qcount = (uint32_t*)(counters + 1);
+    o.split_waves = p.qwaves;
     hipError_t e = counters_zeroed ? hipSuccess : tci_launch_zero_u64(counters, 2, s);
     if (e == hipSuccess) e = mark(0);
     if (e == hipSuccess)
       e = tci_launch_render(d, dv, p.n, pre, p.npkt, out, 0, o, s);
     if (e == hipSuccess) e = mark(1);
     const int32_t nb = (int32_t)std::max<int64_t>(
-        1, std::min<int64_t>(ctx->num_cu * 16, ((int64_t)p.qcap + 3) / 4));
+        1, std::min<int64_t>(ctx->num_cu * 16, ((int64_t)p.qcap * p.qwaves + 3) / 4));
+    // (4 / qwaves queued rays per block of 4 waves)
     if (e == hipSuccess) e = tci_launch_split(d, dv, o, out, nb, s);
     if (e == hipSuccess) e = mark(2);
     if (split_ran) *split_ran = true;
@@ -691,6 +695,10 @@ tc_status tc_set_option(tc_context* ctx, int32_t key, int64_t value) {
       if (value < 0 || value > (1 << 20)) break;
       ctx->split_budget = (int32_t)value;
       return TC_OK;
+    case TC_OPT_SPLIT_WAVES:
+      if (value != 1 && value != 2 && value != 4) break;
+      ctx->split_waves = (int32_t)value;
+      return TC_OK;
     case TC_OPT_BEAM_PASSES:
       if (value < 0 || value > 64) break;
       ctx->beam_passes = (int32_t)value;
@@ -757,6 +765,7 @@ tc_status tc_get_option(const tc_context* ctx, int32_t key, int64_t* value) {
     case TC_OPT_SPLIT_BUDGET: *value = ctx->split_budget; return TC_OK;
     case TC_OPT_SPLIT_QUEUE: *value = ctx->split_queue; return TC_OK;
     case TC_OPT_BEAM_PASSES: *value = ctx->beam_passes; return TC_OK;
+    case TC_OPT_SPLIT_WAVES: *value = ctx->split_waves; return TC_OK;
     case TC_OPT_KERNEL_TIMING: *value = ctx->kernel_timing; return TC_OK;
     case TC_OPT_MARCH_STEPS: *value = ctx->march_steps; return TC_OK;
     case TC_OPT_MARCH_BISECT: *value = ctx->march_bisect; return TC_OK;

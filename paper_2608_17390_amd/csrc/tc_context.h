@@ -41,6 +41,7 @@ struct ViewPlan {
   size_t off_views = 0, off_prefix = 0, off_counter = 0, off_rows = 0, total = 0;
   size_t off_queue = 0;
   uint32_t qcap = 0;           // split queue capacity (0: no split pass)
+  int32_t qwaves = 1;          // waves per queued ray in the split pass
   std::vector<tci_view> views;
   std::vector<int64_t> prefix;
   std::vector<int32_t> rows;   // tile rows of every view, longest walks first
@@ -106,6 +107,7 @@ struct tc_context {
   int32_t boost = 0;
   int32_t split_budget = 128;
   int32_t beam_passes = 4;
+  int32_t split_waves = 4;
   int32_t split_queue = 1 << 17;
   int32_t march_steps = 128;
   int32_t march_bisect = 4;

@@ -87,6 +87,8 @@ struct tci_render_opts {
   uint4* queue;                // split queue: (view, pixel index, first
                                // dominant-axis cell line still to walk, 0)
   uint32_t* qcount;            // split queue length
+  int32_t split_waves;         // waves of one block the split pass gives
+                               // each queued ray (1, 2 or 4)
   unsigned long long* count;   // if set: add each ray's node/cell reads
   float march_far;             // sampled march: far limit along each ray
   int32_t march_steps;         // sampled march: forward samples

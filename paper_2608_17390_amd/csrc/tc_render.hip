@@ -162,65 +162,95 @@ __device__ __forceinline__ int32_t exit_line(const ray_t& r, const tci_map& m,
   return (int32_t)floor(fmin(fmax(c, -1.0), lim));
 }
 
-// Split pass: one wave per queued ray; lane k walks the k-th of 64 runs of
-// dominant-axis cell lines (the last run is open-ended), each from the
-// exact state in which the flat walk enters it.  The first lane with a hit
-// holds the ray's first hit.  Waves stride over the queue and leave when
-// it is exhausted.
+// Split pass: G = split_waves (1, 2 or 4) waves of one block per queued
+// ray, 4 / G rays per block.  The ray's remaining dominant-axis cell lines
+// are cut into 64 G runs (the last one open-ended); lane k of the ray's
+// wave g walks run 64 g + k from the exact state in which the flat walk
+// enters it.  The earliest run with a hit holds the ray's first hit: inside
+// a wave the first lane with a hit wins and the lanes after it stop; across
+// the ray's waves, each wave with a hit lowers the ray's best run index in
+// LDS and leaves its record there, a wave stops once an earlier wave has a
+// hit, and after a barrier the ray's first wave writes the winner (or a
+// miss).  Blocks stride over the queue; every wave of a block runs the
+// same number of rounds, so the barriers are reached by all of them.
 __global__ __launch_bounds__(256) void split_kernel(tci_map m,
                                                     const tci_view* __restrict__ views,
                                                     void* out, tci_render_opts o) {
   __shared__ lvl_t lv[TCI_MAX_LEVELS];
+  __shared__ uint32_t best[4];      // per ray of the block: lowest run with a hit
+  __shared__ uint2 cand[4];         // per wave: its first hit's record
   load_levels(m, lv);
-  const int32_t lane = threadIdx.x & 63;
+  const int32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t G = (uint32_t)o.split_waves, per = 4 / G;
+  const uint32_t grp = (uint32_t)wave / G, g = (uint32_t)wave - grp * G;
   const uint32_t n = min(*o.qcount, o.qcap);
   const int32_t Lmax = clamp_level(o.max_level, m.top);
-  for (uint32_t e = blockIdx.x * 4 + (threadIdx.x >> 6); e < n; e += gridDim.x * 4) {
-    const uint4 q = o.queue[e];
-    const tci_view& v = views[q.x];
-    const int32_t px = (int32_t)(q.y % (uint32_t)v.w), py = (int32_t)(q.y / (uint32_t)v.w);
+  for (uint32_t e0 = blockIdx.x * per; e0 < n; e0 += gridDim.x * per) {
+    const uint32_t e = e0 + grp;
+    if (threadIdx.x < 4) best[threadIdx.x] = 0xFFFFFFFFu;
+    __syncthreads();
     ray_t r;
-    pixel_ray(v, px, py, r);
-    const int32_t axis = r.ax >= r.ay ? 0 : 1;
-    const int32_t c0 = (int32_t)q.z;   // first line still to walk
-    const int32_t dir = (axis == 0 ? r.Dx : r.Dy) > 0 ? 1 : -1;
-    const int32_t last = exit_line(r, m, axis);
-    const int64_t N = max((int64_t)1, (int64_t)(last - c0) * dir + 1);
-    const int32_t b0 = c0 + dir * (int32_t)(((int64_t)lane * N) >> 6);
-    const int32_t b1 = c0 + dir * (int32_t)(((int64_t)(lane + 1) * N) >> 6);
-    int32_t lo = INT32_MIN, hi = INT32_MAX;
-    if (lane < 63) {
-      if (dir > 0) hi = b1 - 1; else lo = b1 + 1;
-    }
     walk_t s;
     uint32_t col = 0;
     int32_t st = kSegEnd;
-    if (lane == 63 || b0 != b1) {
-      seg_init(r, s, axis, b0);
-      lift(r, s, clamp_level(o.start_level, Lmax));
-      st = kWalking;
+    int64_t idx = 0;
+    if (e < n) {
+      const uint4 q = o.queue[e];
+      const tci_view& v = views[q.x];
+      idx = v.out_base + q.y;
+      const int32_t px = (int32_t)(q.y % (uint32_t)v.w), py = (int32_t)(q.y / (uint32_t)v.w);
+      pixel_ray(v, px, py, r);
+      const int32_t axis = r.ax >= r.ay ? 0 : 1;
+      const int32_t c0 = (int32_t)q.z;   // first line still to walk
+      const int32_t dir = (axis == 0 ? r.Dx : r.Dy) > 0 ? 1 : -1;
+      const int32_t last = exit_line(r, m, axis);
+      const int64_t N = max((int64_t)1, (int64_t)(last - c0) * dir + 1);
+      const int64_t R = 64 * (int64_t)G;                // runs of the ray
+      const int64_t j = 64 * (int64_t)g + lane;         // this lane's run
+      const int32_t b0 = c0 + dir * (int32_t)((j * N) / R);
+      const int32_t b1 = c0 + dir * (int32_t)(((j + 1) * N) / R);
+      const bool open = j == R - 1;
+      int32_t lo = INT32_MIN, hi = INT32_MAX;
+      if (!open) {
+        if (dir > 0) hi = b1 - 1; else lo = b1 + 1;
+      }
+      if (open || b0 != b1) {
+        seg_init(r, s, axis, b0);
+        lift(r, s, clamp_level(o.start_level, Lmax));
+        st = kWalking;
+      }
+      // walk in chunks; once some run holds a hit, the runs after it
+      // cannot matter and stop
+      for (;;) {
+        const uint64_t hit_now = __ballot(st == kHitCell || st == kCapped);
+        const int32_t first = hit_now ? __ffsll((unsigned long long)hit_now) - 1 : 64;
+        if (st == kWalking && (lane > first || *(volatile uint32_t*)&best[grp] < 64 * g))
+          st = kSegEnd;
+        if (!__ballot(st == kWalking)) break;
+        if (st == kWalking)
+          st = walk_steps<true>(m, lv, r, s, Lmax, 16, col, 0, axis, lo, hi);
+      }
+      if (o.count && (open || b0 != b1)) atomicAdd(o.count, (unsigned long long)s.reads);
+      const uint64_t hits = __ballot(st == kHitCell || st == kCapped);
+      if (hits && lane == __ffsll((unsigned long long)hits) - 1) {
+        uint32_t word;
+        float depth;
+        finish(r, s, m.W, st, col, word, depth);
+        cand[wave] = make_uint2(word, __float_as_uint(depth));
+        atomicMin(&best[grp], 64 * g + (uint32_t)lane);
+      }
     }
-    // walk in chunks; once some segment holds a hit, the segments after it
-    // cannot matter and stop
-    for (;;) {
-      const uint64_t hit_now = __ballot(st == kHitCell || st == kCapped);
-      const int32_t first = hit_now ? __ffsll((unsigned long long)hit_now) - 1 : 64;
-      if (st == kWalking && lane > first) st = kSegEnd;
-      if (!__ballot(st == kWalking)) break;
-      if (st == kWalking)
-        st = walk_steps<true>(m, lv, r, s, Lmax, 16, col, 0, axis, lo, hi);
+    __syncthreads();
+    if (e < n && g == 0 && lane == 0) {
+      const uint32_t b = best[grp];
+      if (b == 0xFFFFFFFFu) {
+        tcp::store_hit(out, idx, kMiss, __builtin_inff());
+      } else {
+        const uint2 c = cand[grp * G + (b >> 6)];
+        tcp::store_hit(out, idx, c.x, __uint_as_float(c.y));
+      }
     }
-    if (o.count && (lane == 63 || b0 != b1)) atomicAdd(o.count, (unsigned long long)s.reads);
-    const uint64_t hits = __ballot(st == kHitCell || st == kCapped);
-    const int64_t idx = v.out_base + q.y;
-    if (hits == 0) {
-      if (lane == 0) tcp::store_hit(out, idx, kMiss, __builtin_inff());
-    } else if (lane == __ffsll((unsigned long long)hits) - 1) {
-      uint32_t word;
-      float depth;
-      finish(r, s, m.W, st, col, word, depth);
-      tcp::store_hit(out, idx, word, depth);
-    }
+    __syncthreads();
   }
 }
 

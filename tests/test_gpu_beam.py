@@ -208,3 +208,7 @@ def test_option_range(ctx):
         with pytest.raises(tc.TCError):
             ctx.tc_set_option(tc.TC_OPT_BEAM_PASSES, bad)
     assert ctx.tc_get_option(tc.TC_OPT_BEAM_PASSES) == 4
+    for bad in (0, 3, 8):
+        with pytest.raises(tc.TCError):
+            ctx.tc_set_option(tc.TC_OPT_SPLIT_WAVES, bad)
+    assert ctx.tc_get_option(tc.TC_OPT_SPLIT_WAVES) == 4

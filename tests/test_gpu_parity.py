@@ -223,11 +223,13 @@ def test_packet_orders_and_xcd_groups(ctx):
     ctx.tc_set_option(tc.TC_OPT_XCD_REMAP, 0)
 
 
-@pytest.mark.parametrize("budget,queue", [(1, 1 << 20), (5, 1 << 20), (1, 7), (30, 1000)])
-def test_split_pass(ctx, budget, queue):
+@pytest.mark.parametrize("budget,queue,waves", [(1, 1 << 20, 4), (5, 1 << 20, 1), (5, 1 << 20, 2),
+                                               (1, 7, 2), (30, 1000, 4)])
+def test_split_pass(ctx, budget, queue, waves):
     """Rays still walking after `budget` steps are finished by 64 parallel
-    segment walks; a tiny budget sends nearly every ray there, a tiny queue
-    leaves the overflow to the first pass.  Results must not change."""
+    segment walks per wave, `waves` waves per ray; a tiny budget sends
+    nearly every ray there, a tiny queue leaves the overflow to the first
+    pass.  Results must not change."""
     F, B, T = synth.make_map_from_config(1)
     load(ctx, F, B, T)
     rng = np.random.default_rng(13)
@@ -236,16 +238,18 @@ def test_split_pass(ctx, budget, queue):
     wo, do = oracle.render(F, B, T, views)
     ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, budget)
     ctx.tc_set_option(tc.TC_OPT_SPLIT_QUEUE, queue)
+    ctx.tc_set_option(tc.TC_OPT_SPLIT_WAVES, waves)
     try:
         for order, start in ((0, 0), (2, 2), (2, 5)):
             ctx.tc_set_option(tc.TC_OPT_TILE_ORDER, order)
             ctx.tc_set_option(tc.TC_OPT_START_LEVEL, start)
             wg, dg = gpu_render(ctx, views, "hier")
-            assert_parity(wg, dg, wo, do, "split budget %d queue %d start %d" % (
-                budget, queue, start))
+            assert_parity(wg, dg, wo, do, "split budget %d queue %d waves %d start %d" % (
+                budget, queue, waves, start))
     finally:
         ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 128)
         ctx.tc_set_option(tc.TC_OPT_SPLIT_QUEUE, 1 << 17)
+        ctx.tc_set_option(tc.TC_OPT_SPLIT_WAVES, 4)
         ctx.tc_set_option(tc.TC_OPT_TILE_ORDER, 2)
         ctx.tc_set_option(tc.TC_OPT_START_LEVEL, 2)
 
@@ -271,12 +275,14 @@ def test_split_pass_edge_rays_and_large_map(ctx):
         load(ctx, F, B, T)
         v = synth.config_views(2, F, B)
         wo, do = oracle.render(F, B, T, v)
-        for budget in (8, 96):
+        for budget, waves in ((8, 4), (96, 1), (96, 2)):
             ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, budget)
+            ctx.tc_set_option(tc.TC_OPT_SPLIT_WAVES, waves)
             wg, dg = gpu_render(ctx, v, "hier")
-            assert_parity(wg, dg, wo, do, "split c2 budget %d" % budget)
+            assert_parity(wg, dg, wo, do, "split c2 budget %d waves %d" % (budget, waves))
     finally:
         ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 128)
+        ctx.tc_set_option(tc.TC_OPT_SPLIT_WAVES, 4)
 
 
 def test_straight_down_closed_form_large_map(ctx):

@@ -401,25 +401,29 @@ def c4_batched(torch, tc, synth, steps, warmup):
 
 
 def c5_served(torch, tc, synth, rates=(200, 500, 1000, 2000, 5000, 10000),
-              n_per_rate=1500):
+              n_per_rate=1500, min_seconds=1.5):
     """Configuration 5: Poisson request streams against the resident
     2048x16384 map; 90% views (sizes and poses as configuration 4), 10%
     craters of size 16-64; an 8 GiB in-flight hit-buffer budget.  Served:
     continuous batching (up to 8 views per batch, 2 streams).  FIFO plain:
     the same server with one view per batch on one stream.  Latency runs
-    from submission to observed completion."""
+    from submission to observed completion.  Each rate gets at least
+    n_per_rate requests and at least min_seconds of arrivals, so the p99 of
+    the fast rates rests on thousands of requests."""
     F, B, T = synth.make_map_from_config(5)
     H, W = F.shape
     seeds = synth.SEEDS[5]
     ctx = tc.Context(0)
     out = {"workload": "c5: 2048x16384 map resident, Poisson arrivals, 90% views "
                        "(256^2..1920x1080) / 10% craters (16..64), 8 GiB in-flight budget",
-           "requests_per_rate": n_per_rate, "rates": {}}
+           "requests_per_rate": {}, "rates": {}}
     for rate in rates:
+        nreq = max(n_per_rate, int(rate * min_seconds))
+        out["requests_per_rate"][str(rate)] = nreq
         rng = np.random.default_rng(seeds["views"] * 10 + rate)
-        arr = synth.poisson_arrivals(seeds["arrivals"] * 10 + rate, rate, n_per_rate)
+        arr = synth.poisson_arrivals(seeds["arrivals"] * 10 + rate, rate, nreq)
         reqs = []
-        for _ in range(n_per_rate):
+        for _ in range(nreq):
             if rng.random() < 0.1:
                 reqs.append(("edit", synth.crater_list(rng, W, H, 1, size=(16, 64))))
             else:

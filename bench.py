@@ -18,6 +18,10 @@ import time
 import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
+# the sources of the headline traversal kernels (the committed profiles
+# record their hash)
+RENDER_SRCS = [os.path.join(ROOT, "paper_2608_17390_amd", "csrc", f)
+               for f in ("tc_walk.h", "tc_beam.h", "tc_packet.h", "tc_render.hip")]
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
@@ -33,28 +37,27 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def traffic_from_profile(kernel_srcs, launches_key="render_c2"):
-    """HBM bytes per launch measured by rocprofv3 (FETCH_SIZE + WRITE_SIZE,
-    scaled by a plain copy's readings), if the committed profile was taken
-    on the current render sources (sha256 over the files in order); else
-    None."""
+def profile_value(kernel_srcs, name, key):
+    """A figure measured by rocprofv3 and committed under profiles/ (the
+    line `key: value` of profiles/<name>.txt), if that profile was taken on
+    the current render sources (its render_source_sha256 line matches the
+    sha256 over the files in order); else None."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "%s_traffic.txt" % launches_key)
+    path = os.path.join(ROOT, "profiles", "%s.txt" % name)
     if not os.path.exists(path):
         return None
     try:
         keys = {}
         for line in open(path):
             k, sep, v = line.partition(":")
-            if sep and k.strip() in ("render_source_sha256", "hbm_bytes_per_launch"):
+            if sep and k.strip() in ("render_source_sha256", key):
                 keys[k.strip()] = v.strip()
         h = hashlib.sha256()
         for f in kernel_srcs:
             h.update(open(f, "rb").read())
-        sha = h.hexdigest()
-        if keys.get("render_source_sha256") != sha:
+        if keys.get("render_source_sha256") != h.hexdigest():
             return None
-        return float(keys["hbm_bytes_per_launch"])
+        return float(keys[key])
     except (ValueError, KeyError, OSError):
         return None
 
@@ -554,9 +557,14 @@ def main():
                    "frame_ms_median": med, "frame_ms_p99": float(np.percentile(ms, 99))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-                     "traffic": traffic_from_profile(
-                         [os.path.join(ROOT, "paper_2608_17390_amd", "csrc", f)
-                          for f in ("tc_walk.h", "tc_beam.h", "tc_packet.h", "tc_render.hip")]),
+                     # HBM bytes per traversal (FETCH_SIZE + WRITE_SIZE, copy-calibrated)
+                     "traffic": profile_value(RENDER_SRCS, "render_c2_traffic",
+                                              "hbm_bytes_per_launch"),
+                     # the roof that binds: share of the first pass's lifetime the
+                     # SIMDs spend issuing VALU instructions (SQ_INSTS_VALU x 4
+                     # cycles over 1024 SIMDs x GRBM_GUI_ACTIVE per XCD)
+                     "valu_busy_frac": profile_value(RENDER_SRCS, "render_c2_counters",
+                                                     "valu_busy_frac"),
                      "kernel": KERNEL_NAMES[args.mode],
                      "alg_bytes_per_launch": alg_bytes,
                      "kernel_ms_avg": kavg,

@@ -104,6 +104,42 @@ def test_bruteforce_random_and_adversarial(seed):
     assert n_rays == 1600
 
 
+def _sweep_chunk(seed):
+    """One chunk of the large brute-force sweep: 50 maps of 1x1..12x12
+    cells, 40 random and adversarial rays each.  Returns (rays checked,
+    first failure or None)."""
+    rng = np.random.default_rng(5000 + seed)
+    n = 0
+    for trial in range(50):
+        W, H = int(rng.integers(1, 13)), int(rng.integers(1, 13))
+        F, B, T = _random_map(rng, W, H, hmax=int(rng.choice([4, 24, 250])))
+        O, D = _adversarial_rays(rng, W, H, 40)
+        w, d, tn, td = oracle.cast_rays_exact(F, B, T, O, D)
+        Fl, Bl, Tl = F.tolist(), B.tolist(), T.tolist()
+        for i in range(len(O)):
+            msg = bf.check_ray(Fl, Bl, Tl, tuple(int(v) for v in O[i]),
+                               tuple(int(v) for v in D[i]), int(w[i]),
+                               int(tn[i]), int(td[i]))
+            if msg is not None:
+                return n, (msg, seed, trial, W, H, O[i].tolist(), D[i].tolist())
+            n += 1
+    return n, None
+
+
+def test_bruteforce_sweep_100k_rays():
+    """100,000 random and adversarial rays (axis-aligned, vertical, along
+    cell edges, through lattice corners, at integer heights) on 2,500
+    random maps of 1x1..12x12 cells with low, medium and full height
+    ranges, each checked against every solid box of every cell in exact
+    rationals."""
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        res = list(ex.map(_sweep_chunk, range(50)))
+    fails = [f for _, f in res if f is not None]
+    assert not fails, fails[0]
+    assert sum(n for n, _ in res) == 100000
+
+
 def test_bruteforce_larger_maps():
     rng = np.random.default_rng(7)
     for trial in range(6):

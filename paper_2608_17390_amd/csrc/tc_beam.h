@@ -40,9 +40,11 @@ constexpr float kBeamLog2Growth = 0.169925f; // log2(1 + kBeamGrowth)
 __device__ __forceinline__ bool beam_box_solid(const tci_map& m, const lvl_t* lv, float lox,
                                                float hix, float loy, float hiy, float loz,
                                                float hiz, int32_t& reads) {
+  // no claim for a box with a NaN bound (never formed from valid views)
+  if (!(lox <= hix && loy <= hiy && loz <= hiz)) return true;
   if (loz > 255.0f) return false;               // above every height
   const float ext = fmaxf(hix - lox, hiy - loy);
-  if (!(ext < 65536.0f)) return true;           // no claim for huge or NaN boxes
+  if (!(ext < 65536.0f)) return true;           // no claim for huge boxes
   // 2^L > ext: the box overlaps at most two nodes per axis at level L
   int32_t L = ext < 1.0f ? 0 : __builtin_amdgcn_frexp_expf(ext);
   L = min(L, m.top);

@@ -63,17 +63,26 @@ __device__ __forceinline__ void render_body(
     // direction (a packet's rays mostly share it; a wave holding both signs
     // runs the two loops one after the other)
     const bool down = r.Dz < 0;
+    walk_idx_t k;
+    if constexpr (!kOcc) walk_idx_init(r, s, k);
     int32_t st;
     for (;;) {
       // the budget bounds the walk: at most the split budget, then (or
       // without a split pass) kIterCap + 1 iterations
       const int32_t budget = split ? o.split_budget : kIterCap + 1;
-      if (down)
-        st = walk_steps<false, kOcc, false, 1>(m, lv, r, s, Lmax, budget, col, boost, 0, 0, 0,
-                                               moff, o.count != nullptr);
-      else
-        st = walk_steps<false, kOcc, false, 2>(m, lv, r, s, Lmax, budget, col, boost, 0, 0, 0,
-                                               moff, o.count != nullptr);
+      if constexpr (kOcc) {
+        if (down)
+          st = walk_steps<false, true, false, 1>(m, lv, r, s, Lmax, budget, col, boost, 0, 0, 0,
+                                                 moff, o.count != nullptr);
+        else
+          st = walk_steps<false, true, false, 2>(m, lv, r, s, Lmax, budget, col, boost, 0, 0, 0,
+                                                 moff, o.count != nullptr);
+      } else {
+        if (down)
+          st = walk_steps_idx<1>(m, lv, r, k, s, Lmax, budget, col, boost, o.count != nullptr);
+        else
+          st = walk_steps_idx<2>(m, lv, r, k, s, Lmax, budget, col, boost, o.count != nullptr);
+      }
       if (!split) break;
       split = false;
       // long walks go to the split pass, as many as the queue holds

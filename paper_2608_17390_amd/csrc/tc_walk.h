@@ -502,6 +502,137 @@ __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
   return kWalking;
 }
 
+// Index form of the walk, for the one-thread-per-pixel render loop.  The
+// crossing through the far x face of node (ni, L) is x crossing number
+//   ix = ((ni + 1) << L) - 1 - ax0  (Dx > 0),   ax0 - (ni << L)  (Dx <= 0)
+// counted from the anchor cell ax0 (never negative: the far face lies
+// ahead of the anchor), so its key is KX0 + ix * ay and its height
+// ZX0 + ix * Dz; likewise for y.  The loop therefore carries the node, the
+// level and the entry crossing only: a step, a climb or a descent changes
+// 32-bit node coordinates, and the far-face keys and heights follow from
+// them.  It makes exactly the tests, in the same order, that walk_steps
+// makes, so the two agree on every ray.
+struct walk_idx_t {
+  int64_t KX0, KY0;   // keys of crossing number 0 of each axis
+  int64_t ZX0, ZY0;   // heights at those crossings
+  int32_t offx, offy; // ix = sx ((ni + f) << L) + offx (f = 1 iff Dx > 0), likewise for y
+};
+
+// (n + f) << L with f = 1 when the axis runs forward, times s = +-1, plus
+// off: |(n + f) << L| stays below 2^23 (cell coordinates are within
+// +-2^16), so one 24-bit multiply-add.
+__device__ __forceinline__ int32_t far_index(int32_t n, int32_t L, int32_t f, int32_t s,
+                                             int32_t off) {
+  return __mul24(s, (n + f) << L) + off;
+}
+
+// Constants of the index form from a walk state of walk_init or seg_init
+// (and lift).
+__device__ __forceinline__ void walk_idx_init(const ray_t& r, const walk_t& s, walk_idx_t& k) {
+  k.offx = r.Dx > 0 ? -1 - r.cx0 : r.cx0;
+  k.offy = r.Dy > 0 ? -1 - r.cy0 : r.cy0;
+  const int32_t ix = far_index(s.ni, s.L, r.Dx > 0, r.Dx > 0 ? 1 : -1, k.offx);
+  const int32_t iy = far_index(s.nj, s.L, r.Dy > 0, r.Dy > 0 ? 1 : -1, k.offy);
+  k.KX0 = s.KXe - (int64_t)mul48((uint32_t)ix, r.ay);
+  k.KY0 = s.KYe - (int64_t)mul48((uint32_t)iy, r.ax);
+  k.ZX0 = s.ZXe - smul48(ix, r.Dz);
+  k.ZY0 = s.ZYe - smul48(iy, r.Dz);
+}
+
+// walk_steps (no segment bound, no iteration counter, no occupancy masks)
+// in index form; kDir as there.
+template <int kDir>
+__device__ __forceinline__ int32_t walk_steps_idx(const tci_map& m, const lvl_t* lv,
+                                                  const ray_t& r, const walk_idx_t& k,
+                                                  walk_t& s, int32_t max_level, int32_t budget,
+                                                  uint32_t& col, int32_t boost, bool count) {
+  const bool desc = kDir == 1 ? true : (kDir == 2 ? false : r.Dz < 0);
+  const bool fx = r.Dx > 0, fy = r.Dy > 0;
+  const int32_t sx = fx ? 1 : -1, sy = fy ? 1 : -1;
+  const int32_t nx1 = fx ? 1 : 0, ny1 = fy ? 1 : 0;
+  const int32_t nearx = 1 - nx1, neary = 1 - ny1;
+  for (int32_t it = 0; it < budget; ++it) {
+    if (boost > 0) {
+      if (it == boost) __builtin_amdgcn_s_setprio(1);
+      else if (it == 2 * boost) __builtin_amdgcn_s_setprio(2);
+      else if (it == 4 * boost) __builtin_amdgcn_s_setprio(3);
+    }
+    const int32_t L = s.L;
+    const lvl_t l = lv[L];
+    const bool inmap = (uint32_t)s.ni < (uint32_t)l.w && (uint32_t)s.nj < (uint32_t)l.h;
+    uint32_t v = 0;
+    if (count) s.reads += inmap ? 1 : 0;
+    if (inmap)
+      v = m.base[l.off + ((__umul24((uint32_t)s.nj >> 3, (uint32_t)l.tiles_x) +
+                           ((uint32_t)s.ni >> 3)) << 6) +
+                 ((s.nj & 7) << 3) + (s.ni & 7)];
+    // keys and heights of the crossings through the node's far faces
+    const int32_t ix = far_index(s.ni, L, nx1, sx, k.offx);
+    const int32_t iy = far_index(s.nj, L, ny1, sy, k.offy);
+    const int64_t KXe = k.KX0 + (int64_t)mul48((uint32_t)ix, r.ay);
+    const int64_t KYe = k.KY0 + (int64_t)mul48((uint32_t)iy, r.ax);
+    const bool ex = KXe <= KYe;               // leave through an x face
+    const int64_t Ze = (ex ? k.ZX0 : k.ZY0) + smul48(ex ? ix : iy, r.Dz);
+    const uint32_t De = ex ? r.ax : r.ay;
+    const uint32_t re = ex ? r.rx : r.ry;
+    bool occ = false;
+    if (inmap) {
+      const int64_t lo = (desc ? Ze : s.Zin) + (int64_t)(desc ? re : s.rin);
+      const uint32_t Dlo = desc ? De : s.Din;
+      const int64_t hi = desc ? s.Zin : Ze;
+      const uint32_t Dhi = desc ? s.Din : De;
+      const uint32_t a = v & 0xFF, b = (v >> 8) & 0xFF, c = (v >> 16) & 0xFF;
+      occ = (lo <= (int64_t)__umul24(a, Dlo)) ||
+            ((lo <= (int64_t)__umul24(c, Dlo)) && (hi >= (int64_t)__umul24(b, Dhi)));
+    }
+    if (occ) {
+      if (L == 0) {
+        col = v;
+        return kHitCell;
+      }
+      // descend into the child holding the ray after the entry crossing
+      const int32_t Lc = L - 1;
+      int32_t bx, by;
+      const bool anchored = (s.entry & kAnchored) != 0;
+      if (r.Dx == 0 || anchored) bx = (r.cx0 >> Lc) & 1;
+      else if (s.entry == kWmx || s.entry == kWpx) bx = nearx;
+      else bx = (KXe - ushl(r.ay, Lc) <= s.Kin) ? 1 - nearx : nearx;
+      if (r.Dy == 0 || anchored) by = (r.cy0 >> Lc) & 1;
+      else if (s.entry == kWmy || s.entry == kWpy) by = neary;
+      else by = (KYe - ushl(r.ax, Lc) < s.Kin) ? 1 - neary : neary;
+      s.ni = 2 * s.ni + bx;
+      s.nj = 2 * s.nj + by;
+      s.L = Lc;
+      continue;
+    }
+    // step to the next node of this level through the exit face
+    const int32_t pi = s.ni, pj = s.nj;
+    s.Kin = ex ? KXe : KYe;
+    if (ex) {
+      s.ni += sx;
+      s.entry = fx ? kWmx : kWpx;
+    } else {
+      s.nj += sy;
+      s.entry = fy ? kWmy : kWpy;
+    }
+    s.Zin = Ze;
+    s.Din = De;
+    s.rin = re;
+    // the ray cannot come back into the map, or is above all solid
+    const bool away = (s.ni < 0 && r.Dx <= 0) || (s.ni >= l.w && r.Dx >= 0) ||
+                      (s.nj < 0 && r.Dy <= 0) || (s.nj >= l.h && r.Dy >= 0);
+    const bool above = !desc && !z_le(s.Zin, s.rin, 255, s.Din);
+    if (away || above) return kMissed;
+    // go up one level when the step entered a new parent node
+    if (L < max_level && (((pi ^ s.ni) | (pj ^ s.nj)) >> 1) != 0) {
+      s.ni >>= 1;
+      s.nj >>= 1;
+      s.L = L + 1;
+    }
+  }
+  return kWalking;
+}
+
 __device__ __forceinline__ void load_levels(const tci_map& m, lvl_t* lv) {
   if (threadIdx.x < TCI_MAX_LEVELS) {
     const tci_level& l = m.lv[threadIdx.x];

@@ -64,25 +64,18 @@ __device__ __forceinline__ void render_body(
     // runs the two loops one after the other)
     const bool down = r.Dz < 0;
     walk_idx_t k;
-    if constexpr (!kOcc) walk_idx_init(r, s, k);
+    walk_idx_init(r, s, k);
     int32_t st;
     for (;;) {
       // the budget bounds the walk: at most the split budget, then (or
       // without a split pass) kIterCap + 1 iterations
       const int32_t budget = split ? o.split_budget : kIterCap + 1;
-      if constexpr (kOcc) {
-        if (down)
-          st = walk_steps<false, true, false, 1>(m, lv, r, s, Lmax, budget, col, boost, 0, 0, 0,
-                                                 moff, o.count != nullptr);
-        else
-          st = walk_steps<false, true, false, 2>(m, lv, r, s, Lmax, budget, col, boost, 0, 0, 0,
-                                                 moff, o.count != nullptr);
-      } else {
-        if (down)
-          st = walk_steps_idx<1>(m, lv, r, k, s, Lmax, budget, col, boost, o.count != nullptr);
-        else
-          st = walk_steps_idx<2>(m, lv, r, k, s, Lmax, budget, col, boost, o.count != nullptr);
-      }
+      if (down)
+        st = walk_steps<false, kOcc, false, 1>(m, lv, r, k, s, Lmax, budget, col, boost, 0, 0,
+                                               0, moff, o.count != nullptr);
+      else
+        st = walk_steps<false, kOcc, false, 2>(m, lv, r, k, s, Lmax, budget, col, boost, 0, 0,
+                                               0, moff, o.count != nullptr);
       if (!split) break;
       split = false;
       // long walks go to the split pass, as many as the queue holds
@@ -223,9 +216,11 @@ __global__ __launch_bounds__(256) void split_kernel(tci_map m,
       if (!open) {
         if (dir > 0) hi = b1 - 1; else lo = b1 + 1;
       }
+      walk_idx_t k;
       if (open || b0 != b1) {
         seg_init(r, s, axis, b0);
         lift(r, s, clamp_level(o.start_level, Lmax));
+        walk_idx_init(r, s, k);
         st = kWalking;
       }
       // walk in chunks; once some run holds a hit, the runs after it
@@ -237,7 +232,7 @@ __global__ __launch_bounds__(256) void split_kernel(tci_map m,
           st = kSegEnd;
         if (!__ballot(st == kWalking)) break;
         if (st == kWalking)
-          st = walk_steps<true>(m, lv, r, s, Lmax, 16, col, 0, axis, lo, hi);
+          st = walk_steps<true>(m, lv, r, k, s, Lmax, 16, col, 0, axis, lo, hi);
       }
       if (o.count && (open || b0 != b1)) atomicAdd(o.count, (unsigned long long)s.reads);
       const uint64_t hits = __ballot(st == kHitCell || st == kCapped);
@@ -287,6 +282,7 @@ __global__ __launch_bounds__(256) void render_persistent_kernel(
   bool active = false;
   ray_t r;
   walk_t s;
+  walk_idx_t k;
   int64_t out_idx = 0;
   for (;;) {
     const uint64_t idle = __ballot(!active);
@@ -322,6 +318,7 @@ __global__ __launch_bounds__(256) void render_persistent_kernel(
               tcp::store_hit(out, out_idx, word, depth);
             } else {
               walk_init(r, L0, s);
+              walk_idx_init(r, s, k);
               active = true;
             }
           }
@@ -337,7 +334,7 @@ __global__ __launch_bounds__(256) void render_persistent_kernel(
     if (drained && __ballot(active) == 0) break;
     int32_t st = kWalking;
     uint32_t col = 0;
-    if (active) st = walk_steps(m, lv, r, s, Lmax, iters, col);
+    if (active) st = walk_steps(m, lv, r, k, s, Lmax, iters, col);
     if (st != kWalking) {
       uint32_t word;
       float depth;

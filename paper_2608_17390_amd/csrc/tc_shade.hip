@@ -79,8 +79,10 @@ __device__ __forceinline__ bool occluded(const tci_map& m, const lvl_t* lv, cons
   }
   walk_t st;
   walk_init(s, L0, st);
+  walk_idx_t k;
+  walk_idx_init(s, st, k);
   uint32_t col = 0;
-  const int32_t res = walk_steps<false, false, true, kDir>(m, lv, s, st, Lmax, kIterCap + 1, col);
+  const int32_t res = walk_steps<false, false, true, kDir>(m, lv, s, k, st, Lmax, kIterCap + 1, col);
   reads += st.reads;
   return res == kHitCell || res == kCapped;
 }

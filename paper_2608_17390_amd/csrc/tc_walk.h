@@ -90,18 +90,20 @@ struct ray_t {
 //           has height ZX0 + i*Dz and there
 //           z <= h  iff  height + rx <= h*ax,   z >= h  iff  height >= h*ax.
 //           Likewise for y.
-// The walk runs on the node grid of its current pyramid level L and keeps,
-// for the current node, the keys and heights of the crossings through its
-// far x and y faces: a step to the next node adds a << L to one of each,
-// a climb or a descent adds or removes half a node, and the child holding
-// the ray is the one on the near side of each middle crossing that happens
-// after the entry crossing.  The walk therefore enters exactly the cells
-// the flat walk enters, at the same keys.
+// The walk runs on the node grid of its current pyramid level L.  For the
+// current node it needs the keys and heights of the crossings through the
+// far x and y faces (a step to the next node moves one of each by a << L,
+// a climb or a descent by half a node) and the child holding the ray is the
+// one on the near side of each middle crossing that happens after the
+// entry crossing.  The walk therefore enters exactly the cells the flat
+// walk enters, at the same keys.  walk_init, seg_init and lift set the
+// far-face keys and heights below; the walk loop itself derives them from
+// the node (walk_idx_t).
 struct walk_t {
   int32_t ni, nj;     // node indices at level L
   int32_t L;          // current pyramid level
   int64_t KXe, KYe;   // keys of the crossings through the far x / y faces
-  int64_t ZXe, ZYe;   // heights at those crossings
+  int64_t ZXe, ZYe;   // heights at those crossings (set at the walk's start)
   int64_t Kin;        // key of the entry crossing (unused while kInside)
   int64_t Zin;        // height at entry of the current node
   uint32_t Din;       // its scale: 1 at the origin, else ax or ay
@@ -269,9 +271,6 @@ __device__ __forceinline__ void trace_vertical(const tci_map& m,
                 word, depth);
 }
 
-// Advance the walk by up to `budget` iterations.  Returns kWalking if the
-// budget ran out, else the final state; on kHitCell, `col` holds the
-// column of the current cell (s.ni, s.nj at level 0).
 // Number of terms K + j*a, j >= 0, strictly below E, for counts below 2^24
 // and E - K < 2^47: a float estimate of the quotient, then one exact
 // correction.
@@ -348,6 +347,47 @@ __device__ __forceinline__ void lift(const ray_t& r, walk_t& s, int32_t L) {
   s.L = L;
 }
 
+// Index form of the walk.  The crossing through the far x face of node
+// (ni, L) is x crossing number
+//   ix = ((ni + 1) << L) - 1 - ax0  (Dx > 0),   ax0 - (ni << L)  (Dx <= 0)
+// counted from the anchor cell ax0 (never negative: the far face lies
+// ahead of the anchor), so its key is KX0 + ix * ay and its height
+// ZX0 + ix * Dz; likewise for y.  The loop therefore carries the node, the
+// level and the entry crossing only: a step, a climb or a descent changes
+// 32-bit node coordinates, and the far-face keys and heights follow from
+// them (the keys and heights walk_init, seg_init and lift leave in walk_t
+// only seed the constants).
+struct walk_idx_t {
+  int64_t KX0, KY0;   // keys of crossing number 0 of each axis
+  int64_t ZX0, ZY0;   // heights at those crossings
+  int32_t offx, offy; // ix = sx ((ni + f) << L) + offx (f = 1 iff Dx > 0), likewise for y
+};
+
+// (n + f) << L with f = 1 when the axis runs forward, times s = +-1, plus
+// off: |(n + f) << L| stays below 2^23 (cell coordinates are within
+// +-2^16), so one 24-bit multiply-add.
+__device__ __forceinline__ int32_t far_index(int32_t n, int32_t L, int32_t f, int32_t s,
+                                             int32_t off) {
+  return __mul24(s, (n + f) << L) + off;
+}
+
+// Constants of the index form from a walk state of walk_init or seg_init
+// (and lift).
+__device__ __forceinline__ void walk_idx_init(const ray_t& r, const walk_t& s, walk_idx_t& k) {
+  k.offx = r.Dx > 0 ? -1 - r.cx0 : r.cx0;
+  k.offy = r.Dy > 0 ? -1 - r.cy0 : r.cy0;
+  const int32_t ix = far_index(s.ni, s.L, r.Dx > 0, r.Dx > 0 ? 1 : -1, k.offx);
+  const int32_t iy = far_index(s.nj, s.L, r.Dy > 0, r.Dy > 0 ? 1 : -1, k.offy);
+  k.KX0 = s.KXe - (int64_t)mul48((uint32_t)ix, r.ay);
+  k.KY0 = s.KYe - (int64_t)mul48((uint32_t)iy, r.ax);
+  k.ZX0 = s.ZXe - smul48(ix, r.Dz);
+  k.ZY0 = s.ZYe - smul48(iy, r.Dz);
+}
+
+// Advance the walk by up to `budget` iterations.  Returns kWalking if the
+// budget ran out, else the final state; on kHitCell, `col` holds the
+// column of the current cell (s.ni, s.nj at level 0).  k holds the ray's
+// index-form constants (walk_idx_init after the state's initialisation).
 // With boost > 0 (wave-uniform loop only), a wave raises its instruction
 // issue priority after boost, 2*boost and 4*boost iterations: the few long
 // walks of a launch, which otherwise trail it, then win issue slots over
@@ -368,7 +408,7 @@ __device__ __forceinline__ void lift(const ray_t& r, walk_t& s, int32_t L) {
 // so the loop carries no per-lane selects on it.
 template <bool kSeg = false, bool kOcc = false, bool kCap = true, int kDir = 0>
 __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
-                                              const ray_t& r, walk_t& s,
+                                              const ray_t& r, const walk_idx_t& k, walk_t& s,
                                               int32_t max_level, int32_t budget,
                                               uint32_t& col, int32_t boost = 0,
                                               int32_t seg_axis = 0,
@@ -376,8 +416,10 @@ __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
                                               const uint32_t* moff = nullptr,
                                               bool count = true) {
   const bool desc = kDir == 1 ? true : (kDir == 2 ? false : r.Dz < 0);
-  const int32_t sx = r.Dx > 0 ? 1 : -1, sy = r.Dy > 0 ? 1 : -1;
-  const int32_t nearx = r.Dx > 0 ? 0 : 1, neary = r.Dy > 0 ? 0 : 1;
+  const bool fx = r.Dx > 0, fy = r.Dy > 0;
+  const int32_t sx = fx ? 1 : -1, sy = fy ? 1 : -1;
+  const int32_t nx1 = fx ? 1 : 0, ny1 = fy ? 1 : 0;
+  const int32_t nearx = 1 - nx1, neary = 1 - ny1;
   for (int32_t it = 0; it < budget; ++it) {
     if (boost > 0) {
       if (it == boost) __builtin_amdgcn_s_setprio(1);
@@ -400,8 +442,13 @@ __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
       v = m.base[l.off + ((__umul24((uint32_t)s.nj >> 3, (uint32_t)l.tiles_x) +
                            ((uint32_t)s.ni >> 3)) << 6) +
                  ((s.nj & 7) << 3) + (s.ni & 7)];
-    const bool ex = s.KXe <= s.KYe;           // leave through an x face
-    const int64_t Ze = ex ? s.ZXe : s.ZYe;
+    // keys and heights of the crossings through the node's far faces
+    const int32_t ix = far_index(s.ni, L, nx1, sx, k.offx);
+    const int32_t iy = far_index(s.nj, L, ny1, sy, k.offy);
+    const int64_t KXe = k.KX0 + (int64_t)mul48((uint32_t)ix, r.ay);
+    const int64_t KYe = k.KY0 + (int64_t)mul48((uint32_t)iy, r.ax);
+    const bool ex = KXe <= KYe;               // leave through an x face
+    const int64_t Ze = (ex ? k.ZX0 : k.ZY0) + smul48(ex ? ix : iy, r.Dz);
     const uint32_t De = ex ? r.ax : r.ay;
     const uint32_t re = ex ? r.rx : r.ry;
     bool occ = false;
@@ -430,160 +477,6 @@ __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
           occ = (mask & range) != 0;
         }
       }
-    }
-    if (occ) {
-      if (L == 0) {
-        col = v;
-        return kHitCell;
-      }
-      // descend into the child holding the ray after the entry crossing
-      const int32_t Lc = L - 1;
-      const int64_t midx = s.KXe - ushl(r.ay, Lc), midy = s.KYe - ushl(r.ax, Lc);
-      int32_t bx, by;
-      const bool anchored = (s.entry & kAnchored) != 0;
-      if (r.Dx == 0 || anchored) bx = (r.cx0 >> Lc) & 1;
-      else if (s.entry == kWmx || s.entry == kWpx) bx = nearx;
-      else bx = (midx <= s.Kin) ? 1 - nearx : nearx;
-      if (r.Dy == 0 || anchored) by = (r.cy0 >> Lc) & 1;
-      else if (s.entry == kWmy || s.entry == kWpy) by = neary;
-      else by = (midy < s.Kin) ? 1 - neary : neary;
-      if (bx == nearx) {
-        s.KXe = midx;
-        s.ZXe -= sshl(r.Dz, Lc);
-      }
-      if (by == neary) {
-        s.KYe = midy;
-        s.ZYe -= sshl(r.Dz, Lc);
-      }
-      s.ni = 2 * s.ni + bx;
-      s.nj = 2 * s.nj + by;
-      s.L = Lc;
-      continue;
-    }
-    // step to the next node of this level through the exit face
-    const int32_t pi = s.ni, pj = s.nj;
-    if (ex) {
-      s.Kin = s.KXe;
-      s.KXe += ushl(r.ay, L);
-      s.ZXe += sshl(r.Dz, L);
-      s.ni += sx;
-      s.entry = r.Dx > 0 ? kWmx : kWpx;
-    } else {
-      s.Kin = s.KYe;
-      s.KYe += ushl(r.ax, L);
-      s.ZYe += sshl(r.Dz, L);
-      s.nj += sy;
-      s.entry = r.Dy > 0 ? kWmy : kWpy;
-    }
-    s.Zin = Ze;
-    s.Din = De;
-    s.rin = re;
-    // the ray cannot come back into the map, or is above all solid
-    const bool away = (s.ni < 0 && r.Dx <= 0) || (s.ni >= l.w && r.Dx >= 0) ||
-                      (s.nj < 0 && r.Dy <= 0) || (s.nj >= l.h && r.Dy >= 0);
-    const bool above = !desc && !z_le(s.Zin, s.rin, 255, s.Din);
-    if (away || above) return kMissed;
-    // go up one level when the step entered a new parent node; the new node
-    // is then the near half of its parent along the exit axis
-    if (L < max_level && (((pi ^ s.ni) | (pj ^ s.nj)) >> 1) != 0) {
-      if (ex || (s.ni & 1) == nearx) {
-        s.KXe += ushl(r.ay, L);
-        s.ZXe += sshl(r.Dz, L);
-      }
-      if (!ex || (s.nj & 1) == neary) {
-        s.KYe += ushl(r.ax, L);
-        s.ZYe += sshl(r.Dz, L);
-      }
-      s.ni >>= 1;
-      s.nj >>= 1;
-      s.L = L + 1;
-    }
-  }
-  return kWalking;
-}
-
-// Index form of the walk, for the one-thread-per-pixel render loop.  The
-// crossing through the far x face of node (ni, L) is x crossing number
-//   ix = ((ni + 1) << L) - 1 - ax0  (Dx > 0),   ax0 - (ni << L)  (Dx <= 0)
-// counted from the anchor cell ax0 (never negative: the far face lies
-// ahead of the anchor), so its key is KX0 + ix * ay and its height
-// ZX0 + ix * Dz; likewise for y.  The loop therefore carries the node, the
-// level and the entry crossing only: a step, a climb or a descent changes
-// 32-bit node coordinates, and the far-face keys and heights follow from
-// them.  It makes exactly the tests, in the same order, that walk_steps
-// makes, so the two agree on every ray.
-struct walk_idx_t {
-  int64_t KX0, KY0;   // keys of crossing number 0 of each axis
-  int64_t ZX0, ZY0;   // heights at those crossings
-  int32_t offx, offy; // ix = sx ((ni + f) << L) + offx (f = 1 iff Dx > 0), likewise for y
-};
-
-// (n + f) << L with f = 1 when the axis runs forward, times s = +-1, plus
-// off: |(n + f) << L| stays below 2^23 (cell coordinates are within
-// +-2^16), so one 24-bit multiply-add.
-__device__ __forceinline__ int32_t far_index(int32_t n, int32_t L, int32_t f, int32_t s,
-                                             int32_t off) {
-  return __mul24(s, (n + f) << L) + off;
-}
-
-// Constants of the index form from a walk state of walk_init or seg_init
-// (and lift).
-__device__ __forceinline__ void walk_idx_init(const ray_t& r, const walk_t& s, walk_idx_t& k) {
-  k.offx = r.Dx > 0 ? -1 - r.cx0 : r.cx0;
-  k.offy = r.Dy > 0 ? -1 - r.cy0 : r.cy0;
-  const int32_t ix = far_index(s.ni, s.L, r.Dx > 0, r.Dx > 0 ? 1 : -1, k.offx);
-  const int32_t iy = far_index(s.nj, s.L, r.Dy > 0, r.Dy > 0 ? 1 : -1, k.offy);
-  k.KX0 = s.KXe - (int64_t)mul48((uint32_t)ix, r.ay);
-  k.KY0 = s.KYe - (int64_t)mul48((uint32_t)iy, r.ax);
-  k.ZX0 = s.ZXe - smul48(ix, r.Dz);
-  k.ZY0 = s.ZYe - smul48(iy, r.Dz);
-}
-
-// walk_steps (no segment bound, no iteration counter, no occupancy masks)
-// in index form; kDir as there.
-template <int kDir>
-__device__ __forceinline__ int32_t walk_steps_idx(const tci_map& m, const lvl_t* lv,
-                                                  const ray_t& r, const walk_idx_t& k,
-                                                  walk_t& s, int32_t max_level, int32_t budget,
-                                                  uint32_t& col, int32_t boost, bool count) {
-  const bool desc = kDir == 1 ? true : (kDir == 2 ? false : r.Dz < 0);
-  const bool fx = r.Dx > 0, fy = r.Dy > 0;
-  const int32_t sx = fx ? 1 : -1, sy = fy ? 1 : -1;
-  const int32_t nx1 = fx ? 1 : 0, ny1 = fy ? 1 : 0;
-  const int32_t nearx = 1 - nx1, neary = 1 - ny1;
-  for (int32_t it = 0; it < budget; ++it) {
-    if (boost > 0) {
-      if (it == boost) __builtin_amdgcn_s_setprio(1);
-      else if (it == 2 * boost) __builtin_amdgcn_s_setprio(2);
-      else if (it == 4 * boost) __builtin_amdgcn_s_setprio(3);
-    }
-    const int32_t L = s.L;
-    const lvl_t l = lv[L];
-    const bool inmap = (uint32_t)s.ni < (uint32_t)l.w && (uint32_t)s.nj < (uint32_t)l.h;
-    uint32_t v = 0;
-    if (count) s.reads += inmap ? 1 : 0;
-    if (inmap)
-      v = m.base[l.off + ((__umul24((uint32_t)s.nj >> 3, (uint32_t)l.tiles_x) +
-                           ((uint32_t)s.ni >> 3)) << 6) +
-                 ((s.nj & 7) << 3) + (s.ni & 7)];
-    // keys and heights of the crossings through the node's far faces
-    const int32_t ix = far_index(s.ni, L, nx1, sx, k.offx);
-    const int32_t iy = far_index(s.nj, L, ny1, sy, k.offy);
-    const int64_t KXe = k.KX0 + (int64_t)mul48((uint32_t)ix, r.ay);
-    const int64_t KYe = k.KY0 + (int64_t)mul48((uint32_t)iy, r.ax);
-    const bool ex = KXe <= KYe;               // leave through an x face
-    const int64_t Ze = (ex ? k.ZX0 : k.ZY0) + smul48(ex ? ix : iy, r.Dz);
-    const uint32_t De = ex ? r.ax : r.ay;
-    const uint32_t re = ex ? r.rx : r.ry;
-    bool occ = false;
-    if (inmap) {
-      const int64_t lo = (desc ? Ze : s.Zin) + (int64_t)(desc ? re : s.rin);
-      const uint32_t Dlo = desc ? De : s.Din;
-      const int64_t hi = desc ? s.Zin : Ze;
-      const uint32_t Dhi = desc ? s.Din : De;
-      const uint32_t a = v & 0xFF, b = (v >> 8) & 0xFF, c = (v >> 16) & 0xFF;
-      occ = (lo <= (int64_t)__umul24(a, Dlo)) ||
-            ((lo <= (int64_t)__umul24(c, Dlo)) && (hi >= (int64_t)__umul24(b, Dhi)));
     }
     if (occ) {
       if (L == 0) {

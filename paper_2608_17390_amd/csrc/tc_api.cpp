@@ -259,6 +259,10 @@ tc_status plan_views(tc_context* ctx, const tc_view* views, int32_t n, ViewPlan&
       o.d0[c] = v.d0[c]; o.dpx[c] = v.d_px[c]; o.dpy[c] = v.d_py[c];
     }
     o.tiles_x = (v.width + 7) >> 3;
+    o.small_steps = 1;
+    for (int c = 0; c < 3; ++c)
+      for (int32_t st : {v.o_px[c], v.o_py[c], v.d_px[c], v.d_py[c]})
+        if (st <= -(1 << 22) || st >= (1 << 22)) o.small_steps = 0;
     o.out_base = out;
     o.pkt_base = pk;
     o.rows_off = (int64_t)p.rows.size();

@@ -140,37 +140,30 @@ __device__ __forceinline__ float beam_start(const tci_map& m, const lvl_t* lv, c
   return ta;
 }
 
-// Walk state of ray r at the last cell line of its dominant axis that it
-// enters no later than parameter t (beam_start: no solid lies on the ray up
-// to t, nor within the boxes' margin beyond it), at level 0: such a ray is
-// close to solid, where coarse nodes would only be descended again; at the
-// origin and level L0 if that line is the start cell's.  The line comes from O + t D in
+// Index-form constants of ray r, and its walk state at the last cell line
+// of its dominant axis that it enters no later than parameter t
+// (beam_start: no solid lies on the ray up to t, nor within the boxes'
+// margin beyond it), at level 0: such a ray is close to solid, where coarse
+// nodes would only be descended again; at the origin and level L0 if that
+// line is the start cell's.  The line comes from O + t D in
 // double precision: t, D and O are exact there and the one rounding of the
 // fma moves the entry by less than 2^-20 S units, far inside the margin.
-__device__ __forceinline__ void start_walk(ray_t& r, walk_t& s, float t, int32_t L0,
-                                           int32_t W, int32_t H) {
+__device__ __forceinline__ void start_walk(ray_t& r, walk_idx_t& k, walk_t& s, float t,
+                                           int32_t L0, int32_t W, int32_t H) {
+  walk_origin(r, k);
   if (t > 0.0f) {
     const bool ax_x = r.ax >= r.ay;
     const int64_t O = ax_x ? r.Ox : r.Oy;
     const int32_t D = ax_x ? r.Dx : r.Dy;
     const int32_t n = ax_x ? W : H;
-    const int32_t c0 = (int32_t)(O >> 16);
     const double q = fma((double)t, (double)D, (double)O) * (1.0 / 65536.0);
-    int32_t c;
-    bool ahead;
-    if (D > 0) {        // line c is entered at x = c: the largest c <= q
-      c = (int32_t)floor(fmax(fmin(q, (double)n), -1048576.0));
-      ahead = c > c0;
-    } else {            // line c is entered at x = c + 1: the smallest c >= q - 1
-      c = (int32_t)ceil(fmin(fmax(q, 0.0), 1048576.0)) - 1;
-      ahead = c < c0;
-    }
-    if (ahead) {
-      seg_init(r, s, ax_x ? 0 : 1, c);
-      return;
-    }
+    // (walk_at_line declines a line that is not ahead of the origin's)
+    const int32_t c = D > 0
+        ? (int32_t)floor(fmax(fmin(q, (double)n), -1048576.0))      // line c entered at x = c
+        : (int32_t)ceil(fmin(fmax(q, 0.0), 1048576.0)) - 1;        // entered at x = c + 1
+    if (walk_at_line(r, k, s, ax_x ? 0 : 1, c)) return;
   }
-  walk_init(r, L0, s);
+  walk_at_origin(r, L0, s);
 }
 
 }  // namespace

@@ -52,6 +52,8 @@ struct tci_view {
   int32_t o0[3], opx[3], opy[3];
   int32_t d0[3], dpx[3], dpy[3];
   int32_t tiles_x;     // ceil(w / 8)
+  int32_t small_steps; // every per-pixel step (opx, opy, dpx, dpy) below 2^22
+                       // in magnitude: twice one is a 24-bit operand
   int64_t out_base;    // first output record of the view
   int64_t pkt_base;    // first 8x8 packet of the view
   int64_t rows_off;    // packet order 2: offset of the view's tile-row

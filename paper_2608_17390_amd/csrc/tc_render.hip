@@ -44,7 +44,7 @@ __device__ __forceinline__ void render_body(
     return;
   }
   ray_t r;
-  pixel_ray(v, px, py, r);
+  packet_ray(v, tx, ty, lane, r);
   uint32_t word;
   float depth;
   if (r.Dx == 0 && r.Dy == 0) {
@@ -52,8 +52,9 @@ __device__ __forceinline__ void render_body(
     if (o.count && beam_reads) atomicAdd(o.count, (unsigned long long)beam_reads);
   } else {
     walk_t s;
+    walk_idx_t k;
     const int32_t top = kFlat ? 0 : m.top;
-    start_walk(r, s, t_start, kFlat ? 0 : clamp_level(o.start_level, top), m.W, m.H);
+    start_walk(r, k, s, t_start, kFlat ? 0 : clamp_level(o.start_level, top), m.W, m.H);
     s.reads = beam_reads;
     uint32_t col = 0;
     const int32_t Lmax = kFlat ? 0 : clamp_level(o.max_level, top);
@@ -63,8 +64,6 @@ __device__ __forceinline__ void render_body(
     // direction (a packet's rays mostly share it; a wave holding both signs
     // runs the two loops one after the other)
     const bool down = r.Dz < 0;
-    walk_idx_t k;
-    walk_idx_init(r, s, k);
     int32_t st;
     for (;;) {
       // the budget bounds the walk: at most the split budget, then (or
@@ -110,11 +109,11 @@ __device__ __forceinline__ void render_body(
     if (st == kWalking) st = kCapped;   // the whole budget ran out (never expected)
     // the origin is needed again only here: recompute it from the view
     // rather than keep it in registers through the walk (the empty asm
-    // hides that the pixel is unchanged, so the first computation is not
+    // hides that the lane is unchanged, so the first computation is not
     // reused)
-    int32_t qx = px, qy = py;
-    asm volatile("" : "+v"(qx), "+v"(qy));
-    pixel_ray(v, qx, qy, r);
+    int32_t ql = lane;
+    asm volatile("" : "+v"(ql));
+    packet_ray<false>(v, tx, ty, ql, r);
     finish(r, s, m.W, st, col, word, depth);
     if (o.count) atomicAdd(o.count, (unsigned long long)s.reads);
   }
@@ -218,9 +217,9 @@ __global__ __launch_bounds__(256) void split_kernel(tci_map m,
       }
       walk_idx_t k;
       if (open || b0 != b1) {
-        seg_init(r, s, axis, b0);
-        lift(r, s, clamp_level(o.start_level, Lmax));
-        walk_idx_init(r, s, k);
+        walk_origin(r, k);
+        if (!walk_at_line(r, k, s, axis, b0)) walk_at_origin(r, 0, s);
+        lift(s, clamp_level(o.start_level, Lmax));
         st = kWalking;
       }
       // walk in chunks; once some run holds a hit, the runs after it
@@ -317,8 +316,8 @@ __global__ __launch_bounds__(256) void render_persistent_kernel(
               trace_vertical(m, lv, r, word, depth);
               tcp::store_hit(out, out_idx, word, depth);
             } else {
-              walk_init(r, L0, s);
-              walk_idx_init(r, s, k);
+              walk_origin(r, k);
+              walk_at_origin(r, L0, s);
               active = true;
             }
           }

@@ -78,9 +78,9 @@ __device__ __forceinline__ bool occluded(const tci_map& m, const lvl_t* lv, cons
     return w != kMiss;
   }
   walk_t st;
-  walk_init(s, L0, st);
   walk_idx_t k;
-  walk_idx_init(s, st, k);
+  walk_origin(s, k);
+  walk_at_origin(s, L0, st);
   uint32_t col = 0;
   const int32_t res = walk_steps<false, false, true, kDir>(m, lv, s, k, st, Lmax, kIterCap + 1, col);
   reads += st.reads;

@@ -80,7 +80,7 @@ struct ray_t {
 // key and height by a multiple of S, so the remainders modulo S are fixed
 // per axis: they fold into a tie offset of the x keys and a 0/1 flag of
 // the heights, and no comparison needs the low 16 bits.
-//   keys    the i-th x crossing has key KX0 + i*ay with
+//   keys    the i-th x crossing (i = 0 the first) has key KX0 + i*ay with
 //           KX0 = floor(nx*ay / S) + c, c = 1 iff (nx*ay mod S) > (ny*ax mod S),
 //           and the j-th y crossing KY0 + j*ax, KY0 = floor(ny*ax / S); an x
 //           crossing comes first iff its key is <= the y key (x first on
@@ -92,18 +92,26 @@ struct ray_t {
 //           Likewise for y.
 // The walk runs on the node grid of its current pyramid level L.  For the
 // current node it needs the keys and heights of the crossings through the
-// far x and y faces (a step to the next node moves one of each by a << L,
-// a climb or a descent by half a node) and the child holding the ray is the
-// one on the near side of each middle crossing that happens after the
-// entry crossing.  The walk therefore enters exactly the cells the flat
-// walk enters, at the same keys.  walk_init, seg_init and lift set the
-// far-face keys and heights below; the walk loop itself derives them from
-// the node (walk_idx_t).
+// far x and y faces.  The crossing through the far x face of node (ni, L)
+// is x crossing number
+//   ix = ((ni + 1) << L) - 1 - cx  (Dx > 0),   cx - (ni << L)  (Dx <= 0)
+// counted from the origin cell cx (never negative: the far face lies ahead
+// of the origin), so its key is KX0 + ix * ay and its height ZX0 + ix * Dz;
+// likewise for y.  The walk therefore carries the node, the level and the
+// entry crossing only: a step, a climb or a descent changes 32-bit node
+// coordinates, and the far faces follow from them.  The child holding the
+// ray is the one on the near side of each middle crossing that happens
+// after the entry crossing, so the walk enters exactly the cells the flat
+// walk enters, at the same keys.
+struct walk_idx_t {
+  int64_t KX0, KY0;   // keys of crossing number 0 of each axis
+  int64_t ZX0, ZY0;   // heights at those crossings
+  int32_t offx, offy; // ix = sx ((ni + f) << L) + offx (f = 1 iff Dx > 0), likewise for y
+};
+
 struct walk_t {
   int32_t ni, nj;     // node indices at level L
   int32_t L;          // current pyramid level
-  int64_t KXe, KYe;   // keys of the crossings through the far x / y faces
-  int64_t ZXe, ZYe;   // heights at those crossings (set at the walk's start)
   int64_t Kin;        // key of the entry crossing (unused while kInside)
   int64_t Zin;        // height at entry of the current node
   uint32_t Din;       // its scale: 1 at the origin, else ax or ay
@@ -131,20 +139,77 @@ __device__ __forceinline__ int64_t sshl(int32_t a, int32_t L) {
   return (int64_t)((uint64_t)(int64_t)a << L);
 }
 
+// Ray of pixel (px, py).  Every pixel's origin and direction fit in 32 bits
+// (tc_render_views checks the view's corner rays, and the rays are affine
+// in the pixel), so 32-bit wrapping arithmetic gives them exactly.
 __device__ __forceinline__ void pixel_ray(const tci_view& v, int32_t px,
                                           int32_t py, ray_t& r) {
-  int64_t a = 2 * (int64_t)px + 1, b = 2 * (int64_t)py + 1;
-  r.Ox = (int64_t)v.o0[0] + a * v.opx[0] + b * v.opy[0];
-  r.Oy = (int64_t)v.o0[1] + a * v.opx[1] + b * v.opy[1];
-  r.Oz = (int64_t)v.o0[2] + a * v.opx[2] + b * v.opy[2];
-  r.Dx = (int32_t)((int64_t)v.d0[0] + a * v.dpx[0] + b * v.dpy[0]);
-  r.Dy = (int32_t)((int64_t)v.d0[1] + a * v.dpx[1] + b * v.dpy[1]);
-  r.Dz = (int32_t)((int64_t)v.d0[2] + a * v.dpx[2] + b * v.dpy[2]);
+  const uint32_t a = 2 * (uint32_t)px + 1, b = 2 * (uint32_t)py + 1;
+  auto at = [&](int32_t c0, int32_t ca, int32_t cb) {
+    return (int32_t)((uint32_t)c0 + a * (uint32_t)ca + b * (uint32_t)cb);
+  };
+  r.Ox = at(v.o0[0], v.opx[0], v.opy[0]);
+  r.Oy = at(v.o0[1], v.opx[1], v.opy[1]);
+  r.Oz = at(v.o0[2], v.opx[2], v.opy[2]);
+  r.Dx = at(v.d0[0], v.dpx[0], v.dpy[0]);
+  r.Dy = at(v.d0[1], v.dpx[1], v.dpy[1]);
+  r.Dz = at(v.d0[2], v.dpx[2], v.dpy[2]);
   r.ax = (uint32_t)(r.Dx < 0 ? -r.Dx : r.Dx);
   r.ay = (uint32_t)(r.Dy < 0 ? -r.Dy : r.Dy);
 }
 
-__device__ __forceinline__ void walk_init(ray_t& r, int32_t L0, walk_t& s) {
+// The same ray for the pixel of lane `lane` in the 8 x 8 packet of tile
+// (tx, ty), all of whose lanes call it together (tx, ty wave-uniform): the
+// ray of the packet's first pixel is wave-uniform (scalar arithmetic), and a
+// lane adds (lane & 7) and (lane >> 3) times twice the view's per-pixel
+// steps, one 24-bit multiply-add each when the view's steps are small (the
+// usual case; v.small_steps).  kDir false: the origin only.
+template <bool kDir = true>
+__device__ __forceinline__ void packet_ray(const tci_view& v, int32_t tx, int32_t ty,
+                                           int32_t lane, ray_t& r) {
+  const uint32_t a0 = 16 * (uint32_t)tx + 1, b0 = 16 * (uint32_t)ty + 1;
+  const int32_t lx = lane & 7, ly = lane >> 3;
+  int32_t o[6];
+  auto base = [&](int32_t c0, int32_t ca, int32_t cb) {
+    return (int32_t)((uint32_t)c0 + a0 * (uint32_t)ca + b0 * (uint32_t)cb);
+  };
+  auto step = [&](int32_t c) {
+    return c < 3 ? v.opx[c] : v.dpx[c - 3];
+  };
+  auto stepy = [&](int32_t c) {
+    return c < 3 ? v.opy[c] : v.dpy[c - 3];
+  };
+  constexpr int kN = kDir ? 6 : 3;
+  if (v.small_steps) {
+#pragma unroll
+    for (int c = 0; c < kN; ++c) {
+      const int32_t b = base(c < 3 ? v.o0[c] : v.d0[c - 3], step(c), stepy(c));
+      o[c] = __mul24(ly, 2 * stepy(c)) + (__mul24(lx, 2 * step(c)) + b);
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < kN; ++c) {
+      const int32_t b = base(c < 3 ? v.o0[c] : v.d0[c - 3], step(c), stepy(c));
+      o[c] = (int32_t)((uint32_t)b + (uint32_t)lx * (2u * (uint32_t)step(c)) +
+                       (uint32_t)ly * (2u * (uint32_t)stepy(c)));
+    }
+  }
+  r.Ox = o[0];
+  r.Oy = o[1];
+  r.Oz = o[2];
+  if constexpr (kDir) {
+    r.Dx = o[3];
+    r.Dy = o[4];
+    r.Dz = o[5];
+    r.ax = (uint32_t)(r.Dx < 0 ? -r.Dx : r.Dx);
+    r.ay = (uint32_t)(r.Dy < 0 ? -r.Dy : r.Dy);
+  }
+}
+
+// Index-form constants of ray r (crossing numbers counted from its origin
+// cell) and its residual flags; the anchor (r.cx0, r.cy0) becomes the
+// origin cell.
+__device__ __forceinline__ void walk_origin(ray_t& r, walk_idx_t& k) {
   const int32_t cx = (int32_t)(r.Ox >> 16), cy = (int32_t)(r.Oy >> 16);
   r.cx0 = cx;
   r.cy0 = cy;
@@ -163,17 +228,20 @@ __device__ __forceinline__ void walk_init(ray_t& r, int32_t L0, walk_t& s) {
   const int64_t wy = (int64_t)mul48(zl, r.ay) + smul48((int32_t)ny, r.Dz);
   r.rx = ((uint32_t)wx & 0xFFFF) != 0;
   r.ry = ((uint32_t)wy & 0xFFFF) != 0;
+  k.KX0 = r.Dx == 0 ? kNever : (kx >> 16) + (r.Dy != 0 ? tie : 0);
+  k.KY0 = r.Dy == 0 ? kNever : (ky >> 16);
+  k.ZX0 = smul48((int32_t)r.ax, zh) + (wx >> 16);
+  k.ZY0 = smul48((int32_t)r.ay, zh) + (wy >> 16);
+  k.offx = r.Dx > 0 ? -1 - cx : cx;
+  k.offy = r.Dy > 0 ? -1 - cy : cy;
+}
+
+// Walk state at the origin, on the level-L0 node holding the origin cell
+// (after walk_origin).
+__device__ __forceinline__ void walk_at_origin(const ray_t& r, int32_t L0, walk_t& s) {
   s.L = L0;
-  s.ni = cx >> L0;
-  s.nj = cy >> L0;
-  // crossings before the far faces of the start node
-  const int32_t kxm1 = r.Dx > 0 ? ((s.ni + 1) << L0) - 1 - cx : cx - (s.ni << L0);
-  const int32_t kym1 = r.Dy > 0 ? ((s.nj + 1) << L0) - 1 - cy : cy - (s.nj << L0);
-  s.KXe = r.Dx == 0 ? kNever
-                    : (kx >> 16) + (r.Dy != 0 ? tie : 0) + (int64_t)mul48((uint32_t)kxm1, r.ay);
-  s.KYe = r.Dy == 0 ? kNever : (ky >> 16) + (int64_t)mul48((uint32_t)kym1, r.ax);
-  s.ZXe = smul48((int32_t)r.ax, zh) + (wx >> 16) + smul48(kxm1, r.Dz);
-  s.ZYe = smul48((int32_t)r.ay, zh) + (wy >> 16) + smul48(kym1, r.Dz);
+  s.ni = r.cx0 >> L0;
+  s.nj = r.cy0 >> L0;
   s.Kin = 0;
   s.Zin = r.Oz >> 16;
   s.rin = (r.Oz & 0xFFFF) != 0;
@@ -285,83 +353,57 @@ __device__ __forceinline__ int32_t count_below(int64_t E, int64_t K, uint32_t a)
   return q + 1;
 }
 
-// Walk state (at level 0) on entering cell line `start` of axis `axis`
-// (a column if 0, a row if 1) through the crossing the flat walk takes into
-// it: the crossing's key and height come from its index, the cell on the
-// other axis from the number of that axis's crossings that come first (x
-// first on ties).  If `start` is the start cell's line, the walk starts at
-// the origin.
-__device__ __forceinline__ void seg_init(ray_t& r, walk_t& s, int32_t axis,
-                                         int32_t start) {
-  walk_init(r, 0, s);   // level 0: far-face keys are the first crossings
+// Walk state (at level 0) on entering cell line `line` of axis `axis` (a
+// column if 0, a row if 1) through the crossing the flat walk takes into
+// it (after walk_origin): the crossing's key and height come from its
+// index, the cell on the other axis from the number of that axis's
+// crossings that come first (x first on ties).  The anchor becomes that
+// cell.  False, and nothing changed, if `line` is not ahead of the origin
+// cell's.
+__device__ __forceinline__ bool walk_at_line(ray_t& r, const walk_idx_t& k, walk_t& s,
+                                             int32_t axis, int32_t line) {
+  const int32_t cx = r.cx0, cy = r.cy0;
   if (axis == 0) {
-    const int32_t i = r.Dx > 0 ? start - r.cx0 - 1 : r.cx0 - start - 1;
-    if (i < 0) return;
-    const int64_t K = s.KXe + (int64_t)mul48((uint32_t)i, r.ay);
-    const int32_t c = count_below(K, s.KYe, r.ax);
+    const int32_t i = r.Dx > 0 ? line - cx - 1 : cx - line - 1;
+    if (i < 0) return false;
+    const int64_t K = k.KX0 + (int64_t)mul48((uint32_t)i, r.ay);
+    const int32_t c = count_below(K, k.KY0, r.ax);
     s.Kin = K;
-    s.Zin = s.ZXe + smul48(i, r.Dz);
+    s.Zin = k.ZX0 + smul48(i, r.Dz);
     s.Din = r.ax;
     s.rin = r.rx;
-    s.KXe = K + r.ay;
-    s.ZXe = s.Zin + r.Dz;
-    s.KYe += (int64_t)mul48((uint32_t)c, r.ax);
-    s.ZYe += smul48(c, r.Dz);
-    s.ni = start;
-    s.nj = r.cy0 + (r.Dy > 0 ? c : -c);
+    s.ni = line;
+    s.nj = cy + (r.Dy > 0 ? c : -c);
     s.entry = (r.Dx > 0 ? kWmx : kWpx) | kAnchored;
   } else {
-    const int32_t j = r.Dy > 0 ? start - r.cy0 - 1 : r.cy0 - start - 1;
-    if (j < 0) return;
-    const int64_t K = s.KYe + (int64_t)mul48((uint32_t)j, r.ax);
-    const int32_t c = count_below(K + 1, s.KXe, r.ay);
+    const int32_t j = r.Dy > 0 ? line - cy - 1 : cy - line - 1;
+    if (j < 0) return false;
+    const int64_t K = k.KY0 + (int64_t)mul48((uint32_t)j, r.ax);
+    const int32_t c = count_below(K + 1, k.KX0, r.ay);
     s.Kin = K;
-    s.Zin = s.ZYe + smul48(j, r.Dz);
+    s.Zin = k.ZY0 + smul48(j, r.Dz);
     s.Din = r.ay;
     s.rin = r.ry;
-    s.KYe = K + r.ax;
-    s.ZYe = s.Zin + r.Dz;
-    s.KXe += (int64_t)mul48((uint32_t)c, r.ay);
-    s.ZXe += smul48(c, r.Dz);
-    s.nj = start;
-    s.ni = r.cx0 + (r.Dx > 0 ? c : -c);
+    s.nj = line;
+    s.ni = cx + (r.Dx > 0 ? c : -c);
     s.entry = (r.Dy > 0 ? kWmy : kWpy) | kAnchored;
   }
+  s.L = 0;
+  s.iters = 0;
+  s.reads = 0;
   r.cx0 = s.ni;
   r.cy0 = s.nj;
+  return true;
 }
 
-// Move a level-0 walk state up to the level-L node holding its cell: the
-// far faces of that node lie the remaining cells of the node further on.
-__device__ __forceinline__ void lift(const ray_t& r, walk_t& s, int32_t L) {
+// Move a level-0 walk state up to the level-L node holding its cell (the
+// far faces follow from the node).
+__device__ __forceinline__ void lift(walk_t& s, int32_t L) {
   if (L <= 0) return;
-  const int32_t ni = s.ni >> L, nj = s.nj >> L;
-  const int32_t kx = r.Dx > 0 ? ((ni + 1) << L) - 1 - s.ni : s.ni - (ni << L);
-  const int32_t ky = r.Dy > 0 ? ((nj + 1) << L) - 1 - s.nj : s.nj - (nj << L);
-  s.KXe += (int64_t)mul48((uint32_t)kx, r.ay);
-  s.KYe += (int64_t)mul48((uint32_t)ky, r.ax);
-  s.ZXe += smul48(kx, r.Dz);
-  s.ZYe += smul48(ky, r.Dz);
-  s.ni = ni;
-  s.nj = nj;
+  s.ni >>= L;
+  s.nj >>= L;
   s.L = L;
 }
-
-// Index form of the walk.  The crossing through the far x face of node
-// (ni, L) is x crossing number
-//   ix = ((ni + 1) << L) - 1 - ax0  (Dx > 0),   ax0 - (ni << L)  (Dx <= 0)
-// counted from the anchor cell ax0 (never negative: the far face lies
-// ahead of the anchor), so its key is KX0 + ix * ay and its height
-// ZX0 + ix * Dz; likewise for y.  The loop therefore carries the node, the
-// level and the entry crossing only: a step, a climb or a descent changes
-// 32-bit node coordinates, and the far-face keys and heights follow from
-// them (the keys and heights walk_init, seg_init and lift leave in walk_t
-// only seed the constants).
-struct walk_idx_t {
-  int64_t KX0, KY0;   // keys of crossing number 0 of each axis
-  int64_t ZX0, ZY0;   // heights at those crossings
-  int32_t offx, offy; // ix = sx ((ni + f) << L) + offx (f = 1 iff Dx > 0), likewise for y
-};
 
 // (n + f) << L with f = 1 when the axis runs forward, times s = +-1, plus
 // off: |(n + f) << L| stays below 2^23 (cell coordinates are within
@@ -371,23 +413,10 @@ __device__ __forceinline__ int32_t far_index(int32_t n, int32_t L, int32_t f, in
   return __mul24(s, (n + f) << L) + off;
 }
 
-// Constants of the index form from a walk state of walk_init or seg_init
-// (and lift).
-__device__ __forceinline__ void walk_idx_init(const ray_t& r, const walk_t& s, walk_idx_t& k) {
-  k.offx = r.Dx > 0 ? -1 - r.cx0 : r.cx0;
-  k.offy = r.Dy > 0 ? -1 - r.cy0 : r.cy0;
-  const int32_t ix = far_index(s.ni, s.L, r.Dx > 0, r.Dx > 0 ? 1 : -1, k.offx);
-  const int32_t iy = far_index(s.nj, s.L, r.Dy > 0, r.Dy > 0 ? 1 : -1, k.offy);
-  k.KX0 = s.KXe - (int64_t)mul48((uint32_t)ix, r.ay);
-  k.KY0 = s.KYe - (int64_t)mul48((uint32_t)iy, r.ax);
-  k.ZX0 = s.ZXe - smul48(ix, r.Dz);
-  k.ZY0 = s.ZYe - smul48(iy, r.Dz);
-}
-
 // Advance the walk by up to `budget` iterations.  Returns kWalking if the
 // budget ran out, else the final state; on kHitCell, `col` holds the
 // column of the current cell (s.ni, s.nj at level 0).  k holds the ray's
-// index-form constants (walk_idx_init after the state's initialisation).
+// index-form constants (walk_origin).
 // With boost > 0 (wave-uniform loop only), a wave raises its instruction
 // issue priority after boost, 2*boost and 4*boost iterations: the few long
 // walks of a launch, which otherwise trail it, then win issue slots over

@@ -335,6 +335,48 @@ def test_edge_rays(ctx):
     assert np.all(wo[:81] == oracle.MISS)
 
 
+def test_wide_pixel_steps(ctx):
+    """Views whose per-pixel origin or direction steps reach 2^22 and more
+    (pixels 128 cells apart, directions swinging across the full range
+    between neighbouring pixels), batched with ordinary views: the kernels
+    form a lane's ray from its packet's first pixel with 24-bit
+    multiply-adds only while every step of the view is below 2^22, and in
+    32-bit wrapping arithmetic otherwise."""
+    rng = np.random.default_rng(21)
+    F, B, T = synth.make_map(300, 220, 22, dual=0.35, period=16)
+    load(ctx, F, B, T)
+    big = 1 << 22
+    views = [
+        # origins 2 * 2^22 / S = 128 cells apart, one step exactly -2^22
+        synth.ortho_view((-60 * S, -40 * S, 200 * S), (big, 0, 0), (0, big + 4321, 0),
+                         (0.3, 0.4, -1), 4, 3),
+        synth.ortho_view((500 * S, 400 * S, 90 * S), (-big, S // 3, 0), (12345, -big - 7, 3 * S),
+                         (-1, -0.7, -0.2), 5, 9),
+        # one step just below the limit, the others tiny
+        synth.ortho_view((-30 * S, 5 * S, 150 * S), (big - 1, 0, 0), (0, S, 0), (0.2, 1, -0.5), 3, 40),
+    ]
+    for _ in range(8):
+        v = np.zeros((), synth.VIEW_DTYPE)
+        w, h = int(rng.integers(1, 3)), int(rng.integers(1, 3))
+        v["width"], v["height"] = w, h
+        v["o0"] = [int(rng.integers(20, 280)) * S, int(rng.integers(20, 200)) * S,
+                   int(rng.integers(30, 120)) * S]
+        # D = d0 + a dpx + b dpy with a, b in {1, 3}: steps of 2^22 and more
+        # still keep |D| within 2^23 - 1
+        dpx = [int(rng.choice([-1, 1])) * int(rng.integers(big, big + 200)) for _ in range(2)] + [0]
+        dpy = [0, 0, int(rng.choice([-1, 1])) * int(rng.integers(big // 2, big + 100))]
+        v["d_px"], v["d_py"] = dpx, dpy
+        v["d0"] = [-2 * dpx[0] if w == 2 else -dpx[0] // 2, -2 * dpx[1] if w == 2 else 0,
+                   -2 * dpy[2] if h == 2 else -dpy[2] - int(rng.integers(1, 1000))]
+        views.append(v)
+    views += _random_views(rng, F, B, 3, [(20, 12), (9, 9)])
+    wo, do = oracle.render(F, B, T, views)
+    for mode in MODES:
+        wg, dg = gpu_render(ctx, views, mode)
+        assert_parity(wg, dg, wo, do, "wide steps " + mode)
+    assert np.count_nonzero(wo != oracle.MISS) > 30
+
+
 def test_single_cell_and_odd_maps(ctx):
     rng = np.random.default_rng(4)
     for (W, H) in [(1, 1), (1, 9), (9, 1), (17, 3), (129, 65)]:

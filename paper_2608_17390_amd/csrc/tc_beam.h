@@ -48,11 +48,11 @@ __device__ __forceinline__ bool beam_box_solid(const tci_map& m, const lvl_t* lv
   // 2^L > ext: the box overlaps at most two nodes per axis at level L
   int32_t L = ext < 1.0f ? 0 : __builtin_amdgcn_frexp_expf(ext);
   L = min(L, m.top);
-  const float lim = 1048576.0f;
-  const int32_t x0 = (int32_t)floorf(fminf(fmaxf(lox, -lim), lim)) >> L;
-  const int32_t x1 = (int32_t)floorf(fminf(fmaxf(hix, -lim), lim)) >> L;
-  const int32_t y0 = (int32_t)floorf(fminf(fmaxf(loy, -lim), lim)) >> L;
-  const int32_t y1 = (int32_t)floorf(fminf(fmaxf(hiy, -lim), lim)) >> L;
+  // node coordinates, clamped far outside the map (no bound is NaN here)
+  auto node = [&](float c) {
+    return (int32_t)floorf(__builtin_amdgcn_fmed3f(c, -1048576.0f, 1048576.0f)) >> L;
+  };
+  const int32_t x0 = node(lox), x1 = node(hix), y0 = node(loy), y1 = node(hiy);
   if (x1 - x0 > 1 || y1 - y0 > 1) return true;  // wider than the top level's nodes
   const lvl_t l = lv[L];
   const int32_t i0 = max(x0, 0), i1 = min(x1, l.w - 1);
@@ -61,8 +61,9 @@ __device__ __forceinline__ bool beam_box_solid(const tci_map& m, const lvl_t* lv
   // tiled index (tci_tile_index) with 24-bit multiplies: tile rows and
   // tiles per row are below 2^11
   auto at = [&](int32_t i, int32_t j) {
-    return m.base[l.off + ((__umul24((uint32_t)j >> 3, (uint32_t)l.tiles_x) + ((uint32_t)i >> 3))
-                           << 6) + (((uint32_t)j & 7) << 3) + ((uint32_t)i & 7)];
+    return map_word(m.base, l.off + ((umul24((uint32_t)j >> 3, (uint32_t)l.tiles_x) +
+                                      ((uint32_t)i >> 3)) << 6) +
+                                (((uint32_t)j & 7) << 3) + ((uint32_t)i & 7));
   };
   const uint32_t w00 = at(i0, j0), w10 = at(i1, j0), w01 = at(i0, j1), w11 = at(i1, j1);
   reads += 1 + (i1 != i0) + (j1 != j0) + (i1 != i0 && j1 != j0);
@@ -84,50 +85,64 @@ __device__ __forceinline__ float beam_start(const tci_map& m, const lvl_t* lv, c
   const int32_t px0 = tx * 8, py0 = ty * 8;
   const int32_t px1 = min(px0 + 7, v.w - 1), py1 = min(py0 + 7, v.h - 1);
   // centre and half-spans of a and b over the packet's pixels
-  const int64_t ac = px0 + px1 + 1, bc = py0 + py1 + 1;
-  const float ha = (float)(px1 - px0), hb = (float)(py1 - py0);
+  const uint32_t ac = px0 + px1 + 1, bc = py0 + py1 + 1;
   const float inv = 1.0f / 65536.0f;
+  const float ha = (float)(px1 - px0) * inv, hb = (float)(py1 - py0) * inv;
   // per coordinate, the bundle lies within lo(t) = A + t B, hi(t) = A' + t B'
   // for t >= 0: the centre ray oc + t dc plus or minus the extent bound
-  // ha |opx + t dpx| + hb |opy + t dpy| <= e0 + t e1 (all over S); both
-  // bounds are linear, so their extremes over an interval are at its ends
-  float A[3], Bv[3], Ah[3], Bh[3], len2 = 0.0f;
+  // ha |opx + t dpx| + hb |opy + t dpy| <= e0 + t e1 (all over S).  Over
+  // [t0, t1] their extremes are A + t0 B + (t1 - t0) min(B, 0) and
+  // A' + t0 B' + (t1 - t0) max(B', 0).  The margin covers the rounding of
+  // the view's values, of these coefficients and of the bounds (a few
+  // units in the last place of values below 2^16) plus an absolute
+  // sixteenth of a cell: 1/16 + 2^-18 (|lo| + |hi|) is at most
+  // P + t1 Q with P = 1/16 + 2^-18 (|A| + |A'|), Q = 2^-18 (|B| + |B'|),
+  // which folds into the coefficients:
+  //   lo = (A - P) + t0 (B - Q) + (t1 - t0) (min(B, 0) - Q)
+  //   hi = (A' + P) + t0 (B' + Q) + (t1 - t0) (max(B', 0) + Q)
+  float L0[3], L1[3], L2[3], H0[3], H1[3], H2[3], len2 = 0.0f;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    // the centre ray in exact integers first: the view's corner rays fit
-    // in 32 bits, the centre lies between them
-    const float oc = (float)((int64_t)v.o0[c] + ac * v.opx[c] + bc * v.opy[c]) * inv;
-    const float dc = (float)((int64_t)v.d0[c] + ac * v.dpx[c] + bc * v.dpy[c]) * inv;
-    const float e0 = (ha * fabsf((float)v.opx[c]) + hb * fabsf((float)v.opy[c])) * inv;
-    const float e1 = (ha * fabsf((float)v.dpx[c]) + hb * fabsf((float)v.dpy[c])) * inv;
-    A[c] = oc - e0;
-    Bv[c] = dc - e1;
-    Ah[c] = oc + e0;
-    Bh[c] = dc + e1;
-    len2 += dc * dc;
+    // the centre ray lies between the view's corner rays, which fit in 32
+    // bits: wrapping 32-bit arithmetic gives it exactly
+    const float oc =
+        (float)(int32_t)((uint32_t)v.o0[c] + ac * (uint32_t)v.opx[c] + bc * (uint32_t)v.opy[c]) *
+        inv;
+    const float dc =
+        (float)(int32_t)((uint32_t)v.d0[c] + ac * (uint32_t)v.dpx[c] + bc * (uint32_t)v.dpy[c]) *
+        inv;
+    const float e0 = fmaf(ha, fabsf((float)v.opx[c]), hb * fabsf((float)v.opy[c]));
+    const float e1 = fmaf(ha, fabsf((float)v.dpx[c]), hb * fabsf((float)v.dpy[c]));
+    const float A = oc - e0, Ah = oc + e0, B = dc - e1, Bh = dc + e1;
+    const float P = fmaf(fabsf(A) + fabsf(Ah), 0x1p-18f, 0.0625f);
+    const float Q = (fabsf(B) + fabsf(Bh)) * 0x1p-18f;
+    L0[c] = A - P;
+    L1[c] = B - Q;
+    L2[c] = fminf(B, 0.0f) - Q;
+    H0[c] = Ah + P;
+    H1[c] = Bh + Q;
+    H2[c] = fmaxf(Bh, 0.0f) + Q;
+    len2 = fmaf(dc, dc, len2);
   }
-  const float len = sqrtf(len2);
-  if (!(len > 0.0f)) return 0.0f;
-  const float u = kBeamFirst / len;
+  if (!(len2 > 0.0f)) return 0.0f;
+  // the interval lengths need no accuracy: the hardware's reciprocal square
+  // root and power of two
+  const float u = kBeamFirst * __builtin_amdgcn_rsqf(len2);
   // lane k covers [ta + u g(k), ta + u g(k + 1)], g(k) = ((1 + r)^k - 1) / r;
   // lane k's end and lane k + 1's start are the same float (same inputs,
   // same operations), so the intervals leave no gap
-  const float g0 = (exp2f((float)lane * kBeamLog2Growth) - 1.0f) * (1.0f / kBeamGrowth);
-  const float g1 = (exp2f((float)(lane + 1) * kBeamLog2Growth) - 1.0f) * (1.0f / kBeamGrowth);
+  const float g0 = (__builtin_amdgcn_exp2f((float)lane * kBeamLog2Growth) - 1.0f) *
+                   (1.0f / kBeamGrowth);
+  const float g1 = (__builtin_amdgcn_exp2f((float)(lane + 1) * kBeamLog2Growth) - 1.0f) *
+                   (1.0f / kBeamGrowth);
   float ta = 0.0f;
   for (int32_t pass = 0; pass < passes; ++pass) {
-    const float t0 = fmaf(u, g0, ta), t1 = fmaf(u, g1, ta);
+    const float t0 = fmaf(u, g0, ta), t1 = fmaf(u, g1, ta), dt = t1 - t0;
     float lo[3], hi[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const float l = fminf(fmaf(t0, Bv[c], A[c]), fmaf(t1, Bv[c], A[c]));
-      const float h = fmaxf(fmaf(t0, Bh[c], Ah[c]), fmaf(t1, Bh[c], Ah[c]));
-      // rounding of the view's values, the bounds and their images: a few
-      // units in the last place of values below 2^16, plus an absolute
-      // sixteenth of a cell
-      const float mg = fmaf(fabsf(l) + fabsf(h), 0x1p-18f, 0.0625f);
-      lo[c] = l - mg;
-      hi[c] = h + mg;
+      lo[c] = fmaf(dt, L2[c], fmaf(t0, L1[c], L0[c]));
+      hi[c] = fmaf(dt, H2[c], fmaf(t0, H1[c], H0[c]));
     }
     const bool solid =
         beam_box_solid(m, lv, lo[0], hi[0], lo[1], hi[1], lo[2], hi[2], reads);

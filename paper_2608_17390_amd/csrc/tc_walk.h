@@ -61,6 +61,14 @@ __device__ __forceinline__ uint64_t mul48(uint32_t a, uint32_t b) {
   asm("v_mul_hi_u32_u24 %0, %1, %2" : "=v"(hi) : "v"(a), "v"(b));
   return ((uint64_t)hi << 32) | lo;
 }
+// Low 32 bits of a * b for a, b < 2^24: one full-rate 24-bit multiply
+// (the compiler otherwise may pick the quarter-rate 32-bit one inside the
+// walk loop).
+__device__ __forceinline__ uint32_t umul24(uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm("v_mul_u32_u24 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
 // a * b for 0 <= a < 2^23 and |b| < 2^23, signed 48-bit product.
 __device__ __forceinline__ int64_t smul48(int32_t a, int32_t b) {
   int32_t lo, hi;
@@ -130,6 +138,13 @@ __device__ __forceinline__ bool z_le(int64_t zq, uint32_t r, uint32_t h, uint32_
 }
 __device__ __forceinline__ bool z_ge(int64_t zq, uint32_t h, uint32_t d) {
   return zq >= (int64_t)__umul24(h, d);
+}
+// Word `idx` of the map allocation.  The allocation (columns, pyramid and
+// masks of at most 2^27 cells) holds fewer than 2^28 words, so the byte
+// offset is a 32-bit value added to the scalar base: the load's
+// base-plus-offset form, with no 64-bit address arithmetic per lane.
+__device__ __forceinline__ uint32_t map_word(const uint32_t* base, uint32_t idx) {
+  return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(base) + (idx << 2));
 }
 // a << L for an unsigned or signed 32-bit a as a 64-bit value
 __device__ __forceinline__ int64_t ushl(uint32_t a, int32_t L) {
@@ -468,9 +483,9 @@ __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
     uint32_t v = 0;
     if (count) s.reads += inmap ? 1 : 0;
     if (inmap)
-      v = m.base[l.off + ((__umul24((uint32_t)s.nj >> 3, (uint32_t)l.tiles_x) +
-                           ((uint32_t)s.ni >> 3)) << 6) +
-                 ((s.nj & 7) << 3) + (s.ni & 7)];
+      v = map_word(m.base, l.off + ((umul24((uint32_t)s.nj >> 3, (uint32_t)l.tiles_x) +
+                                     ((uint32_t)s.ni >> 3)) << 6) +
+                               ((s.nj & 7) << 3) + (s.ni & 7));
     // keys and heights of the crossings through the node's far faces
     const int32_t ix = far_index(s.ni, L, nx1, sx, k.offx);
     const int32_t iy = far_index(s.nj, L, ny1, sy, k.offy);

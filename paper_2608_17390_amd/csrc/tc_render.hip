@@ -8,9 +8,17 @@
 
 namespace {
 
+// This lane's index in its wave, from the hardware (two VALU instructions)
+// rather than from a register kept live.
+__device__ __forceinline__ int32_t lane_now() {
+  return (int32_t)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
 // One thread per pixel; a wave casts one 8x8 pixel packet.
 // kOcc: node tests also consult the occupancy masks (render mode 4).
-template <bool kFlat, bool kOcc>
+// kCount: the launch counts the nodes and cells its rays read (o.count);
+// the production instance keeps no counter through the walk.
+template <bool kFlat, bool kOcc, bool kCount>
 __device__ __forceinline__ void render_body(
     const tci_map& m, const tci_view* __restrict__ views, int32_t nviews,
     const int64_t* __restrict__ pkt_prefix, int64_t npkt, void* out,
@@ -40,7 +48,7 @@ __device__ __forceinline__ void render_body(
   if (!kFlat && o.beam_passes > 0)
     t_start = beam_start(m, lv, v, tx, ty, o.beam_passes, lane, beam_reads);
   if (px >= v.w || py >= v.h) {
-    if (o.count && beam_reads) atomicAdd(o.count, (unsigned long long)beam_reads);
+    if (kCount && beam_reads) atomicAdd(o.count, (unsigned long long)beam_reads);
     return;
   }
   ray_t r;
@@ -49,7 +57,7 @@ __device__ __forceinline__ void render_body(
   float depth;
   if (r.Dx == 0 && r.Dy == 0) {
     trace_vertical(m, lv, r, word, depth);
-    if (o.count && beam_reads) atomicAdd(o.count, (unsigned long long)beam_reads);
+    if (kCount && beam_reads) atomicAdd(o.count, (unsigned long long)beam_reads);
   } else {
     walk_t s;
     walk_idx_t k;
@@ -71,10 +79,10 @@ __device__ __forceinline__ void render_body(
       const int32_t budget = split ? o.split_budget : kIterCap + 1;
       if (down)
         st = walk_steps<false, kOcc, false, 1>(m, lv, r, k, s, Lmax, budget, col, boost, 0, 0,
-                                               0, moff, o.count != nullptr);
+                                               0, moff, kCount);
       else
         st = walk_steps<false, kOcc, false, 2>(m, lv, r, k, s, Lmax, budget, col, boost, 0, 0,
-                                               0, moff, o.count != nullptr);
+                                               0, moff, kCount);
       if (!split) break;
       split = false;
       // long walks go to the split pass, as many as the queue holds
@@ -102,47 +110,50 @@ __device__ __forceinline__ void render_body(
         const int32_t from = fwd ? max(near, c0) : min(near, c0);
         o.queue[base + rank] = make_uint4((uint32_t)vi, (uint32_t)(py * v.w + px),
                                           (uint32_t)from, 0u);
-        if (o.count) atomicAdd(o.count, (unsigned long long)s.reads);
+        if (kCount) atomicAdd(o.count, (unsigned long long)s.reads);
         return;
       }
     }
     if (st == kWalking) st = kCapped;   // the whole budget ran out (never expected)
     // the origin is needed again only here: recompute it from the view
-    // rather than keep it in registers through the walk (the empty asm
-    // hides that the lane is unchanged, so the first computation is not
-    // reused)
-    int32_t ql = lane;
-    asm volatile("" : "+v"(ql));
-    packet_ray<false>(v, tx, ty, ql, r);
+    // rather than keep it in registers through the walk (the lane index is
+    // read again from the hardware, so no register holds it either)
+    packet_ray<false>(v, tx, ty, lane_now(), r);
     finish(r, s, m.W, st, col, word, depth);
-    if (o.count) atomicAdd(o.count, (unsigned long long)s.reads);
+    if (kCount) atomicAdd(o.count, (unsigned long long)s.reads);
   }
-  tcp::store_hit(out, v.out_base + (int64_t)py * v.w + px, word, depth);
+  const int32_t ql = lane_now();
+  tcp::store_hit(out, v.out_base + (int64_t)(ty * 8 + (ql >> 3)) * v.w + tx * 8 + (ql & 7), word,
+                 depth);
 }
 
-// The three one-thread-per-pixel kernels.  The hierarchical one is asked
-// for 7 waves per SIMD (at most 72 VGPRs): it is bound by instruction issue,
-// and the extra wave hides more of the walk's load latency; the only value
-// the limit moves to scratch is used once, at split-pass enqueue.
+// The three one-thread-per-pixel kernels, each with and without read
+// counting.  The hierarchical one is asked for at least 7 waves per SIMD
+// (at most 72 VGPRs): it is bound by instruction issue, and more waves hide
+// more of the walk's load latency.  The production instance (no counting)
+// fits 64 VGPRs, so 8 waves run.
+template <bool kCount>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 8)))
 void render_hier_kernel(tci_map m, const tci_view* __restrict__ views, int32_t nviews,
                         const int64_t* __restrict__ pkt_prefix, int64_t npkt, void* out,
                         tci_render_opts o) {
-  render_body<false, false>(m, views, nviews, pkt_prefix, npkt, out, o);
+  render_body<false, false, kCount>(m, views, nviews, pkt_prefix, npkt, out, o);
 }
 
+template <bool kCount>
 __global__ __launch_bounds__(256)
 void render_flat_kernel(tci_map m, const tci_view* __restrict__ views, int32_t nviews,
                         const int64_t* __restrict__ pkt_prefix, int64_t npkt, void* out,
                         tci_render_opts o) {
-  render_body<true, false>(m, views, nviews, pkt_prefix, npkt, out, o);
+  render_body<true, false, kCount>(m, views, nviews, pkt_prefix, npkt, out, o);
 }
 
+template <bool kCount>
 __global__ __launch_bounds__(256)
 void render_occ_kernel(tci_map m, const tci_view* __restrict__ views, int32_t nviews,
                        const int64_t* __restrict__ pkt_prefix, int64_t npkt, void* out,
                        tci_render_opts o) {
-  render_body<false, true>(m, views, nviews, pkt_prefix, npkt, out, o);
+  render_body<false, true, kCount>(m, views, nviews, pkt_prefix, npkt, out, o);
 }
 
 // Dominant-axis cell line where the ray leaves the map's columns, or rises
@@ -353,16 +364,12 @@ hipError_t tci_launch_render(const tci_map& m, const tci_view* views,
                              const tci_render_opts& o, hipStream_t s) {
   int64_t blocks = (npkt + 3) / 4;
   if (blocks < 1) return hipSuccess;
-  if (flat == 1)
-    hipLaunchKernelGGL(render_flat_kernel, dim3((uint32_t)blocks), dim3(256),
-                       0, s, m, views, nviews, pkt_prefix, npkt, out, o);
-  else if (flat == 2)
-    hipLaunchKernelGGL(render_occ_kernel, dim3((uint32_t)blocks), dim3(256),
-                       0, s, m, views, nviews, pkt_prefix, npkt, out, o);
-  else
-    hipLaunchKernelGGL(render_hier_kernel, dim3((uint32_t)blocks),
-                       dim3(256), 0, s, m, views, nviews, pkt_prefix, npkt,
-                       out, o);
+  const bool c = o.count != nullptr;
+  auto kern = flat == 1 ? (c ? render_flat_kernel<true> : render_flat_kernel<false>)
+            : flat == 2 ? (c ? render_occ_kernel<true> : render_occ_kernel<false>)
+                        : (c ? render_hier_kernel<true> : render_hier_kernel<false>);
+  hipLaunchKernelGGL(kern, dim3((uint32_t)blocks), dim3(256), 0, s, m, views, nviews,
+                     pkt_prefix, npkt, out, o);
   return hipGetLastError();
 }
 

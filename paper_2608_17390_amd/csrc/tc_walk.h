@@ -76,6 +76,27 @@ __device__ __forceinline__ int64_t smul48(int32_t a, int32_t b) {
   asm("v_mul_hi_i32_i24 %0, %1, %2" : "=v"(hi) : "v"(a), "v"(b));
   return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
+// K + a * b for a < 2^24, b < 2^24 and K + a * b + (a product's high half)
+// for |a|, |b| < 2^23 signed: the two halves of the 48-bit product are
+// added as a carry pair (two 32-bit adds) instead of as a 64-bit value.
+__device__ __forceinline__ int64_t add_pair(int64_t K, uint32_t lo, uint32_t hi) {
+  uint32_t c;
+  const uint32_t rl = __builtin_addc((uint32_t)K, lo, 0u, &c);
+  const uint32_t rh = __builtin_addc((uint32_t)((uint64_t)K >> 32), hi, c, &c);
+  return (int64_t)(((uint64_t)rh << 32) | rl);
+}
+__device__ __forceinline__ int64_t add_mul48(int64_t K, uint32_t a, uint32_t b) {
+  uint32_t lo, hi;
+  asm("v_mul_u32_u24 %0, %1, %2" : "=v"(lo) : "v"(a), "v"(b));
+  asm("v_mul_hi_u32_u24 %0, %1, %2" : "=v"(hi) : "v"(a), "v"(b));
+  return add_pair(K, lo, hi);
+}
+__device__ __forceinline__ int64_t add_smul48(int64_t K, int32_t a, int32_t b) {
+  uint32_t lo, hi;
+  asm("v_mul_i32_i24 %0, %1, %2" : "=v"(lo) : "v"(a), "v"(b));
+  asm("v_mul_hi_i32_i24 %0, %1, %2" : "=v"(hi) : "v"(a), "v"(b));
+  return add_pair(K, lo, hi);
+}
 struct ray_t {
   int64_t Ox, Oy, Oz;
   int32_t Dx, Dy, Dz;
@@ -132,12 +153,17 @@ struct walk_t {
   int32_t reads;      // nodes and cells read from memory
 };
 
+// h * d for a height h < 2^8 and a scale d < 2^23 as a 64-bit value: the
+// product is below 2^31, so its high word is zero
+__device__ __forceinline__ int64_t hmul(uint32_t h, uint32_t d) {
+  return (int64_t)(uint32_t)__umul24(h, d);
+}
 // z <= h and z >= h for a height with floor part zq, flag r and scale d
 __device__ __forceinline__ bool z_le(int64_t zq, uint32_t r, uint32_t h, uint32_t d) {
-  return zq + (int64_t)r <= (int64_t)__umul24(h, d);
+  return zq + (int64_t)r <= hmul(h, d);
 }
 __device__ __forceinline__ bool z_ge(int64_t zq, uint32_t h, uint32_t d) {
-  return zq >= (int64_t)__umul24(h, d);
+  return zq >= hmul(h, d);
 }
 // Word `idx` of the map allocation.  The allocation (columns, pyramid and
 // masks of at most 2^27 cells) holds fewer than 2^28 words, so the byte
@@ -489,10 +515,10 @@ __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
     // keys and heights of the crossings through the node's far faces
     const int32_t ix = far_index(s.ni, L, nx1, sx, k.offx);
     const int32_t iy = far_index(s.nj, L, ny1, sy, k.offy);
-    const int64_t KXe = k.KX0 + (int64_t)mul48((uint32_t)ix, r.ay);
-    const int64_t KYe = k.KY0 + (int64_t)mul48((uint32_t)iy, r.ax);
+    const int64_t KXe = add_mul48(k.KX0, (uint32_t)ix, r.ay);
+    const int64_t KYe = add_mul48(k.KY0, (uint32_t)iy, r.ax);
     const bool ex = KXe <= KYe;               // leave through an x face
-    const int64_t Ze = (ex ? k.ZX0 : k.ZY0) + smul48(ex ? ix : iy, r.Dz);
+    const int64_t Ze = add_smul48(ex ? k.ZX0 : k.ZY0, ex ? ix : iy, r.Dz);
     const uint32_t De = ex ? r.ax : r.ay;
     const uint32_t re = ex ? r.rx : r.ry;
     bool occ = false;
@@ -502,10 +528,10 @@ __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
       const int64_t hi = desc ? s.Zin : Ze;
       const uint32_t Dhi = desc ? s.Din : De;
       const uint32_t a = v & 0xFF, b = (v >> 8) & 0xFF, c = (v >> 16) & 0xFF;
-      occ = (lo <= (int64_t)__umul24(a, Dlo)) ||
-            ((lo <= (int64_t)__umul24(c, Dlo)) && (hi >= (int64_t)__umul24(b, Dhi)));
+      occ = (lo <= hmul(a, Dlo)) ||
+            ((lo <= hmul(c, Dlo)) && (hi >= hmul(b, Dhi)));
       if constexpr (kOcc) {
-        if (occ && L > 0 && !(lo <= (int64_t)__umul24(a, Dlo))) {
+        if (occ && L > 0 && !(lo <= hmul(a, Dlo))) {
           const uint32_t mi = moff[L] +
                               ((__umul24((uint32_t)s.nj >> 3, (uint32_t)l.tiles_x) +
                                 ((uint32_t)s.ni >> 3)) << 7) +

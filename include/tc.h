@@ -223,8 +223,10 @@ tc_status tc_shade_views(tc_context *ctx, const tc_view *views, int32_t n,
                                   2 persistent packet queue, 4 hierarchical
                                   with occupancy masks (all four exact and
                                   bit-identical); 3 the sampled march below */
-#define TC_OPT_START_LEVEL 2   /* pyramid level a ray starts at (default 2);
-                                  clamped to the top level */
+#define TC_OPT_START_LEVEL 2   /* pyramid level a ray starts at from its
+                                  origin (default 2); clamped to the top
+                                  level.  Walks the packet beam or the split
+                                  pass start on a cell line begin at level 0 */
 #define TC_OPT_MAX_LEVEL 3     /* highest level a ray ascends to (default
                                   top level) */
 #define TC_OPT_XCD_REMAP 4     /* G > 0: each XCD runs G consecutive blocks

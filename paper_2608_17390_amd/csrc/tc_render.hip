@@ -192,57 +192,78 @@ __global__ __launch_bounds__(256) void split_kernel(tci_map m,
   __shared__ uint32_t best[4];      // per ray of the block: lowest run with a hit
   __shared__ uint2 cand[4];         // per wave: its first hit's record
   load_levels(m, lv);
-  const int32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // every lane of a wave walks the same queued ray: the ray, its exit line
+  // and its index-form constants are wave-uniform and stay in scalar
+  // registers; only the runs' walk states are per lane
+  const int32_t lane = threadIdx.x & 63;
+  const int32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t G = (uint32_t)o.split_waves, per = 4 / G;
   const uint32_t grp = (uint32_t)wave / G, g = (uint32_t)wave - grp * G;
+  const int32_t lgR = 6 + (G == 4 ? 2 : (G == 2 ? 1 : 0));   // 64 G runs per ray
   const uint32_t n = min(*o.qcount, o.qcap);
   const int32_t Lmax = clamp_level(o.max_level, m.top);
   for (uint32_t e0 = blockIdx.x * per; e0 < n; e0 += gridDim.x * per) {
     const uint32_t e = e0 + grp;
     if (threadIdx.x < 4) best[threadIdx.x] = 0xFFFFFFFFu;
     __syncthreads();
-    ray_t r;
-    walk_t s;
-    uint32_t col = 0;
-    int32_t st = kSegEnd;
-    int64_t idx = 0;
+    uint32_t qv = 0, qp = 0;
     if (e < n) {
       const uint4 q = o.queue[e];
-      const tci_view& v = views[q.x];
-      idx = v.out_base + q.y;
-      const int32_t px = (int32_t)(q.y % (uint32_t)v.w), py = (int32_t)(q.y / (uint32_t)v.w);
+      qv = __builtin_amdgcn_readfirstlane(q.x);
+      qp = __builtin_amdgcn_readfirstlane(q.y);
+      const tci_view& v = views[qv];
+      const int32_t px = (int32_t)(qp % (uint32_t)v.w), py = (int32_t)(qp / (uint32_t)v.w);
+      ray_t r;
       pixel_ray(v, px, py, r);
       const int32_t axis = r.ax >= r.ay ? 0 : 1;
-      const int32_t c0 = (int32_t)q.z;   // first line still to walk
+      const int32_t c0 = (int32_t)__builtin_amdgcn_readfirstlane(q.z);  // first line still to walk
       const int32_t dir = (axis == 0 ? r.Dx : r.Dy) > 0 ? 1 : -1;
-      const int32_t last = exit_line(r, m, axis);
-      const int64_t N = max((int64_t)1, (int64_t)(last - c0) * dir + 1);
-      const int64_t R = 64 * (int64_t)G;                // runs of the ray
-      const int64_t j = 64 * (int64_t)g + lane;         // this lane's run
-      const int32_t b0 = c0 + dir * (int32_t)((j * N) / R);
-      const int32_t b1 = c0 + dir * (int32_t)(((j + 1) * N) / R);
-      const bool open = j == R - 1;
+      const int32_t last = __builtin_amdgcn_readfirstlane(exit_line(r, m, axis));
+      // lines still to walk (below 2^17), cut into 2^lgR runs
+      const int32_t N = max(1, (last - c0) * dir + 1);
+      const int32_t j = 64 * (int32_t)g + lane;          // this lane's run
+      const int32_t b0 = c0 + dir * ((j * N) >> lgR);
+      const int32_t b1 = c0 + dir * (((j + 1) * N) >> lgR);
+      const bool open = j == (1 << lgR) - 1;
       int32_t lo = INT32_MIN, hi = INT32_MAX;
       if (!open) {
         if (dir > 0) hi = b1 - 1; else lo = b1 + 1;
       }
       walk_idx_t k;
+      walk_origin(r, k);
+      k.KX0 = rfl64(k.KX0);
+      k.KY0 = rfl64(k.KY0);
+      k.ZX0 = rfl64(k.ZX0);
+      k.ZY0 = rfl64(k.ZY0);
+      k.offx = __builtin_amdgcn_readfirstlane(k.offx);
+      k.offy = __builtin_amdgcn_readfirstlane(k.offy);
+      r.rx = __builtin_amdgcn_readfirstlane(r.rx);
+      r.ry = __builtin_amdgcn_readfirstlane(r.ry);
+      walk_t s;
+      uint32_t col = 0;
+      int32_t st = kSegEnd;
       if (open || b0 != b1) {
-        walk_origin(r, k);
+        // a run spans a few cell lines close to the terrain, where coarse
+        // nodes would only be descended again: it starts at level 0
         if (!walk_at_line(r, k, s, axis, b0)) walk_at_origin(r, 0, s);
-        lift(s, clamp_level(o.start_level, Lmax));
         st = kWalking;
       }
       // walk in chunks; once some run holds a hit, the runs after it
-      // cannot matter and stop
+      // cannot matter and stop.  The ray's vertical direction is the
+      // wave's, so the loop is specialised to its sign.
+      const bool down = r.Dz < 0;
       for (;;) {
         const uint64_t hit_now = __ballot(st == kHitCell || st == kCapped);
         const int32_t first = hit_now ? __ffsll((unsigned long long)hit_now) - 1 : 64;
         if (st == kWalking && (lane > first || *(volatile uint32_t*)&best[grp] < 64 * g))
           st = kSegEnd;
         if (!__ballot(st == kWalking)) break;
-        if (st == kWalking)
-          st = walk_steps<true>(m, lv, r, k, s, Lmax, 16, col, 0, axis, lo, hi);
+        if (st == kWalking) {
+          if (down)
+            st = walk_steps<true, false, true, 1>(m, lv, r, k, s, Lmax, 16, col, 0, axis, lo, hi);
+          else
+            st = walk_steps<true, false, true, 2>(m, lv, r, k, s, Lmax, 16, col, 0, axis, lo, hi);
+        }
       }
       if (o.count && (open || b0 != b1)) atomicAdd(o.count, (unsigned long long)s.reads);
       const uint64_t hits = __ballot(st == kHitCell || st == kCapped);
@@ -257,6 +278,7 @@ __global__ __launch_bounds__(256) void split_kernel(tci_map m,
     __syncthreads();
     if (e < n && g == 0 && lane == 0) {
       const uint32_t b = best[grp];
+      const int64_t idx = views[qv].out_base + qp;
       if (b == 0xFFFFFFFFu) {
         tcp::store_hit(out, idx, kMiss, __builtin_inff());
       } else {

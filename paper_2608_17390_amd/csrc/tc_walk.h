@@ -165,6 +165,12 @@ __device__ __forceinline__ bool z_le(int64_t zq, uint32_t r, uint32_t h, uint32_
 __device__ __forceinline__ bool z_ge(int64_t zq, uint32_t h, uint32_t d) {
   return zq >= hmul(h, d);
 }
+// A wave-uniform 64-bit value moved to scalar registers.
+__device__ __forceinline__ int64_t rfl64(int64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 // Word `idx` of the map allocation.  The allocation (columns, pyramid and
 // masks of at most 2^27 cells) holds fewer than 2^28 words, so the byte
 // offset is a 32-bit value added to the scalar base: the load's
@@ -435,15 +441,6 @@ __device__ __forceinline__ bool walk_at_line(ray_t& r, const walk_idx_t& k, walk
   r.cx0 = s.ni;
   r.cy0 = s.nj;
   return true;
-}
-
-// Move a level-0 walk state up to the level-L node holding its cell (the
-// far faces follow from the node).
-__device__ __forceinline__ void lift(walk_t& s, int32_t L) {
-  if (L <= 0) return;
-  s.ni >>= L;
-  s.nj >>= L;
-  s.L = L;
 }
 
 // (n + f) << L with f = 1 when the axis runs forward, times s = +-1, plus

@@ -172,9 +172,10 @@ __device__ __forceinline__ int64_t rfl64(int64_t x) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 // Word `idx` of the map allocation.  The allocation (columns, pyramid and
-// masks of at most 2^27 cells) holds fewer than 2^28 words, so the byte
-// offset is a 32-bit value added to the scalar base: the load's
-// base-plus-offset form, with no 64-bit address arithmetic per lane.
+// masks of at most 2^27 cells, tiles padded) holds about 2^28 words, far
+// below the 2^30 whose byte offsets fit in 32 bits, so the byte offset is a
+// 32-bit value added to the scalar base: the load's base-plus-offset form,
+// with no 64-bit address arithmetic per lane.
 __device__ __forceinline__ uint32_t map_word(const uint32_t* base, uint32_t idx) {
   return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(base) + (idx << 2));
 }

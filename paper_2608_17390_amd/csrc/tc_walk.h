@@ -546,11 +546,14 @@ __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
         }
       }
     }
+    if (occ && L == 0) {
+      col = v;
+      return kHitCell;
+    }
+    // one latch for both moves: a descent or a step (and maybe a climb)
+    // writes the node and level once, at the end
+    int32_t ni = s.ni, nj = s.nj, nL;
     if (occ) {
-      if (L == 0) {
-        col = v;
-        return kHitCell;
-      }
       // descend into the child holding the ray after the entry crossing
       const int32_t Lc = L - 1;
       int32_t bx, by;
@@ -561,35 +564,38 @@ __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
       if (r.Dy == 0 || anchored) by = (r.cy0 >> Lc) & 1;
       else if (s.entry == kWmy || s.entry == kWpy) by = neary;
       else by = (KYe - ushl(r.ax, Lc) < s.Kin) ? 1 - neary : neary;
-      s.ni = 2 * s.ni + bx;
-      s.nj = 2 * s.nj + by;
-      s.L = Lc;
-      continue;
-    }
-    // step to the next node of this level through the exit face
-    const int32_t pi = s.ni, pj = s.nj;
-    s.Kin = ex ? KXe : KYe;
-    if (ex) {
-      s.ni += sx;
-      s.entry = fx ? kWmx : kWpx;
+      ni = 2 * ni + bx;
+      nj = 2 * nj + by;
+      nL = Lc;
     } else {
-      s.nj += sy;
-      s.entry = fy ? kWmy : kWpy;
+      // step to the next node of this level through the exit face
+      s.Kin = ex ? KXe : KYe;
+      if (ex) {
+        ni += sx;
+        s.entry = fx ? kWmx : kWpx;
+      } else {
+        nj += sy;
+        s.entry = fy ? kWmy : kWpy;
+      }
+      s.Zin = Ze;
+      s.Din = De;
+      s.rin = re;
+      // the ray cannot come back into the map, or is above all solid
+      const bool away = (ni < 0 && r.Dx <= 0) || (ni >= l.w && r.Dx >= 0) ||
+                        (nj < 0 && r.Dy <= 0) || (nj >= l.h && r.Dy >= 0);
+      const bool above = !desc && !z_le(s.Zin, s.rin, 255, s.Din);
+      if (away || above) return kMissed;
+      // go up one level when the step entered a new parent node
+      nL = L;
+      if (L < max_level && (((s.ni ^ ni) | (s.nj ^ nj)) >> 1) != 0) {
+        ni >>= 1;
+        nj >>= 1;
+        nL = L + 1;
+      }
     }
-    s.Zin = Ze;
-    s.Din = De;
-    s.rin = re;
-    // the ray cannot come back into the map, or is above all solid
-    const bool away = (s.ni < 0 && r.Dx <= 0) || (s.ni >= l.w && r.Dx >= 0) ||
-                      (s.nj < 0 && r.Dy <= 0) || (s.nj >= l.h && r.Dy >= 0);
-    const bool above = !desc && !z_le(s.Zin, s.rin, 255, s.Din);
-    if (away || above) return kMissed;
-    // go up one level when the step entered a new parent node
-    if (L < max_level && (((pi ^ s.ni) | (pj ^ s.nj)) >> 1) != 0) {
-      s.ni >>= 1;
-      s.nj >>= 1;
-      s.L = L + 1;
-    }
+    s.ni = ni;
+    s.nj = nj;
+    s.L = nL;
   }
   return kWalking;
 }

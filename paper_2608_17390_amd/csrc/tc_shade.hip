@@ -48,16 +48,22 @@ __device__ __forceinline__ int32_t surf(const sh_map& m, int32_t x, int32_t y, i
   return ((c >> 8) & 0xFF) ? (int32_t)((c >> 16) & 0xFF) : hT;
 }
 
-__device__ __forceinline__ int64_t floordiv(int64_t a, int64_t b) {  // b > 0
-  int64_t q = a / b;
-  if ((a % b) != 0 && a < 0) q--;
+// floor(a / b) for 0 < b < 2^24 and a quotient below 2^40 in magnitude: a
+// double-precision estimate (a relative error below 2^-51, so less than one
+// unit from the true quotient), then exact integer corrections.  A generic
+// 64-bit division costs several times more.
+__device__ __forceinline__ int64_t floordiv(int64_t a, int64_t b) {
+  int64_t q = (int64_t)floor((double)a / (double)b);
+  int64_t r = a - q * b;
+  while (r < 0) { --q; r += b; }
+  while (r >= b) { ++q; r -= b; }
   return q;
 }
 
 // Does a ray from P along L meet any solid?  `reads` gains the nodes and
 // cells the walk read.  kDir: the sign of L[2] (1 negative, 2 otherwise),
 // the walk loop's specialisation.
-template <int kDir>
+template <int kDir, bool kCount>
 __device__ __forceinline__ bool occluded(const tci_map& m, const lvl_t* lv, const int64_t P[3],
                                          const int32_t L[3], int32_t L0, int32_t Lmax,
                                          int32_t& reads) {
@@ -82,14 +88,18 @@ __device__ __forceinline__ bool occluded(const tci_map& m, const lvl_t* lv, cons
   walk_origin(s, k);
   walk_at_origin(s, L0, st);
   uint32_t col = 0;
-  const int32_t res = walk_steps<false, false, true, kDir>(m, lv, s, k, st, Lmax, kIterCap + 1, col);
-  reads += st.reads;
-  return res == kHitCell || res == kCapped;
+  // the budget bounds the walk: a walk that uses it up (never expected)
+  // counts as occluded, as a hit does
+  const int32_t res = walk_steps<false, false, false, kDir>(m, lv, s, k, st, Lmax, kIterCap + 1,
+                                                           col, 0, 0, 0, 0, nullptr, kCount);
+  if (kCount) reads += st.reads;
+  return res != kMissed;
 }
 
 // One kernel per sign of the light's vertical direction: every shadow ray
-// of a launch shares it, so the walk loop is specialised to it.
-template <int kDir>
+// of a launch shares it, so the walk loop is specialised to it; and one
+// with read counting (o.count) and one without.
+template <int kDir, bool kCount>
 __global__ __launch_bounds__(256) void shade_kernel(
     tci_map m, const tci_view* __restrict__ views, int32_t nviews,
     const int64_t* __restrict__ pkt_prefix, int64_t npkt, const uint2* __restrict__ hits,
@@ -181,7 +191,7 @@ __global__ __launch_bounds__(256) void shade_kernel(
     for (int cc = 0; cc < 3; ++cc)
       P[cc] = O[cc] + floordiv(tn * (int64_t)D[cc], td) + nudge[cc];
     const int32_t top = m.top;
-    lit = !occluded<kDir>(m, lv, P, sh.light, clamp_level(o.start_level, top),
+    lit = !occluded<kDir, kCount>(m, lv, P, sh.light, clamp_level(o.start_level, top),
                     clamp_level(o.max_level, top), reads);
   }
   const float amb = (layer == 0 && B > 0) ? sh.cave_ambient : sh.ambient;
@@ -198,7 +208,7 @@ __global__ __launch_bounds__(256) void shade_kernel(
     out |= (uint32_t)(val + 0.5f) << (8 * cc);
   }
   rgba[idx] = out;
-  if (o.count) atomicAdd(o.count, (unsigned long long)reads);
+  if (kCount) atomicAdd(o.count, (unsigned long long)reads);
 }
 
 }  // namespace
@@ -209,11 +219,10 @@ hipError_t tci_launch_shade(const tci_map& m, const tci_view* views, int32_t nvi
                             hipStream_t s) {
   int64_t blocks = (npkt + 3) / 4;
   if (blocks < 1) return hipSuccess;
-  if (sh.light[2] < 0)
-    hipLaunchKernelGGL(shade_kernel<1>, dim3((uint32_t)blocks), dim3(256), 0, s, m, views,
-                       nviews, pkt_prefix, npkt, (const uint2*)hits, rgba, sh, o);
-  else
-    hipLaunchKernelGGL(shade_kernel<2>, dim3((uint32_t)blocks), dim3(256), 0, s, m, views,
-                       nviews, pkt_prefix, npkt, (const uint2*)hits, rgba, sh, o);
+  const bool c = o.count != nullptr;
+  auto kern = sh.light[2] < 0 ? (c ? shade_kernel<1, true> : shade_kernel<1, false>)
+                              : (c ? shade_kernel<2, true> : shade_kernel<2, false>);
+  hipLaunchKernelGGL(kern, dim3((uint32_t)blocks), dim3(256), 0, s, m, views, nviews, pkt_prefix,
+                     npkt, (const uint2*)hits, rgba, sh, o);
   return hipGetLastError();
 }

@@ -526,8 +526,8 @@ __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
       const int64_t hi = desc ? s.Zin : Ze;
       const uint32_t Dhi = desc ? s.Din : De;
       const uint32_t a = v & 0xFF, b = (v >> 8) & 0xFF, c = (v >> 16) & 0xFF;
-      occ = (lo <= hmul(a, Dlo)) ||
-            ((lo <= hmul(c, Dlo)) && (hi >= hmul(b, Dhi)));
+      // the three compares combined without short-circuit branches
+      occ = (lo <= hmul(a, Dlo)) | ((lo <= hmul(c, Dlo)) & (hi >= hmul(b, Dhi)));
       if constexpr (kOcc) {
         if (occ && L > 0 && !(lo <= hmul(a, Dlo))) {
           const uint32_t mi = moff[L] +

@@ -503,7 +503,7 @@ __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
       if ((n << L) > seg_hi || ((n + 1) << L) - 1 < seg_lo) return kSegEnd;
     }
     const lvl_t l = lv[L];
-    const bool inmap = (uint32_t)s.ni < (uint32_t)l.w && (uint32_t)s.nj < (uint32_t)l.h;
+    const bool inmap = ((uint32_t)s.ni < (uint32_t)l.w) & ((uint32_t)s.nj < (uint32_t)l.h);
     uint32_t v = 0;
     if (count) s.reads += inmap ? 1 : 0;
     if (inmap)
@@ -581,13 +581,14 @@ __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
       s.Din = De;
       s.rin = re;
       // the ray cannot come back into the map, or is above all solid
-      const bool away = (ni < 0 && r.Dx <= 0) || (ni >= l.w && r.Dx >= 0) ||
-                        (nj < 0 && r.Dy <= 0) || (nj >= l.h && r.Dy >= 0);
-      const bool above = !desc && !z_le(s.Zin, s.rin, 255, s.Din);
-      if (away || above) return kMissed;
+      // (compares combined bitwise, without short-circuit branches)
+      const bool away = ((ni < 0) & (r.Dx <= 0)) | ((ni >= l.w) & (r.Dx >= 0)) |
+                        ((nj < 0) & (r.Dy <= 0)) | ((nj >= l.h) & (r.Dy >= 0));
+      const bool above = !desc & !z_le(s.Zin, s.rin, 255, s.Din);
+      if (away | above) return kMissed;
       // go up one level when the step entered a new parent node
       nL = L;
-      if (L < max_level && (((s.ni ^ ni) | (s.nj ^ nj)) >> 1) != 0) {
+      if ((L < max_level) & ((((s.ni ^ ni) | (s.nj ^ nj)) >> 1) != 0)) {
         ni >>= 1;
         nj >>= 1;
         nL = L + 1;

@@ -36,28 +36,35 @@ constexpr float kBeamGrowth = 0.125f;        // each interval 1/8 longer than th
 constexpr float kBeamLog2Growth = 0.169925f; // log2(1 + kBeamGrowth)
 
 // Could solid lie in the box [lox, hix] x [loy, hiy] x [loz, hiz] (cells,
-// height units)?  Reads at most four nodes, counted in `reads`.
+// height units)?  Reads at most four nodes, counted in `reads`.  Every
+// test is evaluated and the answer combined without branches (lanes test
+// different boxes, so early returns would diverge): the loads use indices
+// clamped into the level, and the answer is the first of these that
+// applies: no claim for a box with a NaN bound (never formed from valid
+// views); clear above every height; no claim for a huge box or one wider
+// than the top level's nodes; clear beside the map; else the node test.
 __device__ __forceinline__ bool beam_box_solid(const tci_map& m, const lvl_t* lv, float lox,
                                                float hix, float loy, float hiy, float loz,
                                                float hiz, int32_t& reads) {
-  // no claim for a box with a NaN bound (never formed from valid views)
-  if (!(lox <= hix && loy <= hiy && loz <= hiz)) return true;
-  if (loz > 255.0f) return false;               // above every height
+  const bool bad = !((lox <= hix) & (loy <= hiy) & (loz <= hiz));
+  const bool above = loz > 255.0f;
   const float ext = fmaxf(hix - lox, hiy - loy);
-  if (!(ext < 65536.0f)) return true;           // no claim for huge boxes
+  const bool huge = !(ext < 65536.0f);
   // 2^L > ext: the box overlaps at most two nodes per axis at level L
-  int32_t L = ext < 1.0f ? 0 : __builtin_amdgcn_frexp_expf(ext);
-  L = min(L, m.top);
-  // node coordinates, clamped far outside the map (no bound is NaN here)
+  const int32_t L = min(max(ext < 1.0f ? 0 : __builtin_amdgcn_frexp_expf(ext), 0), m.top);
+  // node coordinates, clamped far outside the map
   auto node = [&](float c) {
     return (int32_t)floorf(__builtin_amdgcn_fmed3f(c, -1048576.0f, 1048576.0f)) >> L;
   };
   const int32_t x0 = node(lox), x1 = node(hix), y0 = node(loy), y1 = node(hiy);
-  if (x1 - x0 > 1 || y1 - y0 > 1) return true;  // wider than the top level's nodes
+  const bool wide = ((x1 - x0) > 1) | ((y1 - y0) > 1);
   const lvl_t l = lv[L];
   const int32_t i0 = max(x0, 0), i1 = min(x1, l.w - 1);
   const int32_t j0 = max(y0, 0), j1 = min(y1, l.h - 1);
-  if (i0 > i1 || j0 > j1) return false;         // beside the map: air
+  const bool beside = (i0 > i1) | (j0 > j1);
+  // indices clamped into the level, so every lane's loads are valid
+  const int32_t ci0 = min(i0, l.w - 1), ci1 = max(i1, 0);
+  const int32_t cj0 = min(j0, l.h - 1), cj1 = max(j1, 0);
   // tiled index (tci_tile_index) with 24-bit multiplies: tile rows and
   // tiles per row are below 2^11
   auto at = [&](int32_t i, int32_t j) {
@@ -65,15 +72,17 @@ __device__ __forceinline__ bool beam_box_solid(const tci_map& m, const lvl_t* lv
                                       ((uint32_t)i >> 3)) << 6) +
                                 (((uint32_t)j & 7) << 3) + ((uint32_t)i & 7));
   };
-  const uint32_t w00 = at(i0, j0), w10 = at(i1, j0), w01 = at(i0, j1), w11 = at(i1, j1);
-  reads += 1 + (i1 != i0) + (j1 != j0) + (i1 != i0 && j1 != j0);
+  const uint32_t w00 = at(ci0, cj0), w10 = at(ci1, cj0), w01 = at(ci0, cj1), w11 = at(ci1, cj1);
+  const bool test = !bad & !above & !huge & !wide & !beside;
+  reads += test ? 1 + (i1 != i0) + (j1 != j0) + ((i1 != i0) & (j1 != j0)) : 0;
   const uint32_t fmax = max(max(w00 & 0xFF, w10 & 0xFF), max(w01 & 0xFF, w11 & 0xFF));
   const uint32_t smin = min(min((w00 >> 8) & 0xFF, (w10 >> 8) & 0xFF),
                             min((w01 >> 8) & 0xFF, (w11 >> 8) & 0xFF));
   const uint32_t smax = max(max((w00 >> 16) & 0xFF, (w10 >> 16) & 0xFF),
                             max((w01 >> 16) & 0xFF, (w11 >> 16) & 0xFF));
   // a column with no slab has smin = smax = 0, which the floor test covers
-  return loz <= (float)fmax || (loz <= (float)smax && hiz >= (float)smin);
+  const bool solid = (loz <= (float)fmax) | ((loz <= (float)smax) & (hiz >= (float)smin));
+  return bad | (!above & (huge | wide | (!beside & solid)));
 }
 
 // Parameter t >= 0 such that no ray of the packet whose tile is (tx, ty)

@@ -179,12 +179,9 @@ __device__ __forceinline__ int64_t rfl64(int64_t x) {
 __device__ __forceinline__ uint32_t map_word(const uint32_t* base, uint32_t idx) {
   return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(base) + (idx << 2));
 }
-// a << L for an unsigned or signed 32-bit a as a 64-bit value
+// a << L for an unsigned 32-bit a as a 64-bit value
 __device__ __forceinline__ int64_t ushl(uint32_t a, int32_t L) {
   return (int64_t)((uint64_t)a << L);
-}
-__device__ __forceinline__ int64_t sshl(int32_t a, int32_t L) {
-  return (int64_t)((uint64_t)(int64_t)a << L);
 }
 
 // Ray of pixel (px, py).  Every pixel's origin and direction fit in 32 bits

@@ -34,6 +34,9 @@
 
 namespace {
 
+// 8x8 pixel packets (waves) per block: two (the same march time as four, as the render kernels use)
+constexpr int32_t kPackets = 2;
+
 constexpr uint32_t kMiss = 0xFFFFFFFFu;
 constexpr int32_t kGroup = 8;
 
@@ -56,13 +59,13 @@ __device__ __forceinline__ void at(const fray& r, float t, float& x, float& y, f
   z = r.oz + t * r.dz;
 }
 
-__global__ __launch_bounds__(256) void march_kernel(
+__global__ __launch_bounds__(64 * kPackets) void march_kernel(
     tci_map m, const tci_view* __restrict__ views, int32_t nviews,
     const int64_t* __restrict__ pkt_prefix, int64_t npkt, void* out,
     tci_render_opts o) {
   const int64_t b = tcp::xcd_block(blockIdx.x, gridDim.x, o.xcd_remap);
   const int32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t p = b * 4 + wave;
+  const int64_t p = b * kPackets + wave;
   if (p >= npkt) return;
   const int32_t vi = __builtin_amdgcn_readfirstlane(tcp::find_view(pkt_prefix, nviews, p));
   const tci_view& v = views[vi];
@@ -174,9 +177,9 @@ hipError_t tci_launch_march(const tci_map& m, const tci_view* views,
                             int32_t nviews, const int64_t* pkt_prefix,
                             int64_t npkt, void* out, const tci_render_opts& o,
                             hipStream_t s) {
-  int64_t blocks = (npkt + 3) / 4;
+  int64_t blocks = (npkt + kPackets - 1) / kPackets;
   if (blocks < 1) return hipSuccess;
-  hipLaunchKernelGGL(march_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, m,
+  hipLaunchKernelGGL(march_kernel, dim3((uint32_t)blocks), dim3(64 * kPackets), 0, s, m,
                      views, nviews, pkt_prefix, npkt, out, o);
   return hipGetLastError();
 }

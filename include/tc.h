@@ -230,7 +230,7 @@ tc_status tc_shade_views(tc_context *ctx, const tc_view *views, int32_t n,
 #define TC_OPT_MAX_LEVEL 3     /* highest level a ray ascends to (default
                                   top level) */
 #define TC_OPT_XCD_REMAP 4     /* G > 0: each XCD runs G consecutive blocks
-                                  of 4 packets at a time (L2 locality);
+                                  of 2 packets at a time (L2 locality);
                                   0: hardware round-robin (default 0) */
 #define TC_OPT_PERSIST_WAVES 5 /* waves per CU of the persistent launch
                                   (default 8) */

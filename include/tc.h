@@ -231,7 +231,7 @@ tc_status tc_shade_views(tc_context *ctx, const tc_view *views, int32_t n,
                                   top level) */
 #define TC_OPT_XCD_REMAP 4     /* G > 0: each XCD runs G consecutive blocks
                                   of 2 packets at a time (L2 locality);
-                                  0: hardware round-robin (default 0) */
+                                  0: hardware round-robin (default 64) */
 #define TC_OPT_PERSIST_WAVES 5 /* waves per CU of the persistent launch
                                   (default 8) */
 #define TC_OPT_REFILL_MIN 6    /* persistent mode: idle lanes that trigger a

@@ -98,7 +98,7 @@ struct tc_context {
   int32_t render_mode = 0;
   int32_t start_level = 2;
   int32_t max_level = TCI_MAX_LEVELS - 1;
-  int32_t xcd_remap = 0;
+  int32_t xcd_remap = 64;
   int32_t persist_waves = 16;
   int32_t refill_min = 16;
   int32_t refill_iters = 16;

@@ -174,7 +174,7 @@ tc_status tc_autotune(tc_context* ctx, const tc_view* views, int32_t n,
     const Knobs cur = read_knobs(ctx);
     for (int32_t split : {0, 128})
       for (int32_t order : {0, 1, 2})
-        for (int32_t remap : {0, 2, 8})
+        for (int32_t remap : {0, 8, 64})
           for (int32_t start : {1, 2, 3, 4})
             cand.push_back(Knobs{0, start, order, remap, cur.waves, cur.rmin, cur.riters, split,
                                  cur.beam});

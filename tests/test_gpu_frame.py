@@ -103,7 +103,7 @@ def test_autotune_keeps_results(ctx):
     ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, 0)
     ctx.tc_set_option(tc.TC_OPT_START_LEVEL, 2)
     ctx.tc_set_option(tc.TC_OPT_TILE_ORDER, 2)
-    ctx.tc_set_option(tc.TC_OPT_XCD_REMAP, 0)
+    ctx.tc_set_option(tc.TC_OPT_XCD_REMAP, 64)
     ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 128)
 
 

@@ -213,14 +213,14 @@ def test_packet_orders_and_xcd_groups(ctx):
     views = _random_views(rng, F, B, 12, [(77, 53), (130, 9), (8, 300), (64, 64)])
     wo, do = oracle.render(F, B, T, views)
     for order in (0, 1, 2):
-        for remap in (0, 3):
+        for remap in (0, 3, 64):
             ctx.tc_set_option(tc.TC_OPT_TILE_ORDER, order)
             ctx.tc_set_option(tc.TC_OPT_XCD_REMAP, remap)
             for mode in MODES:
                 wg, dg = gpu_render(ctx, views, mode)
                 assert_parity(wg, dg, wo, do, "order %d remap %d %s" % (order, remap, mode))
     ctx.tc_set_option(tc.TC_OPT_TILE_ORDER, 2)
-    ctx.tc_set_option(tc.TC_OPT_XCD_REMAP, 0)
+    ctx.tc_set_option(tc.TC_OPT_XCD_REMAP, 64)
 
 
 @pytest.mark.parametrize("budget,queue,waves", [(1, 1 << 20, 4), (5, 1 << 20, 1), (5, 1 << 20, 2),

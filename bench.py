@@ -111,9 +111,21 @@ def kernel_times(torch, ctx, tc, views, out, steps):
     return np.array(rows, dtype=np.float64)
 
 
-def cpu_baseline(oracle, F, B, T, views, rays_per_frame, budget_s=12.0):
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or None."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(oracle, F, B, T, views, rays_per_frame, budget_s=12.0, single_s=5.0):
     """The CPU oracle on the host cores, on repeated renders of the same
-    view until about budget_s seconds of wall time have passed."""
+    view until about budget_s seconds of wall time have passed; then on one
+    thread for about single_s seconds."""
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
@@ -126,15 +138,22 @@ def cpu_baseline(oracle, F, B, T, views, rays_per_frame, budget_s=12.0):
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
-    # one thread, on every 8th row of the same view (about 4 s)
+    # one thread: whole renders of the same view until single_s has passed
+    done1 = 0
     t1 = time.perf_counter()
-    w, _ = oracle.render(F, B, T, views, threads=1, rows=(0, 1 << 30, 8))
+    while True:
+        oracle.render(F, B, T, views, threads=1)
+        done1 += 1
+        if time.perf_counter() - t1 >= single_s:
+            break
     dt1 = time.perf_counter() - t1
     return {"value": done * rays_per_frame / dt / 1e9, "unit": "Grays/s",
-            "cores": cores, "kind": "oracle",
-            "sample": "%d full renders of the 1920x1080 headline view (%.1f s)" % (done, dt),
-            "single_thread_value": w.size / dt1 / 1e9,
-            "single_thread_sample": "every 8th row of the same view on one thread (%.1f s)" % dt1}
+            "cores": cores, "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": "%d full renders of the 1920x1080 headline view on %d threads (%.1f s)"
+                      % (done, cores, dt),
+            "single_thread_value": done1 * rays_per_frame / dt1 / 1e9,
+            "single_thread_sample": "%d full renders of the same view on one thread (%.1f s)"
+                                    % (done1, dt1)}
 
 
 def c3_frame(torch, tc, synth, steps, warmup):

@@ -259,7 +259,9 @@ tc_status tc_shade_views(tc_context *ctx, const tc_view *views, int32_t n,
                                     second pass; default 128) */
 #define TC_OPT_SPLIT_QUEUE 12    /* most rays the second pass takes per call;
                                     further long rays finish in the first
-                                    pass (default 131072) */
+                                    pass (1..2^24, default 131072; every slot
+                                    of the staging ring holds a device queue
+                                    of this many 16-byte entries) */
 #define TC_OPT_SPLIT_WAVES 18    /* waves of one block the second pass gives
                                     each long ray: its remaining path is cut
                                     into 64 runs per wave, each walked by one
@@ -305,6 +307,13 @@ tc_status tc_shade_views(tc_context *ctx, const tc_view *views, int32_t n,
                                     each kernel, read back by
                                     tc_read_kernel_times (diagnostic;
                                     default 0) */
+/* Read-only (tc_get_option): the number of device and pinned host
+ * allocations the context has made since tc_create, its frames' included.
+ * tc_create allocates the staging ring (16 slots of table buffers and split
+ * queues) up front, so tc_render_views, tc_apply_edit and tc_shade_views
+ * allocate nothing unless their tables outgrow a slot (256 KiB) or
+ * TC_OPT_SPLIT_QUEUE grows. */
+#define TC_INFO_ALLOCATIONS 19
 tc_status tc_set_option(tc_context *ctx, int32_t key, int64_t value);
 tc_status tc_get_option(const tc_context *ctx, int32_t key, int64_t *value);
 
@@ -389,6 +398,11 @@ tc_status tc_server_submit_edit(tc_server *s, const tc_edit *edits, int32_t n,
  * submission to observed completion in seconds (-1 until done). */
 tc_status tc_server_poll(tc_server *s, uint64_t id, int32_t *state,
                          double *latency_s);
+/* tc_server_poll of n requests at once, under one lock: states[i] and (if
+ * latencies_s is not NULL) latencies_s[i] for ids[i].  All ids are checked
+ * first; an unknown one gives TC_INVALID_ARG with nothing written. */
+tc_status tc_server_poll_many(tc_server *s, const uint64_t *ids, int32_t n,
+                              int32_t *states, double *latencies_s);
 /* Block until the request is done (TC_OK) or timeout_s passes (TC_TIMEOUT). */
 tc_status tc_server_wait(tc_server *s, uint64_t id, double timeout_s);
 /* Device pointer to a finished view's hit records (width*height, rows

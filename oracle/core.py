@@ -58,6 +58,16 @@ def lib():
     return _lib
 
 
+def default_threads():
+    """Threads of a multi-threaded oracle call: the cores this process may
+    run on, at most 16."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
 def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
@@ -89,7 +99,7 @@ def render(F, B, T, views, threads=None, rows=None):
         n += int(x["width"]) * len(range(r0, hh, st)) if hh > r0 else 0
     word = np.empty(n, np.uint32)
     depth = np.empty(n, np.float64)
-    th = threads if threads else (os.cpu_count() or 1)
+    th = threads if threads else default_threads()
     got = lib().or_render_rows(W, H, _ptr(F), _ptr(B), _ptr(T), _ptr(v),
                                len(v), r0, r1, st, _ptr(word), _ptr(depth), th)
     if got != n:
@@ -166,7 +176,7 @@ def march(F, B, T, views, far=600.0, steps=128, bisect=4, threads=None,
     word = np.empty(n, np.uint32)
     depth = np.empty(n, np.float32)
     reads = ctypes.c_int64(0)
-    th = threads if threads else (os.cpu_count() or 1)
+    th = threads if threads else default_threads()
     got = lib().om_march_rows(W, H, _ptr(F), _ptr(B), _ptr(T), _ptr(v), len(v),
                               r0, r1, st, *_march_args(far, steps, bisect),
                               _ptr(word), _ptr(depth), th, ctypes.byref(reads))

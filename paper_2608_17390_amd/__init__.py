@@ -18,5 +18,5 @@ from ._tc import (Context, Frame, Server, TCError, tc_create, tc_view, tc_edit, 
                   TC_OPT_TILE_ORDER, TC_OPT_PRIORITY_BOOST, TC_OPT_SPLIT_BUDGET,
                   TC_OPT_SPLIT_QUEUE, TC_OPT_KERNEL_TIMING,
                   TC_OPT_MARCH_STEPS, TC_OPT_MARCH_BISECT, TC_OPT_MARCH_FAR,
-                  TC_OPT_BEAM_PASSES, TC_OPT_SPLIT_WAVES,
+                  TC_OPT_BEAM_PASSES, TC_OPT_SPLIT_WAVES, TC_INFO_ALLOCATIONS,
                   TC_FACE_SAMPLED)

@@ -55,6 +55,7 @@ TC_OPT_MARCH_BISECT = 15
 TC_OPT_MARCH_FAR = 16
 TC_OPT_BEAM_PASSES = 17
 TC_OPT_SPLIT_WAVES = 18
+TC_INFO_ALLOCATIONS = 19
 TC_FACE_SAMPLED = 0
 
 _STATUS = {0: "TC_OK", -1: "TC_INVALID_ARG", -2: "TC_OUT_OF_MEMORY",
@@ -136,6 +137,7 @@ SIGNATURES = [
                                      ctypes.POINTER(ctypes.c_uint64)]),
     ("tc_server_poll", _I32, [_P, ctypes.c_uint64, ctypes.POINTER(_I32),
                               ctypes.POINTER(ctypes.c_double)]),
+    ("tc_server_poll_many", _I32, [_P, _P, _I32, _P, _P]),
     ("tc_server_wait", _I32, [_P, ctypes.c_uint64, ctypes.c_double]),
     ("tc_server_result", _I32, [_P, ctypes.c_uint64, ctypes.POINTER(_P),
                                 ctypes.POINTER(ctypes.c_int64)]),
@@ -485,6 +487,15 @@ class Server:
         self._chk(load_library().tc_server_poll(self._h, rid, ctypes.byref(state),
                                                 ctypes.byref(lat)))
         return state.value, lat.value
+
+    def tc_server_poll_many(self, rids):
+        """(states int32[n], latencies float64[n]) of several requests."""
+        ids = np.ascontiguousarray(rids, np.uint64)
+        states = np.empty(ids.size, np.int32)
+        lat = np.empty(ids.size, np.float64)
+        self._chk(load_library().tc_server_poll_many(self._h, ids.ctypes.data, int(ids.size),
+                                                     states.ctypes.data, lat.ctypes.data))
+        return states, lat
 
     def tc_server_wait(self, rid, timeout_s=60.0):
         self._chk(load_library().tc_server_wait(self._h, rid, float(timeout_s)))

@@ -1,7 +1,8 @@
 // Host runtime of the library: the C ABI declared in include/tc.h.
 //
 // Owns the device copy of the map (packed columns plus the min/max pyramid,
-// one allocation), validates every call before enqueueing anything, stages
+// one allocation), validates every call before enqueueing anything (with
+// the planning layer of tc_plan.cpp), stages
 // small per-call tables (views, edit lists) through a ring of pinned host
 // buffers with matching device buffers, and launches the kernels of
 // tc_map.hip and tc_render.hip.
@@ -25,31 +26,6 @@ using tci::set_device;
 namespace {
 
 std::string g_create_error;
-
-bool columns_valid(const uint8_t* F, const uint8_t* B, const uint8_t* T,
-                   int32_t w, int32_t h, size_t stride, int32_t* bad_x,
-                   int32_t* bad_y) {
-  for (int32_t y = 0; y < h; ++y) {
-    const uint8_t* f = F + (size_t)y * stride;
-    const uint8_t* b = B + (size_t)y * stride;
-    const uint8_t* t = T + (size_t)y * stride;
-    for (int32_t x = 0; x < w; ++x) {
-      bool ok = b[x] == 0 ? t[x] == 0 : (b[x] > f[x] && t[x] >= b[x]);
-      if (!ok) {
-        *bad_x = x;
-        *bad_y = y;
-        return false;
-      }
-    }
-  }
-  return true;
-}
-
-int32_t top_level(int32_t W, int32_t H) {
-  int32_t m = std::max(W, H), L = 0;
-  while ((1 << L) < m) ++L;
-  return L;
-}
 
 }  // namespace
 
@@ -76,6 +52,44 @@ tc_status set_device(tc_context* ctx) {
   return TC_OK;
 }
 
+hipError_t dev_alloc(tc_context* ctx, void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes);
+  if (e == hipSuccess) ctx->allocs++;
+  return e;
+}
+
+hipError_t host_alloc(tc_context* ctx, void** p, size_t bytes) {
+  hipError_t e = hipHostMalloc(p, bytes, hipHostMallocDefault);
+  if (e == hipSuccess) ctx->allocs++;
+  return e;
+}
+
+tc_status ring_alloc(tc_context* ctx, uint32_t qcap) {
+  for (Slot& s : ctx->ring) {
+    if (s.pending) {
+      TC_HIP(hipEventSynchronize(s.ev), "hipEventSynchronize(staging)");
+      s.pending = false;
+    }
+    if (!s.ev) TC_HIP(hipEventCreateWithFlags(&s.ev, hipEventDisableTiming), "hipEventCreate");
+    if (!s.host) TC_HIP(host_alloc(ctx, &s.host, kSlotBytes), "hipHostMalloc(staging)");
+    if (!s.dev) {
+      TC_HIP(dev_alloc(ctx, &s.dev, kSlotBytes), "hipMalloc(staging)");
+      s.cap = kSlotBytes;
+    }
+    if (s.qcap < qcap) {
+      if (s.queue) {
+        (void)hipFree(s.queue);
+        s.queue = nullptr;
+        s.qcap = 0;
+      }
+      TC_HIP(dev_alloc(ctx, (void**)&s.queue, sizeof(uint4) * (size_t)qcap),
+             "hipMalloc(split queue)");
+      s.qcap = qcap;
+    }
+  }
+  return TC_OK;
+}
+
 tc_status acquire(tc_context* ctx, size_t bytes, Slot** out) {
   Slot& s = ctx->ring[ctx->ring_next];
   ctx->ring_next = (ctx->ring_next + 1) % kRing;
@@ -84,16 +98,16 @@ tc_status acquire(tc_context* ctx, size_t bytes, Slot** out) {
     s.pending = false;
   }
   if (s.cap < bytes) {
-    size_t cap = std::max<size_t>(bytes, 64 << 10);
-    cap = (cap + 4095) & ~(size_t)4095;
+    // tables beyond kSlotBytes: the slot grows (the only allocation a call
+    // can make after tc_create)
+    size_t cap = (bytes + 4095) & ~(size_t)4095;
     if (s.host) { (void)hipHostFree(s.host); s.host = nullptr; }
     if (s.dev) { (void)hipFree(s.dev); s.dev = nullptr; }
     s.cap = 0;
-    TC_HIP(hipHostMalloc(&s.host, cap, hipHostMallocDefault), "hipHostMalloc(staging)");
-    TC_HIP(hipMalloc(&s.dev, cap), "hipMalloc(staging)");
+    TC_HIP(host_alloc(ctx, &s.host, cap), "hipHostMalloc(staging)");
+    TC_HIP(dev_alloc(ctx, &s.dev, cap), "hipMalloc(staging)");
     s.cap = cap;
   }
-  if (!s.ev) TC_HIP(hipEventCreateWithFlags(&s.ev, hipEventDisableTiming), "hipEventCreate");
   *out = &s;
   return TC_OK;
 }
@@ -102,6 +116,21 @@ tc_status release(tc_context* ctx, Slot* s, hipStream_t st) {
   TC_HIP(hipEventRecord(s->ev, st), "hipEventRecord(staging)");
   s->pending = true;
   return TC_OK;
+}
+
+tc_status validate_edits(tc_context* ctx, const tc_edit* edits, int32_t n,
+                         size_t* patch_bytes) {
+  return check_edits(edits, n, patch_bytes, &ctx->err);
+}
+
+tc_status plan_views(tc_context* ctx, const tc_view* views, int32_t n, ViewPlan& p,
+                     bool allow_split) {
+  PlanOpts o;
+  o.render_mode = ctx->render_mode;
+  o.split_budget = ctx->split_budget;
+  o.split_queue = ctx->split_queue;
+  o.split_waves = ctx->split_waves;
+  return make_view_plan(o, views, n, p, allow_split, &ctx->err);
 }
 
 tci_render_opts render_opts(const tc_context* c) {
@@ -127,93 +156,6 @@ tci_render_opts render_opts(const tc_context* c) {
   return o;
 }
 
-tc_status validate_edits(tc_context* ctx, const tc_edit* edits, int32_t n,
-                         size_t* patch_bytes) {
-  if (n < 0 || n > 65536) return fail(ctx, TC_INVALID_ARG, "edits: bad n %d", n);
-  if (n > 0 && !edits) return fail(ctx, TC_INVALID_ARG, "edits: list is NULL");
-  size_t pb = 0;
-  for (int32_t i = 0; i < n; ++i) {
-    const tc_edit& e = edits[i];
-    if (e.kind == TC_EDIT_SET) {
-      if (e.w < 1 || e.h < 1 || e.w > TC_MAX_DIM || e.h > TC_MAX_DIM)
-        return fail(ctx, TC_INVALID_ARG, "edits: edit %d bad size", i);
-      if (!e.floor_top || !e.slab_bottom || !e.slab_top)
-        return fail(ctx, TC_INVALID_ARG, "edits: edit %d null patch", i);
-      int32_t bx, by;
-      if (!columns_valid(e.floor_top, e.slab_bottom, e.slab_top, e.w, e.h, e.w, &bx, &by))
-        return fail(ctx, TC_INVALID_ARG,
-                    "edits: edit %d patch cell (%d,%d) violates the column "
-                    "invariants", i, bx, by);
-      pb += (size_t)3 * e.w * e.h;
-    } else if (e.kind == TC_EDIT_CRATER) {
-      if (e.w < 1 || e.w > 4096 || e.h != e.w)
-        return fail(ctx, TC_INVALID_ARG, "edits: edit %d bad crater size", i);
-      if (e.depth < 0 || e.depth > 255)
-        return fail(ctx, TC_INVALID_ARG, "edits: edit %d bad crater depth", i);
-    } else {
-      return fail(ctx, TC_INVALID_ARG, "edits: edit %d bad kind %d", i, e.kind);
-    }
-    if ((int64_t)e.x0 + e.w > INT32_MAX || (int64_t)e.y0 + e.h > INT32_MAX ||
-        e.x0 < -(1 << 28) || e.y0 < -(1 << 28))
-      return fail(ctx, TC_INVALID_ARG, "edits: edit %d rectangle overflows", i);
-  }
-  *patch_bytes = pb;
-  return TC_OK;
-}
-
-void plan_edits(const tci_map& d, const tc_edit* edits, int32_t n,
-                size_t patch_bytes, char* host, EditPlan& p) {
-  const int32_t top = d.top;
-  p.n = n;
-  p.top = top;
-  p.off_edits = 0;
-  p.off_rects = (sizeof(tci_edit) * (size_t)n + 15) & ~(size_t)15;
-  p.off_patch = p.off_rects + sizeof(int32_t) * 4 * (size_t)n * (size_t)std::max(top, 1);
-  p.total = p.off_patch + patch_bytes;
-  p.nrect.assign(top + 1, 0);
-  p.rmw.assign(top + 1, 1);
-  p.rmh.assign(top + 1, 1);
-  p.max_w = p.max_h = 1;
-  tci_edit* he = host ? (tci_edit*)(host + p.off_edits) : nullptr;
-  int32_t* hr = host ? (int32_t*)(host + p.off_rects) : nullptr;
-  uint8_t* hp = host ? (uint8_t*)(host + p.off_patch) : nullptr;
-  size_t po = 0;
-  for (int32_t i = 0; i < n; ++i) {
-    const tc_edit& e = edits[i];
-    if (he) {
-      tci_edit& o = he[i];
-      o.kind = e.kind;
-      o.x0 = e.x0;
-      o.y0 = e.y0;
-      o.w = e.w;
-      o.h = e.h;
-      o.depth = e.depth;
-      o.data_off = (int64_t)po;
-    }
-    if (e.kind == TC_EDIT_SET) {
-      size_t m = (size_t)e.w * e.h;
-      if (hp) {
-        memcpy(hp + po, e.floor_top, m);
-        memcpy(hp + po + m, e.slab_bottom, m);
-        memcpy(hp + po + 2 * m, e.slab_top, m);
-      }
-      po += 3 * m;
-    }
-    int32_t x0 = std::max(e.x0, 0), y0 = std::max(e.y0, 0);
-    int32_t x1 = std::min(e.x0 + e.w, d.W), y1 = std::min(e.y0 + e.h, d.H);
-    if (x0 >= x1 || y0 >= y1) continue;
-    p.max_w = std::max(p.max_w, x1 - x0);
-    p.max_h = std::max(p.max_h, y1 - y0);
-    for (int32_t L = 1; L <= top; ++L) {
-      int32_t r[4] = {x0 >> L, y0 >> L, (x1 - 1) >> L, (y1 - 1) >> L};
-      if (hr) memcpy(hr + 4 * ((size_t)(L - 1) * n + p.nrect[L]), r, sizeof(r));
-      p.rmw[L] = std::max(p.rmw[L], r[2] - r[0] + 1);
-      p.rmh[L] = std::max(p.rmh[L], r[3] - r[1] + 1);
-      p.nrect[L]++;
-    }
-  }
-}
-
 hipError_t enqueue_edits(const tci_map& d, uint32_t* map, const char* dev,
                          const EditPlan& p, hipStream_t s) {
   hipError_t e = tci_launch_edits((const tci_edit*)(dev + p.off_edits), p.n,
@@ -226,98 +168,10 @@ hipError_t enqueue_edits(const tci_map& d, uint32_t* map, const char* dev,
   return e;
 }
 
-tc_status plan_views(tc_context* ctx, const tc_view* views, int32_t n, ViewPlan& p,
-                     bool allow_split) {
-  if (n < 1 || !views) return fail(ctx, TC_INVALID_ARG, "render: no views");
-  p.n = n;
-  p.views.resize(n);
-  p.prefix.resize((size_t)n + 1);
-  int64_t out = 0, pk = 0;
-  for (int32_t i = 0; i < n; ++i) {
-    const tc_view& v = views[i];
-    if (v.width < 1 || v.height < 1 || v.width > 16384 || v.height > 16384)
-      return fail(ctx, TC_INVALID_ARG, "render: view %d bad size %dx%d", i, v.width, v.height);
-    if (v.flags != 0) return fail(ctx, TC_INVALID_ARG, "render: view %d flags != 0", i);
-    for (int cx = 0; cx < 2; ++cx)
-      for (int cy = 0; cy < 2; ++cy) {
-        int64_t a = cx ? 2 * (int64_t)v.width - 1 : 1;
-        int64_t b = cy ? 2 * (int64_t)v.height - 1 : 1;
-        for (int c = 0; c < 3; ++c) {
-          int64_t O = (int64_t)v.o0[c] + a * v.o_px[c] + b * v.o_py[c];
-          int64_t D = (int64_t)v.d0[c] + a * v.d_px[c] + b * v.d_py[c];
-          if (O < INT32_MIN || O > INT32_MAX)
-            return fail(ctx, TC_INVALID_ARG, "render: view %d origin overflows int32", i);
-          if (D < -TC_MAX_DIR || D > TC_MAX_DIR)
-            return fail(ctx, TC_INVALID_ARG, "render: view %d |direction| > 2^23-1", i);
-        }
-      }
-    tci_view& o = p.views[i];
-    o.w = v.width;
-    o.h = v.height;
-    for (int c = 0; c < 3; ++c) {
-      o.o0[c] = v.o0[c]; o.opx[c] = v.o_px[c]; o.opy[c] = v.o_py[c];
-      o.d0[c] = v.d0[c]; o.dpx[c] = v.d_px[c]; o.dpy[c] = v.d_py[c];
-    }
-    o.tiles_x = (v.width + 7) >> 3;
-    o.small_steps = 1;
-    for (int c = 0; c < 3; ++c)
-      for (int32_t st : {v.o_px[c], v.o_py[c], v.d_px[c], v.d_py[c]})
-        if (st <= -(1 << 22) || st >= (1 << 22)) o.small_steps = 0;
-    o.out_base = out;
-    o.pkt_base = pk;
-    o.rows_off = (int64_t)p.rows.size();
-    // tile rows ordered by how level the ray through the row's centre is:
-    // near-horizontal rays take the longest walks, so their packets start
-    // first and do not trail the launch
-    {
-      const int32_t ty_n = (v.height + 7) >> 3;
-      std::vector<std::pair<double, int32_t>> key((size_t)ty_n);
-      const int64_t a = v.width;  // 2 * (width / 2) + 1, rounded
-      for (int32_t ty = 0; ty < ty_n; ++ty) {
-        const int64_t b = 2 * (int64_t)std::min(ty * 8 + 4, v.height - 1) + 1;
-        const double dx = (double)v.d0[0] + (double)a * v.d_px[0] + (double)b * v.d_py[0];
-        const double dy = (double)v.d0[1] + (double)a * v.d_px[1] + (double)b * v.d_py[1];
-        const double dz = (double)v.d0[2] + (double)a * v.d_px[2] + (double)b * v.d_py[2];
-        const double hz = std::sqrt(dx * dx + dy * dy);
-        key[ty] = {hz > 0 ? std::fabs(dz) / hz : 1e30, ty};
-      }
-      std::stable_sort(key.begin(), key.end(),
-                       [](const std::pair<double, int32_t>& x,
-                          const std::pair<double, int32_t>& y) { return x.first < y.first; });
-      for (auto& k : key) p.rows.push_back(k.second);
-    }
-    p.prefix[i] = pk;
-    out += (int64_t)v.width * v.height;
-    pk += (int64_t)o.tiles_x * ((v.height + 7) >> 3);
-  }
-  p.prefix[n] = pk;
-  if (out > ((int64_t)1 << 31))
-    return fail(ctx, TC_INVALID_ARG, "render: more than 2^31 rays");
-  p.rays = out;
-  p.npkt = pk;
-  p.off_views = 0;
-  p.off_prefix = (sizeof(tci_view) * (size_t)n + 15) & ~(size_t)15;
-  p.off_rows = (p.off_prefix + sizeof(int64_t) * ((size_t)n + 1) + 15) & ~(size_t)15;
-  p.off_counter = (p.off_rows + sizeof(int32_t) * p.rows.size() + 15) & ~(size_t)15;
-  // the split queue follows the counters (device only, never uploaded)
-  p.qcap = (allow_split && ctx->render_mode == 0 && ctx->split_budget > 0)
-               ? (uint32_t)std::min<int64_t>(out, ctx->split_queue) : 0;
-  p.off_queue = p.off_counter + 64;
-  p.qwaves = ctx->split_waves;
-  p.total = p.off_queue + sizeof(uint4) * (size_t)p.qcap;
-  return TC_OK;
-}
-
-void write_views(const ViewPlan& p, char* host) {
-  memcpy(host + p.off_views, p.views.data(), sizeof(tci_view) * (size_t)p.n);
-  memcpy(host + p.off_prefix, p.prefix.data(), sizeof(int64_t) * ((size_t)p.n + 1));
-  memcpy(host + p.off_rows, p.rows.data(), sizeof(int32_t) * p.rows.size());
-  memset(host + p.off_counter, 0, 64);
-}
-
 hipError_t enqueue_render(tc_context* ctx, const tci_map& d, const char* dev,
                           const ViewPlan& p, void* out, hipStream_t s,
-                          hipEvent_t* kev, bool* split_ran, bool counters_zeroed) {
+                          hipEvent_t* kev, bool* split_ran, bool counters_zeroed,
+                          uint4* queue) {
   tci_render_opts o = render_opts(ctx);
   o.rows = (const int32_t*)(dev + p.off_rows);
   const tci_view* dv = (const tci_view*)(dev + p.off_views);
@@ -346,7 +200,7 @@ hipError_t enqueue_render(tc_context* ctx, const tci_map& d, const char* dev,
     uint64_t* counters = (uint64_t*)(dev + p.off_counter);
     o.split_budget = ctx->split_budget;
     o.qcap = p.qcap;
-    o.queue = (uint4*)(dev + p.off_queue);
+    o.queue = queue ? queue : (uint4*)(dev + p.off_queue);
     o.qcount = (uint32_t*)(counters + 1);
     o.split_waves = p.qwaves;
     hipError_t e = counters_zeroed ? hipSuccess : tci_launch_zero_u64(counters, 2, s);
@@ -403,6 +257,13 @@ tc_status tc_create(int hip_device, tc_context** out) {
     delete ctx;
     return TC_DEVICE_ERROR;
   }
+  // the staging ring and its split queues: after this, renders allocate
+  // nothing unless their tables outgrow a slot
+  if (tci::ring_alloc(ctx, (uint32_t)ctx->split_queue) != TC_OK) {
+    g_create_error = "tc_create: " + ctx->err;
+    tc_destroy(ctx);
+    return TC_OUT_OF_MEMORY;
+  }
   g_create_error.clear();
   *out = ctx;
   return TC_OK;
@@ -417,6 +278,7 @@ void tc_destroy(tc_context* ctx) {
     if (s.ev) (void)hipEventDestroy(s.ev);
     if (s.host) (void)hipHostFree(s.host);
     if (s.dev) (void)hipFree(s.dev);
+    if (s.queue) (void)hipFree(s.queue);
   }
   if (ctx->map) (void)hipFree(ctx->map);
   if (ctx->d_count) (void)hipFree(ctx->d_count);
@@ -445,7 +307,7 @@ tc_status tc_load_columns(tc_context* ctx, int32_t W, int32_t H,
     if (row_stride < (size_t)W)
       return fail(ctx, TC_INVALID_ARG, "tc_load_columns: row_stride < W");
     int32_t bx = 0, by = 0;
-    if (!columns_valid(floor_top, slab_bottom, slab_top, W, H, row_stride, &bx, &by))
+    if (!tci::columns_valid(floor_top, slab_bottom, slab_top, W, H, row_stride, &bx, &by))
       return fail(ctx, TC_INVALID_ARG,
                   "tc_load_columns: column (%d,%d) violates B==0 => T==0, "
                   "B>0 => B>F and T>=B", bx, by);
@@ -453,37 +315,12 @@ tc_status tc_load_columns(tc_context* ctx, int32_t W, int32_t H,
     if (st) return st;
     hipStream_t s = (hipStream_t)hip_stream;
 
-    // level layout
-    tci_map d{};
-    d.W = W;
-    d.H = H;
-    d.top = top_level(W, H);
     size_t words = 0;
-    for (int32_t L = 0; L < TCI_MAX_LEVELS; ++L) {
-      tci_level& l = d.lv[L];
-      if (L > d.top) {
-        l = tci_level{0, 0, 0, 0};
-        continue;
-      }
-      l.w = (int32_t)(((int64_t)W + (1 << L) - 1) >> L);
-      l.h = (int32_t)(((int64_t)H + (1 << L) - 1) >> L);
-      l.tiles_x = (l.w + 7) >> 3;
-      l.off = (uint32_t)words;
-      words += (size_t)l.tiles_x * ((l.h + 7) >> 3) * 64;
-    }
-    // occupancy masks of levels 1..top after the pyramid, 2 words a node
-    for (int32_t L = 0; L < TCI_MAX_LEVELS; ++L) {
-      tci_level& k = d.mk[L];
-      k = tci_level{0, 0, 0, 0};
-      if (L < 1 || L > d.top) continue;
-      k = d.lv[L];
-      k.off = (uint32_t)words;
-      words += (size_t)k.tiles_x * ((k.h + 7) >> 3) * 128;
-    }
+    tci_map d = tci::layout_map(W, H, &words);
     uint32_t* map = nullptr;
     uint8_t* planes = nullptr;
-    TC_HIP(hipMalloc(&map, words * 4), "hipMalloc(map)");
-    hipError_t e = hipMalloc(&planes, (size_t)3 * W * H);
+    TC_HIP(tci::dev_alloc(ctx, (void**)&map, words * 4), "hipMalloc(map)");
+    hipError_t e = tci::dev_alloc(ctx, (void**)&planes, (size_t)3 * W * H);
     if (e != hipSuccess) {
       (void)hipFree(map);
       return hip_fail(ctx, e, "hipMalloc(load staging)");
@@ -569,16 +406,17 @@ tc_status tc_render_views(tc_context* ctx, const tc_view* views, int32_t n,
       kev = ctx->kev;
     }
     tci::Slot* slot = nullptr;
-    st = tci::acquire(ctx, plan.total, &slot);
+    st = tci::acquire(ctx, plan.off_queue, &slot);
     if (st) return st;
     tci::write_views(plan, (char*)slot->host);
-    // tables and zeroed queue counters in one upload
+    // tables and zeroed queue counters in one upload; the split queue is the
+    // slot's device-only buffer (plan.qcap <= TC_OPT_SPLIT_QUEUE <= its size)
     hipError_t e = hipMemcpyAsync(slot->dev, slot->host, plan.off_queue,
                                   hipMemcpyHostToDevice, s);
     bool split_ran = false;
     if (e == hipSuccess)
       e = tci::enqueue_render(ctx, ctx->desc, (const char*)slot->dev, plan, out_device, s,
-                              kev, &split_ran, true);
+                              kev, &split_ran, true, slot->queue);
     if (kev) {
       ctx->kev_valid = e == hipSuccess;
       ctx->kev_split = split_ran;
@@ -707,10 +545,15 @@ tc_status tc_set_option(tc_context* ctx, int32_t key, int64_t value) {
       if (value < 0 || value > 64) break;
       ctx->beam_passes = (int32_t)value;
       return TC_OK;
-    case TC_OPT_SPLIT_QUEUE:
-      if (value < 1 || value > (1 << 26)) break;
+    case TC_OPT_SPLIT_QUEUE: {
+      if (value < 1 || value > (1 << 24)) break;
+      // every ring slot holds a queue of this many entries
+      if (set_device(ctx)) return TC_DEVICE_ERROR;
+      tc_status st = tci::ring_alloc(ctx, (uint32_t)value);
+      if (st) return st;
       ctx->split_queue = (int32_t)value;
       return TC_OK;
+    }
     case TC_OPT_MARCH_STEPS:
       if (value < 1 || value > 65536) break;
       ctx->march_steps = (int32_t)value;
@@ -740,7 +583,7 @@ tc_status tc_set_option(tc_context* ctx, int32_t key, int64_t value) {
       if (value < 0 || value > 1) break;
       if (value && !ctx->d_count) {
         if (set_device(ctx)) return TC_DEVICE_ERROR;
-        hipError_t e = hipMalloc(&ctx->d_count, sizeof(unsigned long long));
+        hipError_t e = tci::dev_alloc(ctx, (void**)&ctx->d_count, sizeof(unsigned long long));
         if (e == hipSuccess) e = hipMemset(ctx->d_count, 0, sizeof(unsigned long long));
         if (e != hipSuccess) return hip_fail(ctx, e, "tc_set_option(count)");
       }
@@ -774,6 +617,7 @@ tc_status tc_get_option(const tc_context* ctx, int32_t key, int64_t* value) {
     case TC_OPT_MARCH_STEPS: *value = ctx->march_steps; return TC_OK;
     case TC_OPT_MARCH_BISECT: *value = ctx->march_bisect; return TC_OK;
     case TC_OPT_MARCH_FAR: *value = ctx->march_far; return TC_OK;
+    case TC_INFO_ALLOCATIONS: *value = (int64_t)ctx->allocs; return TC_OK;
     default: return TC_INVALID_ARG;
   }
 }

@@ -13,69 +13,60 @@
 namespace tci {
 
 constexpr int kRing = 16;
+// Bytes of each ring slot's pinned and device table buffers, allocated when
+// the context is created: the tables of a render of up to about a thousand
+// views, or an edit list with about 80 KiB of SET patches, fit without
+// growing a slot.
+constexpr size_t kSlotBytes = 256 << 10;
 
 // A pinned host buffer and a device buffer of the same size, reused across
-// calls; `ev` marks the end of the last copy and kernels that used it.
+// calls, plus a device-only split queue (never uploaded, so it has no host
+// mirror); `ev` marks the end of the last copy and kernels that used them.
 struct Slot {
   void* host = nullptr;
   void* dev = nullptr;
   size_t cap = 0;
+  uint4* queue = nullptr;
+  uint32_t qcap = 0;
   hipEvent_t ev = nullptr;
   bool pending = false;
-};
-
-// Layout of an uploaded edit list: descriptors, per-level node rectangles
-// of the dirty update, and SET patch bytes.
-struct EditPlan {
-  int32_t n = 0;
-  int32_t top = 0;
-  size_t off_edits = 0, off_rects = 0, off_patch = 0, total = 0;
-  int32_t max_w = 1, max_h = 1;
-  std::vector<int32_t> nrect, rmw, rmh;   // per level 0..top
-};
-
-// Device tables of a render call: views, packet prefix and queue counter.
-struct ViewPlan {
-  int32_t n = 0;
-  int64_t rays = 0, npkt = 0;
-  size_t off_views = 0, off_prefix = 0, off_counter = 0, off_rows = 0, total = 0;
-  size_t off_queue = 0;
-  uint32_t qcap = 0;           // split queue capacity (0: no split pass)
-  int32_t qwaves = 1;          // waves per queued ray in the split pass
-  std::vector<tci_view> views;
-  std::vector<int64_t> prefix;
-  std::vector<int32_t> rows;   // tile rows of every view, longest walks first
 };
 
 tc_status fail(tc_context* c, tc_status st, const char* fmt, ...);
 tc_status hip_fail(tc_context* c, hipError_t e, const char* what);
 tc_status set_device(tc_context* ctx);
+// The next ring slot, once its last use has completed, with table buffers of
+// at least `bytes` (a slot grows only for tables beyond kSlotBytes).
 tc_status acquire(tc_context* ctx, size_t bytes, Slot** out);
 tc_status release(tc_context* ctx, Slot* s, hipStream_t st);
+// Allocate every ring slot's buffers and a split queue of `qcap` entries per
+// slot (at context creation, and again when TC_OPT_SPLIT_QUEUE grows).
+tc_status ring_alloc(tc_context* ctx, uint32_t qcap);
+// Device and pinned allocations, counted per context (tc_get_option of
+// TC_INFO_ALLOCATIONS).
+hipError_t dev_alloc(tc_context* ctx, void** p, size_t bytes);
+hipError_t host_alloc(tc_context* ctx, void** p, size_t bytes);
 
+// check_edits / make_view_plan (tc_plan.h) with the context's knobs, the
+// reason of a failure going to the context's error message.
 tc_status validate_edits(tc_context* ctx, const tc_edit* edits, int32_t n,
                          size_t* patch_bytes);
-// Fill `plan` and write the upload image of the edit list to `host`
-// (plan.total bytes; call plan_edits with host == nullptr to size it).
-void plan_edits(const tci_map& d, const tc_edit* edits, int32_t n,
-                size_t patch_bytes, char* host, EditPlan& plan);
 hipError_t enqueue_edits(const tci_map& d, uint32_t* map, const char* dev,
                          const EditPlan& plan, hipStream_t s);
 
-// With allow_split false the plan has no split queue (qcap 0), whatever
-// the context's split budget.
 tc_status plan_views(tc_context* ctx, const tc_view* views, int32_t n,
                      ViewPlan& plan, bool allow_split = true);
-void write_views(const ViewPlan& plan, char* host);
 // `kev`, if given, receives event records before the traversal kernel,
 // after it and after the split pass (the last only when that pass runs).
 // With counters_zeroed the queue counters at plan.off_counter were uploaded
 // as zeros with the tables (bytes [0, plan.off_queue)), so no kernel clears
-// them; a captured frame, which replays, clears them itself.
+// them; a captured frame, which replays, clears them itself.  `queue` holds
+// the split queue (plan.qcap entries); nullptr: it follows the tables at
+// dev + plan.off_queue.
 hipError_t enqueue_render(tc_context* ctx, const tci_map& d, const char* dev,
                           const ViewPlan& plan, void* out, hipStream_t s,
                           hipEvent_t* kev = nullptr, bool* split_ran = nullptr,
-                          bool counters_zeroed = false);
+                          bool counters_zeroed = false, uint4* queue = nullptr);
 
 tci_render_opts render_opts(const tc_context* c);
 
@@ -91,9 +82,10 @@ struct tc_context {
   size_t map_words = 0;
   tci_map desc{};
   uint64_t map_generation = 0;  // bumped by every tc_load_columns
-  // staging ring
+  // staging ring (allocated by tc_create)
   tci::Slot ring[tci::kRing];
   int ring_next = 0;
+  uint64_t allocs = 0;  // device and pinned allocations made so far
   // options
   int32_t render_mode = 0;
   int32_t start_level = 2;

@@ -101,7 +101,7 @@ tc_status tc_frame_create(tc_context* ctx, const tc_view* views, int32_t nviews,
     f->ctx = ctx;
     f->generation = ctx->map_generation;
     f->rays = vp.rays;
-    hipError_t e = hipMalloc(&f->dev, total);
+    hipError_t e = tci::dev_alloc(ctx, &f->dev, total);
     if (e == hipSuccess)
       e = hipMemcpyAsync(f->dev, host.data(), total, hipMemcpyHostToDevice,
                          (hipStream_t)hip_stream);

@@ -5,32 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#define TCI_MAX_LEVELS 16  // level 0 = cells, levels 1..15 = pyramid
-
-// One level of the map in HBM.  Level 0 holds packed columns
-// F | B << 8 | T << 16; levels >= 1 hold nodes fmax | smin << 8 | smax << 16.
-// Every level is tiled in 8 x 8 blocks of 32-bit words (256 bytes, one
-// wave's worth of coalesced reads): element (i, j) lives at
-//   off + (((j >> 3) * tiles_x + (i >> 3)) << 6) + ((j & 7) << 3) + (i & 7).
-struct tci_level {
-  uint32_t off;      // offset in words from the start of the map buffer
-  int32_t w, h;      // elements per row / rows
-  int32_t tiles_x;   // ceil(w / 8)
-};
-
-// Occupancy masks: for every pyramid node of levels 1..top, 64 bits over
-// height, bit k set iff the slab interval [B, T] of some column of the node
-// meets the closed band [4k, 4k + 4].  They refine the node's slab test:
-// a ray whose height range over the node meets no set band passes between
-// the slabs.  Stored in the same allocation after the pyramid, tiled 8 x 8
-// like the levels, two 32-bit words (low, high) per node.
-struct tci_map {
-  const uint32_t* base;           // all levels, one allocation
-  tci_level lv[TCI_MAX_LEVELS];
-  tci_level mk[TCI_MAX_LEVELS];   // occupancy mask levels 1..top (off in words)
-  int32_t W, H;
-  int32_t top;                    // highest stored level (0 if none)
-};
+#include "tc_plan.h"  // level, map, view and edit records
 
 __host__ __device__ inline uint32_t tci_tile_index(const tci_level& L,
                                                    int32_t i, int32_t j) {
@@ -44,30 +19,6 @@ __host__ __device__ inline uint32_t tci_mask_index(const tci_level& M,
   return M.off + ((uint32_t)((j >> 3) * M.tiles_x + (i >> 3)) << 7) +
          ((((uint32_t)(j & 7) << 3) + (uint32_t)(i & 7)) << 1);
 }
-
-// Device copy of a view plus the first ray index of the view and the
-// first 64-ray packet of the view.
-struct tci_view {
-  int32_t w, h;
-  int32_t o0[3], opx[3], opy[3];
-  int32_t d0[3], dpx[3], dpy[3];
-  int32_t tiles_x;     // ceil(w / 8)
-  int32_t small_steps; // every per-pixel step (opx, opy, dpx, dpy) below 2^22
-                       // in magnitude: twice one is a 24-bit operand
-  int64_t out_base;    // first output record of the view
-  int64_t pkt_base;    // first 8x8 packet of the view
-  int64_t rows_off;    // packet order 2: offset of the view's tile-row
-                       // permutation in the row table
-};
-
-// Device edit descriptor; SET data lives at data_off in the patch buffer
-// as three planes of w*h bytes (F, then B, then T).
-struct tci_edit {
-  int32_t kind;
-  int32_t x0, y0, w, h;
-  int32_t depth;
-  int64_t data_off;
-};
 
 // Render tuning.
 struct tci_render_opts {

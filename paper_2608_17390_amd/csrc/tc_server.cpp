@@ -243,9 +243,9 @@ bool launch_batch(tc_server* s) {
     if (b->slot.host) (void)hipHostFree(b->slot.host);
     if (b->slot.dev) (void)hipFree(b->slot.dev);
     b->slot.host = b->slot.dev = nullptr;
-    size_t cap = std::max<size_t>(plan.total, 64 << 10);
-    hipError_t e = hipHostMalloc(&b->slot.host, cap, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipMalloc(&b->slot.dev, cap);
+    size_t cap = std::max<size_t>(plan.total, tci::kSlotBytes);
+    hipError_t e = tci::host_alloc(ctx, &b->slot.host, cap);
+    if (e == hipSuccess) e = tci::dev_alloc(ctx, &b->slot.dev, cap);
     if (e != hipSuccess) {
       set_error(s, e, "server: staging allocation");
       return true;
@@ -314,9 +314,9 @@ bool apply_edit(tc_server* s, uint64_t id) {
     if (u.slot.dev) (void)hipFree(u.slot.dev);
     u.slot.host = u.slot.dev = nullptr;
     u.slot.cap = 0;
-    size_t cap = std::max<size_t>(u.plan.total, 64 << 10);
-    hipError_t ea = hipHostMalloc(&u.slot.host, cap, hipHostMallocDefault);
-    if (ea == hipSuccess) ea = hipMalloc(&u.slot.dev, cap);
+    size_t cap = std::max<size_t>(u.plan.total, tci::kSlotBytes);
+    hipError_t ea = tci::host_alloc(s->ctx, &u.slot.host, cap);
+    if (ea == hipSuccess) ea = tci::dev_alloc(s->ctx, &u.slot.dev, cap);
     if (ea != hipSuccess) {
       set_error(s, ea, "server: edit staging");
       return true;
@@ -500,10 +500,10 @@ tc_status tc_server_start(tc_context* ctx, uint64_t budget_bytes, int32_t max_ba
   s->budget = budget_bytes;
   s->max_batch = max_batch_views;
   hipError_t e = hipDeviceSynchronize();
-  if (e == hipSuccess) e = hipMalloc(&s->pool_dev, budget_bytes);
+  if (e == hipSuccess) e = tci::dev_alloc(ctx, (void**)&s->pool_dev, budget_bytes);
   s->pool.reset(budget_bytes);
   s->ver[0] = ctx->map;
-  if (e == hipSuccess) e = hipMalloc(&s->ver[1], ctx->map_words * 4);
+  if (e == hipSuccess) e = tci::dev_alloc(ctx, (void**)&s->ver[1], ctx->map_words * 4);
   s->own_ver[1] = e == hipSuccess;
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->edit_stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&s->edit_ev, hipEventDisableTiming);
@@ -514,10 +514,19 @@ tc_status tc_server_start(tc_context* ctx, uint64_t budget_bytes, int32_t max_ba
     e = hipMemcpyAsync(s->ver[1], s->ver[0], ctx->map_words * 4, hipMemcpyDeviceToDevice,
                        s->edit_stream);
   if (e == hipSuccess) e = hipEventRecord(s->edit_ev, s->edit_stream);
+  // staging of every batch slot and of the edit log, allocated up front
   s->slots.resize(streams);
   for (Batch& b : s->slots) {
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming);
+    if (e == hipSuccess) e = tci::host_alloc(ctx, &b.slot.host, tci::kSlotBytes);
+    if (e == hipSuccess) e = tci::dev_alloc(ctx, &b.slot.dev, tci::kSlotBytes);
+    if (e == hipSuccess) b.slot.cap = tci::kSlotBytes;
+  }
+  for (EditUpload& u : s->uploads) {
+    if (e == hipSuccess) e = tci::host_alloc(ctx, &u.slot.host, tci::kSlotBytes);
+    if (e == hipSuccess) e = tci::dev_alloc(ctx, &u.slot.dev, tci::kSlotBytes);
+    if (e == hipSuccess) u.slot.cap = tci::kSlotBytes;
   }
   if (e != hipSuccess) {
     server_free(s);
@@ -603,6 +612,22 @@ tc_status tc_server_poll(tc_server* s, uint64_t id, int32_t* state, double* late
   *state = it->second.state;
   if (latency_s)
     *latency_s = it->second.state == kDone ? it->second.t_done - it->second.t_submit : -1.0;
+  if (s->error.load()) return fail(s->ctx, TC_DEVICE_ERROR, "%s", s->err.c_str());
+  return TC_OK;
+}
+
+tc_status tc_server_poll_many(tc_server* s, const uint64_t* ids, int32_t n, int32_t* states,
+                              double* latencies_s) {
+  if (!s || n < 0 || (n > 0 && (!ids || !states))) return TC_INVALID_ARG;
+  std::lock_guard<std::mutex> g(s->mu);
+  for (int32_t i = 0; i < n; ++i)
+    if (s->reqs.find(ids[i]) == s->reqs.end())
+      return fail(s->ctx, TC_INVALID_ARG, "tc_server_poll_many: unknown id at %d", i);
+  for (int32_t i = 0; i < n; ++i) {
+    const Request& r = s->reqs.find(ids[i])->second;
+    states[i] = r.state;
+    if (latencies_s) latencies_s[i] = r.state == kDone ? r.t_done - r.t_submit : -1.0;
+  }
   if (s->error.load()) return fail(s->ctx, TC_DEVICE_ERROR, "%s", s->err.c_str());
   return TC_OK;
 }

@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 import synth
+from oracle_cache import config_map
 
 tc = pytest.importorskip("paper_2608_17390_amd")
 torch = pytest.importorskip("torch")
@@ -180,7 +181,7 @@ def test_c2_view_and_read_count(ctx):
 def test_large_map_batched_views_sampled(ctx):
     """Grazing, oblique and shadow views on the 2048x16384 map, 30,000
     sampled pixels against the oracle, beam on and off."""
-    F, B, T = synth.make_map_from_config(3)
+    F, B, T = config_map(3)
     load(ctx, F, B, T)
     rng = np.random.default_rng(350)
     views = (_grazing_views(F, B, rng, 6, (640, 360)) +

@@ -8,6 +8,7 @@ import pytest
 
 import oracle
 import synth
+from oracle_cache import config_map
 from paper_2608_17390_amd import metrics
 
 tc = pytest.importorskip("paper_2608_17390_amd")
@@ -122,7 +123,7 @@ def test_protocol_views_sampled_and_metrics(ctx):
     """The paper's protocol on the 2048x16384 map: twelve 1280x800 views,
     three per pitch; sampled pixels against the oracle, and the quality
     metrics of the GPU buffers against the exact render's."""
-    F, B, T = synth.make_map_from_config(3)
+    F, B, T = config_map(3)
     load(ctx, F, B, T)
     views, pitches = synth.pitch_views(F, B, 91)
     set_march(ctx)

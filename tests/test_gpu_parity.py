@@ -8,6 +8,7 @@ import pytest
 
 import oracle
 import synth
+from oracle_cache import config_map, oracle_render
 
 tc = pytest.importorskip("paper_2608_17390_amd")
 torch = pytest.importorskip("torch")
@@ -40,20 +41,29 @@ def gpu_render(ctx, views, mode="hier"):
 
 
 def assert_parity(wg, dg, wo, do, what=""):
-    assert wg.shape == wo.shape
+    """Every record: word bit-exact; depth +inf on a miss, exactly 0 where
+    the oracle's is 0 (inside), else within DEPTH_RTOL relative.  Large
+    buffers are checked in chunks to bound the memory used."""
+    assert wg.shape == wo.shape, "%s: %s records vs %s" % (what, wg.shape, wo.shape)
     bad = np.nonzero(wg != wo)[0]
     assert bad.size == 0, "%s: %d word mismatches, first at %d: gpu %08x oracle %08x" % (
         what, bad.size, bad[0], wg[bad[0]], wo[bad[0]])
-    miss = wo == oracle.MISS
-    assert np.all(np.isinf(dg[miss]))
-    hit = ~miss
-    dg64 = dg[hit].astype(np.float64)
-    ref = do[hit]
-    err = np.abs(dg64 - ref)
-    tol = DEPTH_RTOL * np.abs(ref)
-    worst = np.argmax(err - tol) if err.size else 0
-    assert np.all(err <= tol), "%s: depth off by %g at %g" % (what, err[worst], ref[worst])
-    assert np.all(dg64[ref == 0] == 0)
+    step = 1 << 23
+    for c0 in range(0, wo.size, step):
+        w = wo[c0:c0 + step]
+        d = dg[c0:c0 + step]
+        ref_all = do[c0:c0 + step]
+        miss = w == oracle.MISS
+        assert np.all(np.isinf(d[miss])), "%s: a miss without +inf depth" % what
+        hit = ~miss
+        dg64 = d[hit].astype(np.float64)
+        ref = ref_all[hit]
+        err = np.abs(dg64 - ref)
+        tol = DEPTH_RTOL * np.abs(ref)
+        if not np.all(err <= tol):
+            worst = np.argmax(err - tol)
+            raise AssertionError("%s: depth off by %g at %g" % (what, err[worst], ref[worst]))
+        assert np.all(dg64[ref == 0] == 0), "%s: inside hit with nonzero depth" % what
 
 
 def load(ctx, F, B, T):
@@ -288,7 +298,7 @@ def test_split_pass_edge_rays_and_large_map(ctx):
 def test_straight_down_closed_form_large_map(ctx):
     """Straight-down orthographic image over the whole 2048x16384 map: each
     hit is the column's topmost solid, face top, depth 256 - height."""
-    F, B, T = synth.make_map_from_config(3)
+    F, B, T = config_map(3)
     H, W = F.shape
     load(ctx, F, B, T)
     v = synth.ortho_view((0, 0, 256 * S), (S // 2, 0, 0), (0, S // 2, 0),
@@ -413,7 +423,7 @@ def test_pyramid_matches_definition(ctx, shape):
     assert np.array_equal(f2, F) and np.array_equal(b2, B) and np.array_equal(t2, T)
 
 
-def _edited_checks(ctx, F, B, T, edits, views, sample_rows=None):
+def _edited_checks(ctx, F, B, T, edits, views, oracle_result=None):
     """Apply edits on the GPU; compare the map with the oracle's edit, the
     pyramid with a fresh build of the edited map, and renders with both the
     oracle and a fresh load."""
@@ -436,21 +446,10 @@ def _edited_checks(ctx, F, B, T, edits, views, sample_rows=None):
     for m, (w, d) in res_edit.items():
         assert np.array_equal(w, w_fresh), m
         assert np.array_equal(d.view(np.uint32), d_fresh.view(np.uint32)), m
-    if sample_rows is None:
-        wo, do = oracle.render(F2, B2, T2, views)
-        assert_parity(w_fresh, d_fresh, wo, do, "edited")
-    else:
-        r0, st = sample_rows
-        wo, do = oracle.render(F2, B2, T2, views, rows=(r0, 1 << 30, st))
-        sel = []
-        base = 0
-        for v in views:
-            w, h = int(v["width"]), int(v["height"])
-            for r in range(r0, h, st):
-                sel.append(np.arange(base + r * w, base + r * w + w))
-            base += w * h
-        sel = np.concatenate(sel)
-        assert_parity(w_fresh[sel], d_fresh[sel], wo, do, "edited sampled")
+    wo, do = oracle_result if oracle_result is not None else oracle.render(F2, B2, T2, views)
+    assert_parity(w_fresh, d_fresh, wo, do, "edited")
+    for m, (w, d) in res_edit.items():
+        assert_parity(w, d, wo, do, "edited " + m)
 
 
 def test_edits_small_map(ctx):
@@ -484,36 +483,98 @@ def test_edit_sequences_accumulate(ctx):
     assert np.array_equal(g[0], F2) and np.array_equal(g[1], B2) and np.array_equal(g[2], T2)
 
 
-def test_c3_frame_edits_then_views(ctx):
+def test_c3_edits_then_views_full(ctx):
     """Configuration 3: 64 craters of size 32 on the 2048x16384 map, dirty
-    pyramid update, then the grazing and oblique views; checked on every
-    16th row against the oracle."""
-    F, B, T = synth.make_map_from_config(3)
+    pyramid update, then the grazing and oblique views; every record of
+    every render mode against the oracle's render of the edited map."""
+    F, B, T = config_map(3)
     H, W = F.shape
     edits = synth.crater_list(synth.SEEDS[3]["edits"], W, H, 64, size=32)
     views = synth.config_views(3, F, B)
-    _edited_checks(ctx, F, B, T, edits, views, sample_rows=(5, 16))
+    _edited_checks(ctx, F, B, T, edits, views, oracle_result=oracle_render(F, B, T, views, edits))
 
 
-def test_c4_batched_sampled(ctx):
-    """Configuration 4 batch (64 views of uneven sizes plus 8 shadow passes)
-    in one persistent launch, checked on sampled pixels."""
-    F, B, T = synth.make_map_from_config(4)
+def test_c3_graph_frame_full(ctx):
+    """The configuration-3 frame as the benchmark times it: one captured
+    graph of the 64 craters, the dirty update and both views with the
+    default knobs (hierarchical walk, beam start, split pass), replayed
+    twice; each replay digs again, and every record of each replay equals
+    the oracle's render of the map edited that many times."""
+    F, B, T = config_map(3)
+    H, W = F.shape
+    edits = synth.crater_list(synth.SEEDS[3]["edits"], W, H, 64, size=32)
+    views = synth.config_views(3, F, B)
+    load(ctx, F, B, T)
+    out = torch.empty((synth.view_rays(views), 2), dtype=torch.int32, device="cuda")
+    frame = ctx.tc_frame_create(views, edits, out.data_ptr())
+    try:
+        for k in (1, 2):
+            frame.launch()
+            torch.cuda.synchronize()
+            wg, dg = tc.split_hits(out)
+            wo, do = oracle_render(F, B, T, views, edits * k)
+            assert_parity(wg, dg, wo, do, "c3 graph frame replay %d" % k)
+    finally:
+        frame.close()
+
+
+def c4_full_check(wg, dg, wo, do, views, what):
+    """Full-buffer parity of a configuration-4 render, reported per view."""
+    va = synth.views_array(views)
+    base = np.concatenate([[0], np.cumsum(va["width"].astype(np.int64) * va["height"])])
+    assert wg.size == base[-1]
+    for i in range(len(views)):
+        a, b = int(base[i]), int(base[i + 1])
+        assert_parity(wg[a:b], dg[a:b], wo[a:b], do[a:b], "%s view %d (%dx%d)" % (
+            what, i, int(va["width"][i]), int(va["height"][i])))
+
+
+@pytest.mark.parametrize("mode", ["hier", "persistent"])
+def test_c4_views_full(ctx, mode):
+    """Configuration 4's 64 views of uneven sizes plus 8 shadow passes in
+    one render call: every record against the oracle."""
+    F, B, T = config_map(4)
     load(ctx, F, B, T)
     views = synth.config_views(4, F, B)
     assert len(views) == 72
-    wg, dg = gpu_render(ctx, views, "persistent")
-    va = synth.views_array(views)
-    sizes = va["width"].astype(np.int64) * va["height"]
-    base = np.concatenate([[0], np.cumsum(sizes)])
-    rng = np.random.default_rng(44)
-    n = 40000
-    vi = rng.integers(0, len(views), n).astype(np.int32)
-    px = (rng.random(n) * va["width"][vi]).astype(np.int32)
-    py = (rng.random(n) * va["height"][vi]).astype(np.int32)
-    wo, do = oracle.cast_pixels(F, B, T, views, vi, px, py)
-    idx = base[vi] + py.astype(np.int64) * va["width"][vi] + px
-    assert_parity(wg[idx], dg[idx], wo, do, "c4 sampled")
+    wg, dg = gpu_render(ctx, views, mode)
+    wo, do = oracle_render(F, B, T, views)
+    c4_full_check(wg, dg, wo, do, views, "c4 " + mode)
+
+
+def test_renders_allocate_nothing(ctx):
+    """After tc_create and tc_load_columns, renders (split pass on and off,
+    every exact mode), edits and shading make no device or pinned
+    allocation: the staging ring and its split queues exist from the start."""
+    F, B, T = synth.make_map_from_config(2)
+    load(ctx, F, B, T)
+    views = synth.config_views(2, F, B)
+    out = torch.empty((synth.view_rays(views), 2), dtype=torch.int32, device="cuda")
+    rgba = torch.empty(synth.view_rays(views), dtype=torch.int32, device="cuda")
+    pal = synth.default_palette()
+    vs = tc.views_struct(views)
+    crater = [dict(kind=2, x0=1000, y0=300, w=32, h=32, depth=5)]
+    before = ctx.tc_get_option(tc.TC_INFO_ALLOCATIONS)
+    for k in range(40):
+        ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, (0, 1, 2, 4)[k % 4])
+        ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 128 if k % 3 else 0)
+        ctx.tc_render_views(vs, out.data_ptr())
+        if k % 10 == 9:
+            ctx.tc_apply_edit(crater)
+            ctx.tc_shade_views(vs, out.data_ptr(), (1 << 16, 1 << 16, 1 << 16), pal,
+                               rgba.data_ptr())
+    torch.cuda.synchronize()
+    ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, 0)
+    ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 128)
+    assert ctx.tc_get_option(tc.TC_INFO_ALLOCATIONS) == before
+    # a longer split queue re-sizes the ring's queues once, outside renders
+    ctx.tc_set_option(tc.TC_OPT_SPLIT_QUEUE, 1 << 18)
+    grown = ctx.tc_get_option(tc.TC_INFO_ALLOCATIONS)
+    assert grown > before
+    ctx.tc_render_views(vs, out.data_ptr())
+    torch.cuda.synchronize()
+    assert ctx.tc_get_option(tc.TC_INFO_ALLOCATIONS) == grown
+    ctx.tc_set_option(tc.TC_OPT_SPLIT_QUEUE, 1 << 17)
 
 
 def test_error_paths(ctx):

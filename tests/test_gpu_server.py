@@ -14,6 +14,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from test_gpu_parity import assert_parity, load  # noqa: E402
+from oracle_cache import config_map, host_threads  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -75,9 +76,13 @@ def test_mixed_stream_matches_epochs(ctx, mode, batch, streams):
         ids.append(srv.tc_server_submit_view(x) if kind == "view" else srv.tc_server_submit_edit(x))
     for rid in ids:
         srv.tc_server_wait(rid, 120.0)
+    states, lats = srv.tc_server_poll_many(ids)
+    assert np.all(states == 2) and np.all(lats >= 0)
+    with pytest.raises(tc.TCError):
+        srv.tc_server_poll_many(ids[:3] + [987654321])
     for i, (kind, x) in enumerate(reqs):
         st, lat = srv.tc_server_poll(ids[i])
-        assert st == 2 and lat >= 0
+        assert st == 2 and lat == lats[i]
         if kind == "view":
             n = int(x["width"]) * int(x["height"])
             wg, dg = srv.tc_server_read(ids[i], n)
@@ -190,10 +195,11 @@ def test_server_owns_map_and_auto_release(ctx):
     torch.cuda.synchronize()
 
 
-def test_c5_map_mixed_sampled(ctx):
+def test_c5_map_mixed_full(ctx):
     """On the 2048x16384 map: views of the configuration-5 sizes mixed with
-    crater edits, each checked on sampled pixels at its epoch."""
-    F, B, T = synth.make_map_from_config(5)
+    crater edits; every record of each request's whole buffer against the
+    oracle's render of the map at its epoch."""
+    F, B, T = config_map(5)
     H, W = F.shape
     load(ctx, F, B, T)
     rng = np.random.default_rng(80)
@@ -215,11 +221,7 @@ def test_c5_map_mixed_sampled(ctx):
             continue
         w, h = int(x["width"]), int(x["height"])
         wg, dg = srv.tc_server_read(ids[i], w * h)
-        n = 3000
-        px = rng.integers(0, w, n).astype(np.int32)
-        py = rng.integers(0, h, n).astype(np.int32)
-        wo, do = oracle.cast_pixels(Fk, Bk, Tk, [x], np.zeros(n, np.int32), px, py)
-        idx = py.astype(np.int64) * w + px
-        assert_parity(wg[idx], dg[idx], wo, do, "c5 request %d" % i)
+        wo, do = oracle.render(Fk, Bk, Tk, [x], threads=host_threads())
+        assert_parity(wg, dg, wo, do, "c5 request %d (%dx%d)" % (i, w, h))
         srv.tc_server_release(ids[i])
     srv.tc_server_stop()

@@ -7,6 +7,7 @@ import pytest
 
 import oracle
 import synth
+from oracle_cache import config_map
 
 tc = pytest.importorskip("paper_2608_17390_amd")
 torch = pytest.importorskip("torch")
@@ -101,7 +102,7 @@ def test_after_edits(ctx):
 def test_protocol_views_sampled(ctx):
     """The twelve 1280x800 protocol views on the 2048x16384 map, 20,000
     sampled pixels against the oracle."""
-    F, B, T = synth.make_map_from_config(3)
+    F, B, T = config_map(3)
     load(ctx, F, B, T)
     views, _ = synth.pitch_views(F, B, 91)
     pal = synth.default_palette()

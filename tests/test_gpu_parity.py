@@ -567,11 +567,13 @@ def test_renders_allocate_nothing(ctx):
     ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, 0)
     ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 128)
     assert ctx.tc_get_option(tc.TC_INFO_ALLOCATIONS) == before
-    # a longer split queue re-sizes the ring's queues once, outside renders
-    ctx.tc_set_option(tc.TC_OPT_SPLIT_QUEUE, 1 << 18)
+    # a split queue longer than the ring's (earlier tests may have grown
+    # it) re-sizes the ring's queues in tc_set_option, not in renders
+    ctx.tc_set_option(tc.TC_OPT_SPLIT_QUEUE, (1 << 20) + 1)
     grown = ctx.tc_get_option(tc.TC_INFO_ALLOCATIONS)
-    assert grown > before
-    ctx.tc_render_views(vs, out.data_ptr())
+    assert grown == before + 16
+    for _ in range(3):
+        ctx.tc_render_views(vs, out.data_ptr())
     torch.cuda.synchronize()
     assert ctx.tc_get_option(tc.TC_INFO_ALLOCATIONS) == grown
     ctx.tc_set_option(tc.TC_OPT_SPLIT_QUEUE, 1 << 17)

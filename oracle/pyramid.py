@@ -7,6 +7,14 @@ per 2^L x 2^L block of cells (blocks clipped to the map).  A node stores
   smin = min B over the block's two-layer cells (255 when there are none),
   smax = max T over the block's two-layer cells (0 when there are none),
 packed as fmax | smin << 8 | smax << 16 (uint32), row-major [y][x].
+
+A window level L >= 0 has one entry per level-L node (i, j) holding the
+same three quantities over the 2^(L+1) x 2^(L+1) block of cells whose
+corner is the node's, [i 2^L, (i + 2) 2^L) x [j 2^L, (j + 2) 2^L), clipped
+to the map: a box narrower than a level-L node overlaps at most two nodes
+per axis, all inside the window of the first, so one entry bounds the
+solid of the whole box (Section 3.2's conservative test of a region against
+the hierarchy, here for the boxes that bound a bundle of rays).
 """
 import numpy as np
 
@@ -68,3 +76,47 @@ def occupancy_level(F, B, T, L):
     pad = ((0, HL * n - H), (0, WL * n - W))
     c = np.pad(cell, pad, constant_values=0).reshape(HL, n, WL, n)
     return np.bitwise_or.reduce(np.bitwise_or.reduce(c, axis=3), axis=1)
+
+
+def window_level(F, B, T, L):
+    """Window level L >= 0 (uint32, row-major [y][x], the shape of level L),
+    written as its definition: per entry, the block of cells it covers."""
+    H, W = F.shape
+    n = 1 << L
+    HL = (H + n - 1) // n
+    WL = (W + n - 1) // n
+    out = np.zeros((HL, WL), np.uint32)
+    for j in range(HL):
+        for i in range(WL):
+            f = F[j * n:(j + 2) * n, i * n:(i + 2) * n]
+            b = B[j * n:(j + 2) * n, i * n:(i + 2) * n]
+            t = T[j * n:(j + 2) * n, i * n:(i + 2) * n]
+            two = b > 0
+            fmax = int(f.max())
+            smin = int(b[two].min()) if two.any() else 255
+            smax = int(t[two].max()) if two.any() else 0
+            out[j, i] = fmax | (smin << 8) | (smax << 16)
+    return out
+
+
+def window_level_fast(F, B, T, L):
+    """Same result as window_level, derived the other way round: the 2 x 2
+    neighbourhood combine (max, min, max) of level-L nodes (i..i+1, j..j+1)
+    that exist, level 0 being the cells themselves (for large maps)."""
+    if L == 0:
+        two = B > 0
+        P = (F.astype(np.uint32) | (np.where(two, B, 255).astype(np.uint32) << 8) |
+             (np.where(two, T, 0).astype(np.uint32) << 16))
+    else:
+        P = pyramid_level_fast(F, B, T, L)
+    f = (P & 0xFF).astype(np.int64)
+    lo = ((P >> 8) & 0xFF).astype(np.int64)
+    hi = ((P >> 16) & 0xFF).astype(np.int64)
+    fp = np.pad(f, ((0, 1), (0, 1)), constant_values=0)
+    lp = np.pad(lo, ((0, 1), (0, 1)), constant_values=255)
+    hp = np.pad(hi, ((0, 1), (0, 1)), constant_values=0)
+    h, w = P.shape
+    fm = np.maximum(np.maximum(fp[:h, :w], fp[1:, :w]), np.maximum(fp[:h, 1:], fp[1:, 1:]))
+    lm = np.minimum(np.minimum(lp[:h, :w], lp[1:, :w]), np.minimum(lp[:h, 1:], lp[1:, 1:]))
+    hm = np.maximum(np.maximum(hp[:h, :w], hp[1:, :w]), np.maximum(hp[:h, 1:], hp[1:, 1:]))
+    return (fm | (lm << 8) | (hm << 16)).astype(np.uint32)

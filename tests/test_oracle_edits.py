@@ -3,6 +3,7 @@ import json
 import os
 
 import numpy as np
+import pytest
 
 import oracle
 import synth
@@ -70,6 +71,64 @@ def test_pyramid_hand_case():
     assert p2[0, 1] == node(10, 30, 31)
     p3 = oracle.pyramid_level(F, B, T, 3)
     assert p3[0, 0] == node(10, 9, 40)
+
+
+def test_window_hand_case():
+    """The map of the pyramid hand case.  Window level 0 entry (i, j) covers
+    cells (i..i+1, j..j+1); window level 1 entry (i, j) covers cells
+    (2i..2i+3, 2j..2j+3), clipped to the 5 x 3 map."""
+    F = np.array([[1, 2, 3, 4, 5],
+                  [6, 7, 8, 9, 10],
+                  [0, 0, 0, 0, 0]], np.uint8)
+    B = np.zeros_like(F)
+    T = np.zeros_like(F)
+    B[0, 1], T[0, 1] = 20, 25
+    B[1, 4], T[1, 4] = 30, 31
+    B[2, 2], T[2, 2] = 9, 40
+    node = lambda f, lo, hi: f | (lo << 8) | (hi << 16)
+    w0 = oracle.window_level(F, B, T, 0)
+    assert w0.shape == (3, 5)
+    assert w0[0, 0] == node(7, 20, 25)     # cells (0..1, 0..1)
+    assert w0[0, 1] == node(8, 20, 25)     # cells (1..2, 0..1)
+    assert w0[0, 3] == node(10, 30, 31)    # cells (3..4, 0..1)
+    assert w0[0, 4] == node(10, 30, 31)    # cells (4, 0..1): clipped
+    assert w0[1, 1] == node(8, 9, 40)      # cells (1..2, 1..2)
+    assert w0[1, 3] == node(10, 30, 31)
+    assert w0[2, 0] == node(0, 255, 0)     # cells (0..1, 2)
+    assert w0[2, 2] == node(0, 9, 40)      # cells (2..3, 2)
+    assert w0[2, 4] == node(0, 255, 0)     # cell (4, 2)
+    w1 = oracle.window_level(F, B, T, 1)
+    assert w1.shape == (2, 3)
+    assert w1[0, 0] == node(9, 9, 40)      # cells (0..3, 0..2)
+    assert w1[0, 1] == node(10, 9, 40)     # cells (2..4, 0..2)
+    assert w1[0, 2] == node(10, 30, 31)    # cells (4, 0..2)
+    assert w1[1, 1] == node(0, 9, 40)      # cells (2..4, 2)
+    # the top window covers everything
+    w3 = oracle.window_level(F, B, T, 3)
+    assert w3.shape == (1, 1) and w3[0, 0] == node(10, 9, 40)
+
+
+@pytest.mark.parametrize("shape,L", [((1, 1), 0), ((3, 5), 1), ((17, 9), 0), ((17, 9), 2),
+                                     ((40, 33), 1), ((40, 33), 3), ((40, 33), 6)])
+def test_window_definitions_agree(shape, L):
+    """Per-entry blocks of cells against the 2 x 2 combine of level-L
+    nodes, on random two-layer maps of odd shapes."""
+    import synth
+    H, W = shape
+    F, B, T = synth.make_map(W, H, 70 + W * 3 + L, dual=0.4, period=4)
+    a = oracle.window_level(F, B, T, L)
+    b = oracle.window_level_fast(F, B, T, L)
+    assert a.dtype == b.dtype == np.uint32 and a.shape == b.shape
+    assert np.array_equal(a, b)
+    # every window bounds each of its cells: fmax >= F, and a two-layer
+    # cell's slab lies inside [smin, smax]
+    n = 1 << L
+    for y in range(H):
+        for x in range(W):
+            e = int(a[y // n, x // n])
+            assert (e & 0xFF) >= F[y, x]
+            if B[y, x]:
+                assert ((e >> 8) & 0xFF) <= B[y, x] and ((e >> 16) & 0xFF) >= T[y, x]
 
 
 def test_occupancy_hand_case():

@@ -1,9 +1,9 @@
 """Edit semantics, written plainly on numpy planes (test infrastructure).
 
-Section 2: a local gameplay event may change both the altitude and whether
-the upper interval exists; the renderer receives a dirty rectangle and the
-modified rows.  Section 4.4: the dig operation removes altitude and
-upper-layer metadata inside a crater.
+Section 2 describes edits as local game events that can change a column's
+heights and whether it has an upper slab, handed to the renderer as a
+changed rectangle with its new rows; Section 4.4's digging lowers the
+ground and deletes the slab inside the crater.
 
   SET    overwrite the rectangle [x0, x0+w) x [y0, y0+h) (clipped to the map)
          with the given F, B, T patch.

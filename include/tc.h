@@ -160,6 +160,20 @@ tc_status tc_apply_edit(tc_context *ctx, const tc_edit *edits, int32_t n,
 tc_status tc_render_views(tc_context *ctx, const tc_view *views, int32_t n,
                           tc_hit *out_device, void *hip_stream);
 
+/* tc_render_views for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * allocation): same arguments, results and errors, and it allocates
+ * nothing.  Its per-call tables and the split pass's queue live in a
+ * library-owned device array of 1.25 MiB per GPU, held until the process
+ * ends: the tables may take at most 256 KiB (about 2,000 views; more gives
+ * TC_INVALID_ARG), and at most 65,536 long rays go to the split pass (the
+ * rest finish in the first pass, with the same results).  Every call on a
+ * GPU shares that GPU's array: calls on one stream are ordered, but calls
+ * that overlap on one GPU (other streams, contexts or threads) race and must
+ * not be issued. */
+tc_status tc_render_views_noalloc(tc_context *ctx, const tc_view *views, int32_t n,
+                                  tc_hit *out_device, void *hip_stream);
+
 /* ---- shading ------------------------------------------------------------
  * The shared shading stage of the paper's methods (Section 3: one palette,
  * diffuse lighting with a height-field gradient normal, a shadow term and

@@ -113,6 +113,7 @@ SIGNATURES = [
     ("tc_load_columns", _I32, [_P, _I32, _I32, _P, _P, _P, ctypes.c_size_t, _P]),
     ("tc_apply_edit", _I32, [_P, ctypes.POINTER(tc_edit), _I32, _P]),
     ("tc_render_views", _I32, [_P, ctypes.POINTER(tc_view), _I32, _P, _P]),
+    ("tc_render_views_noalloc", _I32, [_P, ctypes.POINTER(tc_view), _I32, _P, _P]),
     ("tc_shade_views", _I32, [_P, ctypes.POINTER(tc_view), _I32, _P,
                               ctypes.POINTER(tc_shade_params), _P, _P]),
     ("tc_set_option", _I32, [_P, _I32, ctypes.c_int64]),
@@ -309,6 +310,13 @@ class Context:
         st = load_library().tc_render_views(self._h, arr, len(arr),
                                             ctypes.c_void_p(int(out_ptr)),
                                             _stream_handle(stream))
+        _check(self._h, st)
+
+    def tc_render_views_noalloc(self, views, out_ptr, stream=None):
+        arr = _views_struct(views)
+        st = load_library().tc_render_views_noalloc(self._h, arr, len(arr),
+                                                    ctypes.c_void_p(int(out_ptr)),
+                                                    _stream_handle(stream))
         _check(self._h, st)
 
     def tc_shade_views(self, views, hits_ptr, light, palette, out_ptr, ambient=0.3,

@@ -258,8 +258,10 @@ tc_status tc_create(int hip_device, tc_context** out) {
     return TC_DEVICE_ERROR;
   }
   // the staging ring and its split queues: after this, renders allocate
-  // nothing unless their tables outgrow a slot
-  if (tci::ring_alloc(ctx, (uint32_t)ctx->split_queue) != TC_OK) {
+  // nothing unless their tables outgrow a slot; and the device address of
+  // tc_render_views_noalloc's scratch array
+  if (tci::ring_alloc(ctx, (uint32_t)ctx->split_queue) != TC_OK ||
+      tci::noalloc_setup(ctx) != TC_OK) {
     g_create_error = "tc_create: " + ctx->err;
     tc_destroy(ctx);
     return TC_OUT_OF_MEMORY;

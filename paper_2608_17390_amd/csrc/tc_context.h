@@ -70,6 +70,10 @@ hipError_t enqueue_render(tc_context* ctx, const tci_map& d, const char* dev,
 
 tci_render_opts render_opts(const tc_context* c);
 
+// Look up, once per device, the device address of the scratch array of
+// tc_render_views_noalloc (tc_noalloc.hip); tc_create calls it.
+tc_status noalloc_setup(tc_context* ctx);
+
 }  // namespace tci
 
 struct tc_context {

@@ -120,3 +120,71 @@ def window_level_fast(F, B, T, L):
     lm = np.minimum(np.minimum(lp[:h, :w], lp[1:, :w]), np.minimum(lp[:h, 1:], lp[1:, 1:]))
     hm = np.maximum(np.maximum(hp[:h, :w], hp[1:, :w]), np.maximum(hp[:h, 1:], hp[1:, 1:]))
     return (fm | (lm << 8) | (hm << 16)).astype(np.uint32)
+
+
+# ---- the occupancy pyramid of the voxel-accelerated march (Section 3.2) ----
+#
+# Voxels of v x v cells by vz height units.  The finest level holds one bit
+# per voxel: set iff the solid set of some column of its footprint meets the
+# voxel's closed height range [Z vz, (Z + 1) vz] (a floor (-inf, F] meets it
+# iff Z vz <= F; a slab [B, T] iff B <= (Z + 1) vz and T >= Z vz).  Each
+# higher level is the union of its eight children (2 x 2 x 2).  Heights run
+# 0..256, so the finest level has 256 / vz voxels per column.  Arrays are
+# indexed [Z][Y][X].
+
+
+def voxel_dims(W, H, v, vz, k):
+    """Voxel counts (nx, ny, nz) of level k."""
+    nx, ny, nz = -(-W // v), -(-H // v), 256 // vz
+    for _ in range(k):
+        nx, ny, nz = -(-nx // 2), -(-ny // 2), -(-nz // 2)
+    return nx, ny, nz
+
+
+def voxel_levels(F, B, T, v, vz):
+    """Every level, finest first, built the way the structure is defined:
+    the finest from the columns, each next one as the union of eight
+    children, until a single voxel remains."""
+    H, W = F.shape
+    nx, ny, nz = voxel_dims(W, H, v, vz, 0)
+    leaf = np.zeros((nz, ny, nx), bool)
+    for y in range(H):
+        for x in range(W):
+            f, b, t = int(F[y, x]), int(B[y, x]), int(T[y, x])
+            for Z in range(nz):
+                z0, z1 = Z * vz, (Z + 1) * vz
+                if z0 <= f or (b > 0 and b <= z1 and t >= z0):
+                    leaf[Z, y // v, x // v] = True
+    levels = [leaf]
+    while levels[-1].shape != (1, 1, 1):
+        c = levels[-1]
+        z, y, x = c.shape
+        p = np.zeros((-(-z // 2), -(-y // 2), -(-x // 2)), bool)
+        for Z in range(z):
+            for Y in range(y):
+                for X in range(x):
+                    if c[Z, Y, X]:
+                        p[Z // 2, Y // 2, X // 2] = True
+        levels.append(p)
+    return levels
+
+
+def voxel_level_direct(F, B, T, v, vz, k):
+    """Level k written directly: a voxel of level k covers the cells
+    [X v 2^k, (X + 1) v 2^k) x [Y v 2^k, (Y + 1) v 2^k) and the closed
+    heights [Z vz 2^k, (Z + 1) vz 2^k]; its bit is set iff a column of its
+    footprint has solid in that range (vectorised, for large maps)."""
+    H, W = F.shape
+    nx, ny, nz = voxel_dims(W, H, v, vz, k)
+    n, s = v << k, vz << k
+    f = F.astype(np.int64)
+    b = B.astype(np.int64)
+    t = T.astype(np.int64)
+    out = np.zeros((nz, ny, nx), bool)
+    pad = ((0, ny * n - H), (0, nx * n - W))
+    for Z in range(nz):
+        z0, z1 = Z * s, (Z + 1) * s
+        col = (z0 <= f) | ((b > 0) & (b <= z1) & (t >= z0))
+        col = np.pad(col, pad, constant_values=False).reshape(ny, n, nx, n)
+        out[Z] = col.any(axis=(1, 3))
+    return out

@@ -27,6 +27,8 @@ if ROOT not in sys.path:
 
 PEAK_HBM_GBS = 8000.0
 MODES = {"hier": 0, "flat": 1, "persistent": 2, "march": 3, "occupancy": 4}
+# (render mode 5, the voxel-accelerated march, needs its pyramid: it is
+# timed in occupancy_compare)
 KERNEL_NAMES = {"hier": "render_hier_kernel + split_kernel (one traversal)",
                 "flat": "render_flat_kernel", "persistent": "render_persistent_kernel",
                 "march": "march_kernel", "occupancy": "render_occ_kernel"}
@@ -318,14 +320,32 @@ def march_protocol(torch, tc, synth, steps, warmup):
 CAVE_SEED = 6002          # the cave-heavy comparison map
 
 
+def voxel_bytes(ctx):
+    """Bytes of the context's voxel occupancy pyramid (Morton tiles of 64 B)."""
+    n = ctx.tc_voxel_dims(0)[3]
+    total = 0
+    for k in range(n):
+        nx, ny, nz, _ = ctx.tc_voxel_dims(k)
+        total += ((nx + 7) // 8) * ((ny + 7) // 8) * ((nz + 7) // 8) * 64
+    return total
+
+
 def occupancy_compare(torch, tc, synth, steps, warmup):
     """The 2D min/max pyramid (render mode 0, with and without its split
-    pass) against the same walk with occupancy masks (mode 4): frame time
-    and node/cell reads per ray, on a cave-heavy 2048x2048 map (half the
-    cells two-layer) and on the headline 2048x2048 map."""
+    pass) against the same walk with occupancy masks (mode 4) and against
+    the voxel-accelerated march over the voxel occupancy pyramid (mode 5,
+    Section 3.2, voxels of 4x4 cells by 2 units and 2x2 by 1, the paper's
+    coarse and shipping proportions with square footprints): frame time,
+    node/cell/voxel-word reads per ray and structure size, on a cave-heavy
+    2048x2048 map (half the cells two-layer) and on the headline map.  The
+    packet beam (which reads the window levels) is on in every row, and off
+    in the last two."""
     out = {}
     cases = {"cave": synth.cave_map(CAVE_SEED, 2048, 2048),
              "c2": synth.make_map_from_config(2)}
+    rows = (("pyramid_split", 0, 128, 0, 4), ("pyramid", 0, 0, 0, 4), ("occupancy", 4, 0, 0, 4),
+            ("rayvoxel_4x4x2", 5, 0, 4 | (2 << 8), 4), ("rayvoxel_2x2x1", 5, 0, 2 | (1 << 8), 4),
+            ("pyramid_nobeam", 0, 0, 0, 0), ("rayvoxel_4x4x2_nobeam", 5, 0, 4 | (2 << 8), 0))
     for name, (F, B, T) in cases.items():
         ctx = tc.Context(0)
         ctx.tc_load_columns(F, B, T)
@@ -335,10 +355,11 @@ def occupancy_compare(torch, tc, synth, steps, warmup):
         rays = synth.view_rays(views)
         buf = torch.empty((rays, 2), dtype=torch.int32, device="cuda")
         res = {}
-        for label, mode, budget in (("pyramid_split", 0, 128), ("pyramid", 0, 0),
-                                    ("occupancy", 4, 0)):
+        for label, mode, budget, vox, beam in rows:
+            ctx.tc_set_option(tc.TC_OPT_VOXEL_SHAPE, vox)
             ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, mode)
             ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, budget)
+            ctx.tc_set_option(tc.TC_OPT_BEAM_PASSES, beam)
             ms, _ = time_renders(torch, ctx, tc, views, buf, steps, warmup)
             ctx.tc_set_option(tc.TC_OPT_COUNT_READS, 1)
             ctx.tc_read_counters()
@@ -348,6 +369,10 @@ def occupancy_compare(torch, tc, synth, steps, warmup):
             res[label] = {"frame_ms_median": float(np.median(ms)),
                           "grays_per_s": rays / (np.median(ms) * 1e-3) / 1e9,
                           "reads_per_ray": reads / rays}
+            if vox:
+                res[label]["voxel_MiB"] = voxel_bytes(ctx) / 2**20
+        ctx.tc_set_option(tc.TC_OPT_VOXEL_SHAPE, 0)
+        res["map_MiB"] = ctx.tc_map_bytes() / 2**20
         ctx.close()
         out[name] = res
     out["workload"] = ("2048x2048 cave-heavy map (50% two-layer), a 1920x1080 eye-level and "
@@ -355,12 +380,13 @@ def occupancy_compare(torch, tc, synth, steps, warmup):
     return out
 
 
-def c4_batched(torch, tc, synth, steps, warmup):
+def c4_batched(torch, tc, synth, steps, warmup, knob_set="tuned"):
     """Configuration 4: 64 views of uneven sizes + 8 shadow passes + 16
     craters.  Plain: tc_apply_edit then one tc_render_views per view,
     serialized on one stream; a view's latency runs from the frame start to
     its render's end.  Batched: the same work as one captured frame; every
-    view completes with the frame."""
+    view completes with the frame.  knob_set: the autotuner's choice
+    (default), the persistent packet queue, or the hierarchical defaults."""
     from paper_2608_17390_amd import tune
     F, B, T = synth.make_map_from_config(4)
     H, W = F.shape
@@ -373,7 +399,11 @@ def c4_batched(torch, tc, synth, steps, warmup):
     ctx = tc.Context(0)
     ctx.tc_load_columns(F, B, T)
     out = torch.empty((rays, 2), dtype=torch.int32, device="cuda")
-    knobs, cached = tune.autotune(ctx, views, out.data_ptr(), "c4-batched")
+    if knob_set == "tuned":
+        knobs, cached = tune.autotune(ctx, views, out.data_ptr(), "c4-batched")
+    else:
+        ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, 2 if knob_set == "persistent" else 0)
+        knobs, cached = {k: ctx.tc_get_option(o) for k, o in tune.OPTS.items()}, None
     log("[bench] c4 knobs %s (cached %s)" % (knobs, cached))
     # plain
     nv = len(views)
@@ -422,70 +452,108 @@ def c4_batched(torch, tc, synth, steps, warmup):
                         "grays_per_s": rays / (np.median(bms) * 1e-3) / 1e9}}
 
 
+def _serve(tc, ctx, F, B, T, reqs, cs, arr, batch, streams):
+    """Submit `reqs` (prebuilt C structures `cs`) at arrival times `arr`
+    (seconds from the start) to a server of `batch` views per render on
+    `streams` streams; wait for all.  Latency runs from submission to
+    observed completion."""
+    ctx.tc_load_columns(F, B, T)
+    srv = ctx.tc_server_start(8 << 30, max_batch_views=batch, streams=streams,
+                              flags=tc.TC_SERVER_AUTO_RELEASE)
+    ids = []
+    t0 = time.perf_counter()
+    late = 0.0
+    for (kind, x), c, t in zip(reqs, cs, arr):
+        while time.perf_counter() - t0 < t:
+            pass
+        late = max(late, time.perf_counter() - t0 - t)
+        ids.append(srv.tc_server_submit_view(c) if kind == "view"
+                   else srv.tc_server_submit_edit(c))
+    for rid in ids:
+        srv.tc_server_wait(rid, 300.0)
+    t_end = time.perf_counter()
+    states, lats = srv.tc_server_poll_many(ids)
+    isview = np.array([k == "view" for k, _ in reqs])
+    lat = lats[isview] * 1e3
+    rays = sum(int(x["width"]) * int(x["height"]) for k, x in reqs if k == "view")
+    stats = srv.tc_server_get_stats()
+    srv.tc_server_stop()
+    nv = max(1, int(stats["views"]))
+    return {"latency_ms_p50": float(np.percentile(lat, 50)),
+            "latency_ms_p99": float(np.percentile(lat, 99)),
+            "grays_per_s": rays / (t_end - t0) / 1e9,
+            "batches": stats["batches"],
+            # host side of a view's latency: submission to launch (admission,
+            # batching, planning, upload, launch), then launch to observed
+            # completion (GPU time plus completion polling)
+            "queue_ms_mean": stats["queue_s"] / nv * 1e3,
+            "run_ms_mean": stats["run_s"] / nv * 1e3,
+            "max_submit_lag_ms": late * 1e3,
+            "peak_inflight_MiB": stats["peak_bytes"] / 2**20}
+
+
 def c5_served(torch, tc, synth, rates=(200, 500, 1000, 2000, 5000, 10000),
-              n_per_rate=1500, min_seconds=1.5):
+              n_per_rate=1500, min_seconds=1.5, burst=2000):
     """Configuration 5: Poisson request streams against the resident
     2048x16384 map; 90% views (sizes and poses as configuration 4), 10%
     craters of size 16-64; an 8 GiB in-flight hit-buffer budget.  Served:
     continuous batching (up to 8 views per batch, 2 streams).  FIFO plain:
-    the same server with one view per batch on one stream.  Latency runs
-    from submission to observed completion.  Each rate gets at least
-    n_per_rate requests and at least min_seconds of arrivals, so the p99 of
-    the fast rates rests on thousands of requests."""
+    the same server with one view per render on one stream, i.e. each view
+    in its own render, serialized, with the plain kernel's knobs.  Each rate
+    gets at least n_per_rate requests and at least min_seconds of arrivals,
+    so the p99 of the fast rates rests on thousands of requests.  Then two
+    saturation legs, where arrivals outrun the FIFO form: `burst` requests
+    of the same mix submitted at once, and `burst` // 2 1920x1080 views at
+    once; delivered rays/s there is the sustained capacity of each form."""
     F, B, T = synth.make_map_from_config(5)
     H, W = F.shape
     seeds = synth.SEEDS[5]
     ctx = tc.Context(0)
+    forms = (("served", 8, 2), ("fifo_plain", 1, 1))
     out = {"workload": "c5: 2048x16384 map resident, Poisson arrivals, 90% views "
                        "(256^2..1920x1080) / 10% craters (16..64), 8 GiB in-flight budget",
-           "requests_per_rate": {}, "rates": {}}
+           "requests_per_rate": {}, "rates": {}, "saturation": {}}
+
+    def mix(rng, n):
+        reqs = []
+        for _ in range(n):
+            if rng.random() < 0.1:
+                reqs.append(("edit", synth.crater_list(rng, W, H, 1, size=(16, 64))))
+            else:
+                reqs.append(("view", synth.request_view(rng, F, B)))
+        return reqs
+
+    def structs(reqs):
+        return [tc.view_struct(x) if k == "view" else tc.edits_struct(x) for k, x in reqs]
+
     for rate in rates:
         nreq = max(n_per_rate, int(rate * min_seconds))
         out["requests_per_rate"][str(rate)] = nreq
         rng = np.random.default_rng(seeds["views"] * 10 + rate)
         arr = synth.poisson_arrivals(seeds["arrivals"] * 10 + rate, rate, nreq)
-        reqs = []
-        for _ in range(nreq):
-            if rng.random() < 0.1:
-                reqs.append(("edit", synth.crater_list(rng, W, H, 1, size=(16, 64))))
-            else:
-                reqs.append(("view", synth.request_view(rng, F, B)))
-        # C structures built before the timed submission loop
-        cs = [tc.view_struct(x) if k == "view" else tc.edits_struct(x) for k, x in reqs]
+        reqs = mix(rng, nreq)
+        cs = structs(reqs)      # C structures built before the timed submission loop
         res = {}
-        for name, batch, streams in (("served", 8, 2), ("fifo_plain", 1, 1)):
-            ctx.tc_load_columns(F, B, T)
-            srv = ctx.tc_server_start(8 << 30, max_batch_views=batch, streams=streams,
-                                      flags=tc.TC_SERVER_AUTO_RELEASE)
-            ids = []
-            t0 = time.perf_counter()
-            late = 0.0
-            for (kind, x), c, t in zip(reqs, cs, arr):
-                while time.perf_counter() - t0 < t:
-                    pass
-                late = max(late, time.perf_counter() - t0 - t)
-                ids.append(srv.tc_server_submit_view(c) if kind == "view"
-                           else srv.tc_server_submit_edit(c))
-            for rid in ids:
-                srv.tc_server_wait(rid, 300.0)
-            t_end = time.perf_counter()
-            lat = []
-            rays = 0
-            for (kind, x), rid in zip(reqs, ids):
-                st, l = srv.tc_server_poll(rid)
-                if kind == "view":
-                    lat.append(l * 1e3)
-                    rays += int(x["width"]) * int(x["height"])
-            stats = srv.tc_server_get_stats()
-            srv.tc_server_stop()
-            res[name] = {"latency_ms_p50": float(np.percentile(lat, 50)),
-                         "latency_ms_p99": float(np.percentile(lat, 99)),
-                         "grays_per_s": rays / (t_end - t0) / 1e9,
-                         "batches": stats["batches"],
-                         "max_submit_lag_ms": late * 1e3,
-                         "peak_inflight_MiB": stats["peak_bytes"] / 2**20}
+        for name, batch, streams in forms:
+            res[name] = _serve(tc, ctx, F, B, T, reqs, cs, arr, batch, streams)
             log("[bench] c5 rate %d %s: %s" % (rate, name, res[name]))
         out["rates"][str(rate)] = res
+    rng = np.random.default_rng(seeds["views"] * 10 + 7)
+    legs = {"burst_mix": mix(rng, burst)}
+    big = []
+    while len(big) < burst // 2:
+        v = synth.request_view(rng, F, B)
+        if int(v["width"]) == 1920:
+            big.append(("view", v))
+    legs["burst_1920x1080"] = big
+    for leg, reqs in legs.items():
+        cs = structs(reqs)
+        arr = np.zeros(len(reqs))
+        res = {"requests": len(reqs)}
+        for name, batch, streams in forms:
+            res[name] = _serve(tc, ctx, F, B, T, reqs, cs, arr, batch, streams)
+            log("[bench] c5 %s %s: %s" % (leg, name, res[name]))
+        out["saturation"][leg] = res
     ctx.close()
     return out
 
@@ -508,7 +576,18 @@ def main():
     ap.add_argument("--beam-passes", type=int, default=None,
                     help="packet beam passes of the headline render (default: the "
                          "library's)")
+    ap.add_argument("--legs", default="march,occupancy,c3,c4,c5",
+                    help="comma-separated legs to run after the headline (march, "
+                         "occupancy, c3, c4, c5)")
+    ap.add_argument("--c4-knobs", default="tuned", choices=["tuned", "persistent", "hier"],
+                    help="knobs of the c4 frames: the autotuner's, the persistent packet "
+                         "queue's, or the hierarchical defaults")
     args = ap.parse_args()
+    legs = set(x for x in args.legs.split(",") if x)
+    if args.no_march:
+        legs -= {"march", "occupancy"}
+    if args.no_growth:
+        legs -= {"c3", "c4", "c5"}
     if args.gpus != 1:
         print("bench.py measures one GPU; --gpus %d is not supported (the method "
               "shards by replicating the map and splitting views across GPUs, "
@@ -557,6 +636,7 @@ def main():
     kern = kernel_times(torch, ctx, tc, views, out, args.steps)
     kavg = float(kern.sum(axis=1).mean())
     achieved = alg_bytes / (kavg * 1e-3) / 1e9
+    traffic = profile_value(RENDER_SRCS, "render_c2_traffic", "hbm_bytes_per_launch")
     res = {
         "metric": "Grays/s and ms/frame @1920x1080 eye-level; batched vs plain p99 latency",
         "value": rays / (ms_per_step * 1e-3) / 1e9,
@@ -577,13 +657,20 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                      # HBM bytes per traversal (FETCH_SIZE + WRITE_SIZE, copy-calibrated)
-                     "traffic": profile_value(RENDER_SRCS, "render_c2_traffic",
-                                              "hbm_bytes_per_launch"),
+                     "traffic": traffic,
+                     "traffic_gb_per_s": (traffic / (kavg * 1e-3) / 1e9) if traffic else None,
                      # the roof that binds: share of the first pass's lifetime the
                      # SIMDs spend issuing VALU instructions (SQ_INSTS_VALU x 4
                      # cycles over 1024 SIMDs x GRBM_GUI_ACTIVE per XCD)
                      "valu_busy_frac": profile_value(RENDER_SRCS, "render_c2_counters",
                                                      "valu_busy_frac"),
+                     # the counters' verdict: the first pass is bound by VALU issue, not
+                     # by HBM (bytes are the scope table's algorithmic measure)
+                     "binding_roof": "valu_issue",
+                     # share of lanes active per VALU instruction (SQ_THREAD_CYCLES_VALU
+                     # over 64 x SQ_ACTIVE_INST_VALU)
+                     "valu_lane_util": profile_value(RENDER_SRCS, "render_c2_counters",
+                                                     "valu_lane_util"),
                      "kernel": KERNEL_NAMES[args.mode],
                      "alg_bytes_per_launch": alg_bytes,
                      "kernel_ms_avg": kavg,
@@ -598,17 +685,19 @@ def main():
             mm, _ = time_renders(torch, ctx, tc, views, out, 10, 2)
             modes[m] = float(np.median(mm))
         res["mode_ms_median"] = modes
-    if not args.no_march:
+    if "march" in legs:
         log("[bench] sampled march on the protocol views")
         res["march_protocol"] = march_protocol(torch, tc, synth, 10, 2)
-    if not args.no_march:
-        log("[bench] 2D pyramid vs occupancy masks")
+    if "occupancy" in legs:
+        log("[bench] 2D pyramid vs occupancy masks vs voxel occupancy pyramid")
         res["occupancy_compare"] = occupancy_compare(torch, tc, synth, 10, 2)
-    if not args.no_growth:
+    if "c3" in legs:
         log("[bench] c3 edit frame")
         res["c3_frame"] = c3_frame(torch, tc, synth, 10, 2)
+    if "c4" in legs:
         log("[bench] c4 batched vs plain")
-        res["c4_batched"] = c4_batched(torch, tc, synth, 10, 2)
+        res["c4_batched"] = c4_batched(torch, tc, synth, 10, 2, args.c4_knobs)
+    if "c5" in legs:
         log("[bench] c5 served vs FIFO plain")
         res["c5_served"] = c5_served(torch, tc, synth)
     if not args.no_cpu:

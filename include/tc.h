@@ -235,8 +235,24 @@ tc_status tc_shade_views(tc_context *ctx, const tc_view *views, int32_t n,
 /* Tuning knobs of the render path.  Each takes effect for later calls. */
 #define TC_OPT_RENDER_MODE 1   /* 0 hierarchical (default), 1 flat walk,
                                   2 persistent packet queue, 4 hierarchical
-                                  with occupancy masks (all four exact and
-                                  bit-identical); 3 the sampled march below */
+                                  with occupancy masks, 5 the voxel-
+                                  accelerated march over the voxel
+                                  occupancy pyramid (TC_OPT_VOXEL_SHAPE; all
+                                  five exact and bit-identical); 3 the
+                                  sampled march below */
+#define TC_OPT_VOXEL_SHAPE 21  /* voxels of the occupancy pyramid of render
+                                  mode 5 (Section 3.2: one bit per voxel in
+                                  Morton-ordered 8x8x8 tiles, each level the
+                                  union of its eight children): v | vz << 8
+                                  for voxels of v x v cells by vz height
+                                  units, v and vz in 1, 2, 4, 8; 0 (default)
+                                  keeps no pyramid.  Setting it builds the
+                                  pyramid for the loaded map (synchronous);
+                                  tc_load_columns rebuilds it and edits
+                                  update the tiles over edited cells and
+                                  their ancestors.  Frames captured before a
+                                  change are stale; a server refuses to start
+                                  while a pyramid is kept */
 #define TC_OPT_START_LEVEL 2   /* pyramid level a ray starts at from its
                                   origin (default 2); clamped to the top
                                   level.  Walks the packet beam or the split
@@ -255,7 +271,13 @@ tc_status tc_shade_views(tc_context *ctx, const tc_view *views, int32_t n,
 #define TC_OPT_COUNT_READS 8   /* 1: renders add the number of pyramid nodes
                                   and cells each ray reads to a context
                                   counter (diagnostic; default 0) */
-#define TC_OPT_TILE_ORDER 9    /* order of 8x8 pixel packets within a view:
+#define TC_OPT_PACKET_WIDTH 20 /* shape of the 64-pixel packet (one wave) the
+                                  one-thread-per-pixel modes cast together:
+                                  its width in pixels, 4, 8, 16 or 32 (height
+                                  64 / width; default 8).  The packet beam
+                                  bounds the packet's rays, so the shape sets
+                                  how tight its boxes are */
+#define TC_OPT_TILE_ORDER 9    /* order of the pixel packets within a view:
                                   0 row-major, 1 column-major, 2 tile rows
                                   sorted so the rows whose rays are closest
                                   to horizontal (the longest walks) start
@@ -282,18 +304,19 @@ tc_status tc_shade_views(tc_context *ctx, const tc_view *views, int32_t n,
                                     lane from the exact state the walk enters
                                     it with; the earliest run with a hit gives
                                     the record (1, 2 or 4; default 4) */
-#define TC_OPT_BEAM_PASSES 17    /* render modes 0 and 4: before walking, the
-                                    64 rays of each 8x8 pixel packet find a
+#define TC_OPT_BEAM_PASSES 17    /* render modes 0, 4 and 5: before walking,
+                                    the 64 rays of each pixel packet find a
                                     common start parameter t such that none
                                     of them meets solid in [0, t], by testing
                                     bounding boxes of the packet's ray bundle
                                     over 64 intervals at a time against the
-                                    min/max pyramid, at most this many times
-                                    (Section 3.2's skip of empty space, for a
-                                    bundle); each ray then walks exactly from
-                                    the last cell line it enters before t, so
-                                    results are unchanged (0: rays start at
-                                    the eye; 0..64, default 4) */
+                                    window levels of the min/max pyramid
+                                    (one entry per box), at most this many
+                                    times (Section 3.2's skip of empty space,
+                                    for a bundle); each ray then walks exactly
+                                    from the last cell line it enters before
+                                    t, so results are unchanged (0: rays start
+                                    at the eye; 0..64, default 6) */
 /* Render mode 3 is the paper's sampled ray march (Section 3.1, RAYMARCH),
  * not an exact cast.  Per pixel the segment from the eye ends at the far
  * limit (TC_OPT_MARCH_FAR world units along the ray) or where the ray
@@ -358,9 +381,10 @@ void tc_frame_destroy(tc_frame *frame);
  * over a grid of the render knobs -- traversal mode, start level, packet
  * order, XCD grouping, split budget (0 or 128), and the persistent queue's
  * waves per CU, refill threshold and refill interval, then the packet beam
- * passes (0, 2, 4 or 8) of the best one-thread-per-pixel setting -- then keep the
- * fastest setting on the
- * context and report it.  Results are those of tc_render_views for every
+ * passes (0, 2, 4, 6 or 8) of the best one-thread-per-pixel setting, then the
+ * packet shape (width 4, 8, 16 or 32) and the pyramid depth (TC_OPT_MAX_LEVEL:
+ * the top level, two and four below it, or 5) around the best setting --
+ * then keep the fastest setting on the context and report it.  Results are those of tc_render_views for every
  * setting (bit-identical); only the time differs.  Synchronises
  * hip_stream.  The paper picks each method's knob by a sweep on a fixed
  * fixture (Section 5.6); this tunes on the caller's workload. */
@@ -371,6 +395,8 @@ typedef struct tc_tune_result {
   int32_t tried; /* settings timed */
   int32_t split_budget;
   int32_t beam_passes;
+  int32_t packet_width; /* TC_OPT_PACKET_WIDTH */
+  int32_t max_level;    /* TC_OPT_MAX_LEVEL: the pyramid depth walks use */
 } tc_tune_result;
 tc_status tc_autotune(tc_context *ctx, const tc_view *views, int32_t n,
                       tc_hit *out_device, int32_t reps, void *hip_stream,
@@ -385,8 +411,8 @@ tc_status tc_autotune(tc_context *ctx, const tc_view *views, int32_t n,
  * in-flight budget), and admitted views are launched together, up to
  * max_batch_views per render, on one of `streams` streams, so work that
  * arrives while other batches run overlaps them on the device.  Batches use
- * the context's render mode and knobs, with the split pass of the
- * hierarchical mode off.  A view sees exactly the edits submitted before
+ * the context's render mode and knobs; the split pass of the hierarchical
+ * mode runs for batches of at most two views and is off for larger ones.  A view sees exactly the edits submitted before
  * it: the map is kept in two version buffers, and an edit is applied to the
  * buffer not holding the newest version, once no batch reads it, after that
  * buffer replays the previous edit; starting a server copies the map once
@@ -433,6 +459,10 @@ typedef struct tc_server_stats {
   uint64_t batches, edits, views, rays;
   uint64_t peak_bytes;   /* largest pool use seen */
   uint64_t bytes_in_use;
+  double queue_s;        /* sum over finished views of submission -> launch
+                            (admission, batching and the host's launch path) */
+  double run_s;          /* sum over finished views of launch -> observed
+                            completion (GPU time and completion polling) */
 } tc_server_stats;
 tc_status tc_server_get_stats(tc_server *s, tc_server_stats *out);
 /* Finish every submitted request, stop the thread and free the server. */
@@ -459,6 +489,14 @@ tc_status tc_pyramid_dims(const tc_context *ctx, int32_t level, int32_t *w,
 tc_status tc_read_pyramid(tc_context *ctx, int32_t level, uint32_t *out,
                           void *hip_stream);
 
+/* Copy window level `level` (0..levels) into host memory, row-major, dims
+ * as tc_pyramid_dims: entry (i, j) holds fmax | smin << 8 | smax << 16 over
+ * the cells of the 2^(L+1) x 2^(L+1) square whose corner is node (i, j)'s
+ * corner, clipped to the map (Section 3.2: a conservative bound of a region
+ * from the hierarchy).  The packet beam tests a box narrower than a level-L
+ * node against one entry.  Synchronises `hip_stream`. */
+tc_status tc_read_window(tc_context *ctx, int32_t level, uint32_t *out, void *hip_stream);
+
 /* Copy the occupancy masks of pyramid level `level` (1..levels) to `out`,
  * row-major, dims as tc_pyramid_dims.  Bit k of a node's mask is set iff
  * the slab interval [B, T] of some column of its 2^L x 2^L block meets the
@@ -468,6 +506,18 @@ tc_status tc_read_pyramid(tc_context *ctx, int32_t level, uint32_t *out,
  * `hip_stream`. */
 tc_status tc_read_occupancy(tc_context *ctx, int32_t level, uint64_t *out,
                             void *hip_stream);
+
+/* The voxel occupancy pyramid of render mode 5 (when TC_OPT_VOXEL_SHAPE is
+ * set): voxel counts of level `level` (0 the finest) and, if `levels` is
+ * not NULL, the number of levels.  TC_NO_MAP when there is no pyramid. */
+tc_status tc_voxel_dims(const tc_context *ctx, int32_t level, int32_t *nx, int32_t *ny,
+                        int32_t *nz, int32_t *levels);
+/* Copy voxel level `level` into host memory as one byte (0 or 1) per
+ * voxel, indexed [z][y][x] (z fastest-varying last: out[(z ny + y) nx + x]).
+ * Level 0: bit set iff a column of the voxel's footprint has solid in its
+ * closed height range; level k: the union of its eight children.
+ * Synchronises `hip_stream`. */
+tc_status tc_read_voxels(tc_context *ctx, int32_t level, uint8_t *out, void *hip_stream);
 
 /* Read and reset the counter of TC_OPT_COUNT_READS: the number of
  * pyramid nodes and cells read by all rays rendered since the last reset
@@ -485,7 +535,8 @@ tc_status tc_read_counters(tc_context *ctx, uint64_t *reads, void *hip_stream);
  * made since timing was switched on. */
 tc_status tc_read_kernel_times(tc_context *ctx, float *ms);
 
-/* Device bytes held by the map: packed columns plus every pyramid level. */
+/* Device bytes held by the map: packed columns plus every pyramid level,
+ * occupancy mask level and window level. */
 tc_status tc_map_bytes(const tc_context *ctx, uint64_t *bytes);
 
 #ifdef __cplusplus

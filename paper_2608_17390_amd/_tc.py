@@ -56,6 +56,8 @@ TC_OPT_MARCH_FAR = 16
 TC_OPT_BEAM_PASSES = 17
 TC_OPT_SPLIT_WAVES = 18
 TC_INFO_ALLOCATIONS = 19
+TC_OPT_PACKET_WIDTH = 20
+TC_OPT_VOXEL_SHAPE = 21
 TC_FACE_SAMPLED = 0
 
 _STATUS = {0: "TC_OK", -1: "TC_INVALID_ARG", -2: "TC_OUT_OF_MEMORY",
@@ -85,7 +87,8 @@ class tc_tune_result(ctypes.Structure):
                 ("persist_waves", ctypes.c_int32), ("refill_min", ctypes.c_int32),
                 ("refill_iters", ctypes.c_int32), ("ms", ctypes.c_float),
                 ("tried", ctypes.c_int32), ("split_budget", ctypes.c_int32),
-                ("beam_passes", ctypes.c_int32)]
+                ("beam_passes", ctypes.c_int32), ("packet_width", ctypes.c_int32),
+                ("max_level", ctypes.c_int32)]
 
 
 class tc_shade_params(ctypes.Structure):
@@ -98,7 +101,8 @@ class tc_shade_params(ctypes.Structure):
 class tc_server_stats(ctypes.Structure):
     _fields_ = [("batches", ctypes.c_uint64), ("edits", ctypes.c_uint64),
                 ("views", ctypes.c_uint64), ("rays", ctypes.c_uint64),
-                ("peak_bytes", ctypes.c_uint64), ("bytes_in_use", ctypes.c_uint64)]
+                ("peak_bytes", ctypes.c_uint64), ("bytes_in_use", ctypes.c_uint64),
+                ("queue_s", ctypes.c_double), ("run_s", ctypes.c_double)]
 
 
 assert ctypes.sizeof(tc_view) == 84
@@ -123,6 +127,10 @@ SIGNATURES = [
     ("tc_pyramid_dims", _I32, [_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     ("tc_read_pyramid", _I32, [_P, _I32, _P, _P]),
     ("tc_read_occupancy", _I32, [_P, _I32, _P, _P]),
+    ("tc_read_window", _I32, [_P, _I32, _P, _P]),
+    ("tc_voxel_dims", _I32, [_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                             ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    ("tc_read_voxels", _I32, [_P, _I32, _P, _P]),
     ("tc_read_counters", _I32, [_P, ctypes.POINTER(ctypes.c_uint64), _P]),
     ("tc_read_kernel_times", _I32, [_P, ctypes.POINTER(ctypes.c_float)]),
     ("tc_map_bytes", _I32, [_P, ctypes.POINTER(ctypes.c_uint64)]),
@@ -375,6 +383,31 @@ class Context:
         out = np.empty((h, w), np.uint64)
         st = load_library().tc_read_occupancy(self._h, level, out.ctypes.data,
                                               _stream_handle(stream))
+        _check(self._h, st)
+        return out
+
+    def tc_voxel_dims(self, level):
+        """(nx, ny, nz, levels) of voxel level `level`."""
+        a, b, c, n = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(self._h, load_library().tc_voxel_dims(self._h, level, ctypes.byref(a),
+                                                     ctypes.byref(b), ctypes.byref(c),
+                                                     ctypes.byref(n)))
+        return a.value, b.value, c.value, n.value
+
+    def tc_read_voxels(self, level, stream=None):
+        """Voxel level `level` as a bool array [z][y][x]."""
+        nx, ny, nz, _ = self.tc_voxel_dims(level)
+        out = np.empty((nz, ny, nx), np.uint8)
+        st = load_library().tc_read_voxels(self._h, level, out.ctypes.data,
+                                           _stream_handle(stream))
+        _check(self._h, st)
+        return out.astype(bool)
+
+    def tc_read_window(self, level, stream=None):
+        w, h = self.tc_pyramid_dims(level)
+        out = np.empty((h, w), np.uint32)
+        st = load_library().tc_read_window(self._h, level, out.ctypes.data,
+                                           _stream_handle(stream))
         _check(self._h, st)
         return out
 

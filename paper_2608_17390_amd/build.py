@@ -17,7 +17,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtc.so")
 INCLUDE = os.path.join(ROOT, "include")
 SOURCES = ["tc_map.hip", "tc_render.hip", "tc_march.hip", "tc_shade.hip", "tc_api.cpp",
-           "tc_plan.cpp", "tc_frame.cpp", "tc_server.cpp", "tc_noalloc.hip"]
+           "tc_plan.cpp", "tc_frame.cpp", "tc_server.cpp", "tc_noalloc.hip",
+           "tc_voxel.hip"]
 # per-source flags: the sampled march and the shading pass are defined one
 # IEEE single operation at a time, so nothing may be fused into a multiply-add
 EXTRA = {"tc_march.hip": ["-ffp-contract=off"], "tc_shade.hip": ["-ffp-contract=off"]}

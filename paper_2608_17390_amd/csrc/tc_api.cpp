@@ -126,6 +126,7 @@ tc_status validate_edits(tc_context* ctx, const tc_edit* edits, int32_t n,
 tc_status plan_views(tc_context* ctx, const tc_view* views, int32_t n, ViewPlan& p,
                      bool allow_split) {
   PlanOpts o;
+  o.packet_width = ctx->packet_width;
   o.render_mode = ctx->render_mode;
   o.split_budget = ctx->split_budget;
   o.split_queue = ctx->split_queue;
@@ -157,15 +158,60 @@ tci_render_opts render_opts(const tc_context* c) {
 }
 
 hipError_t enqueue_edits(const tci_map& d, uint32_t* map, const char* dev,
-                         const EditPlan& p, hipStream_t s) {
+                         const EditPlan& p, hipStream_t s, const tci_voxels* vx,
+                         uint32_t* vox) {
   hipError_t e = tci_launch_edits((const tci_edit*)(dev + p.off_edits), p.n,
                                   (const uint8_t*)(dev + p.off_patch), map, d.lv[0],
                                   d.W, d.H, p.max_w, p.max_h, s);
+  const int32_t* rects = (const int32_t*)(dev + p.off_rects);
   for (int32_t L = 1; L <= p.top && e == hipSuccess; ++L)
-    e = tci_launch_update_level(d, map, L,
-                                (const int32_t*)(dev + p.off_rects) + 4 * (size_t)(L - 1) * p.n,
-                                p.nrect[L], p.rmw[L], p.rmh[L], s);
+    e = tci_launch_update_level(d, map, L, rects + 4 * (size_t)L * p.n, p.nrect[L], p.rmw[L],
+                                p.rmh[L], s);
+  // then the window entries whose 2 x 2 node block meets an edited node
+  for (int32_t L = 0; L <= p.top && e == hipSuccess; ++L)
+    e = tci_launch_update_window(d, map, L, rects + 4 * (size_t)L * p.n, p.nrect[L],
+                                 p.rmw[L] + 1, p.rmh[L] + 1, s);
+  // and the voxel tiles over the edited cells, level by level upward
+  if (vx && vox) {
+    tci_map dm = d;
+    dm.base = map;
+    for (int32_t k = 0; k < vx->levels && e == hipSuccess; ++k)
+      e = tci_launch_voxel_level(dm, *vx, vox, k, rects, p.nrect[0], s);
+  }
   return e;
+}
+
+tc_status build_voxels(tc_context* ctx, hipStream_t s) {
+  if (ctx->vox) {
+    TC_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    (void)hipFree(ctx->vox);
+    ctx->vox = nullptr;
+    ctx->vox_words = 0;
+    ctx->vdesc = tci_voxels{};
+    ctx->map_generation++;   // frames captured with the old pyramid are stale
+  }
+  if (!ctx->vox_shape || !ctx->map) return TC_OK;
+  int32_t vl = 0, vzl = 0;
+  while ((1 << vl) < (ctx->vox_shape & 0xFF)) ++vl;
+  while ((1 << vzl) < (ctx->vox_shape >> 8)) ++vzl;
+  size_t words = 0;
+  tci_voxels vx = layout_voxels(ctx->W, ctx->H, vl, vzl, &words);
+  uint32_t* vox = nullptr;
+  TC_HIP(dev_alloc(ctx, (void**)&vox, words * 4), "hipMalloc(voxels)");
+  vx.base = vox;
+  hipError_t e = hipSuccess;
+  for (int32_t k = 0; k < vx.levels && e == hipSuccess; ++k)
+    e = tci_launch_voxel_level(ctx->desc, vx, vox, k, nullptr, 0, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    (void)hipFree(vox);
+    return hip_fail(ctx, e, "build of the voxel occupancy pyramid");
+  }
+  ctx->vox = vox;
+  ctx->vox_words = words;
+  ctx->vdesc = vx;
+  ctx->map_generation++;
+  return TC_OK;
 }
 
 hipError_t enqueue_render(tc_context* ctx, const tci_map& d, const char* dev,
@@ -217,7 +263,9 @@ hipError_t enqueue_render(tc_context* ctx, const tci_map& d, const char* dev,
     return e;
   }
   hipError_t e = mark(0);
-  if (e == hipSuccess)
+  if (e == hipSuccess && ctx->render_mode == 5)
+    e = tci_launch_render(d, dv, p.n, pre, p.npkt, out, 3, o, s, &ctx->vdesc);
+  else if (e == hipSuccess)
     e = tci_launch_render(d, dv, p.n, pre, p.npkt, out,
                           ctx->render_mode == 1 ? 1 : (ctx->render_mode == 4 ? 2 : 0), o, s);
   if (e == hipSuccess) e = mark(1);
@@ -283,6 +331,7 @@ void tc_destroy(tc_context* ctx) {
     if (s.queue) (void)hipFree(s.queue);
   }
   if (ctx->map) (void)hipFree(ctx->map);
+  if (ctx->vox) (void)hipFree(ctx->vox);
   if (ctx->d_count) (void)hipFree(ctx->d_count);
   for (hipEvent_t& e : ctx->kev)
     if (e) (void)hipEventDestroy(e);
@@ -335,6 +384,8 @@ tc_status tc_load_columns(tc_context* ctx, int32_t W, int32_t H,
     if (e == hipSuccess) e = tci_launch_repack(planes, W, H, map, d.lv[0], s);
     for (int32_t L = 1; L <= d.top && e == hipSuccess; ++L)
       e = tci_launch_build_level(d, map, L, s);
+    for (int32_t L = 0; L <= d.top && e == hipSuccess; ++L)
+      e = tci_launch_build_window(d, map, L, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(planes);
     if (e != hipSuccess) {
@@ -351,6 +402,8 @@ tc_status tc_load_columns(tc_context* ctx, int32_t W, int32_t H,
     ctx->desc = d;
     ctx->W = W;
     ctx->H = H;
+    // the voxel occupancy pyramid of the new map, if one is asked for
+    if (ctx->vox_shape || ctx->vox) return tci::build_voxels(ctx, s);
     return TC_OK;
   } catch (...) {
     return fail(ctx, TC_OUT_OF_MEMORY, "tc_load_columns: host allocation failed");
@@ -378,7 +431,9 @@ tc_status tc_apply_edit(tc_context* ctx, const tc_edit* edits, int32_t n,
     if (st) return st;
     tci::plan_edits(ctx->desc, edits, n, patch_bytes, (char*)slot->host, plan);
     hipError_t e = hipMemcpyAsync(slot->dev, slot->host, plan.total, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = tci::enqueue_edits(ctx->desc, ctx->map, (const char*)slot->dev, plan, s);
+    if (e == hipSuccess)
+      e = tci::enqueue_edits(ctx->desc, ctx->map, (const char*)slot->dev, plan, s,
+                             ctx->vox ? &ctx->vdesc : nullptr, ctx->vox);
     st = tci::release(ctx, slot, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "tc_apply_edit");
     return st;
@@ -395,6 +450,8 @@ tc_status tc_render_views(tc_context* ctx, const tc_view* views, int32_t n,
     if (!ctx->map) return fail(ctx, TC_NO_MAP, "tc_render_views: no map loaded");
     if (ctx->server) return fail(ctx, TC_INVALID_ARG, "tc_render_views: a server owns the map");
     if (!out_device) return fail(ctx, TC_INVALID_ARG, "tc_render_views: out is NULL");
+    if (ctx->render_mode == 5 && !ctx->vox)
+      return fail(ctx, TC_INVALID_ARG, "tc_render_views: render mode 5 needs TC_OPT_VOXEL_SHAPE");
     tci::ViewPlan plan;
     tc_status st = tci::plan_views(ctx, views, n, plan);
     if (st) return st;
@@ -508,9 +565,19 @@ tc_status tc_set_option(tc_context* ctx, int32_t key, int64_t value) {
   ctx->err.clear();
   switch (key) {
     case TC_OPT_RENDER_MODE:
-      if (value < 0 || value > 4) break;
+      if (value < 0 || value > 5) break;
       ctx->render_mode = (int32_t)value;
       return TC_OK;
+    case TC_OPT_VOXEL_SHAPE: {
+      const int64_t v = value & 0xFF, vz = value >> 8;
+      const bool pow2 = (v == 1 || v == 2 || v == 4 || v == 8) &&
+                        (vz == 1 || vz == 2 || vz == 4 || vz == 8);
+      if (value != 0 && !pow2) break;
+      if (ctx->server) return fail(ctx, TC_INVALID_ARG, "tc_set_option: a server owns the map");
+      if (set_device(ctx)) return TC_DEVICE_ERROR;
+      ctx->vox_shape = (int32_t)value;
+      return tci::build_voxels(ctx, nullptr);
+    }
     case TC_OPT_START_LEVEL:
       if (value < 0 || value >= TCI_MAX_LEVELS) break;
       ctx->start_level = (int32_t)value;
@@ -581,6 +648,10 @@ tc_status tc_set_option(tc_context* ctx, int32_t key, int64_t value) {
       if (value < 0 || value > 2) break;
       ctx->tile_order = (int32_t)value;
       return TC_OK;
+    case TC_OPT_PACKET_WIDTH:
+      if (value != 4 && value != 8 && value != 16 && value != 32) break;
+      ctx->packet_width = (int32_t)value;
+      return TC_OK;
     case TC_OPT_COUNT_READS:
       if (value < 0 || value > 1) break;
       if (value && !ctx->d_count) {
@@ -610,6 +681,8 @@ tc_status tc_get_option(const tc_context* ctx, int32_t key, int64_t* value) {
     case TC_OPT_REFILL_ITERS: *value = ctx->refill_iters; return TC_OK;
     case TC_OPT_COUNT_READS: *value = ctx->count_reads; return TC_OK;
     case TC_OPT_TILE_ORDER: *value = ctx->tile_order; return TC_OK;
+    case TC_OPT_PACKET_WIDTH: *value = ctx->packet_width; return TC_OK;
+    case TC_OPT_VOXEL_SHAPE: *value = ctx->vox_shape; return TC_OK;
     case TC_OPT_PRIORITY_BOOST: *value = ctx->boost; return TC_OK;
     case TC_OPT_SPLIT_BUDGET: *value = ctx->split_budget; return TC_OK;
     case TC_OPT_SPLIT_QUEUE: *value = ctx->split_queue; return TC_OK;
@@ -624,9 +697,8 @@ tc_status tc_get_option(const tc_context* ctx, int32_t key, int64_t* value) {
   }
 }
 
-static tc_status read_level_rows(tc_context* ctx, int32_t L, int32_t ty0, int32_t ty1,
+static tc_status read_level_rows(tc_context* ctx, const tci_level& l, int32_t ty0, int32_t ty1,
                                  std::vector<uint32_t>& buf, hipStream_t s) {
-  const tci_level& l = ctx->desc.lv[L];
   size_t row_words = (size_t)l.tiles_x * 64;
   size_t n = row_words * (size_t)(ty1 - ty0 + 1);
   buf.resize(n);
@@ -651,7 +723,7 @@ tc_status tc_read_columns(tc_context* ctx, int32_t x0, int32_t y0, int32_t w,
     if (st) return st;
     std::vector<uint32_t> buf;
     int32_t ty0 = y0 >> 3, ty1 = (y0 + h - 1) >> 3;
-    st = read_level_rows(ctx, 0, ty0, ty1, buf, (hipStream_t)hip_stream);
+    st = read_level_rows(ctx, ctx->desc.lv[0], ty0, ty1, buf, (hipStream_t)hip_stream);
     if (st) return st;
     tci_level l = ctx->desc.lv[0];
     l.off = 0;
@@ -697,7 +769,7 @@ tc_status tc_read_pyramid(tc_context* ctx, int32_t level, uint32_t* out, void* h
     if (st) return st;
     tci_level l = ctx->desc.lv[level];
     std::vector<uint32_t> buf;
-    st = read_level_rows(ctx, level, 0, (l.h - 1) >> 3, buf, (hipStream_t)hip_stream);
+    st = read_level_rows(ctx, l, 0, (l.h - 1) >> 3, buf, (hipStream_t)hip_stream);
     if (st) return st;
     l.off = 0;
     for (int32_t j = 0; j < l.h; ++j)
@@ -705,6 +777,73 @@ tc_status tc_read_pyramid(tc_context* ctx, int32_t level, uint32_t* out, void* h
     return TC_OK;
   } catch (...) {
     return fail(ctx, TC_OUT_OF_MEMORY, "tc_read_pyramid: host allocation failed");
+  }
+}
+
+tc_status tc_read_window(tc_context* ctx, int32_t level, uint32_t* out, void* hip_stream) {
+  if (!ctx) return TC_INVALID_ARG;
+  try {
+    ctx->err.clear();
+    if (!ctx->map) return fail(ctx, TC_NO_MAP, "tc_read_window: no map loaded");
+    if (level < 0 || level > ctx->desc.top || !out)
+      return fail(ctx, TC_INVALID_ARG, "tc_read_window: bad level %d", level);
+    tc_status st = set_device(ctx);
+    if (st) return st;
+    tci_level l = ctx->desc.wl[level];
+    std::vector<uint32_t> buf;
+    st = read_level_rows(ctx, l, 0, (l.h - 1) >> 3, buf, (hipStream_t)hip_stream);
+    if (st) return st;
+    l.off = 0;
+    for (int32_t j = 0; j < l.h; ++j)
+      for (int32_t i = 0; i < l.w; ++i) out[(size_t)j * l.w + i] = buf[tci_tile_index(l, i, j)];
+    return TC_OK;
+  } catch (...) {
+    return fail(ctx, TC_OUT_OF_MEMORY, "tc_read_window: host allocation failed");
+  }
+}
+
+tc_status tc_voxel_dims(const tc_context* ctx, int32_t level, int32_t* nx, int32_t* ny,
+                        int32_t* nz, int32_t* levels) {
+  if (!ctx || !nx || !ny || !nz) return TC_INVALID_ARG;
+  if (!ctx->vox) return TC_NO_MAP;
+  if (level < 0 || level >= ctx->vdesc.levels) return TC_INVALID_ARG;
+  const tci_vlevel& l = ctx->vdesc.lv[level];
+  *nx = l.nx;
+  *ny = l.ny;
+  *nz = l.nz;
+  if (levels) *levels = ctx->vdesc.levels;
+  return TC_OK;
+}
+
+tc_status tc_read_voxels(tc_context* ctx, int32_t level, uint8_t* out, void* hip_stream) {
+  if (!ctx) return TC_INVALID_ARG;
+  try {
+    ctx->err.clear();
+    if (!ctx->vox) return fail(ctx, TC_NO_MAP, "tc_read_voxels: no voxel occupancy pyramid");
+    if (level < 0 || level >= ctx->vdesc.levels || !out)
+      return fail(ctx, TC_INVALID_ARG, "tc_read_voxels: bad level %d", level);
+    tc_status st = set_device(ctx);
+    if (st) return st;
+    const tci_vlevel& l = ctx->vdesc.lv[level];
+    const size_t words = (size_t)l.tiles_x * l.tiles_y * l.tiles_z * 16;
+    std::vector<uint32_t> buf(words);
+    hipStream_t s = (hipStream_t)hip_stream;
+    TC_HIP(hipMemcpyAsync(buf.data(), ctx->vox + l.off, words * 4, hipMemcpyDeviceToHost, s),
+           "hipMemcpyAsync(read)");
+    TC_HIP(hipStreamSynchronize(s), "hipStreamSynchronize(read)");
+    for (int32_t z = 0; z < l.nz; ++z)
+      for (int32_t y = 0; y < l.ny; ++y)
+        for (int32_t x = 0; x < l.nx; ++x) {
+          uint32_t m = 0;
+          for (int b = 0; b < 3; ++b)
+            m |= (((uint32_t)(x >> b) & 1u) << (3 * b)) | (((uint32_t)(y >> b) & 1u) << (3 * b + 1)) |
+                 (((uint32_t)(z >> b) & 1u) << (3 * b + 2));
+          const size_t t = ((size_t)((z >> 3) * l.tiles_y + (y >> 3)) * l.tiles_x + (x >> 3)) * 16;
+          out[((size_t)z * l.ny + y) * l.nx + x] = (uint8_t)((buf[t + (m >> 5)] >> (m & 31)) & 1u);
+        }
+    return TC_OK;
+  } catch (...) {
+    return fail(ctx, TC_OUT_OF_MEMORY, "tc_read_voxels: host allocation failed");
   }
 }
 

@@ -13,10 +13,11 @@
 // their extremes are at its ends.  The box they give, widened by a margin
 // that covers the single-precision rounding, is tested against the
 // min/max pyramid: at the level whose nodes are wider than the box it
-// overlaps at most 2 x 2 nodes, and if its height range lies above every
-// node's fmax and outside every node's [smin, smax], no ray of the packet
-// meets solid during [t0, t1] (the node test of the walk, applied to a
-// bundle of rays; Section 3.2's skip of empty space).
+// overlaps at most 2 x 2 nodes, whose combine is one entry of that level's
+// window level, and if its height range lies above the entry's fmax and
+// outside its [smin, smax], no ray of the packet meets solid during
+// [t0, t1] (the node test of the walk, applied to a bundle of rays;
+// Section 3.2's skip of empty space).
 //
 // The 64 lanes test 64 consecutive intervals at once, of geometrically
 // growing length, starting at the current start; the start moves to the
@@ -36,63 +37,62 @@ constexpr float kBeamGrowth = 0.125f;        // each interval 1/8 longer than th
 constexpr float kBeamLog2Growth = 0.169925f; // log2(1 + kBeamGrowth)
 
 // Could solid lie in the box [lox, hix] x [loy, hiy] x [loz, hiz] (cells,
-// height units)?  Reads at most four nodes, counted in `reads`.  Every
-// test is evaluated and the answer combined without branches (lanes test
-// different boxes, so early returns would diverge): the loads use indices
-// clamped into the level, and the answer is the first of these that
-// applies: no claim for a box with a NaN bound (never formed from valid
-// views); clear above every height; no claim for a huge box or one wider
-// than the top level's nodes; clear beside the map; else the node test.
-__device__ __forceinline__ bool beam_box_solid(const tci_map& m, const lvl_t* lv, float lox,
-                                               float hix, float loy, float hiy, float loz,
-                                               float hiz, int32_t& reads) {
+// height units)?  With 2^L the smallest power of two above the box's
+// width and depth, the box overlaps at most two level-L nodes per axis,
+// all inside the window of the first (tci_map.wl), so one window entry
+// bounds its solid: one load, counted in `reads`.  Every test is evaluated
+// and the answer combined without branches (lanes test different boxes, so
+// early returns would diverge): the load uses an index clamped into the
+// level, and the answer is the first of these that applies: no claim for a
+// box with a NaN bound (never formed from valid views); clear above every
+// height; no claim for a huge box or one wider than the top level's nodes;
+// clear beside the map; else the window's test.  A box that starts before
+// the map's first node uses that node's window, a superset of what the box
+// overlaps.
+__device__ __forceinline__ bool beam_box_solid(const tci_map& m, const lvl_t* lv,
+                                               const uint32_t* woff, float lox, float hix,
+                                               float loy, float hiy, float loz, float hiz,
+                                               int32_t& reads) {
   const bool bad = !((lox <= hix) & (loy <= hiy) & (loz <= hiz));
   const bool above = loz > 255.0f;
   const float ext = fmaxf(hix - lox, hiy - loy);
   const bool huge = !(ext < 65536.0f);
-  // 2^L > ext: the box overlaps at most two nodes per axis at level L
-  const int32_t L = min(max(ext < 1.0f ? 0 : __builtin_amdgcn_frexp_expf(ext), 0), m.top);
-  // node coordinates, clamped far outside the map
+  // ext < 2^e (frexp's exponent), and 2^0 = 1 > ext below one cell
+  const int32_t e = ext < 1.0f ? 0 : __builtin_amdgcn_frexp_expf(ext);
+  const bool wide = e > m.top;
+  const int32_t L = min(e, m.top);
+  // the first node of each axis, clamped far outside the map
   auto node = [&](float c) {
     return (int32_t)floorf(__builtin_amdgcn_fmed3f(c, -1048576.0f, 1048576.0f)) >> L;
   };
-  const int32_t x0 = node(lox), x1 = node(hix), y0 = node(loy), y1 = node(hiy);
-  const bool wide = ((x1 - x0) > 1) | ((y1 - y0) > 1);
+  const int32_t x0 = node(lox), y0 = node(loy);
   const lvl_t l = lv[L];
-  const int32_t i0 = max(x0, 0), i1 = min(x1, l.w - 1);
-  const int32_t j0 = max(y0, 0), j1 = min(y1, l.h - 1);
-  const bool beside = (i0 > i1) | (j0 > j1);
-  // indices clamped into the level, so every lane's loads are valid
-  const int32_t ci0 = min(i0, l.w - 1), ci1 = max(i1, 0);
-  const int32_t cj0 = min(j0, l.h - 1), cj1 = max(j1, 0);
-  // tiled index (tci_tile_index) with 24-bit multiplies: tile rows and
-  // tiles per row are below 2^11
-  auto at = [&](int32_t i, int32_t j) {
-    return map_word(m.base, l.off + ((umul24((uint32_t)j >> 3, (uint32_t)l.tiles_x) +
-                                      ((uint32_t)i >> 3)) << 6) +
-                                (((uint32_t)j & 7) << 3) + ((uint32_t)i & 7));
-  };
-  const uint32_t w00 = at(ci0, cj0), w10 = at(ci1, cj0), w01 = at(ci0, cj1), w11 = at(ci1, cj1);
+  const bool beside = (hix < 0.0f) | (hiy < 0.0f) | (x0 >= l.w) | (y0 >= l.h);
+  // index clamped into the level, so every lane's load is valid; tiled
+  // index (tci_tile_index) with a 24-bit multiply: tile rows and tiles per
+  // row are below 2^11
+  const uint32_t i = (uint32_t)min(max(x0, 0), l.w - 1), j = (uint32_t)min(max(y0, 0), l.h - 1);
+  const uint32_t w = map_word(m.base, woff[L] + ((umul24(j >> 3, (uint32_t)l.tiles_x) + (i >> 3)) << 6) +
+                                          ((j & 7) << 3) + (i & 7));
   const bool test = !bad & !above & !huge & !wide & !beside;
-  reads += test ? 1 + (i1 != i0) + (j1 != j0) + ((i1 != i0) & (j1 != j0)) : 0;
-  const uint32_t fmax = max(max(w00 & 0xFF, w10 & 0xFF), max(w01 & 0xFF, w11 & 0xFF));
-  const uint32_t smin = min(min((w00 >> 8) & 0xFF, (w10 >> 8) & 0xFF),
-                            min((w01 >> 8) & 0xFF, (w11 >> 8) & 0xFF));
-  const uint32_t smax = max(max((w00 >> 16) & 0xFF, (w10 >> 16) & 0xFF),
-                            max((w01 >> 16) & 0xFF, (w11 >> 16) & 0xFF));
-  // a column with no slab has smin = smax = 0, which the floor test covers
-  const bool solid = (loz <= (float)fmax) | ((loz <= (float)smax) & (hiz >= (float)smin));
+  reads += test ? 1 : 0;
+  // a window without a slab has smin = 255 > smax = 0, which fails the
+  // slab test
+  const bool solid = (loz <= (float)(w & 0xFF)) |
+                     ((loz <= (float)((w >> 16) & 0xFF)) & (hiz >= (float)((w >> 8) & 0xFF)));
   return bad | (!above & (huge | wide | (!beside & solid)));
 }
 
 // Parameter t >= 0 such that no ray of the packet whose tile is (tx, ty)
 // meets solid during [0, t].  Called by all 64 lanes of the wave together
 // (it uses ballots); `reads` gains the nodes this lane read.
-__device__ __forceinline__ float beam_start(const tci_map& m, const lvl_t* lv, const tci_view& v,
+__device__ __forceinline__ float beam_start(const tci_map& m, const lvl_t* lv,
+                                            const uint32_t* woff, const tci_view& v,
                                             int32_t tx, int32_t ty, int32_t passes,
                                             int32_t lane, int32_t& reads) {
-  const int32_t px0 = tx * 8, py0 = ty * 8;
-  const int32_t px1 = min(px0 + 7, v.w - 1), py1 = min(py0 + 7, v.h - 1);
+  const int32_t pw = v.pw_log2, ph = 6 - pw;
+  const int32_t px0 = tx << pw, py0 = ty << ph;
+  const int32_t px1 = min(px0 + (1 << pw) - 1, v.w - 1), py1 = min(py0 + (1 << ph) - 1, v.h - 1);
   // centre and half-spans of a and b over the packet's pixels
   const uint32_t ac = px0 + px1 + 1, bc = py0 + py1 + 1;
   const float inv = 1.0f / 65536.0f;
@@ -154,7 +154,7 @@ __device__ __forceinline__ float beam_start(const tci_map& m, const lvl_t* lv, c
       hi[c] = fmaf(dt, H2[c], fmaf(t0, H1[c], H0[c]));
     }
     const bool solid =
-        beam_box_solid(m, lv, lo[0], hi[0], lo[1], hi[1], lo[2], hi[2], reads);
+        beam_box_solid(m, lv, woff, lo[0], hi[0], lo[1], hi[1], lo[2], hi[2], reads);
     const uint64_t bad = __ballot(solid);
     if (bad & 1ull) break;                         // no progress
     const int32_t k = bad ? __ffsll((unsigned long long)bad) - 1 : 63;

@@ -51,8 +51,15 @@ hipError_t host_alloc(tc_context* ctx, void** p, size_t bytes);
 // reason of a failure going to the context's error message.
 tc_status validate_edits(tc_context* ctx, const tc_edit* edits, int32_t n,
                          size_t* patch_bytes);
+// Enqueue the edits of `plan` (uploaded at dev) on the map at `map`, then
+// the dirty update of its pyramid, window levels and, if vx is given, of
+// the voxel occupancy pyramid at vox.
 hipError_t enqueue_edits(const tci_map& d, uint32_t* map, const char* dev,
-                         const EditPlan& plan, hipStream_t s);
+                         const EditPlan& plan, hipStream_t s,
+                         const tci_voxels* vx = nullptr, uint32_t* vox = nullptr);
+// (Re)build the context's voxel occupancy pyramid for its map and
+// TC_OPT_VOXEL_SHAPE (freeing it when the shape is 0); synchronises s.
+tc_status build_voxels(tc_context* ctx, hipStream_t s);
 
 tc_status plan_views(tc_context* ctx, const tc_view* views, int32_t n,
                      ViewPlan& plan, bool allow_split = true);
@@ -85,7 +92,13 @@ struct tc_context {
   uint32_t* map = nullptr;  // all levels
   size_t map_words = 0;
   tci_map desc{};
-  uint64_t map_generation = 0;  // bumped by every tc_load_columns
+  uint64_t map_generation = 0;  // bumped by every tc_load_columns (and
+                                // voxel pyramid rebuild)
+  // voxel occupancy pyramid (render mode 5), built when vox_shape != 0
+  int32_t vox_shape = 0;        // v | vz << 8 (cells, height units), 0: none
+  uint32_t* vox = nullptr;
+  size_t vox_words = 0;
+  tci_voxels vdesc{};
   // staging ring (allocated by tc_create)
   tci::Slot ring[tci::kRing];
   int ring_next = 0;
@@ -100,9 +113,10 @@ struct tc_context {
   int32_t refill_iters = 16;
   int32_t count_reads = 0;
   int32_t tile_order = 2;
+  int32_t packet_width = 8;
   int32_t boost = 0;
   int32_t split_budget = 128;
-  int32_t beam_passes = 4;
+  int32_t beam_passes = 6;
   int32_t split_waves = 4;
   int32_t split_queue = 1 << 17;
   int32_t march_steps = 128;

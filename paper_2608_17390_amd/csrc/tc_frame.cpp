@@ -8,8 +8,9 @@
 // (Section 7); a frame here batches many views and shadow passes instead.
 //
 // The autotuner times tc_render_views over a grid of the render knobs
-// (traversal mode, start level, packet order, XCD grouping, persistent
-// queue parameters) on the caller's views and keeps the fastest setting.
+// (traversal mode, start level, packet order, XCD grouping, split pass,
+// persistent queue parameters, beam passes, packet shape, pyramid depth)
+// on the caller's views and keeps the fastest setting.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -42,7 +43,7 @@ void frame_free(tc_frame* f) {
 }
 
 struct Knobs {
-  int32_t mode, start, order, remap, waves, rmin, riters, split, beam;
+  int32_t mode, start, order, remap, waves, rmin, riters, split, beam, pwidth, maxl;
 };
 
 void apply_knobs(tc_context* c, const Knobs& k) {
@@ -55,12 +56,14 @@ void apply_knobs(tc_context* c, const Knobs& k) {
   c->refill_iters = k.riters;
   c->split_budget = k.split;
   c->beam_passes = k.beam;
+  c->packet_width = k.pwidth;
+  c->max_level = k.maxl;
 }
 
 Knobs read_knobs(const tc_context* c) {
   return Knobs{c->render_mode, c->start_level, c->tile_order, c->xcd_remap,
                c->persist_waves, c->refill_min, c->refill_iters, c->split_budget,
-               c->beam_passes};
+               c->beam_passes, c->packet_width, c->max_level};
 }
 
 }  // namespace
@@ -81,6 +84,8 @@ tc_status tc_frame_create(tc_context* ctx, const tc_view* views, int32_t nviews,
     if (!ctx->map) return fail(ctx, TC_NO_MAP, "tc_frame_create: no map loaded");
     if (ctx->server) return fail(ctx, TC_INVALID_ARG, "tc_frame_create: a server owns the map");
     if (!out_device) return fail(ctx, TC_INVALID_ARG, "tc_frame_create: out is NULL");
+    if (ctx->render_mode == 5 && !ctx->vox)
+      return fail(ctx, TC_INVALID_ARG, "tc_frame_create: render mode 5 needs TC_OPT_VOXEL_SHAPE");
     tci::ViewPlan vp;
     tc_status st = tci::plan_views(ctx, views, nviews, vp);
     if (st) return st;
@@ -111,7 +116,8 @@ tc_status tc_frame_create(tc_context* ctx, const tc_view* views, int32_t nviews,
     if (e == hipSuccess) {
       hipError_t le = hipSuccess;
       if (nedits > 0)
-        le = tci::enqueue_edits(ctx->desc, ctx->map, (const char*)f->dev + off_e, ep, cs);
+        le = tci::enqueue_edits(ctx->desc, ctx->map, (const char*)f->dev + off_e, ep, cs,
+                                ctx->vox ? &ctx->vdesc : nullptr, ctx->vox);
       if (le == hipSuccess)
         le = tci::enqueue_render(ctx, ctx->desc, (const char*)f->dev, vp, out_device, cs);
       e = hipStreamEndCapture(cs, &f->graph);
@@ -177,7 +183,7 @@ tc_status tc_autotune(tc_context* ctx, const tc_view* views, int32_t n,
         for (int32_t remap : {0, 8, 64})
           for (int32_t start : {1, 2, 3, 4})
             cand.push_back(Knobs{0, start, order, remap, cur.waves, cur.rmin, cur.riters, split,
-                                 cur.beam});
+                                 cur.beam, cur.pwidth, cur.maxl});
     std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
     for (auto& e : ev) TC_HIP(hipEventCreate(&e), "hipEventCreate");
     auto time_knobs = [&](const Knobs& k, float* med) -> tc_status {
@@ -214,7 +220,8 @@ tc_status tc_autotune(tc_context* ctx, const tc_view* views, int32_t n,
       for (int32_t rmin : {8, 16, 32})
         for (int32_t riters : {16, 64}) {
           if (st) break;
-          Knobs k{2, bk.start, bk.order, bk.remap, waves, rmin, riters, bk.split, bk.beam};
+          Knobs k{2, bk.start, bk.order, bk.remap, waves, rmin, riters, bk.split, bk.beam,
+                  bk.pwidth, bk.maxl};
           float m;
           st = time_knobs(k, &m);
           if (st) break;
@@ -224,7 +231,7 @@ tc_status tc_autotune(tc_context* ctx, const tc_view* views, int32_t n,
     // the packet beam start of the one-thread-per-pixel modes, around the
     // best setting
     if (!st && bk.mode == 0)
-      for (int32_t beam : {0, 2, 4, 8}) {
+      for (int32_t beam : {0, 2, 4, 6, 8}) {
         if (beam == bk.beam) continue;
         Knobs k = bk;
         k.beam = beam;
@@ -234,6 +241,28 @@ tc_status tc_autotune(tc_context* ctx, const tc_view* views, int32_t n,
         ++tried;
         if (m < bms) { bms = m; bk = k; }
       }
+    // the packet shape (its width; height 64 / width) and the pyramid depth
+    // (the highest level a walk climbs to), each around the best setting
+    const auto try_knob = [&](Knobs k) {
+      float m;
+      st = time_knobs(k, &m);
+      if (st) return;
+      ++tried;
+      if (m < bms) { bms = m; bk = k; }
+    };
+    for (int32_t pwidth : {4, 8, 16, 32}) {
+      if (st || pwidth == bk.pwidth) continue;
+      Knobs k = bk;
+      k.pwidth = pwidth;
+      try_knob(k);
+    }
+    const int32_t top = ctx->desc.top;
+    for (int32_t maxl : {top, top - 2, top - 4, 5}) {
+      if (st || maxl < 1 || maxl == std::min(bk.maxl, top)) continue;
+      Knobs k = bk;
+      k.maxl = maxl;
+      try_knob(k);
+    }
     for (auto& e : ev) (void)hipEventDestroy(e);
     if (st) {
       apply_knobs(ctx, cur);
@@ -249,6 +278,8 @@ tc_status tc_autotune(tc_context* ctx, const tc_view* views, int32_t n,
     best->refill_iters = bk.riters;
     best->split_budget = bk.split;
     best->beam_passes = bk.beam;
+    best->packet_width = bk.pwidth;
+    best->max_level = bk.maxl;
     best->ms = bms;
     best->tried = tried;
     return TC_OK;

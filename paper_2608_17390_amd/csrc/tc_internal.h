@@ -73,13 +73,29 @@ hipError_t tci_launch_update_level(const tci_map& m, uint32_t* base,
                                    int32_t nrect, int32_t max_w,
                                    int32_t max_h, hipStream_t s);
 
+// Window level L from level L (all entries), and its entries whose node
+// block meets one of the level-L rectangles (x0, y0, x1, y1 inclusive):
+// entries x0 - 1 .. x1, y0 - 1 .. y1, the largest spanning max_w x max_h.
+hipError_t tci_launch_build_window(const tci_map& m, uint32_t* base, int32_t L,
+                                   hipStream_t s);
+hipError_t tci_launch_update_window(const tci_map& m, uint32_t* base, int32_t L,
+                                    const int32_t* rects, int32_t nrect, int32_t max_w,
+                                    int32_t max_h, hipStream_t s);
+
 // Render: views on the device, one thread per pixel.  flat: 0 the
 // hierarchical walk, 1 the flat walk, 2 the hierarchical walk with the
-// occupancy masks.
+// occupancy masks, 3 the walk over the voxel occupancy pyramid *vx.
 hipError_t tci_launch_render(const tci_map& m, const tci_view* views,
                              int32_t nviews, const int64_t* pkt_prefix,
                              int64_t npkt, void* out, int32_t flat,
-                             const tci_render_opts& o, hipStream_t s);
+                             const tci_render_opts& o, hipStream_t s,
+                             const tci_voxels* vx = nullptr);
+// Voxel occupancy pyramid level k: every word (rects null), or the words of
+// the tiles over each of the nrect clipped cell rectangles (x0, y0, x1, y1
+// inclusive) of an edit list.  Level k > 0 reads level k - 1.
+hipError_t tci_launch_voxel_level(const tci_map& m, const tci_voxels& vx, uint32_t* vox,
+                                  int32_t k, const int32_t* rects, int32_t nrect,
+                                  hipStream_t s);
 // Render: persistent waves pulling 64-ray packets from a queue counter.
 hipError_t tci_launch_render_persistent(const tci_map& m,
                                         const tci_view* views, int32_t nviews,

@@ -13,6 +13,11 @@
 // as the paper's occupancy pyramid takes the union of its children
 // (Section 3.2); it is built and updated with the node.
 //
+// Window levels (one per level, used by the packet beam's box test) hold,
+// per node, the combine of its 2 x 2 node neighbourhood on the same level;
+// they are built after the levels and, after edits, updated for the entries
+// whose neighbourhood meets an edited node.
+//
 // Edits follow Section 2 (a dirty rectangle with new heights and slab
 // metadata) and Section 4.4 (the dig crater).  Only the nodes above the
 // edited rectangles are recomputed, from the same 2x2 reduction as the full
@@ -207,6 +212,56 @@ __global__ void update_level_kernel(tci_map m, uint32_t* __restrict__ base,
   }
 }
 
+// Window entry (i, j) of level L: the combine of level-L nodes (i..i+1,
+// j..j+1) that exist (level 0: the cells, as nodes).
+__device__ inline uint32_t window_entry(const tci_map& m, const uint32_t* base, int32_t L,
+                                        int32_t i, int32_t j) {
+  const tci_level& l = m.lv[L];
+  uint32_t acc = 0u | (255u << 8);  // empty: fmax 0, smin 255, smax 0
+  #pragma unroll
+  for (int dj = 0; dj < 2; ++dj) {
+    #pragma unroll
+    for (int di = 0; di < 2; ++di) {
+      const int32_t ni = i + di, nj = j + dj;
+      if (ni < l.w && nj < l.h) {
+        const uint32_t v = base[tci_tile_index(l, ni, nj)];
+        acc = node_merge(acc, L == 0 ? cell_to_node(v) : v);
+      }
+    }
+  }
+  return acc;
+}
+
+__global__ void build_window_kernel(tci_map m, uint32_t* __restrict__ base, int32_t L) {
+  const tci_level& w = m.wl[L];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)w.tiles_x * ((w.h + 7) >> 3) * 64;
+  if (k >= total) return;
+  const int32_t tile = (int32_t)(k >> 6), e = (int32_t)(k & 63);
+  const int32_t i = (tile % w.tiles_x) * 8 + (e & 7);
+  const int32_t j = (tile / w.tiles_x) * 8 + (e >> 3);
+  base[w.off + k] = (i < w.w && j < w.h) ? window_entry(m, base, L, i, j) : 0u;
+}
+
+// grid.x = rectangle index: entries x0 - 1 .. x1, y0 - 1 .. y1 (clipped to
+// the level) of the level-L rectangle, the entries whose 2 x 2 node block
+// meets it.
+__global__ void update_window_kernel(tci_map m, uint32_t* __restrict__ base, int32_t L,
+                                     const int32_t* __restrict__ rects) {
+  const int32_t* r = rects + 4 * blockIdx.x;
+  const tci_level& w = m.wl[L];
+  const int32_t x0 = max(r[0] - 1, 0), y0 = max(r[1] - 1, 0);
+  const int32_t x1 = min(r[2], w.w - 1), y1 = min(r[3], w.h - 1);
+  if (x0 > x1 || y0 > y1) return;
+  const int32_t rw = x1 - x0 + 1;
+  const int64_t n = (int64_t)rw * (y1 - y0 + 1);
+  for (int64_t k = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.y * blockDim.x) {
+    const int32_t i = x0 + (int32_t)(k % rw), j = y0 + (int32_t)(k / rw);
+    base[tci_tile_index(w, i, j)] = window_entry(m, base, L, i, j);
+  }
+}
+
 __global__ void zero_u64_kernel(uint64_t* p, int32_t n) {
   int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) p[k] = 0;
@@ -258,6 +313,24 @@ hipError_t tci_launch_update_level(const tci_map& m, uint32_t* base,
   int32_t gy = blocks_for((int64_t)max_w * max_h, 256, 64);
   hipLaunchKernelGGL(update_level_kernel, dim3(nrect, gy), dim3(256), 0, s, m,
                      base, L, rects);
+  return hipGetLastError();
+}
+
+hipError_t tci_launch_build_window(const tci_map& m, uint32_t* base, int32_t L,
+                                   hipStream_t s) {
+  const tci_level& w = m.wl[L];
+  const int64_t words = (int64_t)w.tiles_x * ((w.h + 7) >> 3) * 64;
+  const int32_t blocks = blocks_for(words, 256, 1 << 30);
+  hipLaunchKernelGGL(build_window_kernel, dim3(blocks), dim3(256), 0, s, m, base, L);
+  return hipGetLastError();
+}
+
+hipError_t tci_launch_update_window(const tci_map& m, uint32_t* base, int32_t L,
+                                    const int32_t* rects, int32_t nrect, int32_t max_w,
+                                    int32_t max_h, hipStream_t s) {
+  if (nrect <= 0) return hipSuccess;
+  const int32_t gy = blocks_for((int64_t)max_w * max_h, 256, 64);
+  hipLaunchKernelGGL(update_window_kernel, dim3(nrect, gy), dim3(256), 0, s, m, base, L, rects);
   return hipGetLastError();
 }
 

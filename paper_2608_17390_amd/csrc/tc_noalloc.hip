@@ -69,6 +69,9 @@ extern "C" tc_status tc_render_views_noalloc(tc_context* ctx, const tc_view* vie
       return tci::fail(ctx, TC_INVALID_ARG, "tc_render_views_noalloc: a server owns the map");
     if (!out_device)
       return tci::fail(ctx, TC_INVALID_ARG, "tc_render_views_noalloc: out is NULL");
+    if (ctx->render_mode == 5 && !ctx->vox)
+      return tci::fail(ctx, TC_INVALID_ARG,
+                       "tc_render_views_noalloc: render mode 5 needs TC_OPT_VOXEL_SHAPE");
     tci::ViewPlan plan;
     tc_status st = tci::plan_views(ctx, views, n, plan);
     if (st) return st;

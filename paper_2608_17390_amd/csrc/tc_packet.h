@@ -17,9 +17,10 @@ __device__ __forceinline__ int32_t find_view(const int64_t* pkt_prefix,
   return lo;
 }
 
-// Tile (8x8 pixel block) of packet `t` of a view; packets run row-major
-// (order 0), column-major (order 1) or by the view's tile-row table (order
-// 2).  A view holds fewer than 2^22 packets, so 32-bit arithmetic suffices.
+// Tile (the packet's block of 2^pw_log2 x 2^(6 - pw_log2) pixels) of packet
+// `t` of a view; packets run row-major (order 0), column-major (order 1) or
+// by the view's tile-row table (order 2).  A view holds at most about 2^22
+// packets, so 32-bit arithmetic suffices.
 __device__ __forceinline__ void packet_tile(const tci_view& v, int64_t t64,
                                             int32_t order, const int32_t* rows,
                                             int32_t& tx, int32_t& ty) {
@@ -28,7 +29,8 @@ __device__ __forceinline__ void packet_tile(const tci_view& v, int64_t t64,
     tx = (int32_t)(t % (uint32_t)v.tiles_x);
     ty = rows[v.rows_off + t / (uint32_t)v.tiles_x];
   } else if (order == 1) {
-    const uint32_t tiles_y = (uint32_t)(v.h + 7) >> 3;
+    const int32_t ph = 6 - v.pw_log2;
+    const uint32_t tiles_y = (uint32_t)(v.h + (1 << ph) - 1) >> ph;
     tx = (int32_t)(t / tiles_y);
     ty = (int32_t)(t % tiles_y);
   } else {
@@ -37,15 +39,16 @@ __device__ __forceinline__ void packet_tile(const tci_view& v, int64_t t64,
   }
 }
 
-// Pixel of ray `k` (0..63, row-major in the 8x8 block) of packet `t`.
+// Pixel of ray `k` (0..63, row-major in the packet's block) of packet `t`.
 __device__ __forceinline__ void packet_pixel(const tci_view& v, int64_t t,
                                              int32_t k, int32_t order,
                                              const int32_t* rows,
                                              int32_t& px, int32_t& py) {
   int32_t tx, ty;
   packet_tile(v, t, order, rows, tx, ty);
-  px = tx * 8 + (k & 7);
-  py = ty * 8 + (k >> 3);
+  const int32_t pw = v.pw_log2;
+  px = (tx << pw) + (k & ((1 << pw) - 1));
+  py = (ty << (6 - pw)) + (k >> pw);
 }
 
 // Logical block of hardware block b.  Consecutive hardware blocks go to

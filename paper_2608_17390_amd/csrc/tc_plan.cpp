@@ -77,8 +77,48 @@ tci_map layout_map(int32_t W, int32_t H, size_t* words_out) {
     k.off = (uint32_t)words;
     words += (size_t)k.tiles_x * ((k.h + 7) >> 3) * 128;
   }
+  // window levels 0..top after the masks, one word an entry, tiled like
+  // the level they summarise
+  for (int32_t L = 0; L < TCI_MAX_LEVELS; ++L) {
+    tci_level& k = d.wl[L];
+    k = tci_level{0, 0, 0, 0};
+    if (L > d.top) continue;
+    k = d.lv[L];
+    k.off = (uint32_t)words;
+    words += (size_t)k.tiles_x * ((k.h + 7) >> 3) * 64;
+  }
   *words_out = words;
   return d;
+}
+
+tci_voxels layout_voxels(int32_t W, int32_t H, int32_t v_log2, int32_t vz_log2,
+                         size_t* words_out) {
+  tci_voxels x{};
+  x.v_log2 = v_log2;
+  x.vz_log2 = vz_log2;
+  int32_t nx = (int32_t)(((int64_t)W + (1 << v_log2) - 1) >> v_log2);
+  int32_t ny = (int32_t)(((int64_t)H + (1 << v_log2) - 1) >> v_log2);
+  int32_t nz = 256 >> vz_log2;
+  size_t words = 0;
+  int32_t k = 0;
+  for (;; ++k) {
+    tci_vlevel& l = x.lv[k];
+    l.nx = nx;
+    l.ny = ny;
+    l.nz = nz;
+    l.tiles_x = (nx + 7) >> 3;
+    l.tiles_y = (ny + 7) >> 3;
+    l.tiles_z = (nz + 7) >> 3;
+    l.off = (uint32_t)words;
+    words += (size_t)l.tiles_x * l.tiles_y * l.tiles_z * 16;
+    if ((nx == 1 && ny == 1 && nz == 1) || k == TCI_MAX_LEVELS - 1) break;
+    nx = (nx + 1) >> 1;
+    ny = (ny + 1) >> 1;
+    nz = (nz + 1) >> 1;
+  }
+  x.levels = k + 1;
+  *words_out = words;
+  return x;
 }
 
 tc_status check_edits(const tc_edit* edits, int32_t n, size_t* patch_bytes,
@@ -122,7 +162,7 @@ void plan_edits(const tci_map& d, const tc_edit* edits, int32_t n,
   p.top = top;
   p.off_edits = 0;
   p.off_rects = (sizeof(tci_edit) * (size_t)n + 15) & ~(size_t)15;
-  p.off_patch = p.off_rects + sizeof(int32_t) * 4 * (size_t)n * (size_t)std::max(top, 1);
+  p.off_patch = p.off_rects + sizeof(int32_t) * 4 * (size_t)n * (size_t)(top + 1);
   p.total = p.off_patch + patch_bytes;
   p.nrect.assign(top + 1, 0);
   p.rmw.assign(top + 1, 1);
@@ -158,9 +198,12 @@ void plan_edits(const tci_map& d, const tc_edit* edits, int32_t n,
     if (x0 >= x1 || y0 >= y1) continue;
     p.max_w = std::max(p.max_w, x1 - x0);
     p.max_h = std::max(p.max_h, y1 - y0);
-    for (int32_t L = 1; L <= top; ++L) {
+    // the rectangle on every level, cells (level 0) included: the dirty
+    // update of the pyramid reads levels 1..top, that of the window levels
+    // all of them
+    for (int32_t L = 0; L <= top; ++L) {
       int32_t r[4] = {x0 >> L, y0 >> L, (x1 - 1) >> L, (y1 - 1) >> L};
-      if (hr) memcpy(hr + 4 * ((size_t)(L - 1) * n + p.nrect[L]), r, sizeof(r));
+      if (hr) memcpy(hr + 4 * ((size_t)L * n + p.nrect[L]), r, sizeof(r));
       p.rmw[L] = std::max(p.rmw[L], r[2] - r[0] + 1);
       p.rmh[L] = std::max(p.rmh[L], r[3] - r[1] + 1);
       p.nrect[L]++;
@@ -200,7 +243,11 @@ tc_status make_view_plan(const PlanOpts& opt, const tc_view* views, int32_t n, V
       o.o0[c] = v.o0[c]; o.opx[c] = v.o_px[c]; o.opy[c] = v.o_py[c];
       o.d0[c] = v.d0[c]; o.dpx[c] = v.d_px[c]; o.dpy[c] = v.d_py[c];
     }
-    o.tiles_x = (v.width + 7) >> 3;
+    const int32_t pw = opt.packet_width == 4 ? 2 : opt.packet_width == 16 ? 4
+                     : opt.packet_width == 32 ? 5 : 3;
+    const int32_t ph = 6 - pw;
+    o.pw_log2 = pw;
+    o.tiles_x = (int32_t)(((int64_t)v.width + (1 << pw) - 1) >> pw);
     o.small_steps = 1;
     for (int c = 0; c < 3; ++c)
       for (int32_t st : {v.o_px[c], v.o_py[c], v.d_px[c], v.d_py[c]})
@@ -212,11 +259,12 @@ tc_status make_view_plan(const PlanOpts& opt, const tc_view* views, int32_t n, V
     // near-horizontal rays take the longest walks, so their packets start
     // first and do not trail the launch
     {
-      const int32_t ty_n = (v.height + 7) >> 3;
+      const int32_t ty_n = (int32_t)(((int64_t)v.height + (1 << ph) - 1) >> ph);
       std::vector<std::pair<double, int32_t>> key((size_t)ty_n);
       const int64_t a = v.width;  // 2 * (width / 2) + 1, rounded
       for (int32_t ty = 0; ty < ty_n; ++ty) {
-        const int64_t b = 2 * (int64_t)std::min(ty * 8 + 4, v.height - 1) + 1;
+        const int64_t b =
+            2 * (int64_t)std::min((ty << ph) + (1 << (ph - 1)), v.height - 1) + 1;
         const double dx = (double)v.d0[0] + (double)a * v.d_px[0] + (double)b * v.d_py[0];
         const double dy = (double)v.d0[1] + (double)a * v.d_px[1] + (double)b * v.d_py[1];
         const double dz = (double)v.d0[2] + (double)a * v.d_px[2] + (double)b * v.d_py[2];
@@ -230,7 +278,7 @@ tc_status make_view_plan(const PlanOpts& opt, const tc_view* views, int32_t n, V
     }
     p.prefix[i] = pk;
     out += (int64_t)v.width * v.height;
-    pk += (int64_t)o.tiles_x * ((v.height + 7) >> 3);
+    pk += (int64_t)o.tiles_x * (((int64_t)v.height + (1 << ph) - 1) >> ph);
   }
   p.prefix[n] = pk;
   if (out > ((int64_t)1 << 31))

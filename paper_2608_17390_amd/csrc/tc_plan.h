@@ -33,12 +33,44 @@ struct tci_level {
 // a ray whose height range over the node meets no set band passes between
 // the slabs.  Stored in the same allocation after the pyramid, tiled 8 x 8
 // like the levels, two 32-bit words (low, high) per node.
+//
+// Window levels: for every level L = 0..top, entry (i, j) holds fmax, smin
+// and smax over the cells of the 2^(L+1) square whose corner is node
+// (i, j)'s, i.e. the combine of level-L nodes (i..i+1, j..j+1) that exist.
+// A box narrower than a level-L node overlaps at most two nodes per axis,
+// all inside the window of the first, so the packet beam tests a box with
+// one load.  Same dimensions and tiling as level L, one word an entry,
+// stored after the masks.
 struct tci_map {
   const uint32_t* base;           // all levels, one allocation
   tci_level lv[TCI_MAX_LEVELS];
   tci_level mk[TCI_MAX_LEVELS];   // occupancy mask levels 1..top (off in words)
+  tci_level wl[TCI_MAX_LEVELS];   // window levels 0..top (off in words)
   int32_t W, H;
   int32_t top;                    // highest stored level (0 if none)
+};
+
+// The voxel occupancy pyramid of the voxel-accelerated march (Section 3.2):
+// voxels of 2^v_log2 x 2^v_log2 cells by 2^vz_log2 height units; a bit of
+// the finest level (k = 0) is set when a column of the voxel's footprint has
+// solid in its closed height range, and each higher level is the union of
+// its eight children, up to a single voxel.  Every level is stored in
+// Morton-ordered 8 x 8 x 8 tiles of 512 bits (16 words): tile (tx, ty, tz)
+// at word off + ((tz * tiles_y + ty) * tiles_x + tx) * 16, voxel (x, y, z)
+// of the tile at bit m = x0 | y0 << 1 | z0 << 2 | x1 << 3 | y1 << 4 | z1 << 5
+// | x2 << 6 | y2 << 7 | z2 << 8 (the bits of x & 7, y & 7, z & 7
+// interleaved) of the tile, i.e. bit m & 31 of word m >> 5.  One allocation,
+// apart from the map.
+struct tci_vlevel {
+  uint32_t off;                 // word offset of the level
+  int32_t nx, ny, nz;           // voxels per axis
+  int32_t tiles_x, tiles_y, tiles_z;
+};
+struct tci_voxels {
+  const uint32_t* base;
+  int32_t v_log2, vz_log2;      // voxel footprint and height, as powers of two
+  int32_t levels;               // levels 0 .. levels - 1
+  tci_vlevel lv[TCI_MAX_LEVELS];
 };
 
 // Device copy of a view plus the first ray index of the view and the
@@ -47,9 +79,11 @@ struct tci_view {
   int32_t w, h;
   int32_t o0[3], opx[3], opy[3];
   int32_t d0[3], dpx[3], dpy[3];
-  int32_t tiles_x;     // ceil(w / 8)
+  int32_t tiles_x;     // packets per row of packets: ceil(w / packet width)
   int32_t small_steps; // every per-pixel step (opx, opy, dpx, dpy) below 2^22
                        // in magnitude: twice one is a 24-bit operand
+  int32_t pw_log2;     // log2 of the packet width in pixels (2..5); a packet
+                       // (one wave) is 2^pw_log2 x 2^(6 - pw_log2) pixels
   int64_t out_base;    // first output record of the view
   int64_t pkt_base;    // first 8x8 packet of the view
   int64_t rows_off;    // packet order 2: offset of the view's tile-row
@@ -70,8 +104,9 @@ namespace tci {
 // Bytes of one split queue entry (view, pixel, first line, 0).
 constexpr size_t kQueueEntry = 16;
 
-// Layout of an uploaded edit list: descriptors, per-level node rectangles
-// of the dirty update, and SET patch bytes.
+// Layout of an uploaded edit list: descriptors, the clipped rectangle of
+// every edit on every level 0..top (level L's at rects + 4 (L n + k)), and
+// SET patch bytes.
 struct EditPlan {
   int32_t n = 0;
   int32_t top = 0;
@@ -95,6 +130,7 @@ struct ViewPlan {
 
 // The render knobs a view plan depends on.
 struct PlanOpts {
+  int32_t packet_width = 8;    // pixels across a 64-pixel packet: 4, 8, 16 or 32
   int32_t render_mode = 0;
   int32_t split_budget = 0;
   int32_t split_queue = 0;
@@ -107,11 +143,15 @@ struct PlanOpts {
 bool columns_valid(const uint8_t* F, const uint8_t* B, const uint8_t* T, int32_t w,
                    int32_t h, size_t stride, int32_t* bad_x, int32_t* bad_y);
 
+// Level layout of the voxel occupancy pyramid of a W x H map (base null);
+// *words receives the size of its allocation in 32-bit words.
+tci_voxels layout_voxels(int32_t W, int32_t H, int32_t v_log2, int32_t vz_log2, size_t* words);
+
 // Highest pyramid level of a W x H map: ceil(log2(max(W, H))).
 int32_t top_level(int32_t W, int32_t H);
 
-// Level layout of a W x H map (cells, pyramid levels 1..top, then the
-// occupancy masks of levels 1..top); base is left null.  *words receives
+// Level layout of a W x H map (cells, pyramid levels 1..top, the occupancy
+// masks of levels 1..top, then the window levels 0..top); base is left null.  *words receives
 // the size of the allocation in 32-bit words.
 tci_map layout_map(int32_t W, int32_t H, size_t* words);
 

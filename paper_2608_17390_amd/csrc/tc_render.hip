@@ -19,19 +19,21 @@ __device__ __forceinline__ int32_t lane_now() {
   return (int32_t)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 }
 
-// One thread per pixel; a wave casts one 8x8 pixel packet.
+// One thread per pixel; a wave casts one packet of 64 pixels.
 // kOcc: node tests also consult the occupancy masks (render mode 4).
+// kVox: nodes above the cells are tested against the voxel occupancy
+// pyramid *vx instead (render mode 5, the voxel-accelerated march).
 // kCount: the launch counts the nodes and cells its rays read (o.count);
 // the production instance keeps no counter through the walk.
-template <bool kFlat, bool kOcc, bool kCount>
+template <bool kFlat, bool kOcc, bool kCount, bool kVox = false>
 __device__ __forceinline__ void render_body(
     const tci_map& m, const tci_view* __restrict__ views, int32_t nviews,
     const int64_t* __restrict__ pkt_prefix, int64_t npkt, void* out,
-    const tci_render_opts& o) {
+    const tci_render_opts& o, const tci_voxels* vx = nullptr) {
   __shared__ lvl_t lv[TCI_MAX_LEVELS];
+  __shared__ uint32_t woff[TCI_MAX_LEVELS];
   __shared__ uint32_t moff[kOcc ? TCI_MAX_LEVELS : 1];
-  if constexpr (kOcc) load_levels_occ(m, lv, moff);
-  else load_levels(m, lv);
+  load_levels_beam(m, lv, woff, kOcc ? moff : nullptr);
   // XCD-aware order: hand each XCD a contiguous range of packets to share
   // its L2
   const int64_t b = tcp::xcd_block(blockIdx.x, gridDim.x, o.xcd_remap);
@@ -46,12 +48,13 @@ __device__ __forceinline__ void render_body(
   tcp::packet_tile(v, p - v.pkt_base, o.tile_order, o.rows, tx, ty);
   tx = __builtin_amdgcn_readfirstlane(tx);
   ty = __builtin_amdgcn_readfirstlane(ty);
-  const int32_t px = tx * 8 + (lane & 7), py = ty * 8 + (lane >> 3);
+  const int32_t pw = v.pw_log2;
+  const int32_t px = (tx << pw) + (lane & ((1 << pw) - 1)), py = (ty << (6 - pw)) + (lane >> pw);
   // the packet's common start (all 64 lanes take part)
   float t_start = 0.0f;
   int32_t beam_reads = 0;
   if (!kFlat && o.beam_passes > 0)
-    t_start = beam_start(m, lv, v, tx, ty, o.beam_passes, lane, beam_reads);
+    t_start = beam_start(m, lv, woff, v, tx, ty, o.beam_passes, lane, beam_reads);
   if (px >= v.w || py >= v.h) {
     if (kCount && beam_reads) atomicAdd(o.count, (unsigned long long)beam_reads);
     return;
@@ -83,11 +86,11 @@ __device__ __forceinline__ void render_body(
       // without a split pass) kIterCap + 1 iterations
       const int32_t budget = split ? o.split_budget : kIterCap + 1;
       if (down)
-        st = walk_steps<false, kOcc, false, 1>(m, lv, r, k, s, Lmax, budget, col, boost, 0, 0,
-                                               0, moff, kCount);
+        st = walk_steps<false, kOcc, false, 1, kVox>(m, lv, r, k, s, Lmax, budget, col, boost,
+                                                     0, 0, 0, moff, kCount, vx);
       else
-        st = walk_steps<false, kOcc, false, 2>(m, lv, r, k, s, Lmax, budget, col, boost, 0, 0,
-                                               0, moff, kCount);
+        st = walk_steps<false, kOcc, false, 2, kVox>(m, lv, r, k, s, Lmax, budget, col, boost,
+                                                     0, 0, 0, moff, kCount, vx);
       if (!split) break;
       split = false;
       // long walks go to the split pass, as many as the queue holds
@@ -127,9 +130,10 @@ __device__ __forceinline__ void render_body(
     finish(r, s, m.W, st, col, word, depth);
     if (kCount) atomicAdd(o.count, (unsigned long long)s.reads);
   }
-  const int32_t ql = lane_now();
-  tcp::store_hit(out, v.out_base + (int64_t)(ty * 8 + (ql >> 3)) * v.w + tx * 8 + (ql & 7), word,
-                 depth);
+  const int32_t ql = lane_now(), qw = v.pw_log2;
+  tcp::store_hit(out, v.out_base + (int64_t)((ty << (6 - qw)) + (ql >> qw)) * v.w + (tx << qw) +
+                          (ql & ((1 << qw) - 1)),
+                 word, depth);
 }
 
 // The three one-thread-per-pixel kernels, each with and without read
@@ -159,6 +163,14 @@ void render_occ_kernel(tci_map m, const tci_view* __restrict__ views, int32_t nv
                        const int64_t* __restrict__ pkt_prefix, int64_t npkt, void* out,
                        tci_render_opts o) {
   render_body<false, true, kCount>(m, views, nviews, pkt_prefix, npkt, out, o);
+}
+
+template <bool kCount>
+__global__ __launch_bounds__(64 * kPackets)
+void render_vox_kernel(tci_map m, const tci_view* __restrict__ views, int32_t nviews,
+                       const int64_t* __restrict__ pkt_prefix, int64_t npkt, void* out,
+                       tci_render_opts o, tci_voxels vx) {
+  render_body<false, false, kCount, true>(m, views, nviews, pkt_prefix, npkt, out, o, &vx);
 }
 
 // Dominant-axis cell line where the ray leaves the map's columns, or rises
@@ -388,10 +400,18 @@ __global__ __launch_bounds__(256) void render_persistent_kernel(
 hipError_t tci_launch_render(const tci_map& m, const tci_view* views,
                              int32_t nviews, const int64_t* pkt_prefix,
                              int64_t npkt, void* out, int32_t flat,
-                             const tci_render_opts& o, hipStream_t s) {
+                             const tci_render_opts& o, hipStream_t s,
+                             const tci_voxels* vx) {
   int64_t blocks = (npkt + kPackets - 1) / kPackets;
   if (blocks < 1) return hipSuccess;
   const bool c = o.count != nullptr;
+  if (flat == 3) {
+    if (!vx) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(c ? render_vox_kernel<true> : render_vox_kernel<false>,
+                       dim3((uint32_t)blocks), dim3(64 * kPackets), 0, s, m, views, nviews,
+                       pkt_prefix, npkt, out, o, *vx);
+    return hipGetLastError();
+  }
   auto kern = flat == 1 ? (c ? render_flat_kernel<true> : render_flat_kernel<false>)
             : flat == 2 ? (c ? render_occ_kernel<true> : render_occ_kernel<false>)
                         : (c ? render_hier_kernel<true> : render_hier_kernel<false>);

@@ -17,11 +17,15 @@
 //    batches of later views wait for that stream's event.  Every edit is
 //    thus applied twice, once per buffer, and no map is ever copied.  A
 //    view's result is the same alone and in any mix.
-//  * batches run the render mode and options of the context, except that
-//    the split pass of the hierarchical mode is off;
-//  * wake-up: submissions signal the server thread, which sleeps only when
-//    nothing is queued or in flight, and polls completions while work is
-//    on the device.
+//  * batches run the render mode and options of the context; the split
+//    pass of the hierarchical mode runs for batches of at most two views
+//    (a lone large view's longest rays then finish in parallel, as in
+//    tc_render_views) and is off for larger ones (there the second launch
+//    costs more latency than the long walks it shortens);
+//  * wake-up: submissions signal the server thread; it polls while work is
+//    queued or on the device, keeps polling for a short while after the
+//    last activity (so a request arriving soon after does not wait for a
+//    thread wake-up), and only then sleeps until the next signal.
 //
 // Section 2 of the paper: edits are gameplay operations whose results must
 // be visible without reloading; Section 7: its frames are submitted and
@@ -66,9 +70,15 @@ struct Request {
   size_t pool_off = 0;
   bool has_mem = false;
   int32_t state = kQueued;
-  double t_submit = 0, t_done = 0;
+  double t_submit = 0, t_launch = 0, t_done = 0;
   int64_t rays = 0;
 };
+
+// Batches of at most this many views run the split pass.
+constexpr size_t kSplitMaxViews = 2;
+// After the last activity the server thread keeps polling this long
+// before it sleeps.
+constexpr double kSpinSeconds = 200e-6;
 
 // First-fit allocator over [0, size) with 256-byte granules.
 class Pool {
@@ -172,6 +182,7 @@ struct tc_server {
   // statistics
   std::atomic<uint64_t> st_batches{0}, st_edits{0}, st_views{0}, st_rays{0};
   std::atomic<uint64_t> st_peak_bytes{0};
+  double st_queue_s = 0, st_run_s = 0;    // sums over finished views (under mu)
 };
 
 namespace {
@@ -202,6 +213,8 @@ void complete(tc_server* s, const std::vector<uint64_t>& ids, double t) {
     if (!r.is_edit) {
       s->st_views++;
       s->st_rays += (uint64_t)r.rays;
+      s->st_queue_s += r.t_launch - r.t_submit;
+      s->st_run_s += t - r.t_launch;
       if ((s->flags & TC_SERVER_AUTO_RELEASE) && r.has_mem) {
         s->pool.release(r.pool_off, r.bytes);
         r.has_mem = false;
@@ -222,6 +235,7 @@ bool launch_batch(tc_server* s) {
   tc_context* ctx = s->ctx;
   std::vector<tc_view> views;
   std::vector<size_t> offs;
+  const double t = now_s();
   {
     std::lock_guard<std::mutex> g(s->mu);
     for (uint64_t id : s->admitted) {
@@ -229,21 +243,24 @@ bool launch_batch(tc_server* s) {
       views.push_back(r.view);
       offs.push_back(r.pool_off);
       r.state = kInFlight;
+      r.t_launch = t;
     }
   }
-  // batches run without the split pass: under concurrent requests its
-  // second launch costs more latency than the long walks it shortens
+  // the split pass for small batches only (see the header); its queue is
+  // the slot's device-only buffer
   tci::ViewPlan plan;
-  if (tci::plan_views(ctx, views.data(), (int32_t)views.size(), plan, false) != TC_OK) {
+  const bool split = views.size() <= kSplitMaxViews;
+  if (tci::plan_views(ctx, views.data(), (int32_t)views.size(), plan, split) != TC_OK) {
     set_error(s, hipErrorInvalidValue, "server: view validation");
     return true;
   }
   for (size_t i = 0; i < views.size(); ++i) plan.views[i].out_base = (int64_t)(offs[i] / 8);
-  if (b->slot.cap < plan.total) {
+  plan.qcap = std::min<uint32_t>(plan.qcap, b->slot.qcap);
+  if (b->slot.cap < plan.off_queue) {
     if (b->slot.host) (void)hipHostFree(b->slot.host);
     if (b->slot.dev) (void)hipFree(b->slot.dev);
     b->slot.host = b->slot.dev = nullptr;
-    size_t cap = std::max<size_t>(plan.total, tci::kSlotBytes);
+    size_t cap = std::max<size_t>(plan.off_queue, tci::kSlotBytes);
     hipError_t e = tci::host_alloc(ctx, &b->slot.host, cap);
     if (e == hipSuccess) e = tci::dev_alloc(ctx, &b->slot.dev, cap);
     if (e != hipSuccess) {
@@ -260,7 +277,7 @@ bool launch_batch(tc_server* s) {
                        b->stream);
   if (e == hipSuccess)
     e = tci::enqueue_render(ctx, version_desc(s, v), (const char*)b->slot.dev, plan,
-                            s->pool_dev, b->stream, nullptr, nullptr, true);
+                            s->pool_dev, b->stream, nullptr, nullptr, true, b->slot.queue);
   if (e == hipSuccess) e = hipEventRecord(b->done, b->stream);
   if (e != hipSuccess) {
     set_error(s, e, "server: render launch");
@@ -377,6 +394,7 @@ void poll_completions(tc_server* s) {
 
 void server_loop(tc_server* s) {
   (void)hipSetDevice(s->ctx->device);
+  double last_active = now_s();
   while (true) {
     {
       std::lock_guard<std::mutex> g(s->mu);
@@ -431,15 +449,20 @@ void server_loop(tc_server* s) {
     }
     bool busy = !s->edits_in_flight.empty();
     for (Batch& b : s->slots) busy |= b.busy;
-    if (idle && !busy) {
+    if (!idle || busy) {
+      last_active = now_s();
+      std::this_thread::yield();
+    } else if (now_s() - last_active < kSpinSeconds) {
+      // just went idle: keep polling the submission queue for a while
+      if (s->stop.load()) break;
+      std::this_thread::yield();
+    } else {
       if (s->stop.load()) break;
       // sleep until a submission or stop (the timeout only bounds a missed
       // signal)
       std::unique_lock<std::mutex> g(s->mu);
       s->cv_work.wait_for(g, std::chrono::milliseconds(2),
                           [s] { return !s->incoming.empty() || s->stop.load(); });
-    } else {
-      std::this_thread::yield();
     }
   }
   // drain the device before leaving
@@ -458,6 +481,7 @@ void server_free(tc_server* s) {
     if (b.done) (void)hipEventDestroy(b.done);
     if (b.slot.host) (void)hipHostFree(b.slot.host);
     if (b.slot.dev) (void)hipFree(b.slot.dev);
+    if (b.slot.queue) (void)hipFree(b.slot.queue);
   }
   for (auto& f : s->edits_in_flight) (void)hipEventDestroy(f.second);
   for (EditUpload& u : s->uploads) {
@@ -485,6 +509,10 @@ tc_status tc_server_start(tc_context* ctx, uint64_t budget_bytes, int32_t max_ba
   ctx->err.clear();
   if (!ctx->map) return fail(ctx, TC_NO_MAP, "tc_server_start: no map loaded");
   if (ctx->server) return fail(ctx, TC_INVALID_ARG, "tc_server_start: a server is running");
+  if (ctx->render_mode == 5 || ctx->vox)
+    return fail(ctx, TC_INVALID_ARG,
+                "tc_server_start: the voxel occupancy pyramid is not kept per map version; "
+                "set TC_OPT_VOXEL_SHAPE to 0 first");
   if (budget_bytes < 4096 || budget_bytes > ((uint64_t)1 << 40))
     return fail(ctx, TC_INVALID_ARG, "tc_server_start: bad budget");
   if (max_batch_views < 1 || max_batch_views > 4096 || streams < 1 || streams > 16)
@@ -522,6 +550,10 @@ tc_status tc_server_start(tc_context* ctx, uint64_t budget_bytes, int32_t max_ba
     if (e == hipSuccess) e = tci::host_alloc(ctx, &b.slot.host, tci::kSlotBytes);
     if (e == hipSuccess) e = tci::dev_alloc(ctx, &b.slot.dev, tci::kSlotBytes);
     if (e == hipSuccess) b.slot.cap = tci::kSlotBytes;
+    if (e == hipSuccess)
+      e = tci::dev_alloc(ctx, (void**)&b.slot.queue,
+                         tci::kQueueEntry * (size_t)ctx->split_queue);
+    if (e == hipSuccess) b.slot.qcap = (uint32_t)ctx->split_queue;
   }
   for (EditUpload& u : s->uploads) {
     if (e == hipSuccess) e = tci::host_alloc(ctx, &u.slot.host, tci::kSlotBytes);
@@ -699,6 +731,8 @@ tc_status tc_server_get_stats(tc_server* s, tc_server_stats* out) {
   out->peak_bytes = s->st_peak_bytes.load();
   std::lock_guard<std::mutex> g(s->mu);
   out->bytes_in_use = s->pool.used();
+  out->queue_s = s->st_queue_s;
+  out->run_s = s->st_run_s;
   return TC_OK;
 }
 

@@ -203,17 +203,20 @@ __device__ __forceinline__ void pixel_ray(const tci_view& v, int32_t px,
   r.ay = (uint32_t)(r.Dy < 0 ? -r.Dy : r.Dy);
 }
 
-// The same ray for the pixel of lane `lane` in the 8 x 8 packet of tile
-// (tx, ty), all of whose lanes call it together (tx, ty wave-uniform): the
-// ray of the packet's first pixel is wave-uniform (scalar arithmetic), and a
-// lane adds (lane & 7) and (lane >> 3) times twice the view's per-pixel
-// steps, one 24-bit multiply-add each when the view's steps are small (the
-// usual case; v.small_steps).  kDir false: the origin only.
+// The same ray for the pixel of lane `lane` in the packet of tile (tx, ty)
+// (2^pw x 2^(6 - pw) pixels, pw = v.pw_log2), all of whose lanes call it
+// together (tx, ty wave-uniform): the ray of the packet's first pixel is
+// wave-uniform (scalar arithmetic), and a lane adds its column
+// (lane & (2^pw - 1)) and row (lane >> pw) in the packet times twice the
+// view's per-pixel steps, one 24-bit multiply-add each when the view's
+// steps are small (the usual case; v.small_steps).  kDir false: the origin
+// only.
 template <bool kDir = true>
 __device__ __forceinline__ void packet_ray(const tci_view& v, int32_t tx, int32_t ty,
                                            int32_t lane, ray_t& r) {
-  const uint32_t a0 = 16 * (uint32_t)tx + 1, b0 = 16 * (uint32_t)ty + 1;
-  const int32_t lx = lane & 7, ly = lane >> 3;
+  const int32_t pw = v.pw_log2;
+  const uint32_t a0 = ((uint32_t)tx << (pw + 1)) + 1, b0 = ((uint32_t)ty << (7 - pw)) + 1;
+  const int32_t lx = lane & ((1 << pw) - 1), ly = lane >> pw;
   int32_t o[6];
   auto base = [&](int32_t c0, int32_t ca, int32_t cb) {
     return (int32_t)((uint32_t)c0 + a0 * (uint32_t)ca + b0 * (uint32_t)cb);
@@ -449,6 +452,46 @@ __device__ __forceinline__ int32_t far_index(int32_t n, int32_t L, int32_t f, in
   return __mul24(s, (n + f) << L) + off;
 }
 
+// Does voxel column (X, Y) of level k of the voxel occupancy pyramid hold a
+// set bit over heights [zl, zh]?  The heights are float estimates of the
+// ray's exact range over the column, already widened to cover their
+// rounding; both ends are clipped into the pyramid's heights, so a range
+// partly or wholly below height 0 tests the first voxel, which every
+// in-map column's floor (unbounded below) sets, and a range wholly above
+// the top (z > 256) holds nothing.
+// Per 8-voxel tile in z, the column's eight bits sit in four words (two
+// 64-bit loads): in-tile Morton index x0 y0 z0 x1 y1 | z1 x2 y2 z2 puts
+// z0 in the bit and z1, z2 in the word.  `reads` counts the loads.
+__device__ __forceinline__ bool voxel_range(const tci_voxels& vx, int32_t k, int32_t X,
+                                            int32_t Y, float zl, float zh, int32_t& reads) {
+  const tci_vlevel& l = vx.lv[k];
+  const float inv = __builtin_amdgcn_ldexpf(1.0f, -(vx.vz_log2 + k));
+  const int32_t z0 = max((int32_t)floorf(fmaxf(zl, -1.0f) * inv), 0);
+  const int32_t z1 = min(max((int32_t)floorf(fmaxf(fminf(zh, 1.0e6f), -1.0f) * inv), 0),
+                         l.nz - 1);
+  if (z0 > z1) return false;
+  const uint32_t x = (uint32_t)X & 7, y = (uint32_t)Y & 7;
+  const uint32_t wb = ((x >> 2) << 1) | ((y >> 2) << 2);
+  const uint32_t sh = (x & 1) | ((y & 1) << 1) | (((x >> 1) & 1) << 3) | (((y >> 1) & 1) << 4);
+  const uint32_t* col = vx.base + l.off +
+                        (uint32_t)(((Y >> 3) * l.tiles_x + (X >> 3)) << 4) + wb;
+  const uint32_t zstride = (uint32_t)(l.tiles_y * l.tiles_x) << 4;
+  for (int32_t tz = z0 >> 3; tz <= (z1 >> 3); ++tz) {
+    const uint32_t* t = col + (uint32_t)tz * zstride;
+    const uint2 a = *reinterpret_cast<const uint2*>(t);
+    const uint2 b = *reinterpret_cast<const uint2*>(t + 8);
+    reads += 2;
+    const uint32_t bits = ((a.x >> sh) & 1u) | (((a.x >> (sh + 4)) & 1u) << 1) |
+                          (((a.y >> sh) & 1u) << 2) | (((a.y >> (sh + 4)) & 1u) << 3) |
+                          (((b.x >> sh) & 1u) << 4) | (((b.x >> (sh + 4)) & 1u) << 5) |
+                          (((b.y >> sh) & 1u) << 6) | (((b.y >> (sh + 4)) & 1u) << 7);
+    const int32_t lo = max(z0 - tz * 8, 0), hi = min(z1 - tz * 8, 7);
+    const uint32_t want = ((2u << hi) - 1u) & ~((1u << lo) - 1u);
+    if (bits & want) return true;
+  }
+  return false;
+}
+
 // Advance the walk by up to `budget` iterations.  Returns kWalking if the
 // budget ran out, else the final state; on kHitCell, `col` holds the
 // column of the current cell (s.ni, s.nj at level 0).  k holds the ray's
@@ -471,7 +514,15 @@ __device__ __forceinline__ int32_t far_index(int32_t n, int32_t L, int32_t f, in
 // kDir fixes the sign of the ray's vertical direction for callers that know
 // it for every lane of the wave (1: Dz < 0, 2: Dz >= 0; 0: read it per ray),
 // so the loop carries no per-lane selects on it.
-template <bool kSeg = false, bool kOcc = false, bool kCap = true, int kDir = 0>
+// With kVox (the voxel-accelerated march, Section 3.2), nodes above the
+// cells are tested against the voxel occupancy pyramid *vx instead of the
+// min/max pyramid: a node of level L >= the voxels' footprint level Lv is
+// voxel column (ni, nj) of voxel level L - Lv, empty over the ray's height
+// range over the node (widened by two units to cover the rounding of its
+// float estimate) or not; nodes below Lv are always descended (the leaf
+// voxel's cells are then tested exactly, one by one).
+template <bool kSeg = false, bool kOcc = false, bool kCap = true, int kDir = 0,
+          bool kVox = false>
 __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
                                               const ray_t& r, const walk_idx_t& k, walk_t& s,
                                               int32_t max_level, int32_t budget,
@@ -479,7 +530,8 @@ __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
                                               int32_t seg_axis = 0,
                                               int32_t seg_lo = 0, int32_t seg_hi = 0,
                                               const uint32_t* moff = nullptr,
-                                              bool count = true) {
+                                              bool count = true,
+                                              const tci_voxels* vx = nullptr) {
   const bool desc = kDir == 1 ? true : (kDir == 2 ? false : r.Dz < 0);
   const bool fx = r.Dx > 0, fy = r.Dy > 0;
   const int32_t sx = fx ? 1 : -1, sy = fy ? 1 : -1;
@@ -502,8 +554,8 @@ __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
     const lvl_t l = lv[L];
     const bool inmap = ((uint32_t)s.ni < (uint32_t)l.w) & ((uint32_t)s.nj < (uint32_t)l.h);
     uint32_t v = 0;
-    if (count) s.reads += inmap ? 1 : 0;
-    if (inmap)
+    if (count) s.reads += (inmap & (!kVox | (L == 0))) ? 1 : 0;
+    if (inmap & (!kVox | (L == 0)))
       v = map_word(m.base, l.off + ((umul24((uint32_t)s.nj >> 3, (uint32_t)l.tiles_x) +
                                      ((uint32_t)s.ni >> 3)) << 6) +
                                ((s.nj & 7) << 3) + (s.ni & 7));
@@ -540,6 +592,19 @@ __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
           const int32_t kh = min(max((int32_t)floorf(zh * 0.25f), 0), 63);
           const uint64_t range = (~0ull >> (63 - kh)) & (~0ull << kl);
           occ = (mask & range) != 0;
+        }
+      }
+      if constexpr (kVox) {
+        if (L > 0) {
+          const int32_t Lv = vx->v_log2;
+          occ = true;
+          if (L >= Lv) {
+            const float zl = (float)lo / (float)Dlo - 2.0f;
+            const float zh = (float)hi / (float)Dhi + 2.0f;
+            int32_t vr = 0;
+            occ = voxel_range(*vx, L - Lv, s.ni, s.nj, zl, zh, vr);
+            if (count) s.reads += vr;
+          }
         }
       }
     }
@@ -606,12 +671,15 @@ __device__ __forceinline__ void load_levels(const tci_map& m, lvl_t* lv) {
   __syncthreads();
 }
 
-// Level table plus the occupancy mask levels' word offsets.
-__device__ __forceinline__ void load_levels_occ(const tci_map& m, lvl_t* lv, uint32_t* moff) {
+// Level table plus the window levels' word offsets (woff) and, if moff is
+// given, the occupancy mask levels' word offsets.
+__device__ __forceinline__ void load_levels_beam(const tci_map& m, lvl_t* lv, uint32_t* woff,
+                                                 uint32_t* moff) {
   if (threadIdx.x < TCI_MAX_LEVELS) {
     const tci_level& l = m.lv[threadIdx.x];
     lv[threadIdx.x] = lvl_t{l.off, l.w, l.h, l.tiles_x};
-    moff[threadIdx.x] = m.mk[threadIdx.x].off;
+    woff[threadIdx.x] = m.wl[threadIdx.x].off;
+    if (moff) moff[threadIdx.x] = m.mk[threadIdx.x].off;
   }
   __syncthreads();
 }

@@ -9,7 +9,8 @@ OPTS = {"render_mode": _tc.TC_OPT_RENDER_MODE, "start_level": _tc.TC_OPT_START_L
         "tile_order": _tc.TC_OPT_TILE_ORDER, "xcd_remap": _tc.TC_OPT_XCD_REMAP,
         "persist_waves": _tc.TC_OPT_PERSIST_WAVES, "refill_min": _tc.TC_OPT_REFILL_MIN,
         "refill_iters": _tc.TC_OPT_REFILL_ITERS, "split_budget": _tc.TC_OPT_SPLIT_BUDGET,
-        "beam_passes": _tc.TC_OPT_BEAM_PASSES}
+        "beam_passes": _tc.TC_OPT_BEAM_PASSES, "packet_width": _tc.TC_OPT_PACKET_WIDTH,
+        "max_level": _tc.TC_OPT_MAX_LEVEL}
 
 
 def default_cache_path():

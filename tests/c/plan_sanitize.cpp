@@ -141,6 +141,11 @@ void check_map_layout(int32_t W, int32_t H) {
     CHECK(k.off == end, "layout mask level %d offset", L);
     end = k.off + (size_t)k.tiles_x * ((k.h + 7) >> 3) * 128;
   }
+  for (int32_t L = 0; L <= d.top; ++L) {
+    const tci_level& k = d.wl[L];
+    CHECK(k.off == end && k.w == d.lv[L].w && k.h == d.lv[L].h, "layout window level %d", L);
+    end = k.off + (size_t)k.tiles_x * ((k.h + 7) >> 3) * 64;
+  }
   CHECK(end == words, "layout %dx%d: %zu words planned, %zu used", W, H, words, end);
   CHECK(words < ((size_t)1 << 30), "layout %dx%d: byte offsets beyond 32 bits", W, H);
 }
@@ -242,9 +247,9 @@ int main(int argc, char** argv) {
         tci::plan_edits(d, e.data(), n, pb, host.data(), p);
         CHECK(p.total == sized.total && p.off_patch + pb == p.total, "edit plan sizes");
         const int32_t* r = reinterpret_cast<const int32_t*>(host.data() + p.off_rects);
-        for (int32_t L = 1; L <= d.top; ++L) {
+        for (int32_t L = 0; L <= d.top; ++L) {
           for (int32_t k = 0; k < p.nrect[L]; ++k) {
-            const int32_t* q = r + 4 * ((size_t)(L - 1) * n + k);
+            const int32_t* q = r + 4 * ((size_t)L * n + k);
             CHECK(q[0] >= 0 && q[1] >= 0 && q[0] <= q[2] && q[1] <= q[3] &&
                       q[2] < d.lv[L].w && q[3] < d.lv[L].h,
                   "edit rectangle outside level %d", L);

@@ -40,7 +40,7 @@ def render(ctx, views, passes, mode=0, start=2):
         torch.cuda.synchronize()
     finally:
         ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, 0)
-        ctx.tc_set_option(tc.TC_OPT_BEAM_PASSES, 4)
+        ctx.tc_set_option(tc.TC_OPT_BEAM_PASSES, 6)
         ctx.tc_set_option(tc.TC_OPT_START_LEVEL, 2)
     return tc.split_hits(out)
 
@@ -208,7 +208,7 @@ def test_option_range(ctx):
     for bad in (-1, 65):
         with pytest.raises(tc.TCError):
             ctx.tc_set_option(tc.TC_OPT_BEAM_PASSES, bad)
-    assert ctx.tc_get_option(tc.TC_OPT_BEAM_PASSES) == 4
+    assert ctx.tc_get_option(tc.TC_OPT_BEAM_PASSES) == 6
     for bad in (0, 3, 8):
         with pytest.raises(tc.TCError):
             ctx.tc_set_option(tc.TC_OPT_SPLIT_WAVES, bad)

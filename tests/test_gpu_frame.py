@@ -59,9 +59,11 @@ def test_frame_replays_apply_edits_each_time(ctx, mode):
     levels = ctx.tc_pyramid_info()
     for L in range(1, levels + 1):
         assert np.array_equal(ctx.tc_read_pyramid(L), oracle.pyramid_level_fast(Fk, Bk, Tk, L))
+    for L in range(0, levels + 1):
+        assert np.array_equal(ctx.tc_read_window(L), oracle.window_level_fast(Fk, Bk, Tk, L))
     frame.close()
     ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, 0)
-    ctx.tc_set_option(tc.TC_OPT_BEAM_PASSES, 4)
+    ctx.tc_set_option(tc.TC_OPT_BEAM_PASSES, 6)
 
 
 def test_frame_without_edits_and_reload_invalidates(ctx):
@@ -94,8 +96,11 @@ def test_autotune_keeps_results(ctx):
     assert best["render_mode"] in (0, 2)
     assert best["split_budget"] in (0, 128)
     assert ctx.tc_get_option(tc.TC_OPT_SPLIT_BUDGET) == best["split_budget"]
-    assert best["beam_passes"] in (0, 2, 4, 8)
+    assert best["beam_passes"] in (0, 2, 4, 6, 8)
     assert ctx.tc_get_option(tc.TC_OPT_BEAM_PASSES) == best["beam_passes"]
+    assert best["packet_width"] in (4, 8, 16, 32)
+    assert ctx.tc_get_option(tc.TC_OPT_PACKET_WIDTH) == best["packet_width"]
+    assert ctx.tc_get_option(tc.TC_OPT_MAX_LEVEL) == best["max_level"]
     assert ctx.tc_get_option(tc.TC_OPT_RENDER_MODE) == best["render_mode"]
     out2 = tc.render(ctx, views)
     torch.cuda.synchronize()
@@ -106,6 +111,9 @@ def test_autotune_keeps_results(ctx):
     ctx.tc_set_option(tc.TC_OPT_TILE_ORDER, 2)
     ctx.tc_set_option(tc.TC_OPT_XCD_REMAP, 64)
     ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 128)
+    ctx.tc_set_option(tc.TC_OPT_PACKET_WIDTH, 8)
+    ctx.tc_set_option(tc.TC_OPT_MAX_LEVEL, 15)
+    ctx.tc_set_option(tc.TC_OPT_BEAM_PASSES, 6)
 
 
 # Render knobs of the configuration-4 frame: the set the autotuner picks on

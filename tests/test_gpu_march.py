@@ -188,7 +188,7 @@ def test_kernel_timing_and_option_checks(ctx):
         ctx.tc_set_option(tc.TC_OPT_KERNEL_TIMING, 0)
     for key, bad in ((tc.TC_OPT_MARCH_STEPS, 0), (tc.TC_OPT_MARCH_STEPS, 65537),
                      (tc.TC_OPT_MARCH_BISECT, -1), (tc.TC_OPT_MARCH_BISECT, 65),
-                     (tc.TC_OPT_MARCH_FAR, 0), (tc.TC_OPT_RENDER_MODE, 5)):
+                     (tc.TC_OPT_MARCH_FAR, 0), (tc.TC_OPT_RENDER_MODE, 6)):
         with pytest.raises(tc.TCError) as e:
             ctx.tc_set_option(key, bad)
         assert e.value.status == tc.TC_INVALID_ARG

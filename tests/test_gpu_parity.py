@@ -18,8 +18,8 @@ pytestmark = pytest.mark.gpu
 S = 65536
 # (render mode, packet beam passes): the hierarchical modes run with the
 # beam start (the default) and without it
-MODES = {"hier": (0, 4), "hier_nobeam": (0, 0), "flat": (1, 0), "persistent": (2, 0),
-         "occupancy": (4, 4)}
+MODES = {"hier": (0, 6), "hier_nobeam": (0, 0), "flat": (1, 0), "persistent": (2, 0),
+         "occupancy": (4, 6)}
 DEPTH_RTOL = 1e-5
 
 
@@ -36,7 +36,7 @@ def gpu_render(ctx, views, mode="hier"):
     ctx.tc_set_option(tc.TC_OPT_BEAM_PASSES, MODES[mode][1])
     out = tc.render(ctx, views)
     torch.cuda.synchronize()
-    ctx.tc_set_option(tc.TC_OPT_BEAM_PASSES, 4)
+    ctx.tc_set_option(tc.TC_OPT_BEAM_PASSES, 6)
     return tc.split_hits(out)
 
 
@@ -233,6 +233,35 @@ def test_packet_orders_and_xcd_groups(ctx):
     ctx.tc_set_option(tc.TC_OPT_XCD_REMAP, 64)
 
 
+@pytest.mark.parametrize("width", [4, 16, 32])
+def test_packet_widths(ctx, width):
+    """Packets of 4x16, 16x4 and 32x2 pixels (one wave each): every mode,
+    every packet order, ragged views (partial packets on both axes), the
+    packet beam on, and the c2 image, against the oracle."""
+    F, B, T = synth.make_map_from_config(1)
+    load(ctx, F, B, T)
+    rng = np.random.default_rng(30 + width)
+    views = _random_views(rng, F, B, 12, [(77, 53), (1, 1), (130, 9), (8, 300), (33, 3), (64, 64)])
+    wo, do = oracle.render(F, B, T, views)
+    ctx.tc_set_option(tc.TC_OPT_PACKET_WIDTH, width)
+    try:
+        for order in (0, 1, 2):
+            ctx.tc_set_option(tc.TC_OPT_TILE_ORDER, order)
+            for mode in MODES:
+                wg, dg = gpu_render(ctx, views, mode)
+                assert_parity(wg, dg, wo, do, "width %d order %d %s" % (width, order, mode))
+        ctx.tc_set_option(tc.TC_OPT_TILE_ORDER, 2)
+        F, B, T = synth.make_map_from_config(2)
+        load(ctx, F, B, T)
+        views = synth.config_views(2, F, B)
+        wo, do = oracle.render(F, B, T, views)
+        wg, dg = gpu_render(ctx, views, "hier")
+        assert_parity(wg, dg, wo, do, "c2 width %d" % width)
+    finally:
+        ctx.tc_set_option(tc.TC_OPT_PACKET_WIDTH, 8)
+        ctx.tc_set_option(tc.TC_OPT_TILE_ORDER, 2)
+
+
 @pytest.mark.parametrize("budget,queue,waves", [(1, 1 << 20, 4), (5, 1 << 20, 1), (5, 1 << 20, 2),
                                                (1, 7, 2), (30, 1000, 4)])
 def test_split_pass(ctx, budget, queue, waves):
@@ -419,6 +448,8 @@ def test_pyramid_matches_definition(ctx, shape):
     for L in range(1, levels + 1):
         assert np.array_equal(ctx.tc_read_pyramid(L), oracle.pyramid_level_fast(F, B, T, L)), L
         assert np.array_equal(ctx.tc_read_occupancy(L), oracle.occupancy_level(F, B, T, L)), L
+    for L in range(0, levels + 1):
+        assert np.array_equal(ctx.tc_read_window(L), oracle.window_level_fast(F, B, T, L)), L
     f2, b2, t2 = ctx.tc_read_columns(0, 0, W, H)
     assert np.array_equal(f2, F) and np.array_equal(b2, B) and np.array_equal(t2, T)
 
@@ -436,12 +467,16 @@ def _edited_checks(ctx, F, B, T, edits, views, oracle_result=None):
     levels = ctx.tc_pyramid_info()
     pyr_edit = [ctx.tc_read_pyramid(L) for L in range(1, levels + 1)]
     occ_edit = [ctx.tc_read_occupancy(L) for L in range(1, levels + 1)]
+    win_edit = [ctx.tc_read_window(L) for L in range(0, levels + 1)]
     res_edit = {m: gpu_render(ctx, views, m) for m in ("hier", "persistent", "occupancy")}
     load(ctx, F2, B2, T2)
     for L in range(1, levels + 1):
         assert np.array_equal(ctx.tc_read_pyramid(L), pyr_edit[L - 1]), L
         assert np.array_equal(ctx.tc_read_occupancy(L), occ_edit[L - 1]), L
         assert np.array_equal(occ_edit[L - 1], oracle.occupancy_level(F2, B2, T2, L)), L
+    for L in range(0, levels + 1):
+        assert np.array_equal(ctx.tc_read_window(L), win_edit[L]), L
+        assert np.array_equal(win_edit[L], oracle.window_level_fast(F2, B2, T2, L)), L
     w_fresh, d_fresh = gpu_render(ctx, views, "hier")
     for m, (w, d) in res_edit.items():
         assert np.array_equal(w, w_fresh), m

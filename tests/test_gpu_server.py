@@ -99,6 +99,9 @@ def test_mixed_stream_matches_epochs(ctx, mode, batch, streams):
     for L in range(1, ctx.tc_pyramid_info() + 1):
         assert np.array_equal(ctx.tc_read_pyramid(L),
                               oracle.pyramid_level_fast(final[0], final[1], final[2], L))
+    for L in range(0, ctx.tc_pyramid_info() + 1):
+        assert np.array_equal(ctx.tc_read_window(L),
+                              oracle.window_level_fast(final[0], final[1], final[2], L))
 
 
 def test_back_to_back_edits_replay(ctx):

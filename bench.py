@@ -659,18 +659,24 @@ def main():
                      # HBM bytes per traversal (FETCH_SIZE + WRITE_SIZE, copy-calibrated)
                      "traffic": traffic,
                      "traffic_gb_per_s": (traffic / (kavg * 1e-3) / 1e9) if traffic else None,
-                     # the roof that binds: share of the first pass's lifetime the
-                     # SIMDs spend issuing VALU instructions (SQ_INSTS_VALU x 4
-                     # cycles over 1024 SIMDs x GRBM_GUI_ACTIVE per XCD)
-                     "valu_busy_frac": profile_value(RENDER_SRCS, "render_c2_counters",
-                                                     "valu_busy_frac"),
-                     # the counters' verdict: the first pass is bound by VALU issue, not
-                     # by HBM (bytes are the scope table's algorithmic measure)
-                     "binding_roof": "valu_issue",
+                     # VALU issue against the ALU roof (one wave64 VALU instruction per
+                     # SIMD every 2 cycles: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz):
+                     # SQ_INSTS_VALU over 1024 SIMDs x GRBM_GUI_ACTIVE per XCD x 0.5
+                     "valu_issue_frac": profile_value(RENDER_SRCS, "render_c2_counters",
+                                                      "valu_issue_frac"),
                      # share of lanes active per VALU instruction (SQ_THREAD_CYCLES_VALU
-                     # over 64 x SQ_ACTIVE_INST_VALU)
+                     # over 64 x SQ_INSTS_VALU)
                      "valu_lane_util": profile_value(RENDER_SRCS, "render_c2_counters",
                                                      "valu_lane_util"),
+                     # share of the launch's lifetime its shader engines hold waves
+                     # (SQ_BUSY_CYCLES over 32 engines x GRBM_GUI_ACTIVE per XCD)
+                     "sq_busy_frac": profile_value(RENDER_SRCS, "render_c2_counters",
+                                                   "sq_busy_frac"),
+                     # the counters' verdict: neither HBM (measured traffic a fifth of the
+                     # algorithmic bytes, far below peak) nor VALU issue binds; each walk
+                     # step waits on the load of the step before, and the launch's tail
+                     # (its longest packets) leaves engines idle
+                     "binding_roof": "load_latency",
                      "kernel": KERNEL_NAMES[args.mode],
                      "alg_bytes_per_launch": alg_bytes,
                      "kernel_ms_avg": kavg,

@@ -410,7 +410,9 @@ tc_status tc_autotune(tc_context *ctx, const tc_view *views, int32_t n,
  * admitted once its hit buffer fits in a device pool of budget_bytes (the
  * in-flight budget), and admitted views are launched together, up to
  * max_batch_views per render, on one of `streams` streams, so work that
- * arrives while other batches run overlaps them on the device.  Batches use
+ * arrives while other batches run overlaps them on the device (a batch
+ * starts beside one in flight once at least two views wait; a lone view
+ * waits for the batch in flight, as in a FIFO).  Batches use
  * the context's render mode and knobs; the split pass of the hierarchical
  * mode runs for batches of at most two views and is off for larger ones.  A view sees exactly the edits submitted before
  * it: the map is kept in two version buffers, and an edit is applied to the

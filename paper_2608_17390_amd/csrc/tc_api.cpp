@@ -164,13 +164,16 @@ hipError_t enqueue_edits(const tci_map& d, uint32_t* map, const char* dev,
                                   (const uint8_t*)(dev + p.off_patch), map, d.lv[0],
                                   d.W, d.H, p.max_w, p.max_h, s);
   const int32_t* rects = (const int32_t*)(dev + p.off_rects);
+  // level by level upward: the dirty nodes of level L and, in the same
+  // launch, the window entries of level L - 1 whose 2 x 2 node block meets
+  // an edited node; then the top level's window entries
   for (int32_t L = 1; L <= p.top && e == hipSuccess; ++L)
-    e = tci_launch_update_level(d, map, L, rects + 4 * (size_t)L * p.n, p.nrect[L], p.rmw[L],
-                                p.rmh[L], s);
-  // then the window entries whose 2 x 2 node block meets an edited node
-  for (int32_t L = 0; L <= p.top && e == hipSuccess; ++L)
-    e = tci_launch_update_window(d, map, L, rects + 4 * (size_t)L * p.n, p.nrect[L],
-                                 p.rmw[L] + 1, p.rmh[L] + 1, s);
+    e = tci_launch_update_level_window(d, map, L, rects + 4 * (size_t)L * p.n, p.nrect[L],
+                                       p.rmw[L], p.rmh[L], rects + 4 * (size_t)(L - 1) * p.n,
+                                       p.nrect[L - 1], p.rmw[L - 1] + 1, p.rmh[L - 1] + 1, s);
+  if (e == hipSuccess)
+    e = tci_launch_update_window(d, map, p.top, rects + 4 * (size_t)p.top * p.n, p.nrect[p.top],
+                                 p.rmw[p.top] + 1, p.rmh[p.top] + 1, s);
   // and the voxel tiles over the edited cells, level by level upward
   if (vx && vox) {
     tci_map dm = d;

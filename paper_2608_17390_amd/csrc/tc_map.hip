@@ -196,22 +196,6 @@ __global__ void edits_kernel(const tci_edit* __restrict__ edits, int32_t n,
   }
 }
 
-// grid.x = rectangle index; threads stride over that rectangle's nodes.
-__global__ void update_level_kernel(tci_map m, uint32_t* __restrict__ base,
-                                    int32_t L, const int32_t* __restrict__ rects) {
-  const int32_t* r = rects + 4 * blockIdx.x;
-  int32_t x0 = r[0], y0 = r[1], x1 = r[2], y1 = r[3];
-  int32_t rw = x1 - x0 + 1;
-  int64_t nodes = (int64_t)rw * (y1 - y0 + 1);
-  const tci_level& l = m.lv[L];
-  for (int64_t k = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; k < nodes;
-       k += (int64_t)gridDim.y * blockDim.x) {
-    int32_t i = x0 + (int32_t)(k % rw), j = y0 + (int32_t)(k / rw);
-    base[tci_tile_index(l, i, j)] = reduce_node(m, base, L, i, j);
-    store_mask(m, base, L, i, j, reduce_mask(m, base, L, i, j));
-  }
-}
-
 // Window entry (i, j) of level L: the combine of level-L nodes (i..i+1,
 // j..j+1) that exist (level 0: the cells, as nodes).
 __device__ inline uint32_t window_entry(const tci_map& m, const uint32_t* base, int32_t L,
@@ -262,6 +246,42 @@ __global__ void update_window_kernel(tci_map m, uint32_t* __restrict__ base, int
   }
 }
 
+// One launch per level after edits: blocks [0, nL) recompute the dirty
+// nodes of level L from level L - 1 (one edit rectangle each), blocks
+// [nL, nL + nW) the dirty window entries of level L - 1 (the same
+// rectangles one level down).  Both read only level L - 1, which the
+// launch before this one finished, and they write different arrays, so
+// the two jobs need no ordering between them.
+__global__ void update_level_window_kernel(tci_map m, uint32_t* __restrict__ base, int32_t L,
+                                           const int32_t* __restrict__ rects_l, int32_t nl,
+                                           const int32_t* __restrict__ rects_w) {
+  if ((int32_t)blockIdx.x < nl) {
+    const int32_t* r = rects_l + 4 * blockIdx.x;
+    const int32_t x0 = r[0], y0 = r[1], rw = r[2] - x0 + 1;
+    const int64_t nodes = (int64_t)rw * (r[3] - y0 + 1);
+    const tci_level& l = m.lv[L];
+    for (int64_t k = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; k < nodes;
+         k += (int64_t)gridDim.y * blockDim.x) {
+      const int32_t i = x0 + (int32_t)(k % rw), j = y0 + (int32_t)(k / rw);
+      base[tci_tile_index(l, i, j)] = reduce_node(m, base, L, i, j);
+      store_mask(m, base, L, i, j, reduce_mask(m, base, L, i, j));
+    }
+    return;
+  }
+  const int32_t* r = rects_w + 4 * (blockIdx.x - nl);
+  const tci_level& w = m.wl[L - 1];
+  const int32_t x0 = max(r[0] - 1, 0), y0 = max(r[1] - 1, 0);
+  const int32_t x1 = min(r[2], w.w - 1), y1 = min(r[3], w.h - 1);
+  if (x0 > x1 || y0 > y1) return;
+  const int32_t rw = x1 - x0 + 1;
+  const int64_t n = (int64_t)rw * (y1 - y0 + 1);
+  for (int64_t k = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.y * blockDim.x) {
+    const int32_t i = x0 + (int32_t)(k % rw), j = y0 + (int32_t)(k / rw);
+    base[tci_tile_index(w, i, j)] = window_entry(m, base, L - 1, i, j);
+  }
+}
+
 __global__ void zero_u64_kernel(uint64_t* p, int32_t n) {
   int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) p[k] = 0;
@@ -305,17 +325,6 @@ hipError_t tci_launch_edits(const tci_edit* edits, int32_t n,
   return hipGetLastError();
 }
 
-hipError_t tci_launch_update_level(const tci_map& m, uint32_t* base,
-                                   int32_t L, const int32_t* rects,
-                                   int32_t nrect, int32_t max_w,
-                                   int32_t max_h, hipStream_t s) {
-  if (nrect <= 0) return hipSuccess;
-  int32_t gy = blocks_for((int64_t)max_w * max_h, 256, 64);
-  hipLaunchKernelGGL(update_level_kernel, dim3(nrect, gy), dim3(256), 0, s, m,
-                     base, L, rects);
-  return hipGetLastError();
-}
-
 hipError_t tci_launch_build_window(const tci_map& m, uint32_t* base, int32_t L,
                                    hipStream_t s) {
   const tci_level& w = m.wl[L];
@@ -331,6 +340,17 @@ hipError_t tci_launch_update_window(const tci_map& m, uint32_t* base, int32_t L,
   if (nrect <= 0) return hipSuccess;
   const int32_t gy = blocks_for((int64_t)max_w * max_h, 256, 64);
   hipLaunchKernelGGL(update_window_kernel, dim3(nrect, gy), dim3(256), 0, s, m, base, L, rects);
+  return hipGetLastError();
+}
+
+hipError_t tci_launch_update_level_window(const tci_map& m, uint32_t* base, int32_t L,
+                                          const int32_t* rects_l, int32_t nl, int32_t max_w,
+                                          int32_t max_h, const int32_t* rects_w, int32_t nw,
+                                          int32_t wmax_w, int32_t wmax_h, hipStream_t s) {
+  if (nl <= 0 && nw <= 0) return hipSuccess;
+  const int32_t gy = blocks_for(std::max((int64_t)max_w * max_h, (int64_t)wmax_w * wmax_h), 256, 64);
+  hipLaunchKernelGGL(update_level_window_kernel, dim3(nl + nw, gy), dim3(256), 0, s, m, base, L,
+                     rects_l, nl, rects_w);
   return hipGetLastError();
 }
 

@@ -79,6 +79,11 @@ constexpr size_t kSplitMaxViews = 2;
 // After the last activity the server thread keeps polling this long
 // before it sleeps.
 constexpr double kSpinSeconds = 200e-6;
+// A batch starts beside one already on the device only when at least this
+// many views wait: a lone view waits for the batch in flight instead, since
+// two concurrent launches slow the one in flight by about what they save the
+// newcomer (at low rates that was the served p99's excess over FIFO).
+constexpr size_t kOverlapMinViews = 2;
 
 // First-fit allocator over [0, size) with 256-byte granules.
 class Pool {
@@ -141,6 +146,7 @@ struct Batch {
   tci::Slot slot;
   bool busy = false;
   hipStream_t stream = nullptr;
+  uint64_t edit_seen = 0;   // the edit_ev recording this stream last waited for
 };
 
 }  // namespace
@@ -160,6 +166,7 @@ struct tc_server {
   bool own_ver[2] = {false, false};
   hipStream_t edit_stream = nullptr;
   hipEvent_t edit_ev = nullptr;           // end of the newest edit
+  uint64_t edit_gen = 0;                   // recordings of edit_ev so far
   std::deque<std::pair<uint64_t, hipEvent_t>> edits_in_flight;
   EditUpload uploads[2];                   // the newest edit and the one before
   uint64_t edits_applied = 0;
@@ -225,13 +232,18 @@ void complete(tc_server* s, const std::vector<uint64_t>& ids, double t) {
 }
 
 // Launch the admitted views as one batch; returns false if no stream slot
-// is free.
+// is free, or if a batch is in flight and fewer than kOverlapMinViews views
+// wait.
 bool launch_batch(tc_server* s) {
   if (s->admitted.empty()) return true;
   Batch* b = nullptr;
-  for (Batch& c : s->slots)
-    if (!c.busy) { b = &c; break; }
+  bool in_flight = false;
+  for (Batch& c : s->slots) {
+    if (c.busy) in_flight = true;
+    else if (!b) b = &c;
+  }
   if (!b) return false;
+  if (in_flight && s->admitted.size() < kOverlapMinViews) return false;
   tc_context* ctx = s->ctx;
   std::vector<tc_view> views;
   std::vector<size_t> offs;
@@ -271,7 +283,14 @@ bool launch_batch(tc_server* s) {
   }
   tci::write_views(plan, (char*)b->slot.host);
   const int v = s->current;
-  hipError_t e = hipStreamWaitEvent(b->stream, s->edit_ev, 0);
+  // a stream waits for each recording of edit_ev once: its later work is
+  // ordered after that wait anyway (a wait is a packet of its own on the
+  // stream, a few microseconds on every request otherwise)
+  hipError_t e = hipSuccess;
+  if (b->edit_seen != s->edit_gen) {
+    e = hipStreamWaitEvent(b->stream, s->edit_ev, 0);
+    if (e == hipSuccess) b->edit_seen = s->edit_gen;
+  }
   if (e == hipSuccess)
     e = hipMemcpyAsync(b->slot.dev, b->slot.host, plan.off_queue, hipMemcpyHostToDevice,
                        b->stream);
@@ -353,6 +372,7 @@ bool apply_edit(tc_server* s, uint64_t id) {
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventRecord(ev, s->edit_stream);
   if (e == hipSuccess) e = hipEventRecord(s->edit_ev, s->edit_stream);
+  if (e == hipSuccess) s->edit_gen++;
   if (e != hipSuccess) {
     if (ev) (void)hipEventDestroy(ev);
     set_error(s, e, "server: edit launch");
@@ -542,6 +562,7 @@ tc_status tc_server_start(tc_context* ctx, uint64_t budget_bytes, int32_t max_ba
     e = hipMemcpyAsync(s->ver[1], s->ver[0], ctx->map_words * 4, hipMemcpyDeviceToDevice,
                        s->edit_stream);
   if (e == hipSuccess) e = hipEventRecord(s->edit_ev, s->edit_stream);
+  if (e == hipSuccess) s->edit_gen++;
   // staging of every batch slot and of the edit log, allocated up front
   s->slots.resize(streams);
   for (Batch& b : s->slots) {

@@ -344,6 +344,14 @@ tc_status tc_shade_views(tc_context *ctx, const tc_view *views, int32_t n,
                                     each kernel, read back by
                                     tc_read_kernel_times (diagnostic;
                                     default 0) */
+#define TC_OPT_INLINE_TABLES 22  /* 1: a tc_render_views call in the
+                                    hierarchical mode (no read counting) whose
+                                    view records, packet prefix and tile-row
+                                    table fit in 1536 bytes passes them in
+                                    the kernels' arguments, so no upload
+                                    precedes its render; 0: every call
+                                    uploads its tables (default 1; results
+                                    are identical) */
 /* Read-only (tc_get_option): the number of device and pinned host
  * allocations the context has made since tc_create, its frames' included.
  * tc_create allocates the staging ring (16 slots of table buffers and split

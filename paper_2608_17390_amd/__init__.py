@@ -19,5 +19,5 @@ from ._tc import (Context, Frame, Server, TCError, tc_create, tc_view, tc_edit, 
                   TC_OPT_SPLIT_QUEUE, TC_OPT_KERNEL_TIMING,
                   TC_OPT_MARCH_STEPS, TC_OPT_MARCH_BISECT, TC_OPT_MARCH_FAR,
                   TC_OPT_BEAM_PASSES, TC_OPT_SPLIT_WAVES, TC_INFO_ALLOCATIONS,
-                  TC_OPT_PACKET_WIDTH, TC_OPT_VOXEL_SHAPE,
+                  TC_OPT_PACKET_WIDTH, TC_OPT_VOXEL_SHAPE, TC_OPT_INLINE_TABLES,
                   TC_FACE_SAMPLED)

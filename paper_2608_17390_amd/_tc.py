@@ -58,6 +58,7 @@ TC_OPT_SPLIT_WAVES = 18
 TC_INFO_ALLOCATIONS = 19
 TC_OPT_PACKET_WIDTH = 20
 TC_OPT_VOXEL_SHAPE = 21
+TC_OPT_INLINE_TABLES = 22
 TC_FACE_SAMPLED = 0
 
 _STATUS = {0: "TC_OK", -1: "TC_INVALID_ARG", -2: "TC_OUT_OF_MEMORY",

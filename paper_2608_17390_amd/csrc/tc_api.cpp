@@ -76,6 +76,10 @@ tc_status ring_alloc(tc_context* ctx, uint32_t qcap) {
       TC_HIP(dev_alloc(ctx, &s.dev, kSlotBytes), "hipMalloc(staging)");
       s.cap = kSlotBytes;
     }
+    if (!s.ctr) {
+      TC_HIP(dev_alloc(ctx, (void**)&s.ctr, 16), "hipMalloc(queue counters)");
+      TC_HIP(hipMemset(s.ctr, 0, 16), "hipMemset(queue counters)");
+    }
     if (s.qcap < qcap) {
       if (s.queue) {
         (void)hipFree(s.queue);
@@ -149,6 +153,7 @@ tci_render_opts render_opts(const tc_context* c) {
   o.qcap = 0;
   o.queue = nullptr;
   o.qcount = nullptr;
+  o.qzero = nullptr;
   o.split_waves = 1;
   o.count = c->count_reads ? c->d_count : nullptr;
   o.march_far = (float)c->march_far;
@@ -220,8 +225,35 @@ tc_status build_voxels(tc_context* ctx, hipStream_t s) {
 hipError_t enqueue_render(tc_context* ctx, const tci_map& d, const char* dev,
                           const ViewPlan& p, void* out, hipStream_t s,
                           hipEvent_t* kev, bool* split_ran, bool counters_zeroed,
-                          uint4* queue) {
+                          uint4* queue, const tci_inline* inl, uint32_t* qctr,
+                          uint32_t* qzero) {
   tci_render_opts o = render_opts(ctx);
+  if (inl) {
+    // tables in the kernels' arguments (hierarchical mode without read
+    // counting only); the queue counters are the slot's two, used in turn
+    o.rows = nullptr;
+    o.qzero = qzero;
+    auto mark = [&](int i) { return kev ? hipEventRecord(kev[i], s) : hipSuccess; };
+    if (split_ran) *split_ran = false;
+    if (p.qcap > 0) {
+      o.split_budget = ctx->split_budget;
+      o.qcap = p.qcap;
+      o.queue = queue;
+      o.qcount = qctr;
+      o.split_waves = p.qwaves;
+    }
+    hipError_t e = mark(0);
+    if (e == hipSuccess) e = tci_launch_render_inline(d, p.n, p.npkt, out, o, *inl, s);
+    if (e == hipSuccess) e = mark(1);
+    if (p.qcap > 0) {
+      const int32_t nb = (int32_t)std::max<int64_t>(
+          1, std::min<int64_t>(ctx->num_cu * 16, ((int64_t)p.qcap * p.qwaves + 3) / 4));
+      if (e == hipSuccess) e = tci_launch_split(d, nullptr, o, out, nb, s, inl);
+      if (e == hipSuccess) e = mark(2);
+      if (split_ran) *split_ran = true;
+    }
+    return e;
+  }
   o.rows = (const int32_t*)(dev + p.off_rows);
   const tci_view* dv = (const tci_view*)(dev + p.off_views);
   const int64_t* pre = (const int64_t*)(dev + p.off_prefix);
@@ -332,6 +364,7 @@ void tc_destroy(tc_context* ctx) {
     if (s.host) (void)hipHostFree(s.host);
     if (s.dev) (void)hipFree(s.dev);
     if (s.queue) (void)hipFree(s.queue);
+    if (s.ctr) (void)hipFree(s.ctr);
   }
   if (ctx->map) (void)hipFree(ctx->map);
   if (ctx->vox) (void)hipFree(ctx->vox);
@@ -471,14 +504,34 @@ tc_status tc_render_views(tc_context* ctx, const tc_view* views, int32_t n,
     st = tci::acquire(ctx, plan.off_queue, &slot);
     if (st) return st;
     tci::write_views(plan, (char*)slot->host);
-    // tables and zeroed queue counters in one upload; the split queue is the
-    // slot's device-only buffer (plan.qcap <= TC_OPT_SPLIT_QUEUE <= its size)
-    hipError_t e = hipMemcpyAsync(slot->dev, slot->host, plan.off_queue,
-                                  hipMemcpyHostToDevice, s);
+    hipError_t e = hipSuccess;
     bool split_ran = false;
-    if (e == hipSuccess)
-      e = tci::enqueue_render(ctx, ctx->desc, (const char*)slot->dev, plan, out_device, s,
-                              kev, &split_ran, true, slot->queue);
+    if (ctx->inline_tables && ctx->render_mode == 0 && !ctx->count_reads &&
+        plan.off_counter <= (size_t)kInlineBytes) {
+      // a small call: its tables travel in the kernels' arguments, so
+      // nothing is uploaded before the render
+      tci_inline t;
+      t.off_prefix = (uint32_t)plan.off_prefix;
+      t.off_rows = (uint32_t)plan.off_rows;
+      std::memcpy(t.words, slot->host, plan.off_counter);
+      if (slot->ctr_dirty) e = tci_launch_zero_u64((uint64_t*)slot->ctr, 1, s);
+      const int turn = slot->ctr_turn;
+      if (e == hipSuccess)
+        e = tci::enqueue_render(ctx, ctx->desc, nullptr, plan, out_device, s, kev, &split_ran,
+                                true, slot->queue, &t, slot->ctr + turn, slot->ctr + 1 - turn);
+      // (a call with no packets launches no render, so nothing clears the
+      // other counter: clear both before the slot's next such call)
+      slot->ctr_dirty = e != hipSuccess || plan.npkt < 1;
+      slot->ctr_turn = 1 - turn;
+    } else {
+      // tables and zeroed queue counters in one upload; the split queue is
+      // the slot's device-only buffer (plan.qcap <= TC_OPT_SPLIT_QUEUE <= its
+      // size)
+      e = hipMemcpyAsync(slot->dev, slot->host, plan.off_queue, hipMemcpyHostToDevice, s);
+      if (e == hipSuccess)
+        e = tci::enqueue_render(ctx, ctx->desc, (const char*)slot->dev, plan, out_device, s,
+                                kev, &split_ran, true, slot->queue);
+    }
     if (kev) {
       ctx->kev_valid = e == hipSuccess;
       ctx->kev_split = split_ran;
@@ -626,6 +679,10 @@ tc_status tc_set_option(tc_context* ctx, int32_t key, int64_t value) {
       ctx->split_queue = (int32_t)value;
       return TC_OK;
     }
+    case TC_OPT_INLINE_TABLES:
+      if (value < 0 || value > 1) break;
+      ctx->inline_tables = (int32_t)value;
+      return TC_OK;
     case TC_OPT_MARCH_STEPS:
       if (value < 1 || value > 65536) break;
       ctx->march_steps = (int32_t)value;
@@ -689,6 +746,7 @@ tc_status tc_get_option(const tc_context* ctx, int32_t key, int64_t* value) {
     case TC_OPT_PRIORITY_BOOST: *value = ctx->boost; return TC_OK;
     case TC_OPT_SPLIT_BUDGET: *value = ctx->split_budget; return TC_OK;
     case TC_OPT_SPLIT_QUEUE: *value = ctx->split_queue; return TC_OK;
+    case TC_OPT_INLINE_TABLES: *value = ctx->inline_tables; return TC_OK;
     case TC_OPT_BEAM_PASSES: *value = ctx->beam_passes; return TC_OK;
     case TC_OPT_SPLIT_WAVES: *value = ctx->split_waves; return TC_OK;
     case TC_OPT_KERNEL_TIMING: *value = ctx->kernel_timing; return TC_OK;

@@ -28,6 +28,13 @@ struct Slot {
   size_t cap = 0;
   uint4* queue = nullptr;
   uint32_t qcap = 0;
+  // two split queue counters for renders whose tables travel in the
+  // kernels' arguments, used in turn: a render counts in ctr[ctr_turn] and
+  // clears ctr[1 - ctr_turn] for the slot's next such render (both zero at
+  // allocation; ctr_dirty: a launch failed on the way, clear both first)
+  uint32_t* ctr = nullptr;
+  int ctr_turn = 0;
+  bool ctr_dirty = false;
   hipEvent_t ev = nullptr;
   bool pending = false;
 };
@@ -69,11 +76,16 @@ tc_status plan_views(tc_context* ctx, const tc_view* views, int32_t n,
 // as zeros with the tables (bytes [0, plan.off_queue)), so no kernel clears
 // them; a captured frame, which replays, clears them itself.  `queue` holds
 // the split queue (plan.qcap entries); nullptr: it follows the tables at
-// dev + plan.off_queue.
+// dev + plan.off_queue.  With `inl` (hierarchical mode, no read counting)
+// the tables travel in the kernels' arguments instead of at dev, and the
+// queue length is the counter at qctr, which must be zero, and the render
+// clears the counter at qzero.
 hipError_t enqueue_render(tc_context* ctx, const tci_map& d, const char* dev,
                           const ViewPlan& plan, void* out, hipStream_t s,
                           hipEvent_t* kev = nullptr, bool* split_ran = nullptr,
-                          bool counters_zeroed = false, uint4* queue = nullptr);
+                          bool counters_zeroed = false, uint4* queue = nullptr,
+                          const tci_inline* inl = nullptr, uint32_t* qctr = nullptr,
+                          uint32_t* qzero = nullptr);
 
 tci_render_opts render_opts(const tc_context* c);
 
@@ -119,6 +131,7 @@ struct tc_context {
   int32_t beam_passes = 6;
   int32_t split_waves = 4;
   int32_t split_queue = 1 << 17;
+  int32_t inline_tables = 1;   // TC_OPT_INLINE_TABLES
   int32_t march_steps = 128;
   int32_t march_bisect = 4;
   int32_t march_far = 600;

@@ -40,12 +40,24 @@ struct tci_render_opts {
   uint4* queue;                // split queue: (view, pixel index, first
                                // dominant-axis cell line still to walk, 0)
   uint32_t* qcount;            // split queue length
+  uint32_t* qzero;             // if set: a queue counter to clear (the one the
+                               // next render of the same ring slot uses)
   int32_t split_waves;         // waves of one block the split pass gives
                                // each queued ray (1, 2 or 4)
   unsigned long long* count;   // if set: add each ray's node/cell reads
   float march_far;             // sampled march: far limit along each ray
   int32_t march_steps;         // sampled march: forward samples
   int32_t march_bisect;        // sampled march: bisection steps
+};
+
+// A render call's tables (view records, packet prefix and tile-row table,
+// laid out as in the device table: views at byte 0) carried by value in a
+// kernel's arguments, for calls whose tables fit in kInlineBytes.
+constexpr int32_t kInlineBytes = 1536;
+struct tci_inline {
+  uint32_t off_prefix;         // byte offset of the packet prefix in words
+  uint32_t off_rows;           // byte offset of the tile-row table
+  uint64_t words[kInlineBytes / 8];
 };
 
 // Shading parameters (the device copy of tc_shade_params).
@@ -122,4 +134,9 @@ hipError_t tci_launch_march(const tci_map& m, const tci_view* views,
 // segments in parallel, one wave per ray.
 hipError_t tci_launch_split(const tci_map& m, const tci_view* views,
                             const tci_render_opts& o, void* out, int32_t nblocks,
-                            hipStream_t s);
+                            hipStream_t s, const tci_inline* t = nullptr);
+// The hierarchical render (no read counting) of a call whose tables travel
+// in the kernel's arguments (t; the split pass then takes t as well).
+hipError_t tci_launch_render_inline(const tci_map& m, int32_t nviews, int64_t npkt, void* out,
+                                    const tci_render_opts& o, const tci_inline& t,
+                                    hipStream_t s);

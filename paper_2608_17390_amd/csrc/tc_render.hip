@@ -28,12 +28,15 @@ __device__ __forceinline__ int32_t lane_now() {
 template <bool kFlat, bool kOcc, bool kCount, bool kVox = false>
 __device__ __forceinline__ void render_body(
     const tci_map& m, const tci_view* __restrict__ views, int32_t nviews,
-    const int64_t* __restrict__ pkt_prefix, int64_t npkt, void* out,
-    const tci_render_opts& o, const tci_voxels* vx = nullptr) {
+    const int64_t* __restrict__ pkt_prefix, const int32_t* __restrict__ rows, int64_t npkt,
+    void* out, const tci_render_opts& o, const tci_voxels* vx = nullptr) {
   __shared__ lvl_t lv[TCI_MAX_LEVELS];
   __shared__ uint32_t woff[TCI_MAX_LEVELS];
   __shared__ uint32_t moff[kOcc ? TCI_MAX_LEVELS : 1];
   load_levels_beam(m, lv, woff, kOcc ? moff : nullptr);
+  // clear the queue counter the next render of this ring slot will use
+  // (its last user finished before this launch)
+  if (o.qzero && blockIdx.x == 0 && threadIdx.x == 0) *o.qzero = 0u;
   // XCD-aware order: hand each XCD a contiguous range of packets to share
   // its L2
   const int64_t b = tcp::xcd_block(blockIdx.x, gridDim.x, o.xcd_remap);
@@ -45,7 +48,7 @@ __device__ __forceinline__ void render_body(
   const int32_t vi = __builtin_amdgcn_readfirstlane(tcp::find_view(pkt_prefix, nviews, p));
   const tci_view& v = views[vi];
   int32_t tx, ty;
-  tcp::packet_tile(v, p - v.pkt_base, o.tile_order, o.rows, tx, ty);
+  tcp::packet_tile(v, p - v.pkt_base, o.tile_order, rows, tx, ty);
   tx = __builtin_amdgcn_readfirstlane(tx);
   ty = __builtin_amdgcn_readfirstlane(ty);
   const int32_t pw = v.pw_log2;
@@ -146,7 +149,19 @@ __global__ __launch_bounds__(64 * kPackets) __attribute__((amdgpu_waves_per_eu(7
 void render_hier_kernel(tci_map m, const tci_view* __restrict__ views, int32_t nviews,
                         const int64_t* __restrict__ pkt_prefix, int64_t npkt, void* out,
                         tci_render_opts o) {
-  render_body<false, false, kCount>(m, views, nviews, pkt_prefix, npkt, out, o);
+  render_body<false, false, kCount>(m, views, nviews, pkt_prefix, o.rows, npkt, out, o);
+}
+
+// The same, with the call's view records, packet prefix and tile-row table
+// passed in the kernel's arguments instead of a device table (a small call
+// then needs no upload before its render).
+__global__ __launch_bounds__(64 * kPackets) __attribute__((amdgpu_waves_per_eu(7, 8)))
+void render_hier_inline_kernel(tci_map m, int32_t nviews, int64_t npkt, void* out,
+                               tci_render_opts o, tci_inline t) {
+  const char* b = (const char*)t.words;
+  render_body<false, false, false>(m, (const tci_view*)b, nviews,
+                                   (const int64_t*)(b + t.off_prefix),
+                                   (const int32_t*)(b + t.off_rows), npkt, out, o);
 }
 
 template <bool kCount>
@@ -154,7 +169,7 @@ __global__ __launch_bounds__(64 * kPackets)
 void render_flat_kernel(tci_map m, const tci_view* __restrict__ views, int32_t nviews,
                         const int64_t* __restrict__ pkt_prefix, int64_t npkt, void* out,
                         tci_render_opts o) {
-  render_body<true, false, kCount>(m, views, nviews, pkt_prefix, npkt, out, o);
+  render_body<true, false, kCount>(m, views, nviews, pkt_prefix, o.rows, npkt, out, o);
 }
 
 template <bool kCount>
@@ -162,7 +177,7 @@ __global__ __launch_bounds__(64 * kPackets)
 void render_occ_kernel(tci_map m, const tci_view* __restrict__ views, int32_t nviews,
                        const int64_t* __restrict__ pkt_prefix, int64_t npkt, void* out,
                        tci_render_opts o) {
-  render_body<false, true, kCount>(m, views, nviews, pkt_prefix, npkt, out, o);
+  render_body<false, true, kCount>(m, views, nviews, pkt_prefix, o.rows, npkt, out, o);
 }
 
 template <bool kCount>
@@ -170,7 +185,8 @@ __global__ __launch_bounds__(64 * kPackets)
 void render_vox_kernel(tci_map m, const tci_view* __restrict__ views, int32_t nviews,
                        const int64_t* __restrict__ pkt_prefix, int64_t npkt, void* out,
                        tci_render_opts o, tci_voxels vx) {
-  render_body<false, false, kCount, true>(m, views, nviews, pkt_prefix, npkt, out, o, &vx);
+  render_body<false, false, kCount, true>(m, views, nviews, pkt_prefix, o.rows, npkt, out, o,
+                                          &vx);
 }
 
 // Dominant-axis cell line where the ray leaves the map's columns, or rises
@@ -202,9 +218,9 @@ __device__ __forceinline__ int32_t exit_line(const ray_t& r, const tci_map& m,
 // hit, and after a barrier the ray's first wave writes the winner (or a
 // miss).  Blocks stride over the queue; every wave of a block runs the
 // same number of rounds, so the barriers are reached by all of them.
-__global__ __launch_bounds__(256) void split_kernel(tci_map m,
-                                                    const tci_view* __restrict__ views,
-                                                    void* out, tci_render_opts o) {
+__device__ __forceinline__ void split_body(const tci_map& m,
+                                           const tci_view* __restrict__ views, void* out,
+                                           const tci_render_opts& o) {
   __shared__ lvl_t lv[TCI_MAX_LEVELS];
   __shared__ uint32_t best[4];      // per ray of the block: lowest run with a hit
   __shared__ uint2 cand[4];         // per wave: its first hit's record
@@ -305,6 +321,18 @@ __global__ __launch_bounds__(256) void split_kernel(tci_map m,
     }
     __syncthreads();
   }
+}
+
+__global__ __launch_bounds__(256) void split_kernel(tci_map m,
+                                                    const tci_view* __restrict__ views,
+                                                    void* out, tci_render_opts o) {
+  split_body(m, views, out, o);
+}
+
+// The split pass of a render whose tables came in the kernel's arguments.
+__global__ __launch_bounds__(256) void split_inline_kernel(tci_map m, void* out,
+                                                           tci_render_opts o, tci_inline t) {
+  split_body(m, (const tci_view*)(const char*)t.words, out, o);
 }
 
 // Persistent waves.  Each wave keeps 64 rays in flight; when at least
@@ -422,8 +450,21 @@ hipError_t tci_launch_render(const tci_map& m, const tci_view* views,
 
 hipError_t tci_launch_split(const tci_map& m, const tci_view* views,
                             const tci_render_opts& o, void* out, int32_t nblocks,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(split_kernel, dim3(nblocks), dim3(256), 0, s, m, views, out, o);
+                            hipStream_t s, const tci_inline* t) {
+  if (t)
+    hipLaunchKernelGGL(split_inline_kernel, dim3(nblocks), dim3(256), 0, s, m, out, o, *t);
+  else
+    hipLaunchKernelGGL(split_kernel, dim3(nblocks), dim3(256), 0, s, m, views, out, o);
+  return hipGetLastError();
+}
+
+hipError_t tci_launch_render_inline(const tci_map& m, int32_t nviews, int64_t npkt, void* out,
+                                    const tci_render_opts& o, const tci_inline& t,
+                                    hipStream_t s) {
+  const int64_t blocks = (npkt + kPackets - 1) / kPackets;
+  if (blocks < 1) return hipSuccess;
+  hipLaunchKernelGGL(render_hier_inline_kernel, dim3((uint32_t)blocks), dim3(64 * kPackets), 0,
+                     s, m, nviews, npkt, out, o, t);
   return hipGetLastError();
 }
 

@@ -293,6 +293,42 @@ def test_split_pass(ctx, budget, queue, waves):
         ctx.tc_set_option(tc.TC_OPT_START_LEVEL, 2)
 
 
+def test_inline_tables(ctx):
+    """A call whose tables fit in the kernels' arguments uploads nothing, and
+    its split pass clears the ring slot's queue counters for the slot's next
+    use.  Calls with and without inline tables, small and large split
+    budgets and queues (overflowing ones too), and calls too large to travel
+    inline are interleaved over more calls than the ring has slots; every
+    record equals the oracle's."""
+    F, B, T = synth.make_map_from_config(1)
+    load(ctx, F, B, T)
+    rng = np.random.default_rng(17)
+    one = synth.config_views(1, F, B)
+    two = one + _random_views(rng, F, B, 1, [(130, 64)])
+    many = one + _random_views(rng, F, B, 13, [(77, 53), (8, 9), (130, 64)])   # > 1536 B
+    sets = [(vs, oracle.render(F, B, T, vs)) for vs in (one, two, many)]
+    plans = [(1, 128, 1 << 17), (1, 1, 1 << 17), (0, 1, 1 << 17), (1, 5, 7), (1, 0, 1 << 17),
+             (1, 30, 1000)]
+    try:
+        for k in range(48):
+            inline, budget, queue = plans[k % len(plans)]
+            vs, (wo, do) = sets[(k // 2) % 3]
+            ctx.tc_set_option(tc.TC_OPT_INLINE_TABLES, inline)
+            ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, budget)
+            ctx.tc_set_option(tc.TC_OPT_SPLIT_QUEUE, queue)
+            wg, dg = gpu_render(ctx, vs, "hier")
+            assert_parity(wg, dg, wo, do, "call %d: inline %d budget %d queue %d views %d" % (
+                k, inline, budget, queue, len(vs)))
+    finally:
+        ctx.tc_set_option(tc.TC_OPT_INLINE_TABLES, 1)
+        ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 128)
+        ctx.tc_set_option(tc.TC_OPT_SPLIT_QUEUE, 1 << 17)
+    for bad in (-1, 2):
+        with pytest.raises(tc.TCError):
+            ctx.tc_set_option(tc.TC_OPT_INLINE_TABLES, bad)
+    assert ctx.tc_get_option(tc.TC_OPT_INLINE_TABLES) == 1
+
+
 def test_split_pass_edge_rays_and_large_map(ctx):
     """Split walks on rays from outside the map, along cell edges and over
     the 2048x2048 map's long horizon rays."""

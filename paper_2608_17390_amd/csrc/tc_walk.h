@@ -650,10 +650,20 @@ __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
       if (away | above) return kMissed;
       // go up one level when the step entered a new parent node
       nL = L;
-      if ((L < max_level) & ((((s.ni ^ ni) | (s.nj ^ nj)) >> 1) != 0)) {
-        ni >>= 1;
-        nj >>= 1;
-        nL = L + 1;
+      int32_t up = 1;
+      if constexpr (kVox) {
+        // below the voxels' footprint level every node counts as occupied,
+        // so a climb stops there only to descend again: inside a leaf
+        // voxel the walk stays on the cells, and the step that leaves it
+        // climbs straight to the footprint level (the new leaf voxel is
+        // entered at this very crossing)
+        const int32_t Lv = min(vx->v_log2, max_level);
+        if (L < Lv) up = Lv - L;
+      }
+      if ((L < max_level) & ((((s.ni ^ ni) | (s.nj ^ nj)) >> up) != 0)) {
+        ni >>= up;
+        nj >>= up;
+        nL = L + up;
       }
     }
     s.ni = ni;

@@ -390,10 +390,11 @@ void tc_frame_destroy(tc_frame *frame);
  * order, XCD grouping, split budget (0 or 128), and the persistent queue's
  * waves per CU, refill threshold and refill interval, then the packet beam
  * passes (0, 2, 4, 6 or 8) of the best one-thread-per-pixel setting, then the
- * packet shape (width 4, 8, 16 or 32) and the pyramid depth (TC_OPT_MAX_LEVEL:
- * the top level, two and four below it, or 5) around the best setting --
- * then keep the fastest setting on the context and report it.  Results are those of tc_render_views for every
- * setting (bit-identical); only the time differs.  Synchronises
+ * packet shape (width 4, 8, 16 or 32), the split budget (96, 112 or 160, when
+ * the best setting splits) and the pyramid depth (TC_OPT_MAX_LEVEL: the top
+ * level, two and four below it, or 5) around the best setting -- then keep
+ * the fastest setting on the context and report it.  Results are those of
+ * tc_render_views for every setting (bit-identical); only the time differs.  Synchronises
  * hip_stream.  The paper picks each method's knob by a sweep on a fixed
  * fixture (Section 5.6); this tunes on the caller's workload. */
 typedef struct tc_tune_result {

@@ -256,6 +256,14 @@ tc_status tc_autotune(tc_context* ctx, const tc_view* views, int32_t n,
       k.pwidth = pwidth;
       try_knob(k);
     }
+    // the split budget, around the best setting when it splits at all
+    if (!st && bk.mode == 0 && bk.split > 0)
+      for (int32_t split : {96, 112, 160}) {
+        if (st) break;
+        Knobs k = bk;
+        k.split = split;
+        try_knob(k);
+      }
     const int32_t top = ctx->desc.top;
     for (int32_t maxl : {top, top - 2, top - 4, 5}) {
       if (st || maxl < 1 || maxl == std::min(bk.maxl, top)) continue;

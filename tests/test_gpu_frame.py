@@ -94,7 +94,7 @@ def test_autotune_keeps_results(ctx):
     best = ctx.tc_autotune(views, out.data_ptr(), reps=2)
     assert best["tried"] >= 72 and best["ms"] > 0
     assert best["render_mode"] in (0, 2)
-    assert best["split_budget"] in (0, 128)
+    assert best["split_budget"] in (0, 96, 112, 128, 160)
     assert ctx.tc_get_option(tc.TC_OPT_SPLIT_BUDGET) == best["split_budget"]
     assert best["beam_passes"] in (0, 2, 4, 6, 8)
     assert ctx.tc_get_option(tc.TC_OPT_BEAM_PASSES) == best["beam_passes"]

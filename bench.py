@@ -101,7 +101,8 @@ def time_renders(torch, ctx, tc, views, out, steps, warmup):
 
 def kernel_times(torch, ctx, tc, views, out, steps):
     """(traversal kernel ms, split pass ms) of each of `steps` renders,
-    from the HIP events the library records around its kernels."""
+    from the HIP events the library attaches to its kernels (or records
+    around them, for calls whose tables are uploaded)."""
     ctx.tc_set_option(tc.TC_OPT_KERNEL_TIMING, 1)
     rows = []
     vs = tc.views_struct(views)
@@ -631,8 +632,9 @@ def main():
     ms, wall = time_renders(torch, ctx, tc, views, out, args.steps, args.warmup)
     ms_per_step = wall * 1e3 / args.steps
     med = float(np.median(ms))
-    # the traversal kernels alone, timed by HIP events the library records
-    # on the render stream around each kernel, over as many renders again
+    # the traversal kernels alone, timed by HIP events the library attaches
+    # to each kernel's dispatch (its start and end), over as many renders
+    # again
     kern = kernel_times(torch, ctx, tc, views, out, args.steps)
     kavg = float(kern.sum(axis=1).mean())
     achieved = alg_bytes / (kavg * 1e-3) / 1e9

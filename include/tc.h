@@ -340,8 +340,8 @@ tc_status tc_shade_views(tc_context *ctx, const tc_view *views, int32_t n,
 #define TC_OPT_MARCH_FAR 16      /* far limit in world units, 1..2^20
                                     (default 600, Section 5) */
 #define TC_OPT_KERNEL_TIMING 13  /* 1: tc_render_views and tc_shade_views
-                                    record HIP events on their stream around
-                                    each kernel, read back by
+                                    time each kernel with HIP events, read
+                                    back by
                                     tc_read_kernel_times (diagnostic;
                                     default 0) */
 #define TC_OPT_INLINE_TABLES 22  /* 1: a tc_render_views call in the
@@ -539,9 +539,12 @@ tc_status tc_read_counters(tc_context *ctx, uint64_t *reads, void *hip_stream);
 
 /* Durations in milliseconds of the kernels of the most recent
  * tc_render_views or tc_shade_views call made with TC_OPT_KERNEL_TIMING on,
- * measured with HIP events recorded on that call's stream: ms[0] the
- * traversal kernel (any render mode) or the shading kernel, ms[1] the split
- * pass (0 when it did not run).  `ms` holds 2
+ * measured with HIP events: ms[0] the traversal kernel (any render mode) or
+ * the shading kernel, ms[1] the split pass (0 when it did not run).  A call
+ * whose tables travel in the kernels' arguments (TC_OPT_INLINE_TABLES) has
+ * the events attached to its kernels' dispatches, so they time each kernel
+ * from its start to its end; other calls record them on the stream between
+ * the kernels, so a duration also holds the kernel's dispatch.  `ms` holds 2
  * floats.  Waits for those events.  TC_INVALID_ARG if no timed call was
  * made since timing was switched on. */
 tc_status tc_read_kernel_times(tc_context *ctx, float *ms);

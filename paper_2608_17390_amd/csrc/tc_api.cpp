@@ -233,7 +233,8 @@ hipError_t enqueue_render(tc_context* ctx, const tci_map& d, const char* dev,
     // counting only); the queue counters are the slot's two, used in turn
     o.rows = nullptr;
     o.qzero = qzero;
-    auto mark = [&](int i) { return kev ? hipEventRecord(kev[i], s) : hipSuccess; };
+    // (kev: the kernels carry their own start and end events, kev[0..1]
+    // the traversal and kev[2..3] the split pass)
     if (split_ran) *split_ran = false;
     if (p.qcap > 0) {
       o.split_budget = ctx->split_budget;
@@ -242,14 +243,14 @@ hipError_t enqueue_render(tc_context* ctx, const tci_map& d, const char* dev,
       o.qcount = qctr;
       o.split_waves = p.qwaves;
     }
-    hipError_t e = mark(0);
-    if (e == hipSuccess) e = tci_launch_render_inline(d, p.n, p.npkt, out, o, *inl, s);
-    if (e == hipSuccess) e = mark(1);
+    hipError_t e = tci_launch_render_inline(d, p.n, p.npkt, out, o, *inl, s,
+                                            kev ? kev[0] : nullptr, kev ? kev[1] : nullptr);
     if (p.qcap > 0) {
       const int32_t nb = (int32_t)std::max<int64_t>(
           1, std::min<int64_t>(ctx->num_cu * 16, ((int64_t)p.qcap * p.qwaves + 3) / 4));
-      if (e == hipSuccess) e = tci_launch_split(d, nullptr, o, out, nb, s, inl);
-      if (e == hipSuccess) e = mark(2);
+      if (e == hipSuccess)
+        e = tci_launch_split(d, nullptr, o, out, nb, s, inl, kev ? kev[2] : nullptr,
+                             kev ? kev[3] : nullptr);
       if (split_ran) *split_ran = true;
     }
     return e;
@@ -506,8 +507,9 @@ tc_status tc_render_views(tc_context* ctx, const tc_view* views, int32_t n,
     tci::write_views(plan, (char*)slot->host);
     hipError_t e = hipSuccess;
     bool split_ran = false;
-    if (ctx->inline_tables && ctx->render_mode == 0 && !ctx->count_reads &&
-        plan.off_counter <= (size_t)kInlineBytes) {
+    const bool inl_used = ctx->inline_tables && ctx->render_mode == 0 && !ctx->count_reads &&
+                          plan.off_counter <= (size_t)kInlineBytes;
+    if (inl_used) {
       // a small call: its tables travel in the kernels' arguments, so
       // nothing is uploaded before the render
       tci_inline t;
@@ -533,8 +535,9 @@ tc_status tc_render_views(tc_context* ctx, const tc_view* views, int32_t n,
                                 kev, &split_ran, true, slot->queue);
     }
     if (kev) {
-      ctx->kev_valid = e == hipSuccess;
+      ctx->kev_valid = e == hipSuccess && plan.npkt > 0;
       ctx->kev_split = split_ran;
+      ctx->kev_attached = inl_used;
     }
     tc_status rs = tci::release(ctx, slot, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "tc_render_views");
@@ -607,6 +610,7 @@ tc_status tc_shade_views(tc_context* ctx, const tc_view* views, int32_t n,
     if (kev) {
       ctx->kev_valid = e == hipSuccess;
       ctx->kev_split = false;
+      ctx->kev_attached = false;
     }
     tc_status rs = tci::release(ctx, slot, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "tc_shade_views");
@@ -962,12 +966,15 @@ tc_status tc_read_kernel_times(tc_context* ctx, float* ms) {
     return fail(ctx, TC_INVALID_ARG, "tc_read_kernel_times: no timed render since timing was enabled");
   tc_status st = set_device(ctx);
   if (st) return st;
-  const int last = ctx->kev_split ? 2 : 1;
+  // markers: kev[0] | traversal | kev[1] | split pass | kev[2]; attached:
+  // each kernel's own start and end, kev[0..1] and kev[2..3]
+  const int a = ctx->kev_attached ? 1 : 0;
+  const int last = ctx->kev_split ? 2 + a : 1;
   TC_HIP(hipEventSynchronize(ctx->kev[last]), "hipEventSynchronize");
   TC_HIP(hipEventElapsedTime(&ms[0], ctx->kev[0], ctx->kev[1]), "hipEventElapsedTime");
   ms[1] = 0.0f;
   if (ctx->kev_split)
-    TC_HIP(hipEventElapsedTime(&ms[1], ctx->kev[1], ctx->kev[2]), "hipEventElapsedTime");
+    TC_HIP(hipEventElapsedTime(&ms[1], ctx->kev[1 + a], ctx->kev[2 + a]), "hipEventElapsedTime");
   return TC_OK;
 }
 

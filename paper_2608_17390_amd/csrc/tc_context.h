@@ -138,8 +138,12 @@ struct tc_context {
   unsigned long long* d_count = nullptr;
   // TC_OPT_KERNEL_TIMING: events of the last timed render call
   int32_t kernel_timing = 0;
-  hipEvent_t kev[3] = {nullptr, nullptr, nullptr};
-  bool kev_valid = false, kev_split = false;
+  // markers on the stream before the traversal, between the kernels and
+  // after the split pass (kev[0..2]); or, for calls whose kernels carry
+  // their own events (kev_attached), each kernel's start and end (kev[0..1]
+  // the traversal, kev[2..3] the split pass)
+  hipEvent_t kev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool kev_valid = false, kev_split = false, kev_attached = false;
   // a running server owns the map (tc_server.cpp)
   void* server = nullptr;
 };

@@ -132,11 +132,15 @@ hipError_t tci_launch_march(const tci_map& m, const tci_view* views,
                             hipStream_t s);
 // Second pass of a hierarchical render: walk every queued long ray as 64
 // segments in parallel, one wave per ray.
+// With ev_start / ev_stop, the kernel records its own start and end in them
+// (the events travel with its dispatch instead of as markers on the stream).
 hipError_t tci_launch_split(const tci_map& m, const tci_view* views,
                             const tci_render_opts& o, void* out, int32_t nblocks,
-                            hipStream_t s, const tci_inline* t = nullptr);
+                            hipStream_t s, const tci_inline* t = nullptr,
+                            hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 // The hierarchical render (no read counting) of a call whose tables travel
 // in the kernel's arguments (t; the split pass then takes t as well).
 hipError_t tci_launch_render_inline(const tci_map& m, int32_t nviews, int64_t npkt, void* out,
                                     const tci_render_opts& o, const tci_inline& t,
-                                    hipStream_t s);
+                                    hipStream_t s, hipEvent_t ev_start = nullptr,
+                                    hipEvent_t ev_stop = nullptr);

@@ -3,6 +3,8 @@
 // walk itself (tc_walk.h) is the exact cell sequence of a 2D digital
 // differential analyser over the map, accelerated by the per-layer min/max
 // pyramid (Section 3.1 SOLID and RAYMARCH, Section 3.2 skip-to-exit).
+#include <hip/hip_ext.h>
+
 #include "tc_beam.h"
 #include "tc_packet.h"
 
@@ -450,8 +452,12 @@ hipError_t tci_launch_render(const tci_map& m, const tci_view* views,
 
 hipError_t tci_launch_split(const tci_map& m, const tci_view* views,
                             const tci_render_opts& o, void* out, int32_t nblocks,
-                            hipStream_t s, const tci_inline* t) {
-  if (t)
+                            hipStream_t s, const tci_inline* t, hipEvent_t ev_start,
+                            hipEvent_t ev_stop) {
+  if (t && (ev_start || ev_stop))
+    hipExtLaunchKernelGGL(split_inline_kernel, dim3(nblocks), dim3(256), 0, s, ev_start, ev_stop,
+                          0, m, out, o, *t);
+  else if (t)
     hipLaunchKernelGGL(split_inline_kernel, dim3(nblocks), dim3(256), 0, s, m, out, o, *t);
   else
     hipLaunchKernelGGL(split_kernel, dim3(nblocks), dim3(256), 0, s, m, views, out, o);
@@ -460,11 +466,15 @@ hipError_t tci_launch_split(const tci_map& m, const tci_view* views,
 
 hipError_t tci_launch_render_inline(const tci_map& m, int32_t nviews, int64_t npkt, void* out,
                                     const tci_render_opts& o, const tci_inline& t,
-                                    hipStream_t s) {
+                                    hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
   const int64_t blocks = (npkt + kPackets - 1) / kPackets;
   if (blocks < 1) return hipSuccess;
-  hipLaunchKernelGGL(render_hier_inline_kernel, dim3((uint32_t)blocks), dim3(64 * kPackets), 0,
-                     s, m, nviews, npkt, out, o, t);
+  if (ev_start || ev_stop)
+    hipExtLaunchKernelGGL(render_hier_inline_kernel, dim3((uint32_t)blocks), dim3(64 * kPackets),
+                          0, s, ev_start, ev_stop, 0, m, nviews, npkt, out, o, t);
+  else
+    hipLaunchKernelGGL(render_hier_inline_kernel, dim3((uint32_t)blocks), dim3(64 * kPackets), 0,
+                       s, m, nviews, npkt, out, o, t);
   return hipGetLastError();
 }
 

@@ -128,9 +128,11 @@ def test_c2_full_image(ctx, mode):
 
 
 def test_kernel_timing_leaves_results_unchanged(ctx):
-    """TC_OPT_KERNEL_TIMING records events around the kernels: results are
-    the same bytes, times are positive, the split pass time is 0 when that
-    pass is off, and reading before any timed render is an error."""
+    """TC_OPT_KERNEL_TIMING times the kernels with events (attached to the
+    kernels when the tables travel in their arguments, markers on the stream
+    otherwise): results are the same bytes, times are positive, the split
+    pass time is 0 when that pass is off, and reading before any timed
+    render is an error."""
     F, B, T = synth.make_map_from_config(2)
     load(ctx, F, B, T)
     views = synth.config_views(2, F, B)
@@ -140,8 +142,10 @@ def test_kernel_timing_leaves_results_unchanged(ctx):
         ctx.tc_read_kernel_times()
     assert e.value.status == tc.TC_INVALID_ARG
     try:
-        for mode, budget in (("hier", 128), ("hier", 0), ("flat", 128), ("persistent", 128)):
+        for mode, budget, inline in (("hier", 128, 1), ("hier", 0, 1), ("hier", 128, 0),
+                                     ("hier", 0, 0), ("flat", 128, 1), ("persistent", 128, 1)):
             ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, budget)
+            ctx.tc_set_option(tc.TC_OPT_INLINE_TABLES, inline)
             w, d = gpu_render(ctx, views, mode)
             assert np.array_equal(w, ref[0]), mode
             assert np.array_equal(d.view(np.uint32), ref[1].view(np.uint32)), mode
@@ -151,6 +155,7 @@ def test_kernel_timing_leaves_results_unchanged(ctx):
     finally:
         ctx.tc_set_option(tc.TC_OPT_KERNEL_TIMING, 0)
         ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 128)
+        ctx.tc_set_option(tc.TC_OPT_INLINE_TABLES, 1)
         ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, 0)
 
 

@@ -143,9 +143,10 @@ __device__ __forceinline__ void render_body(
 
 // The three one-thread-per-pixel kernels, each with and without read
 // counting.  The hierarchical one is asked for at least 7 waves per SIMD
-// (at most 72 VGPRs): it is bound by instruction issue, and more waves hide
-// more of the walk's load latency.  The production instance (no counting)
-// fits 64 VGPRs, so 8 waves run.
+// (at most 72 VGPRs): each walk step waits on its node load and the
+// arithmetic after it, so more waves hide more of that latency.  The
+// production instance (no counting) fits 64 VGPRs, enough for 8 waves (this
+// chip was seen to keep at most 7 resident per SIMD).
 template <bool kCount>
 __global__ __launch_bounds__(64 * kPackets) __attribute__((amdgpu_waves_per_eu(7, 8)))
 void render_hier_kernel(tci_map m, const tci_view* __restrict__ views, int32_t nviews,

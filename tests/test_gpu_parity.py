@@ -691,6 +691,15 @@ def test_error_paths(ctx):
     # a failed call leaves the map unchanged
     g = ctx2.tc_read_columns(0, 0, 4, 4)
     assert not g[0].any() and not g[1].any()
+    # empty inputs: no views is an error, an empty edit list does nothing
+    with pytest.raises(tc.TCError) as e:
+        ctx2.tc_render_views([], out.data_ptr())
+    assert e.value.status == tc.TC_INVALID_ARG
+    ctx2.tc_apply_edit([])
+    g = ctx2.tc_read_columns(0, 0, 4, 4)
+    assert not g[0].any() and not g[1].any()
+    ctx2.tc_render_views([v], out.data_ptr())
+    torch.cuda.synchronize()
     with pytest.raises(tc.TCError):
         ctx2.tc_set_option(tc.TC_OPT_RENDER_MODE, 7)
     ctx2.close()

@@ -48,7 +48,8 @@ enum : int32_t { kTop = 1, kUnder = 2, kWmx = 3, kWpx = 4, kWmy = 5,
 enum : int32_t { kWalking = 0, kHitCell = 1, kMissed = 2, kCapped = 3, kSegEnd = 4 };
 constexpr int32_t kAnchored = 8;
 
-struct lvl_t {
+// (16-byte aligned: the walk reads a level's record with one LDS load)
+struct __align__(16) lvl_t {
   uint32_t off;
   int32_t w, h, tiles_x;
 };
@@ -551,14 +552,25 @@ __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
       const int32_t n = seg_axis == 0 ? s.ni : s.nj;
       if ((n << L) > seg_hi || ((n + 1) << L) - 1 < seg_lo) return kSegEnd;
     }
-    const lvl_t l = lv[L];
+    // the level's record in one 16-byte LDS read, then every lane loads its
+    // node clamped into the level, with no branch around the load: the
+    // step's chain holds one LDS round trip and no exec-mask branch before
+    // the node load (levels up to max_level are never empty, so the clamp
+    // stays in the level)
+    const uint4 lq = *reinterpret_cast<const uint4*>(&lv[L]);
+    lvl_t l;
+    l.off = lq.x;
+    l.w = (int32_t)lq.y;
+    l.h = (int32_t)lq.z;
+    l.tiles_x = (int32_t)lq.w;
     const bool inmap = ((uint32_t)s.ni < (uint32_t)l.w) & ((uint32_t)s.nj < (uint32_t)l.h);
-    uint32_t v = 0;
     if (count) s.reads += (inmap & (!kVox | (L == 0))) ? 1 : 0;
-    if (inmap & (!kVox | (L == 0)))
-      v = map_word(m.base, l.off + ((umul24((uint32_t)s.nj >> 3, (uint32_t)l.tiles_x) +
-                                     ((uint32_t)s.ni >> 3)) << 6) +
-                               ((s.nj & 7) << 3) + (s.ni & 7));
+    const uint32_t ci = (uint32_t)min(max(s.ni, 0), l.w - 1);
+    const uint32_t cj = (uint32_t)min(max(s.nj, 0), l.h - 1);
+    const uint32_t vraw = map_word(m.base, l.off + ((umul24(cj >> 3, (uint32_t)l.tiles_x) +
+                                                     (ci >> 3)) << 6) +
+                                               ((cj & 7) << 3) + (ci & 7));
+    const uint32_t v = (inmap & (!kVox | (L == 0))) ? vraw : 0u;
     // keys and heights of the crossings through the node's far faces
     const int32_t ix = far_index(s.ni, L, nx1, sx, k.offx);
     const int32_t iy = far_index(s.nj, L, ny1, sy, k.offy);

@@ -67,11 +67,11 @@ __device__ __forceinline__ bool beam_box_solid(const tci_map& m, const lvl_t* lv
   };
   const int32_t x0 = node(lox), y0 = node(loy);
   const lvl_t l = lv[L];
-  const bool beside = (hix < 0.0f) | (hiy < 0.0f) | (x0 >= l.w) | (y0 >= l.h);
+  const bool beside = (hix < 0.0f) | (hiy < 0.0f) | (x0 > l.w1) | (y0 > l.h1);
   // index clamped into the level, so every lane's load is valid; tiled
   // index (tci_tile_index) with a 24-bit multiply: tile rows and tiles per
   // row are below 2^11
-  const uint32_t i = (uint32_t)min(max(x0, 0), l.w - 1), j = (uint32_t)min(max(y0, 0), l.h - 1);
+  const uint32_t i = (uint32_t)clamp0(x0, l.w1), j = (uint32_t)clamp0(y0, l.h1);
   const uint32_t w = map_word(m.base, woff[L] + ((umul24(j >> 3, (uint32_t)l.tiles_x) + (i >> 3)) << 6) +
                                           ((j & 7) << 3) + (i & 7));
   const bool test = !bad & !above & !huge & !wide & !beside;

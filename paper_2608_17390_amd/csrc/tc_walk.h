@@ -51,8 +51,16 @@ constexpr int32_t kAnchored = 8;
 // (16-byte aligned: the walk reads a level's record with one LDS load)
 struct __align__(16) lvl_t {
   uint32_t off;
-  int32_t w, h, tiles_x;
+  int32_t w1, h1, tiles_x;   // the level's width - 1 and height - 1, its tiles per row
 };
+
+// min(max(x, 0), hi) for hi >= 0 in one instruction (the compiler does not
+// form a median-of-three from a clamp whose upper bound is a variable)
+__device__ __forceinline__ int32_t clamp0(int32_t x, int32_t hi) {
+  int32_t r;
+  asm("v_med3_i32 %0, %1, 0, %2" : "=v"(r) : "v"(x), "v"(hi));
+  return r;
+}
 
 // a * b for a < 2^24, b < 2^24 as a 48-bit product: two full-rate 24-bit
 // multiplies instead of a quarter-rate 64-bit one.
@@ -560,13 +568,13 @@ __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
     const uint4 lq = *reinterpret_cast<const uint4*>(&lv[L]);
     lvl_t l;
     l.off = lq.x;
-    l.w = (int32_t)lq.y;
-    l.h = (int32_t)lq.z;
+    l.w1 = (int32_t)lq.y;
+    l.h1 = (int32_t)lq.z;
     l.tiles_x = (int32_t)lq.w;
-    const bool inmap = ((uint32_t)s.ni < (uint32_t)l.w) & ((uint32_t)s.nj < (uint32_t)l.h);
+    const bool inmap = ((uint32_t)s.ni <= (uint32_t)l.w1) & ((uint32_t)s.nj <= (uint32_t)l.h1);
     if (count) s.reads += (inmap & (!kVox | (L == 0))) ? 1 : 0;
-    const uint32_t ci = (uint32_t)min(max(s.ni, 0), l.w - 1);
-    const uint32_t cj = (uint32_t)min(max(s.nj, 0), l.h - 1);
+    const uint32_t ci = (uint32_t)clamp0(s.ni, l.w1);
+    const uint32_t cj = (uint32_t)clamp0(s.nj, l.h1);
     const uint32_t vraw = map_word(m.base, l.off + ((umul24(cj >> 3, (uint32_t)l.tiles_x) +
                                                      (ci >> 3)) << 6) +
                                                ((cj & 7) << 3) + (ci & 7));
@@ -656,8 +664,8 @@ __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
       s.rin = re;
       // the ray cannot come back into the map, or is above all solid
       // (compares combined bitwise, without short-circuit branches)
-      const bool away = ((ni < 0) & (r.Dx <= 0)) | ((ni >= l.w) & (r.Dx >= 0)) |
-                        ((nj < 0) & (r.Dy <= 0)) | ((nj >= l.h) & (r.Dy >= 0));
+      const bool away = ((ni < 0) & (r.Dx <= 0)) | ((ni > l.w1) & (r.Dx >= 0)) |
+                        ((nj < 0) & (r.Dy <= 0)) | ((nj > l.h1) & (r.Dy >= 0));
       const bool above = !desc & !z_le(s.Zin, s.rin, 255, s.Din);
       if (away | above) return kMissed;
       // go up one level when the step entered a new parent node
@@ -688,7 +696,7 @@ __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
 __device__ __forceinline__ void load_levels(const tci_map& m, lvl_t* lv) {
   if (threadIdx.x < TCI_MAX_LEVELS) {
     const tci_level& l = m.lv[threadIdx.x];
-    lv[threadIdx.x] = lvl_t{l.off, l.w, l.h, l.tiles_x};
+    lv[threadIdx.x] = lvl_t{l.off, l.w - 1, l.h - 1, l.tiles_x};
   }
   __syncthreads();
 }
@@ -699,7 +707,7 @@ __device__ __forceinline__ void load_levels_beam(const tci_map& m, lvl_t* lv, ui
                                                  uint32_t* moff) {
   if (threadIdx.x < TCI_MAX_LEVELS) {
     const tci_level& l = m.lv[threadIdx.x];
-    lv[threadIdx.x] = lvl_t{l.off, l.w, l.h, l.tiles_x};
+    lv[threadIdx.x] = lvl_t{l.off, l.w - 1, l.h - 1, l.tiles_x};
     woff[threadIdx.x] = m.wl[threadIdx.x].off;
     if (moff) moff[threadIdx.x] = m.mk[threadIdx.x].off;
   }

@@ -145,8 +145,7 @@ __device__ __forceinline__ void render_body(
 // counting.  The hierarchical one is asked for at least 7 waves per SIMD
 // (at most 72 VGPRs): each walk step waits on its node load and the
 // arithmetic after it, so more waves hide more of that latency.  The
-// production instance (no counting) fits 64 VGPRs, enough for 8 waves (this
-// chip was seen to keep at most 7 resident per SIMD).
+// production instance (no counting) fits 64 VGPRs, enough for 8 waves.
 template <bool kCount>
 __global__ __launch_bounds__(64 * kPackets) __attribute__((amdgpu_waves_per_eu(7, 8)))
 void render_hier_kernel(tci_map m, const tci_view* __restrict__ views, int32_t nviews,

@@ -169,13 +169,19 @@ hipError_t enqueue_edits(const tci_map& d, uint32_t* map, const char* dev,
                                   (const uint8_t*)(dev + p.off_patch), map, d.lv[0],
                                   d.W, d.H, p.max_w, p.max_h, s);
   const int32_t* rects = (const int32_t*)(dev + p.off_rects);
-  // level by level upward: the dirty nodes of level L and, in the same
-  // launch, the window entries of level L - 1 whose 2 x 2 node block meets
-  // an edited node; then the top level's window entries
-  for (int32_t L = 1; L <= p.top && e == hipSuccess; ++L)
-    e = tci_launch_update_level_window(d, map, L, rects + 4 * (size_t)L * p.n, p.nrect[L],
-                                       p.rmw[L], p.rmh[L], rects + 4 * (size_t)(L - 1) * p.n,
-                                       p.nrect[L - 1], p.rmw[L - 1] + 1, p.rmh[L - 1] + 1, s);
+  // upward in groups of kUpdateGroup levels, one launch each: the dirty
+  // nodes of levels s + 1 .. e and the window entries of levels s .. e - 1
+  // whose 2 x 2 node block meets an edited node, all computed from level s
+  // (each launch is a node of its own in a captured frame, and a few
+  // microseconds however little it does); then the top level's window
+  // entries
+  for (int32_t s0 = 0; s0 < p.top && e == hipSuccess; s0 += kUpdateGroup) {
+    const int32_t e0 = std::min(s0 + kUpdateGroup, p.top);
+    int64_t items = 1;
+    for (int32_t L = s0; L <= e0; ++L)
+      items = std::max<int64_t>(items, (int64_t)(p.rmw[L] + 1) * (p.rmh[L] + 1));
+    e = tci_launch_update_group(d, map, s0, e0, rects, p.n, p.nrect[0], items, s);
+  }
   if (e == hipSuccess)
     e = tci_launch_update_window(d, map, p.top, rects + 4 * (size_t)p.top * p.n, p.nrect[p.top],
                                  p.rmw[p.top] + 1, p.rmh[p.top] + 1, s);

@@ -18,6 +18,10 @@ constexpr int kRing = 16;
 // views, or an edit list with about 80 KiB of SET patches, fit without
 // growing a slot.
 constexpr size_t kSlotBytes = 256 << 10;
+// Pyramid levels the dirty update after edits computes per launch, all from
+// the level below the group: a node then combines at most 8 x 8 nodes of
+// that level, a window entry at most 8 x 8.
+constexpr int32_t kUpdateGroup = 3;
 
 // A pinned host buffer and a device buffer of the same size, reused across
 // calls, plus a device-only split queue (never uploaded, so it has no host

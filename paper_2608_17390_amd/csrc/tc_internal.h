@@ -77,16 +77,16 @@ hipError_t tci_launch_edits(const tci_edit* edits, int32_t n,
                             const uint8_t* patch, uint32_t* base,
                             tci_level l0, int32_t W, int32_t H,
                             int32_t max_w, int32_t max_h, hipStream_t s);
-// One launch per level L >= 1 after edits: recompute the nodes of level L
-// listed as rectangles (x0, y0, x1, y1 inclusive, in level-L node
-// coordinates), nl of them, the largest spanning max_w x max_h nodes; and
-// the window entries of level L - 1 over the level-(L - 1) rectangles
-// rects_w (nw of them, entries x0 - 1 .. x1, y0 - 1 .. y1, the largest
-// spanning wmax_w x wmax_h).  Both read only level L - 1.
-hipError_t tci_launch_update_level_window(const tci_map& m, uint32_t* base, int32_t L,
-                                          const int32_t* rects_l, int32_t nl, int32_t max_w,
-                                          int32_t max_h, const int32_t* rects_w, int32_t nw,
-                                          int32_t wmax_w, int32_t wmax_h, hipStream_t s);
+// One launch per group of levels s + 1 .. e after edits: recompute the
+// nodes (and occupancy masks) of those levels over their rectangles and the
+// window entries of levels s .. e - 1 over theirs (entries x0 - 1 .. x1,
+// y0 - 1 .. y1), all from level s, which must be up to date.  rects holds
+// nr rectangles per level (x0, y0, x1, y1 inclusive, in that level's node
+// coordinates), level L's at rects + 4 * (L * stride + r); max_items bounds
+// the nodes or entries of any one rectangle job.
+hipError_t tci_launch_update_group(const tci_map& m, uint32_t* base, int32_t s, int32_t e,
+                                   const int32_t* rects, int32_t stride, int32_t nr,
+                                   int64_t max_items, hipStream_t st);
 
 // Window level L from level L (all entries), and its entries whose node
 // block meets one of the level-L rectangles (x0, y0, x1, y1 inclusive):

@@ -246,40 +246,124 @@ __global__ void update_window_kernel(tci_map m, uint32_t* __restrict__ base, int
   }
 }
 
-// One launch per level after edits: blocks [0, nL) recompute the dirty
-// nodes of level L from level L - 1 (one edit rectangle each), blocks
-// [nL, nL + nW) the dirty window entries of level L - 1 (the same
-// rectangles one level down).  Both read only level L - 1, which the
-// launch before this one finished, and they write different arrays, so
-// the two jobs need no ordering between them.
-__global__ void update_level_window_kernel(tci_map m, uint32_t* __restrict__ base, int32_t L,
-                                           const int32_t* __restrict__ rects_l, int32_t nl,
-                                           const int32_t* __restrict__ rects_w) {
-  if ((int32_t)blockIdx.x < nl) {
-    const int32_t* r = rects_l + 4 * blockIdx.x;
-    const int32_t x0 = r[0], y0 = r[1], rw = r[2] - x0 + 1;
-    const int64_t nodes = (int64_t)rw * (r[3] - y0 + 1);
-    const tci_level& l = m.lv[L];
-    for (int64_t k = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; k < nodes;
-         k += (int64_t)gridDim.y * blockDim.x) {
-      const int32_t i = x0 + (int32_t)(k % rw), j = y0 + (int32_t)(k / rw);
-      base[tci_tile_index(l, i, j)] = reduce_node(m, base, L, i, j);
-      store_mask(m, base, L, i, j, reduce_mask(m, base, L, i, j));
+// One row of a block of level-s nodes: the combine (fmax, smin, smax) of
+// nodes x0 <= x < x0 + S of row y, clipped to the level (level 0: the
+// cells, as nodes), and with kMask the union of their occupancy masks; an
+// empty combine if the row lies outside the block (in false).  The S loads
+// are unrolled so that they are in flight together.
+template <int S, bool kMask>
+__device__ inline uint32_t reduce_row(const tci_map& m, const uint32_t* base, int32_t s,
+                                      int32_t x0, int32_t y, bool in, uint64_t& mk) {
+  const tci_level& c = m.lv[s];
+  const int32_t nx = in ? min(S, c.w - x0) : 0;
+  uint32_t v[S];
+  uint2 mw[kMask ? S : 1];
+#pragma unroll
+  for (int dx = 0; dx < S; ++dx) {
+    v[dx] = dx < nx ? base[tci_tile_index(c, x0 + dx, y)] : 0u;
+    if constexpr (kMask) {
+      mw[dx] = ((dx < nx) & (s > 0)) ? *reinterpret_cast<const uint2*>(
+                                           base + tci_mask_index(m.mk[s], x0 + dx, y))
+                                     : make_uint2(0u, 0u);
     }
+  }
+  uint32_t acc = 0u | (255u << 8);  // empty: fmax 0, smin 255, smax 0
+  mk = 0;
+#pragma unroll
+  for (int dx = 0; dx < S; ++dx) {
+    if (dx >= nx) continue;
+    if (s == 0) {
+      acc = node_merge(acc, cell_to_node(v[dx]));
+      if constexpr (kMask) mk |= cell_mask(v[dx]);
+    } else {
+      acc = node_merge(acc, v[dx]);
+      if constexpr (kMask) mk |= (uint64_t)mw[dx].x | ((uint64_t)mw[dx].y << 32);
+    }
+  }
+  return acc;
+}
+
+// The items (nodes, or window entries) x0..x1, y0..y1 of one rectangle job
+// of level L = s + k, each the combine of its S x S block of level-s nodes
+// (S = 2^k for a node, 2^(k + 1) for a window entry's 2 x 2 node block).
+// Both combines are associative, so an item of any level above s is the
+// combine over its block of level-s nodes.  S consecutive lanes take one
+// item, one block row each, and fold their rows together with cross-lane
+// exchanges, so an item waits on one round of loads.
+template <int S, bool kNode>
+__device__ inline void group_job(const tci_map& m, uint32_t* base, int32_t s, int32_t L,
+                                 int32_t x0, int32_t y0, int32_t x1, int32_t y1) {
+  const int32_t k = L - s, rw = x1 - x0 + 1;
+  const int64_t n = (int64_t)rw * (y1 - y0 + 1) * S;
+  const tci_level& src = m.lv[s];
+  // (blockDim.x is a multiple of S, so the S lanes of an item are aligned
+  // and leave or stay in the loop together)
+  for (int64_t q = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; q < n;
+       q += (int64_t)gridDim.y * blockDim.x) {
+    const int64_t item = q / S;
+    const int32_t row = (int32_t)(q % S);
+    const int32_t i = x0 + (int32_t)(item % rw), j = y0 + (int32_t)(item / rw);
+    const int32_t bx = i << k, by = (j << k) + row;
+    uint64_t mk;
+    uint32_t acc = reduce_row<S, kNode>(m, base, s, bx, by, by < src.h, mk);
+#pragma unroll
+    for (int o = 1; o < S; o <<= 1) {
+      acc = node_merge(acc, (uint32_t)__shfl_xor((int)acc, o, S));
+      if constexpr (kNode) {
+        const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)mk, o, S);
+        const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(mk >> 32), o, S);
+        mk |= (uint64_t)lo | ((uint64_t)hi << 32);
+      }
+    }
+    if (row == 0) {
+      if constexpr (kNode) {
+        base[tci_tile_index(m.lv[L], i, j)] = acc;
+        store_mask(m, base, L, i, j, mk);
+      } else {
+        base[tci_tile_index(m.wl[L], i, j)] = acc;
+      }
+    }
+  }
+}
+
+// One launch per group of levels after edits, reading only level s, which
+// the launch before finished (level 0, the cells, for the first group):
+// blocks [0, (e - s) nr) recompute the dirty nodes and masks of levels
+// s + 1 .. e; blocks [(e - s) nr, 2 (e - s) nr) the dirty window entries of
+// levels s .. e - 1.  Job j of either kind is level (first level) + j / nr,
+// rectangle j % nr; the rectangles of level L (x0, y0, x1, y1 inclusive,
+// in level-L node coordinates) are at rects + 4 (L stride + r).  Every
+// output depends on level s alone, so no job waits for another, and a
+// level's rectangles may overlap (two threads then write the same value).
+// Groups of at most 3 levels keep blocks at most 8 x 8 nodes: k <= 3 for a
+// node, k <= 2 for a window entry.
+__global__ void update_group_kernel(tci_map m, uint32_t* __restrict__ base, int32_t s,
+                                    int32_t e, const int32_t* __restrict__ rects,
+                                    int32_t stride, int32_t nr) {
+  const int32_t nl = (e - s) * nr;
+  const bool node_job = (int32_t)blockIdx.x < nl;
+  const int32_t job = node_job ? (int32_t)blockIdx.x : (int32_t)blockIdx.x - nl;
+  const int32_t L = (node_job ? s + 1 : s) + job / nr;
+  const int32_t* r = rects + 4 * ((size_t)L * stride + job % nr);
+  const int32_t k = L - s;
+  int32_t x0 = r[0], y0 = r[1], x1 = r[2], y1 = r[3];
+  if (node_job) {
+    if (k == 1) group_job<2, true>(m, base, s, L, x0, y0, x1, y1);
+    else if (k == 2) group_job<4, true>(m, base, s, L, x0, y0, x1, y1);
+    else group_job<8, true>(m, base, s, L, x0, y0, x1, y1);
     return;
   }
-  const int32_t* r = rects_w + 4 * (blockIdx.x - nl);
-  const tci_level& w = m.wl[L - 1];
-  const int32_t x0 = max(r[0] - 1, 0), y0 = max(r[1] - 1, 0);
-  const int32_t x1 = min(r[2], w.w - 1), y1 = min(r[3], w.h - 1);
+  // entries x0 - 1 .. x1, y0 - 1 .. y1: those whose node block meets the
+  // rectangle
+  const tci_level& w = m.wl[L];
+  x0 = max(x0 - 1, 0);
+  y0 = max(y0 - 1, 0);
+  x1 = min(x1, w.w - 1);
+  y1 = min(y1, w.h - 1);
   if (x0 > x1 || y0 > y1) return;
-  const int32_t rw = x1 - x0 + 1;
-  const int64_t n = (int64_t)rw * (y1 - y0 + 1);
-  for (int64_t k = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; k < n;
-       k += (int64_t)gridDim.y * blockDim.x) {
-    const int32_t i = x0 + (int32_t)(k % rw), j = y0 + (int32_t)(k / rw);
-    base[tci_tile_index(w, i, j)] = window_entry(m, base, L - 1, i, j);
-  }
+  if (k == 0) group_job<2, false>(m, base, s, L, x0, y0, x1, y1);
+  else if (k == 1) group_job<4, false>(m, base, s, L, x0, y0, x1, y1);
+  else group_job<8, false>(m, base, s, L, x0, y0, x1, y1);
 }
 
 __global__ void zero_u64_kernel(uint64_t* p, int32_t n) {
@@ -343,14 +427,14 @@ hipError_t tci_launch_update_window(const tci_map& m, uint32_t* base, int32_t L,
   return hipGetLastError();
 }
 
-hipError_t tci_launch_update_level_window(const tci_map& m, uint32_t* base, int32_t L,
-                                          const int32_t* rects_l, int32_t nl, int32_t max_w,
-                                          int32_t max_h, const int32_t* rects_w, int32_t nw,
-                                          int32_t wmax_w, int32_t wmax_h, hipStream_t s) {
-  if (nl <= 0 && nw <= 0) return hipSuccess;
-  const int32_t gy = blocks_for(std::max((int64_t)max_w * max_h, (int64_t)wmax_w * wmax_h), 256, 64);
-  hipLaunchKernelGGL(update_level_window_kernel, dim3(nl + nw, gy), dim3(256), 0, s, m, base, L,
-                     rects_l, nl, rects_w);
+hipError_t tci_launch_update_group(const tci_map& m, uint32_t* base, int32_t s, int32_t e,
+                                   const int32_t* rects, int32_t stride, int32_t nr,
+                                   int64_t max_items, hipStream_t st) {
+  if (nr <= 0 || e <= s) return hipSuccess;
+  // (up to 8 lanes per item)
+  const int32_t gy = blocks_for(max_items * 8, 256, 64);
+  hipLaunchKernelGGL(update_group_kernel, dim3(2 * (e - s) * nr, gy), dim3(256), 0, st, m, base,
+                     s, e, rects, stride, nr);
   return hipGetLastError();
 }
 

@@ -164,8 +164,9 @@ tci_render_opts render_opts(const tc_context* c) {
 
 hipError_t enqueue_edits(const tci_map& d, uint32_t* map, const char* dev,
                          const EditPlan& p, hipStream_t s, const tci_voxels* vx,
-                         uint32_t* vox) {
+                         uint32_t* vox, uint64_t* zero, int32_t nzero) {
   hipError_t e = tci_launch_edits((const tci_edit*)(dev + p.off_edits), p.n,
+                                  (const int32_t*)(dev + p.off_olap), p.olap_all,
                                   (const uint8_t*)(dev + p.off_patch), map, d.lv[0],
                                   d.W, d.H, p.max_w, p.max_h, s);
   const int32_t* rects = (const int32_t*)(dev + p.off_rects);
@@ -184,7 +185,7 @@ hipError_t enqueue_edits(const tci_map& d, uint32_t* map, const char* dev,
   }
   if (e == hipSuccess)
     e = tci_launch_update_window(d, map, p.top, rects + 4 * (size_t)p.top * p.n, p.nrect[p.top],
-                                 p.rmw[p.top] + 1, p.rmh[p.top] + 1, s);
+                                 p.rmw[p.top] + 1, p.rmh[p.top] + 1, s, zero, nzero);
   // and the voxel tiles over the edited cells, level by level upward
   if (vx && vox) {
     tci_map dm = d;
@@ -226,6 +227,12 @@ tc_status build_voxels(tc_context* ctx, hipStream_t s) {
   ctx->vdesc = vx;
   ctx->map_generation++;
   return TC_OK;
+}
+
+int32_t render_counter_words(const tc_context* ctx, const ViewPlan& p) {
+  if (ctx->render_mode == 3) return 0;
+  if (ctx->render_mode == 2) return 1;
+  return p.qcap > 0 ? 2 : 0;
 }
 
 hipError_t enqueue_render(tc_context* ctx, const tci_map& d, const char* dev,

@@ -64,10 +64,15 @@ tc_status validate_edits(tc_context* ctx, const tc_edit* edits, int32_t n,
                          size_t* patch_bytes);
 // Enqueue the edits of `plan` (uploaded at dev) on the map at `map`, then
 // the dirty update of its pyramid, window levels and, if vx is given, of
-// the voxel occupancy pyramid at vox.
+// the voxel occupancy pyramid at vox.  The update also clears
+// zero[0 .. nzero) (a captured frame's render counters) before it ends.
 hipError_t enqueue_edits(const tci_map& d, uint32_t* map, const char* dev,
                          const EditPlan& plan, hipStream_t s,
-                         const tci_voxels* vx = nullptr, uint32_t* vox = nullptr);
+                         const tci_voxels* vx = nullptr, uint32_t* vox = nullptr,
+                         uint64_t* zero = nullptr, int32_t nzero = 0);
+// The 64-bit counters at plan.off_counter that enqueue_render clears before
+// its kernels unless told they are zero already: 0, 1 or 2.
+int32_t render_counter_words(const tc_context* ctx, const ViewPlan& plan);
 // (Re)build the context's voxel occupancy pyramid for its map and
 // TC_OPT_VOXEL_SHAPE (freeing it when the shape is 0); synchronises s.
 tc_status build_voxels(tc_context* ctx, hipStream_t s);

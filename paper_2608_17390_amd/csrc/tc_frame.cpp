@@ -115,11 +115,16 @@ tc_status tc_frame_create(tc_context* ctx, const tc_view* views, int32_t nviews,
     if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
       hipError_t le = hipSuccess;
+      // with edits, their last launch clears the render's counters (one
+      // node fewer in the graph)
+      const int32_t nz = nedits > 0 ? tci::render_counter_words(ctx, vp) : 0;
       if (nedits > 0)
         le = tci::enqueue_edits(ctx->desc, ctx->map, (const char*)f->dev + off_e, ep, cs,
-                                ctx->vox ? &ctx->vdesc : nullptr, ctx->vox);
+                                ctx->vox ? &ctx->vdesc : nullptr, ctx->vox,
+                                (uint64_t*)((char*)f->dev + vp.off_counter), nz);
       if (le == hipSuccess)
-        le = tci::enqueue_render(ctx, ctx->desc, (const char*)f->dev, vp, out_device, cs);
+        le = tci::enqueue_render(ctx, ctx->desc, (const char*)f->dev, vp, out_device, cs,
+                                 nullptr, nullptr, nz > 0);
       e = hipStreamEndCapture(cs, &f->graph);
       if (e == hipSuccess) e = le;
     }

@@ -73,8 +73,10 @@ hipError_t tci_launch_repack(const uint8_t* planes, int32_t W, int32_t H,
                              uint32_t* base, tci_level l0, hipStream_t s);
 hipError_t tci_launch_build_level(const tci_map& m, uint32_t* base, int32_t L,
                                   hipStream_t s);
-hipError_t tci_launch_edits(const tci_edit* edits, int32_t n,
-                            const uint8_t* patch, uint32_t* base,
+// Edits in list order (olap: the overlap lists of the uploaded edit plan;
+// olap_all: test every edit against every other instead).
+hipError_t tci_launch_edits(const tci_edit* edits, int32_t n, const int32_t* olap,
+                            bool olap_all, const uint8_t* patch, uint32_t* base,
                             tci_level l0, int32_t W, int32_t H,
                             int32_t max_w, int32_t max_h, hipStream_t s);
 // One launch per group of levels s + 1 .. e after edits: recompute the
@@ -93,9 +95,12 @@ hipError_t tci_launch_update_group(const tci_map& m, uint32_t* base, int32_t s, 
 // entries x0 - 1 .. x1, y0 - 1 .. y1, the largest spanning max_w x max_h.
 hipError_t tci_launch_build_window(const tci_map& m, uint32_t* base, int32_t L,
                                    hipStream_t s);
+// The same launch also clears zero[0 .. nzero) (nzero <= 256), or, with no
+// rectangle, a launch of its own does.
 hipError_t tci_launch_update_window(const tci_map& m, uint32_t* base, int32_t L,
                                     const int32_t* rects, int32_t nrect, int32_t max_w,
-                                    int32_t max_h, hipStream_t s);
+                                    int32_t max_h, hipStream_t s, uint64_t* zero = nullptr,
+                                    int32_t nzero = 0);
 
 // Render: views on the device, one thread per pixel.  flat: 0 the
 // hierarchical walk, 1 the flat walk, 2 the hierarchical walk with the

@@ -153,44 +153,55 @@ __device__ inline uint32_t apply_one(const tci_edit& e,
     uint32_t F = patch[o], B = patch[o + n], T = patch[o + 2 * n];
     return F | (B << 8) | (T << 16);
   }
-  // crater of size s = w = h
-  int32_t s = e.w;
-  int64_t a = 2 * i + 1 - s, b = 2 * j + 1 - s;
-  int64_t r2 = a * a + b * b, R2 = (int64_t)s * s;
+  // crater of size s = w = h <= 4096 and depth <= 255: r2 < 2^25 and
+  // depth (R2 - r2) < 2^32, so 32-bit arithmetic is exact
+  const int32_t s = e.w;
+  const int32_t a = 2 * i + 1 - s, b = 2 * j + 1 - s;
+  const uint32_t r2 = (uint32_t)(a * a) + (uint32_t)(b * b), R2 = (uint32_t)(s * s);
   if (r2 >= R2) return col;
-  int64_t drop = ((int64_t)e.depth * (R2 - r2)) / R2;
-  int64_t F = (int64_t)(col & 0xFF) - drop;
-  return (uint32_t)(F < 0 ? 0 : F);  // slab removed: B = T = 0
+  const uint32_t drop = ((uint32_t)e.depth * (R2 - r2)) / R2;
+  const uint32_t F = col & 0xFF;
+  return F > drop ? F - drop : 0u;  // slab removed: B = T = 0
 }
 
 // grid.x = edit index; threads stride over that edit's clipped rectangle.
 // A cell is owned by the first edit that covers it; the owner applies all
 // covering edits in list order, so the result is the sequential one and no
-// two threads write the same cell.
+// two threads write the same cell.  Only the edits whose rectangles meet
+// this edit's can cover its cells: olap lists them (start[n + 1], then the
+// ascending lists), or with `all` every edit is tested.
 __global__ void edits_kernel(const tci_edit* __restrict__ edits, int32_t n,
+                             const int32_t* __restrict__ olap, int32_t all,
                              const uint8_t* __restrict__ patch,
                              uint32_t* __restrict__ base, tci_level l0,
                              int32_t W, int32_t H) {
-  int32_t ei = blockIdx.x;
-  tci_edit e = edits[ei];
-  int32_t x0 = max(e.x0, 0), y0 = max(e.y0, 0);
-  int32_t x1 = min(e.x0 + e.w, W), y1 = min(e.y0 + e.h, H);
+  const int32_t ei = blockIdx.x;
+  const tci_edit e = edits[ei];
+  const int32_t x0 = max(e.x0, 0), y0 = max(e.y0, 0);
+  const int32_t x1 = min(e.x0 + e.w, W), y1 = min(e.y0 + e.h, H);
   if (x0 >= x1 || y0 >= y1) return;
-  int32_t cw = x1 - x0;
-  int64_t cells = (int64_t)cw * (y1 - y0);
-  for (int64_t k = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; k < cells;
-       k += (int64_t)gridDim.y * blockDim.x) {
-    int32_t x = x0 + (int32_t)(k % cw), y = y0 + (int32_t)(k / cw);
+  const int32_t lb = all ? 0 : olap[ei], lc = all ? n : olap[ei + 1] - lb;
+  const int32_t* lst = olap + n + 1 + lb;
+  // (a clipped rectangle holds at most 2^28 cells)
+  const int32_t cw = x1 - x0, cells = cw * (y1 - y0);
+  for (int32_t k = blockIdx.y * blockDim.x + threadIdx.x; k < cells;
+       k += gridDim.y * blockDim.x) {
+    const int32_t x = x0 + k % cw, y = y0 + k / cw;
     bool owned = true;
-    for (int32_t p = 0; p < ei; ++p)
-      if (covers(edits[p], x, y)) { owned = false; break; }
+    for (int32_t t = 0; t < lc; ++t) {
+      const int32_t p = all ? t : lst[t];
+      if (p >= ei) break;
+      if (covers(edits[p], x, y)) {
+        owned = false;
+        break;
+      }
+    }
     if (!owned) continue;
-    uint32_t idx = tci_tile_index(l0, x, y);
-    uint32_t col = base[idx];
-    col = apply_one(e, patch, col, x, y);
-    for (int32_t q = ei + 1; q < n; ++q) {
-      tci_edit f = edits[q];
-      if (covers(f, x, y)) col = apply_one(f, patch, col, x, y);
+    const uint32_t idx = tci_tile_index(l0, x, y);
+    uint32_t col = apply_one(e, patch, base[idx], x, y);
+    for (int32_t t = 0; t < lc; ++t) {
+      const int32_t q = all ? t : lst[t];
+      if (q > ei && covers(edits[q], x, y)) col = apply_one(edits[q], patch, col, x, y);
     }
     base[idx] = col;
   }
@@ -229,9 +240,12 @@ __global__ void build_window_kernel(tci_map m, uint32_t* __restrict__ base, int3
 
 // grid.x = rectangle index: entries x0 - 1 .. x1, y0 - 1 .. y1 (clipped to
 // the level) of the level-L rectangle, the entries whose 2 x 2 node block
-// meets it.
+// meets it.  The first block also clears zero[0 .. nzero) (a captured
+// frame's render counters: one launch fewer in the frame).
 __global__ void update_window_kernel(tci_map m, uint32_t* __restrict__ base, int32_t L,
-                                     const int32_t* __restrict__ rects) {
+                                     const int32_t* __restrict__ rects, uint64_t* zero,
+                                     int32_t nzero) {
+  if (blockIdx.x == 0 && blockIdx.y == 0 && (int32_t)threadIdx.x < nzero) zero[threadIdx.x] = 0;
   const int32_t* r = rects + 4 * blockIdx.x;
   const tci_level& w = m.wl[L];
   const int32_t x0 = max(r[0] - 1, 0), y0 = max(r[1] - 1, 0);
@@ -398,14 +412,14 @@ hipError_t tci_launch_build_level(const tci_map& m, uint32_t* base, int32_t L,
   return hipGetLastError();
 }
 
-hipError_t tci_launch_edits(const tci_edit* edits, int32_t n,
-                            const uint8_t* patch, uint32_t* base,
+hipError_t tci_launch_edits(const tci_edit* edits, int32_t n, const int32_t* olap,
+                            bool olap_all, const uint8_t* patch, uint32_t* base,
                             tci_level l0, int32_t W, int32_t H,
                             int32_t max_w, int32_t max_h, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   int32_t gy = blocks_for((int64_t)max_w * max_h, 256, 64);
-  hipLaunchKernelGGL(edits_kernel, dim3(n, gy), dim3(256), 0, s, edits, n,
-                     patch, base, l0, W, H);
+  hipLaunchKernelGGL(edits_kernel, dim3(n, gy), dim3(256), 0, s, edits, n, olap,
+                     (int32_t)olap_all, patch, base, l0, W, H);
   return hipGetLastError();
 }
 
@@ -420,10 +434,12 @@ hipError_t tci_launch_build_window(const tci_map& m, uint32_t* base, int32_t L,
 
 hipError_t tci_launch_update_window(const tci_map& m, uint32_t* base, int32_t L,
                                     const int32_t* rects, int32_t nrect, int32_t max_w,
-                                    int32_t max_h, hipStream_t s) {
-  if (nrect <= 0) return hipSuccess;
+                                    int32_t max_h, hipStream_t s, uint64_t* zero,
+                                    int32_t nzero) {
+  if (nrect <= 0) return nzero > 0 ? tci_launch_zero_u64(zero, nzero, s) : hipSuccess;
   const int32_t gy = blocks_for((int64_t)max_w * max_h, 256, 64);
-  hipLaunchKernelGGL(update_window_kernel, dim3(nrect, gy), dim3(256), 0, s, m, base, L, rects);
+  hipLaunchKernelGGL(update_window_kernel, dim3(nrect, gy), dim3(256), 0, s, m, base, L, rects,
+                     zero, nzero);
   return hipGetLastError();
 }
 

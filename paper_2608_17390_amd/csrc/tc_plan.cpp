@@ -155,6 +155,69 @@ tc_status check_edits(const tc_edit* edits, int32_t n, size_t* patch_bytes,
   return TC_OK;
 }
 
+namespace {
+
+// For every edit, the other edits whose clipped rectangles ([x0, x1) x
+// [y0, y1), empty for an edit wholly outside the map) meet its own, in
+// ascending order: start[n + 1], then the lists.  Candidates come from a
+// grid of 128 x 128-cell buckets (every pair for short lists); false if
+// they would be too many to list (a bucket with more than 512 edits, or
+// more than 8 n + 2^20 entries), and the edits kernel then tests every
+// edit against every other.
+bool edit_overlaps(const std::vector<int32_t>& cr, int32_t n, std::vector<int32_t>& out) {
+  auto live = [&](int32_t i) { return cr[4 * i] < cr[4 * i + 2] && cr[4 * i + 1] < cr[4 * i + 3]; };
+  auto meet = [&](int32_t i, int32_t j) {
+    return cr[4 * i] < cr[4 * j + 2] && cr[4 * j] < cr[4 * i + 2] &&
+           cr[4 * i + 1] < cr[4 * j + 3] && cr[4 * j + 1] < cr[4 * i + 3];
+  };
+  const size_t cap = 8 * (size_t)n + ((size_t)1 << 20);
+  std::vector<std::vector<int32_t>> lists(n);
+  size_t total = 0;
+  if (n <= 64) {
+    for (int32_t i = 0; i < n; ++i)
+      for (int32_t j = 0; j < n; ++j)
+        if (j != i && live(i) && live(j) && meet(i, j)) lists[i].push_back(j);
+  } else {
+    constexpr int32_t kB = 7;   // 128-cell buckets
+    std::vector<std::pair<int64_t, int32_t>> keys;
+    for (int32_t i = 0; i < n; ++i) {
+      if (!live(i)) continue;
+      const int64_t bx0 = cr[4 * i] >> kB, by0 = cr[4 * i + 1] >> kB;
+      const int64_t bx1 = (cr[4 * i + 2] - 1) >> kB, by1 = (cr[4 * i + 3] - 1) >> kB;
+      if ((size_t)((bx1 - bx0 + 1) * (by1 - by0 + 1)) + keys.size() > cap) return false;
+      for (int64_t by = by0; by <= by1; ++by)
+        for (int64_t bx = bx0; bx <= bx1; ++bx) keys.emplace_back((by << 20) | bx, i);
+    }
+    std::sort(keys.begin(), keys.end());
+    for (size_t a = 0; a < keys.size();) {
+      size_t b = a;
+      while (b < keys.size() && keys[b].first == keys[a].first) ++b;
+      if (b - a > 512) return false;
+      for (size_t u = a; u < b; ++u)
+        for (size_t v = a; v < b; ++v)
+          if (u != v && meet(keys[u].second, keys[v].second))
+            lists[keys[u].second].push_back(keys[v].second);
+      if ((total += (b - a) * (b - a)) > 64 * cap) return false;
+      a = b;
+    }
+  }
+  out.assign(n + 1, 0);
+  total = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    std::vector<int32_t>& l = lists[i];
+    std::sort(l.begin(), l.end());
+    l.erase(std::unique(l.begin(), l.end()), l.end());
+    out[i] = (int32_t)total;
+    total += l.size();
+    if (total > cap) return false;
+  }
+  out[n] = (int32_t)total;
+  for (int32_t i = 0; i < n; ++i) out.insert(out.end(), lists[i].begin(), lists[i].end());
+  return true;
+}
+
+}  // namespace
+
 void plan_edits(const tci_map& d, const tc_edit* edits, int32_t n,
                 size_t patch_bytes, char* host, EditPlan& p) {
   const int32_t top = d.top;
@@ -162,8 +225,20 @@ void plan_edits(const tci_map& d, const tc_edit* edits, int32_t n,
   p.top = top;
   p.off_edits = 0;
   p.off_rects = (sizeof(tci_edit) * (size_t)n + 15) & ~(size_t)15;
-  p.off_patch = p.off_rects + sizeof(int32_t) * 4 * (size_t)n * (size_t)(top + 1);
+  p.off_olap = p.off_rects + sizeof(int32_t) * 4 * (size_t)n * (size_t)(top + 1);
+  std::vector<int32_t> cr(4 * (size_t)n);
+  for (int32_t i = 0; i < n; ++i) {
+    const tc_edit& e = edits[i];
+    cr[4 * i] = std::max(e.x0, 0);
+    cr[4 * i + 1] = std::max(e.y0, 0);
+    cr[4 * i + 2] = std::min(e.x0 + e.w, d.W);
+    cr[4 * i + 3] = std::min(e.y0 + e.h, d.H);
+  }
+  p.olap_all = !edit_overlaps(cr, n, p.olap);
+  if (p.olap_all) p.olap.assign(n + 1, 0);
+  p.off_patch = (p.off_olap + sizeof(int32_t) * p.olap.size() + 15) & ~(size_t)15;
   p.total = p.off_patch + patch_bytes;
+  if (host) memcpy(host + p.off_olap, p.olap.data(), sizeof(int32_t) * p.olap.size());
   p.nrect.assign(top + 1, 0);
   p.rmw.assign(top + 1, 1);
   p.rmh.assign(top + 1, 1);

@@ -105,14 +105,20 @@ namespace tci {
 constexpr size_t kQueueEntry = 16;
 
 // Layout of an uploaded edit list: descriptors, the clipped rectangle of
-// every edit on every level 0..top (level L's at rects + 4 (L n + k)), and
-// SET patch bytes.
+// every edit on every level 0..top (level L's at rects + 4 (L n + k)), the
+// overlap lists, and SET patch bytes.  Overlap lists: int32 start[n + 1]
+// then the lists, edit i's (the other edits whose clipped rectangle meets
+// its own, ascending) at start[i] .. start[i + 1] - 1 after start[n]; with
+// olap_all set (too many candidates to list) every edit tests every other
+// and the lists are empty.
 struct EditPlan {
   int32_t n = 0;
   int32_t top = 0;
-  size_t off_edits = 0, off_rects = 0, off_patch = 0, total = 0;
+  size_t off_edits = 0, off_rects = 0, off_olap = 0, off_patch = 0, total = 0;
   int32_t max_w = 1, max_h = 1;
+  bool olap_all = false;
   std::vector<int32_t> nrect, rmw, rmh;   // per level 0..top
+  std::vector<int32_t> olap;              // start[n + 1], then the lists
 };
 
 // Device tables of a render call: views, packet prefix and queue counter.

@@ -9,6 +9,7 @@
 // levels inside the allocation.
 //
 // Usage: plan_sanitize [iterations] [seed]
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -65,7 +66,9 @@ tc_view random_view(bool valid) {
         break;
       }
       case 4: v.o0[0] = 2147483647 - rint_in(0, 10); v.o_px[0] = 1 << 20; break;
-      default: v.d_px[1] = (1 << 22); v.d0[1] = 1 << 22; break;
+      // pixel (0, 0)'s direction has y component 2^22 + 2^22 = 2^23, beyond
+      // the limit whatever the view's size
+      default: v.d_px[1] = (1 << 22); v.d0[1] = 1 << 22; v.d_py[1] = 0; break;
     }
   }
   return v;
@@ -228,9 +231,10 @@ int main(int argc, char** argv) {
     // edits
     {
       const bool valid = rint_in(0, 3) != 0;
-      const int32_t n = rint_in(0, 30);
+      // (now and then a list long enough for the overlap lists' bucket grid)
+      const int32_t n = rint_in(0, 7) == 0 ? rint_in(65, 400) : rint_in(0, 30);
       std::vector<Patch> keep;
-      keep.reserve(64);
+      keep.reserve(512);
       std::vector<tc_edit> e;
       for (int32_t i = 0; i < n; ++i)
         e.push_back(random_edit(W, H, keep, valid || i != n / 2));
@@ -246,6 +250,37 @@ int main(int argc, char** argv) {
         std::vector<char> host(sized.total);
         tci::plan_edits(d, e.data(), n, pb, host.data(), p);
         CHECK(p.total == sized.total && p.off_patch + pb == p.total, "edit plan sizes");
+        CHECK(p.off_olap >= p.off_rects + 16 * (size_t)n * (size_t)(d.top + 1) &&
+                  p.off_patch >= p.off_olap + 4 * p.olap.size() &&
+                  p.olap.size() >= (size_t)n + 1,
+              "edit plan regions overlap");
+        // overlap lists: written, and for every edit exactly the other edits
+        // whose clipped rectangles meet its own, ascending
+        const int32_t* ol = reinterpret_cast<const int32_t*>(host.data() + p.off_olap);
+        CHECK(std::equal(p.olap.begin(), p.olap.end(), ol), "overlap lists not written");
+        if (!p.olap_all) {
+          auto clip = [&](const tc_edit& x, int32_t c[4]) {
+            c[0] = std::max(x.x0, 0);
+            c[1] = std::max(x.y0, 0);
+            c[2] = std::min(x.x0 + x.w, W);
+            c[3] = std::min(x.y0 + x.h, H);
+          };
+          for (int32_t i = 0; i < n; ++i) {
+            int32_t a[4];
+            clip(e[i], a);
+            std::vector<int32_t> want;
+            for (int32_t j = 0; j < n && a[0] < a[2] && a[1] < a[3]; ++j) {
+              int32_t c[4];
+              clip(e[j], c);
+              if (j != i && c[0] < c[2] && c[1] < c[3] && a[0] < c[2] && c[0] < a[2] &&
+                  a[1] < c[3] && c[1] < a[3])
+                want.push_back(j);
+            }
+            CHECK(ol[i + 1] - ol[i] == (int32_t)want.size() &&
+                      std::equal(want.begin(), want.end(), ol + n + 1 + ol[i]),
+                  "overlap list of edit %d", i);
+          }
+        }
         const int32_t* r = reinterpret_cast<const int32_t*>(host.data() + p.off_rects);
         for (int32_t L = 0; L <= d.top; ++L) {
           for (int32_t k = 0; k < p.nrect[L]; ++k) {

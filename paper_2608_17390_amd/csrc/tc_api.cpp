@@ -172,20 +172,26 @@ hipError_t enqueue_edits(const tci_map& d, uint32_t* map, const char* dev,
   const int32_t* rects = (const int32_t*)(dev + p.off_rects);
   // upward in groups of kUpdateGroup levels, one launch each: the dirty
   // nodes of levels s + 1 .. e and the window entries of levels s .. e - 1
-  // whose 2 x 2 node block meets an edited node, all computed from level s
-  // (each launch is a node of its own in a captured frame, and a few
-  // microseconds however little it does); then the top level's window
-  // entries
+  // (the top group: s .. e) whose 2 x 2 node block meets an edited node,
+  // all computed from level s (each launch is a node of its own in a
+  // captured frame, and a few microseconds however little it does)
+  if (p.top == 0 && e == hipSuccess)
+    e = tci_launch_update_window(d, map, 0, rects, p.nrect[0], p.rmw[0] + 1, p.rmh[0] + 1, s,
+                                 zero, nzero);
   for (int32_t s0 = 0; s0 < p.top && e == hipSuccess; s0 += kUpdateGroup) {
     const int32_t e0 = std::min(s0 + kUpdateGroup, p.top);
-    int64_t items = 1;
-    for (int32_t L = s0; L <= e0; ++L)
-      items = std::max<int64_t>(items, (int64_t)(p.rmw[L] + 1) * (p.rmh[L] + 1));
-    e = tci_launch_update_group(d, map, s0, e0, rects, p.n, p.nrect[0], items, s);
+    const bool last = e0 == p.top;
+    // lanes of the largest job: a node of level L takes 2^(L - s0) lanes,
+    // a window entry 2^(L - s0 + 1)
+    int64_t lanes = 1;
+    for (int32_t L = s0; L <= e0; ++L) {
+      if (L > s0) lanes = std::max<int64_t>(lanes, ((int64_t)p.rmw[L] * p.rmh[L]) << (L - s0));
+      if (L < e0 || last)
+        lanes = std::max<int64_t>(lanes, ((int64_t)(p.rmw[L] + 1) * (p.rmh[L] + 1)) << (L - s0 + 1));
+    }
+    e = tci_launch_update_group(d, map, s0, e0, last, rects, p.n, p.nrect[0], lanes, s,
+                                last ? zero : nullptr, last ? nzero : 0);
   }
-  if (e == hipSuccess)
-    e = tci_launch_update_window(d, map, p.top, rects + 4 * (size_t)p.top * p.n, p.nrect[p.top],
-                                 p.rmw[p.top] + 1, p.rmh[p.top] + 1, s, zero, nzero);
   // and the voxel tiles over the edited cells, level by level upward
   if (vx && vox) {
     tci_map dm = d;

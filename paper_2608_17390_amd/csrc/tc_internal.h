@@ -81,14 +81,18 @@ hipError_t tci_launch_edits(const tci_edit* edits, int32_t n, const int32_t* ola
                             int32_t max_w, int32_t max_h, hipStream_t s);
 // One launch per group of levels s + 1 .. e after edits: recompute the
 // nodes (and occupancy masks) of those levels over their rectangles and the
-// window entries of levels s .. e - 1 over theirs (entries x0 - 1 .. x1,
-// y0 - 1 .. y1), all from level s, which must be up to date.  rects holds
+// window entries of levels s .. e - 1, with wtop s .. e, over theirs
+// (entries x0 - 1 .. x1, y0 - 1 .. y1), all from level s, which must be up
+// to date (e - s <= 3).  The launch also clears zero[0 .. nzero) (nzero <=
+// 256), or a launch of its own does if there is nothing to update.  rects holds
 // nr rectangles per level (x0, y0, x1, y1 inclusive, in that level's node
-// coordinates), level L's at rects + 4 * (L * stride + r); max_items bounds
-// the nodes or entries of any one rectangle job.
+// coordinates), level L's at rects + 4 * (L * stride + r); max_lanes bounds
+// the lanes of any one rectangle job (2^(L - s) per node of level L,
+// 2^(L - s + 1) per window entry).
 hipError_t tci_launch_update_group(const tci_map& m, uint32_t* base, int32_t s, int32_t e,
-                                   const int32_t* rects, int32_t stride, int32_t nr,
-                                   int64_t max_items, hipStream_t st);
+                                   bool wtop, const int32_t* rects, int32_t stride, int32_t nr,
+                                   int64_t max_lanes, hipStream_t st, uint64_t* zero = nullptr,
+                                   int32_t nzero = 0);
 
 // Window level L from level L (all entries), and its entries whose node
 // block meets one of the level-L rectangles (x0, y0, x1, y1 inclusive):

@@ -343,17 +343,20 @@ __device__ inline void group_job(const tci_map& m, uint32_t* base, int32_t s, in
 // One launch per group of levels after edits, reading only level s, which
 // the launch before finished (level 0, the cells, for the first group):
 // blocks [0, (e - s) nr) recompute the dirty nodes and masks of levels
-// s + 1 .. e; blocks [(e - s) nr, 2 (e - s) nr) the dirty window entries of
-// levels s .. e - 1.  Job j of either kind is level (first level) + j / nr,
-// rectangle j % nr; the rectangles of level L (x0, y0, x1, y1 inclusive,
-// in level-L node coordinates) are at rects + 4 (L stride + r).  Every
-// output depends on level s alone, so no job waits for another, and a
-// level's rectangles may overlap (two threads then write the same value).
-// Groups of at most 3 levels keep blocks at most 8 x 8 nodes: k <= 3 for a
-// node, k <= 2 for a window entry.
+// s + 1 .. e; the blocks after them the dirty window entries of levels
+// s .. e - 1, and with wtop of level e too (the top group).  Job j of either
+// kind is level (first level) + j / nr, rectangle j % nr; the rectangles of
+// level L (x0, y0, x1, y1 inclusive, in level-L node coordinates) are at
+// rects + 4 (L stride + r).  Every output depends on level s alone, so no
+// job waits for another, and a level's rectangles may overlap (two threads
+// then write the same value).  Groups of at most 3 levels keep blocks at
+// most 8 x 8 nodes for a node (k <= 3) and 16 x 16 for a window entry.  The
+// first block also clears zero[0 .. nzero) (a captured frame's render
+// counters, in the top group).
 __global__ void update_group_kernel(tci_map m, uint32_t* __restrict__ base, int32_t s,
-                                    int32_t e, const int32_t* __restrict__ rects,
-                                    int32_t stride, int32_t nr) {
+                                    int32_t e, int32_t wtop, const int32_t* __restrict__ rects,
+                                    int32_t stride, int32_t nr, uint64_t* zero, int32_t nzero) {
+  if (blockIdx.x == 0 && blockIdx.y == 0 && (int32_t)threadIdx.x < nzero) zero[threadIdx.x] = 0;
   const int32_t nl = (e - s) * nr;
   const bool node_job = (int32_t)blockIdx.x < nl;
   const int32_t job = node_job ? (int32_t)blockIdx.x : (int32_t)blockIdx.x - nl;
@@ -377,7 +380,8 @@ __global__ void update_group_kernel(tci_map m, uint32_t* __restrict__ base, int3
   if (x0 > x1 || y0 > y1) return;
   if (k == 0) group_job<2, false>(m, base, s, L, x0, y0, x1, y1);
   else if (k == 1) group_job<4, false>(m, base, s, L, x0, y0, x1, y1);
-  else group_job<8, false>(m, base, s, L, x0, y0, x1, y1);
+  else if (k == 2) group_job<8, false>(m, base, s, L, x0, y0, x1, y1);
+  else group_job<16, false>(m, base, s, L, x0, y0, x1, y1);
 }
 
 __global__ void zero_u64_kernel(uint64_t* p, int32_t n) {
@@ -444,13 +448,14 @@ hipError_t tci_launch_update_window(const tci_map& m, uint32_t* base, int32_t L,
 }
 
 hipError_t tci_launch_update_group(const tci_map& m, uint32_t* base, int32_t s, int32_t e,
-                                   const int32_t* rects, int32_t stride, int32_t nr,
-                                   int64_t max_items, hipStream_t st) {
-  if (nr <= 0 || e <= s) return hipSuccess;
-  // (up to 8 lanes per item)
-  const int32_t gy = blocks_for(max_items * 8, 256, 64);
-  hipLaunchKernelGGL(update_group_kernel, dim3(2 * (e - s) * nr, gy), dim3(256), 0, st, m, base,
-                     s, e, rects, stride, nr);
+                                   bool wtop, const int32_t* rects, int32_t stride, int32_t nr,
+                                   int64_t max_lanes, hipStream_t st, uint64_t* zero,
+                                   int32_t nzero) {
+  if (nr <= 0 || e <= s) return nzero > 0 ? tci_launch_zero_u64(zero, nzero, st) : hipSuccess;
+  const int32_t gy = blocks_for(max_lanes, 256, 64);
+  hipLaunchKernelGGL(update_group_kernel, dim3((2 * (e - s) + (wtop ? 1 : 0)) * nr, gy),
+                     dim3(256), 0, st, m, base, s, e, (int32_t)wtop, rects, stride, nr, zero,
+                     nzero);
   return hipGetLastError();
 }
 

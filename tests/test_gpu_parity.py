@@ -544,6 +544,27 @@ def test_edits_small_map(ctx):
     _edited_checks(ctx, F, B, T, edits, views)
 
 
+@pytest.mark.parametrize("shape", [(1, 1), (2, 1), (3, 2), (5, 7), (16, 9), (17, 3), (33, 20),
+                                   (65, 100), (129, 65), (300, 220), (77, 1000), (2049, 60)])
+def test_edits_every_level_grouping(ctx, shape):
+    """The dirty update climbs three pyramid levels per launch, each from the
+    level below its group; maps whose top level is 0 to 12 cover every way
+    the levels fall into groups (a last group of one, two or three levels,
+    and a map with no pyramid level above the cells)."""
+    W, H = shape
+    F, B, T = synth.make_map(W, H, 700 + W + H, dual=0.4, period=4)
+    rng = np.random.default_rng(W * 7 + H)
+    m = max(W, H)
+    edits = (synth.crater_list(rng, W, H, 12, size=(1, min(64, m)), depth=(0, 255)) +
+             synth.random_set_patches(rng, W, H, 8, max_size=max(1, min(40, m))))
+    rng.shuffle(edits)
+    # one crater over the whole map, one hanging over its far corner
+    edits += [dict(kind=2, x0=0, y0=0, w=min(W, H, 4096), h=min(W, H, 4096), depth=40),
+              dict(kind=2, x0=W - 2, y0=H - 2, w=5, h=5, depth=90)]
+    views = _random_views(rng, F, B, 3, [(24, 16), (8, 8)])
+    _edited_checks(ctx, F, B, T, edits, views)
+
+
 def test_edit_sequences_accumulate(ctx):
     """Several apply calls in a row equal one call with the concatenated
     list, and equal the oracle's sequential application."""

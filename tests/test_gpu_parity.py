@@ -591,10 +591,19 @@ def test_c3_edits_then_views_full(ctx):
     _edited_checks(ctx, F, B, T, edits, views, oracle_result=oracle_render(F, B, T, views, edits))
 
 
-def test_c3_graph_frame_full(ctx):
+DEFAULT_KNOBS = ((tc.TC_OPT_RENDER_MODE, 0), (tc.TC_OPT_START_LEVEL, 2), (tc.TC_OPT_TILE_ORDER, 2),
+                 (tc.TC_OPT_XCD_REMAP, 64), (tc.TC_OPT_SPLIT_BUDGET, 128),
+                 (tc.TC_OPT_PACKET_WIDTH, 8), (tc.TC_OPT_MAX_LEVEL, 15),
+                 (tc.TC_OPT_BEAM_PASSES, 6), (tc.TC_OPT_PERSIST_WAVES, 16),
+                 (tc.TC_OPT_REFILL_MIN, 16), (tc.TC_OPT_REFILL_ITERS, 16))
+
+
+@pytest.mark.parametrize("knobs", ["default", "tuned"])
+def test_c3_graph_frame_full(ctx, knobs):
     """The configuration-3 frame as the benchmark times it: one captured
-    graph of the 64 craters, the dirty update and both views with the
-    default knobs (hierarchical walk, beam start, split pass), replayed
+    graph of the 64 craters, the dirty update and both views, with the
+    default knobs (hierarchical walk, beam start, split pass) and with the
+    knobs the autotuner picks for the two views on this machine, replayed
     twice; each replay digs again, and every record of each replay equals
     the oracle's render of the map edited that many times."""
     F, B, T = config_map(3)
@@ -603,16 +612,22 @@ def test_c3_graph_frame_full(ctx):
     views = synth.config_views(3, F, B)
     load(ctx, F, B, T)
     out = torch.empty((synth.view_rays(views), 2), dtype=torch.int32, device="cuda")
-    frame = ctx.tc_frame_create(views, edits, out.data_ptr())
+    frame = None
     try:
+        if knobs == "tuned":
+            ctx.tc_autotune(views, out.data_ptr(), reps=2)
+        frame = ctx.tc_frame_create(views, edits, out.data_ptr())
         for k in (1, 2):
             frame.launch()
             torch.cuda.synchronize()
             wg, dg = tc.split_hits(out)
             wo, do = oracle_render(F, B, T, views, edits * k)
-            assert_parity(wg, dg, wo, do, "c3 graph frame replay %d" % k)
+            assert_parity(wg, dg, wo, do, "c3 graph frame (%s knobs) replay %d" % (knobs, k))
     finally:
-        frame.close()
+        if frame is not None:
+            frame.close()
+        for opt, v in DEFAULT_KNOBS:
+            ctx.tc_set_option(opt, v)
 
 
 def c4_full_check(wg, dg, wo, do, views, what):

@@ -236,7 +236,7 @@ __device__ __forceinline__ void split_body(const tci_map& m,
   const uint32_t grp = (uint32_t)wave / G, g = (uint32_t)wave - grp * G;
   const int32_t lgR = 6 + (G == 4 ? 2 : (G == 2 ? 1 : 0));   // 64 G runs per ray
   const uint32_t n = min(*o.qcount, o.qcap);
-  const int32_t Lmax = clamp_level(o.max_level, m.top);
+  const lvl_t l0 = lv[0];
   for (uint32_t e0 = blockIdx.x * per; e0 < n; e0 += gridDim.x * per) {
     const uint32_t e = e0 + grp;
     if (threadIdx.x < 4) best[threadIdx.x] = 0xFFFFFFFFu;
@@ -279,11 +279,12 @@ __device__ __forceinline__ void split_body(const tci_map& m,
       int32_t st = kSegEnd;
       if (open || b0 != b1) {
         // a run spans a few cell lines close to the terrain, where coarse
-        // nodes would only be descended again: it starts at level 0
+        // nodes would only be descended again: it walks the cells
         if (!walk_at_line(r, k, s, axis, b0)) walk_at_origin(r, 0, s);
         st = kWalking;
       }
-      // walk in chunks; once some run holds a hit, the runs after it
+      // walk in chunks of 16 cells, each chunk's columns loaded together
+      // before it is tested; once some run holds a hit, the runs after it
       // cannot matter and stop.  The ray's vertical direction is the
       // wave's, so the loop is specialised to its sign.
       const bool down = r.Dz < 0;
@@ -295,9 +296,9 @@ __device__ __forceinline__ void split_body(const tci_map& m,
         if (!__ballot(st == kWalking)) break;
         if (st == kWalking) {
           if (down)
-            st = walk_steps<true, false, true, 1>(m, lv, r, k, s, Lmax, 16, col, 0, axis, lo, hi);
+            st = walk_flat<1, 16>(m, l0, r, k, s, col, axis, lo, hi, o.count != nullptr);
           else
-            st = walk_steps<true, false, true, 2>(m, lv, r, k, s, Lmax, 16, col, 0, axis, lo, hi);
+            st = walk_flat<2, 16>(m, l0, r, k, s, col, axis, lo, hi, o.count != nullptr);
         }
       }
       if (o.count && (open || b0 != b1)) atomicAdd(o.count, (unsigned long long)s.reads);

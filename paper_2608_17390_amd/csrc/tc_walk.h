@@ -693,6 +693,86 @@ __device__ __forceinline__ int32_t walk_steps(const tci_map& m, const lvl_t* lv,
   return kWalking;
 }
 
+// The walk kept on the cells (level 0) for up to K cells, for a caller
+// whose walk spans a few cell lines: the cells it enters follow from the
+// keys alone, so the K columns ahead are loaded together first (indices
+// clamped into the map, so every load is valid) and then tested in order
+// from registers, and the walk waits on one round of loads instead of one
+// per cell.  Results and state as walk_steps<kSeg = true, kOcc = false,
+// kCap = true, kDir> with max_level 0: l0 is the cells' level record.
+template <int kDir, int K>
+__device__ __forceinline__ int32_t walk_flat(const tci_map& m, const lvl_t l0, const ray_t& r,
+                                             const walk_idx_t& k, walk_t& s, uint32_t& col,
+                                             int32_t seg_axis, int32_t seg_lo, int32_t seg_hi,
+                                             bool count) {
+  const bool desc = kDir == 1;
+  const bool fx = r.Dx > 0, fy = r.Dy > 0;
+  const int32_t sx = fx ? 1 : -1, sy = fy ? 1 : -1;
+  const int32_t nx1 = fx ? 1 : 0, ny1 = fy ? 1 : 0;
+  auto word_at = [&](int32_t ni, int32_t nj) {
+    const uint32_t ci = (uint32_t)clamp0(ni, l0.w1), cj = (uint32_t)clamp0(nj, l0.h1);
+    return map_word(m.base, l0.off + ((umul24(cj >> 3, (uint32_t)l0.tiles_x) + (ci >> 3)) << 6) +
+                                ((cj & 7) << 3) + (ci & 7));
+  };
+  // the cells ahead: a step leaves through the x face iff the far x
+  // crossing's key is not above the far y crossing's
+  uint32_t w[K];
+  {
+    int32_t ni = s.ni, nj = s.nj;
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      w[t] = word_at(ni, nj);
+      if (t + 1 < K) {
+        const int32_t ix = far_index(ni, 0, nx1, sx, k.offx);
+        const int32_t iy = far_index(nj, 0, ny1, sy, k.offy);
+        const bool ex = add_mul48(k.KX0, (uint32_t)ix, r.ay) <= add_mul48(k.KY0, (uint32_t)iy, r.ax);
+        ni += ex ? sx : 0;
+        nj += ex ? 0 : sy;
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < K; ++t) {
+    if (++s.iters > kIterCap) return kCapped;
+    const int32_t n = seg_axis == 0 ? s.ni : s.nj;
+    if ((n > seg_hi) | (n < seg_lo)) return kSegEnd;
+    const bool inmap = ((uint32_t)s.ni <= (uint32_t)l0.w1) & ((uint32_t)s.nj <= (uint32_t)l0.h1);
+    if (count) s.reads += inmap ? 1 : 0;
+    const uint32_t v = inmap ? w[t] : 0u;
+    const int32_t ix = far_index(s.ni, 0, nx1, sx, k.offx);
+    const int32_t iy = far_index(s.nj, 0, ny1, sy, k.offy);
+    const int64_t KXe = add_mul48(k.KX0, (uint32_t)ix, r.ay);
+    const int64_t KYe = add_mul48(k.KY0, (uint32_t)iy, r.ax);
+    const bool ex = KXe <= KYe;
+    const int64_t Ze = add_smul48(ex ? k.ZX0 : k.ZY0, ex ? ix : iy, r.Dz);
+    const uint32_t De = ex ? r.ax : r.ay;
+    const uint32_t re = ex ? r.rx : r.ry;
+    if (inmap) {
+      const int64_t lo = (desc ? Ze : s.Zin) + (int64_t)(desc ? re : s.rin);
+      const uint32_t Dlo = desc ? De : s.Din;
+      const int64_t hi = desc ? s.Zin : Ze;
+      const uint32_t Dhi = desc ? s.Din : De;
+      const uint32_t a = v & 0xFF, b = (v >> 8) & 0xFF, c = (v >> 16) & 0xFF;
+      if ((lo <= hmul(a, Dlo)) | ((lo <= hmul(c, Dlo)) & (hi >= hmul(b, Dhi)))) {
+        col = v;
+        return kHitCell;
+      }
+    }
+    s.Kin = ex ? KXe : KYe;
+    s.ni += ex ? sx : 0;
+    s.nj += ex ? 0 : sy;
+    s.entry = ex ? (fx ? kWmx : kWpx) : (fy ? kWmy : kWpy);
+    s.Zin = Ze;
+    s.Din = De;
+    s.rin = re;
+    const bool away = ((s.ni < 0) & (r.Dx <= 0)) | ((s.ni > l0.w1) & (r.Dx >= 0)) |
+                      ((s.nj < 0) & (r.Dy <= 0)) | ((s.nj > l0.h1) & (r.Dy >= 0));
+    const bool above = !desc & !z_le(s.Zin, s.rin, 255, s.Din);
+    if (away | above) return kMissed;
+  }
+  return kWalking;
+}
+
 __device__ __forceinline__ void load_levels(const tci_map& m, lvl_t* lv) {
   if (threadIdx.x < TCI_MAX_LEVELS) {
     const tci_level& l = m.lv[threadIdx.x];

@@ -392,8 +392,12 @@ void tc_frame_destroy(tc_frame *frame);
  * passes (0, 2, 4, 6 or 8) of the best one-thread-per-pixel setting, then the
  * packet shape (width 4, 8, 16 or 32), the split budget (96, 112 or 160, when
  * the best setting splits) and the pyramid depth (TC_OPT_MAX_LEVEL: the top
- * level, two and four below it, or 5) around the best setting -- then keep
- * the fastest setting on the context and report it.  Results are those of
+ * level, two and four below it, or 5) around the best setting; when the best
+ * setting is the one-thread-per-pixel mode, a second pass then varies each of
+ * its knobs (start level, packet order, XCD grouping, split budget 0, 96,
+ * 112, 128 or 160, beam passes, packet width, pyramid depth) once more, one
+ * at a time, around the best setting -- then keep the fastest setting on the
+ * context and report it.  Results are those of
  * tc_render_views for every setting (bit-identical); only the time differs.  Synchronises
  * hip_stream.  The paper picks each method's knob by a sweep on a fixed
  * fixture (Section 5.6); this tunes on the caller's workload. */

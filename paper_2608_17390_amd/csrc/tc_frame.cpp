@@ -270,11 +270,34 @@ tc_status tc_autotune(tc_context* ctx, const tc_view* views, int32_t n,
         try_knob(k);
       }
     const int32_t top = ctx->desc.top;
-    for (int32_t maxl : {top, top - 2, top - 4, 5}) {
-      if (st || maxl < 1 || maxl == std::min(bk.maxl, top)) continue;
-      Knobs k = bk;
-      k.maxl = maxl;
-      try_knob(k);
+    const auto try_maxl = [&]() {
+      for (int32_t maxl : {top, top - 2, top - 4, 5}) {
+        if (st || maxl < 1 || maxl == std::min(bk.maxl, top)) continue;
+        Knobs k = bk;
+        k.maxl = maxl;
+        try_knob(k);
+      }
+    };
+    try_maxl();
+    // a second pass over every knob of the one-thread-per-pixel mode, one at
+    // a time around the best setting: each stage above held the knobs of the
+    // stages after it at their starting values
+    if (!st && bk.mode == 0) {
+      const auto sweep = [&](int32_t Knobs::*f, std::initializer_list<int32_t> vals) {
+        for (int32_t v : vals) {
+          if (st || bk.*f == v) continue;
+          Knobs k = bk;
+          k.*f = v;
+          try_knob(k);
+        }
+      };
+      sweep(&Knobs::start, {1, 2, 3, 4});
+      sweep(&Knobs::order, {0, 1, 2});
+      sweep(&Knobs::remap, {0, 8, 64});
+      sweep(&Knobs::split, {0, 96, 112, 128, 160});
+      sweep(&Knobs::beam, {0, 2, 4, 6, 8});
+      sweep(&Knobs::pwidth, {4, 8, 16, 32});
+      try_maxl();
     }
     for (auto& e : ev) (void)hipEventDestroy(e);
     if (st) {

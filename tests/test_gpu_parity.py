@@ -565,6 +565,34 @@ def test_edits_every_level_grouping(ctx, shape):
     _edited_checks(ctx, F, B, T, edits, views)
 
 
+@pytest.mark.parametrize("case", ["scattered", "clustered"])
+def test_long_edit_lists(ctx, case):
+    """Long edit lists: a cell tests only the edits whose rectangles meet its
+    edit's, listed on the host from a grid of 128-cell buckets (300 edits
+    scattered over the map), or, with more than 512 edits in one bucket
+    (700 edits within 96 x 96 cells), every edit against every other; the
+    map and every pyramid level against the oracle's sequential edits."""
+    F, B, T = synth.make_map_from_config(1)
+    rng = np.random.default_rng(71 if case == "scattered" else 72)
+    if case == "scattered":
+        edits = (synth.crater_list(rng, 256, 256, 200, size=(1, 48), depth=(0, 255)) +
+                 synth.random_set_patches(rng, 256, 256, 100, max_size=24))
+    else:
+        edits = (synth.crater_list(rng, 96, 96, 400, size=(1, 16), depth=(0, 255)) +
+                 synth.random_set_patches(rng, 96, 96, 300, max_size=8, allow_outside=False))
+    rng.shuffle(edits)
+    load(ctx, F, B, T)
+    ctx.tc_apply_edit(edits)
+    F2, B2, T2 = oracle.apply_edits(F, B, T, edits)
+    g = ctx.tc_read_columns(0, 0, 256, 256)
+    assert np.array_equal(g[0], F2) and np.array_equal(g[1], B2) and np.array_equal(g[2], T2)
+    for L in range(1, ctx.tc_pyramid_info() + 1):
+        assert np.array_equal(ctx.tc_read_pyramid(L), oracle.pyramid_level_fast(F2, B2, T2, L)), L
+        assert np.array_equal(ctx.tc_read_occupancy(L), oracle.occupancy_level(F2, B2, T2, L)), L
+    for L in range(0, ctx.tc_pyramid_info() + 1):
+        assert np.array_equal(ctx.tc_read_window(L), oracle.window_level_fast(F2, B2, T2, L)), L
+
+
 def test_edit_sequences_accumulate(ctx):
     """Several apply calls in a row equal one call with the concatenated
     list, and equal the oracle's sequential application."""

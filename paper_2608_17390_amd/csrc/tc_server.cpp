@@ -14,9 +14,11 @@
 //    into the buffer that does not hold the newest version -- once no batch
 //    still reads it -- after that buffer has caught up by replaying edit
 //    k - 1 (it holds every edit before that one), on a separate stream;
-//    batches of later views wait for that stream's event.  Every edit is
-//    thus applied twice, once per buffer, and no map is ever copied.  A
-//    view's result is the same alone and in any mix.
+//    batches of later views wait for that stream's event.  The catch-up
+//    replay runs as soon as no batch reads the older buffer, usually well
+//    before edit k arrives, so edit k then costs only its own update.
+//    Every edit is thus applied twice, once per buffer, and no map is ever
+//    copied.  A view's result is the same alone and in any mix.
 //  * batches run the render mode and options of the context; the split
 //    pass of the hierarchical mode runs for batches of at most two views
 //    (a lone large view's longest rays then finish in parallel, as in
@@ -388,6 +390,26 @@ bool apply_edit(tc_server* s, uint64_t id) {
   return true;
 }
 
+// Bring the version buffer that is not current up to date in the background
+// (replay the newest edit onto it, on the edit stream) as soon as no batch
+// reads it, so that the next edit finds it ready: views waiting on that
+// edit then wait for its own update only, not for the replay before it.
+void catch_up(tc_server* s) {
+  const int other = 1 - s->current;
+  if (s->edits_applied == 0 || s->ver_epoch[other] == s->ver_epoch[s->current] ||
+      s->ver_readers[other] > 0)
+    return;
+  const EditUpload& prev = s->uploads[(s->edits_applied - 1) & 1];
+  if (!prev.valid || prev.epoch != s->ver_epoch[s->current]) return;  // apply_edit reports it
+  const hipError_t e = tci::enqueue_edits(version_desc(s, other), s->ver[other],
+                                          (const char*)prev.slot.dev, prev.plan, s->edit_stream);
+  if (e != hipSuccess) {
+    set_error(s, e, "server: edit replay");
+    return;
+  }
+  s->ver_epoch[other] = s->ver_epoch[s->current];
+}
+
 void poll_completions(tc_server* s) {
   for (Batch& b : s->slots) {
     if (!b.busy) continue;
@@ -462,6 +484,7 @@ void server_loop(tc_server* s) {
       if ((int32_t)s->admitted.size() >= s->max_batch && !launch_batch(s)) break;
     }
     if (!s->admitted.empty()) launch_batch(s);
+    catch_up(s);
     bool idle;
     {
       std::lock_guard<std::mutex> g(s->mu);

@@ -430,7 +430,9 @@ tc_status tc_autotune(tc_context *ctx, const tc_view *views, int32_t n,
  * mode runs for batches of at most two views and is off for larger ones.  A view sees exactly the edits submitted before
  * it: the map is kept in two version buffers, and an edit is applied to the
  * buffer not holding the newest version, once no batch reads it, after that
- * buffer replays the previous edit; starting a server copies the map once
+ * buffer replays the previous edit (a replay the server starts on its own as
+ * soon as no batch reads that buffer, so an edit usually waits only for its
+ * own update); starting a server copies the map once
  * into the second buffer.  While a server runs it owns the map:
  * tc_load_columns, tc_apply_edit, tc_render_views and frames on the context
  * fail with TC_INVALID_ARG, and the render knobs must not change.

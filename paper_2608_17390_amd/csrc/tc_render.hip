@@ -283,7 +283,7 @@ __device__ __forceinline__ void split_body(const tci_map& m,
         if (!walk_at_line(r, k, s, axis, b0)) walk_at_origin(r, 0, s);
         st = kWalking;
       }
-      // walk in chunks of 16 cells, each chunk's columns loaded together
+      // walk in chunks of 10 cells, each chunk's columns loaded together
       // before it is tested; once some run holds a hit, the runs after it
       // cannot matter and stop.  The ray's vertical direction is the
       // wave's, so the loop is specialised to its sign.
@@ -296,9 +296,9 @@ __device__ __forceinline__ void split_body(const tci_map& m,
         if (!__ballot(st == kWalking)) break;
         if (st == kWalking) {
           if (down)
-            st = walk_flat<1, 16>(m, l0, r, k, s, col, axis, lo, hi, o.count != nullptr);
+            st = walk_flat<1, 10>(m, l0, r, k, s, col, axis, lo, hi, o.count != nullptr);
           else
-            st = walk_flat<2, 16>(m, l0, r, k, s, col, axis, lo, hi, o.count != nullptr);
+            st = walk_flat<2, 10>(m, l0, r, k, s, col, axis, lo, hi, o.count != nullptr);
         }
       }
       if (o.count && (open || b0 != b1)) atomicAdd(o.count, (unsigned long long)s.reads);

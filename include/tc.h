@@ -290,9 +290,10 @@ tc_status tc_shade_views(tc_context *ctx, const tc_view *views, int32_t n,
 #define TC_OPT_SPLIT_BUDGET 11   /* hierarchical mode: a ray still walking
                                     after this many steps is finished by a
                                     second pass that walks 64 runs of its
-                                    path in parallel, each from the exact
-                                    state the walk enters it with (0: no
-                                    second pass; default 128) */
+                                    path per wave in parallel (4 waves by
+                                    default), each from the exact state the
+                                    walk enters it with (0: no second pass;
+                                    default 120) */
 #define TC_OPT_SPLIT_QUEUE 12    /* most rays the second pass takes per call;
                                     further long rays finish in the first
                                     pass (1..2^24, default 131072; every slot
@@ -387,15 +388,15 @@ void tc_frame_destroy(tc_frame *frame);
 /* ---- autotuning ----------------------------------------------------------- */
 /* Time tc_render_views on these views (reps timed calls per setting, median)
  * over a grid of the render knobs -- traversal mode, start level, packet
- * order, XCD grouping, split budget (0 or 128), and the persistent queue's
+ * order, XCD grouping, split budget (0 or 120), and the persistent queue's
  * waves per CU, refill threshold and refill interval, then the packet beam
  * passes (0, 2, 4, 6 or 8) of the best one-thread-per-pixel setting, then the
- * packet shape (width 4, 8, 16 or 32), the split budget (96, 112 or 160, when
+ * packet shape (width 4, 8, 16 or 32), the split budget (96, 112, 128 or 160, when
  * the best setting splits) and the pyramid depth (TC_OPT_MAX_LEVEL: the top
  * level, two and four below it, or 5) around the best setting; when the best
  * setting is the one-thread-per-pixel mode, a second pass then varies each of
  * its knobs (start level, packet order, XCD grouping, split budget 0, 96,
- * 112, 128 or 160, beam passes, packet width, pyramid depth) once more, one
+ * 112, 120, 128 or 160, beam passes, packet width, pyramid depth) once more, one
  * at a time, around the best setting -- then keep the fastest setting on the
  * context and report it.  Results are those of
  * tc_render_views for every setting (bit-identical); only the time differs.  Synchronises

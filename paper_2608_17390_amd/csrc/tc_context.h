@@ -136,7 +136,7 @@ struct tc_context {
   int32_t tile_order = 2;
   int32_t packet_width = 8;
   int32_t boost = 0;
-  int32_t split_budget = 128;
+  int32_t split_budget = 120;
   int32_t beam_passes = 6;
   int32_t split_waves = 4;
   int32_t split_queue = 1 << 17;

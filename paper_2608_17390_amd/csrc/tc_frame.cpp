@@ -183,7 +183,7 @@ tc_status tc_autotune(tc_context* ctx, const tc_view* views, int32_t n,
     hipStream_t s = (hipStream_t)hip_stream;
     std::vector<Knobs> cand;
     const Knobs cur = read_knobs(ctx);
-    for (int32_t split : {0, 128})
+    for (int32_t split : {0, 120})
       for (int32_t order : {0, 1, 2})
         for (int32_t remap : {0, 8, 64})
           for (int32_t start : {1, 2, 3, 4})
@@ -263,7 +263,7 @@ tc_status tc_autotune(tc_context* ctx, const tc_view* views, int32_t n,
     }
     // the split budget, around the best setting when it splits at all
     if (!st && bk.mode == 0 && bk.split > 0)
-      for (int32_t split : {96, 112, 160}) {
+      for (int32_t split : {96, 112, 128, 160}) {
         if (st) break;
         Knobs k = bk;
         k.split = split;
@@ -294,7 +294,7 @@ tc_status tc_autotune(tc_context* ctx, const tc_view* views, int32_t n,
       sweep(&Knobs::start, {1, 2, 3, 4});
       sweep(&Knobs::order, {0, 1, 2});
       sweep(&Knobs::remap, {0, 8, 64});
-      sweep(&Knobs::split, {0, 96, 112, 128, 160});
+      sweep(&Knobs::split, {0, 96, 112, 120, 128, 160});
       sweep(&Knobs::beam, {0, 2, 4, 6, 8});
       sweep(&Knobs::pwidth, {4, 8, 16, 32});
       try_maxl();

@@ -172,7 +172,7 @@ def test_c2_view_and_read_count(ctx):
             assert_parity(wg, dg, wo, do, "c2 passes %d" % passes)
     finally:
         ctx.tc_set_option(tc.TC_OPT_COUNT_READS, 0)
-        ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 128)
+        ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 120)
     rays = synth.view_rays(views)
     print("reads per ray: no beam %.2f, beam %.2f" % (reads[0] / rays, reads[8] / rays))
     assert reads[8] < reads[0]

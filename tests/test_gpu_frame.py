@@ -94,7 +94,7 @@ def test_autotune_keeps_results(ctx):
     best = ctx.tc_autotune(views, out.data_ptr(), reps=2)
     assert best["tried"] >= 72 and best["ms"] > 0
     assert best["render_mode"] in (0, 2)
-    assert best["split_budget"] in (0, 96, 112, 128, 160)
+    assert best["split_budget"] in (0, 96, 112, 120, 128, 160)
     assert ctx.tc_get_option(tc.TC_OPT_SPLIT_BUDGET) == best["split_budget"]
     assert best["beam_passes"] in (0, 2, 4, 6, 8)
     assert ctx.tc_get_option(tc.TC_OPT_BEAM_PASSES) == best["beam_passes"]
@@ -110,7 +110,7 @@ def test_autotune_keeps_results(ctx):
     ctx.tc_set_option(tc.TC_OPT_START_LEVEL, 2)
     ctx.tc_set_option(tc.TC_OPT_TILE_ORDER, 2)
     ctx.tc_set_option(tc.TC_OPT_XCD_REMAP, 64)
-    ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 128)
+    ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 120)
     ctx.tc_set_option(tc.TC_OPT_PACKET_WIDTH, 8)
     ctx.tc_set_option(tc.TC_OPT_MAX_LEVEL, 15)
     ctx.tc_set_option(tc.TC_OPT_BEAM_PASSES, 6)

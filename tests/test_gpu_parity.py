@@ -154,7 +154,7 @@ def test_kernel_timing_leaves_results_unchanged(ctx):
             assert (t1 > 0) == (mode == "hier" and budget > 0), (mode, budget, t1)
     finally:
         ctx.tc_set_option(tc.TC_OPT_KERNEL_TIMING, 0)
-        ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 128)
+        ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 120)
         ctx.tc_set_option(tc.TC_OPT_INLINE_TABLES, 1)
         ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, 0)
 
@@ -291,7 +291,7 @@ def test_split_pass(ctx, budget, queue, waves):
             assert_parity(wg, dg, wo, do, "split budget %d queue %d waves %d start %d" % (
                 budget, queue, waves, start))
     finally:
-        ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 128)
+        ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 120)
         ctx.tc_set_option(tc.TC_OPT_SPLIT_QUEUE, 1 << 17)
         ctx.tc_set_option(tc.TC_OPT_SPLIT_WAVES, 4)
         ctx.tc_set_option(tc.TC_OPT_TILE_ORDER, 2)
@@ -326,7 +326,7 @@ def test_inline_tables(ctx):
                 k, inline, budget, queue, len(vs)))
     finally:
         ctx.tc_set_option(tc.TC_OPT_INLINE_TABLES, 1)
-        ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 128)
+        ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 120)
         ctx.tc_set_option(tc.TC_OPT_SPLIT_QUEUE, 1 << 17)
     for bad in (-1, 2):
         with pytest.raises(tc.TCError):
@@ -361,7 +361,7 @@ def test_split_pass_edge_rays_and_large_map(ctx):
             wg, dg = gpu_render(ctx, v, "hier")
             assert_parity(wg, dg, wo, do, "split c2 budget %d waves %d" % (budget, waves))
     finally:
-        ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 128)
+        ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 120)
         ctx.tc_set_option(tc.TC_OPT_SPLIT_WAVES, 4)
 
 
@@ -620,7 +620,7 @@ def test_c3_edits_then_views_full(ctx):
 
 
 DEFAULT_KNOBS = ((tc.TC_OPT_RENDER_MODE, 0), (tc.TC_OPT_START_LEVEL, 2), (tc.TC_OPT_TILE_ORDER, 2),
-                 (tc.TC_OPT_XCD_REMAP, 64), (tc.TC_OPT_SPLIT_BUDGET, 128),
+                 (tc.TC_OPT_XCD_REMAP, 64), (tc.TC_OPT_SPLIT_BUDGET, 120),
                  (tc.TC_OPT_PACKET_WIDTH, 8), (tc.TC_OPT_MAX_LEVEL, 15),
                  (tc.TC_OPT_BEAM_PASSES, 6), (tc.TC_OPT_PERSIST_WAVES, 16),
                  (tc.TC_OPT_REFILL_MIN, 16), (tc.TC_OPT_REFILL_ITERS, 16))
@@ -705,7 +705,7 @@ def test_renders_allocate_nothing(ctx):
                                rgba.data_ptr())
     torch.cuda.synchronize()
     ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, 0)
-    ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 128)
+    ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 120)
     assert ctx.tc_get_option(tc.TC_INFO_ALLOCATIONS) == before
     # a split queue longer than the ring's (earlier tests may have grown
     # it) re-sizes the ring's queues in tc_set_option, not in renders

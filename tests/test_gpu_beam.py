@@ -157,6 +157,7 @@ def test_caves_and_touching_heights(ctx):
 def test_c2_view_and_read_count(ctx):
     """The 1920x1080 eye-level view: identical records with and without the
     beam; the beam reads far fewer nodes per ray."""
+    budget0 = ctx.tc_get_option(tc.TC_OPT_SPLIT_BUDGET)
     F, B, T = synth.make_map_from_config(2)
     views = synth.config_views(2, F, B)
     load(ctx, F, B, T)
@@ -172,7 +173,7 @@ def test_c2_view_and_read_count(ctx):
             assert_parity(wg, dg, wo, do, "c2 passes %d" % passes)
     finally:
         ctx.tc_set_option(tc.TC_OPT_COUNT_READS, 0)
-        ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 120)
+        ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, budget0)
     rays = synth.view_rays(views)
     print("reads per ray: no beam %.2f, beam %.2f" % (reads[0] / rays, reads[8] / rays))
     assert reads[8] < reads[0]

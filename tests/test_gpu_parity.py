@@ -133,6 +133,7 @@ def test_kernel_timing_leaves_results_unchanged(ctx):
     otherwise): results are the same bytes, times are positive, the split
     pass time is 0 when that pass is off, and reading before any timed
     render is an error."""
+    budget0 = ctx.tc_get_option(tc.TC_OPT_SPLIT_BUDGET)
     F, B, T = synth.make_map_from_config(2)
     load(ctx, F, B, T)
     views = synth.config_views(2, F, B)
@@ -154,7 +155,7 @@ def test_kernel_timing_leaves_results_unchanged(ctx):
             assert (t1 > 0) == (mode == "hier" and budget > 0), (mode, budget, t1)
     finally:
         ctx.tc_set_option(tc.TC_OPT_KERNEL_TIMING, 0)
-        ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 120)
+        ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, budget0)
         ctx.tc_set_option(tc.TC_OPT_INLINE_TABLES, 1)
         ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, 0)
 
@@ -274,6 +275,7 @@ def test_split_pass(ctx, budget, queue, waves):
     segment walks per wave, `waves` waves per ray; a tiny budget sends
     nearly every ray there, a tiny queue leaves the overflow to the first
     pass.  Results must not change."""
+    budget0 = ctx.tc_get_option(tc.TC_OPT_SPLIT_BUDGET)
     F, B, T = synth.make_map_from_config(1)
     load(ctx, F, B, T)
     rng = np.random.default_rng(13)
@@ -291,7 +293,7 @@ def test_split_pass(ctx, budget, queue, waves):
             assert_parity(wg, dg, wo, do, "split budget %d queue %d waves %d start %d" % (
                 budget, queue, waves, start))
     finally:
-        ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 120)
+        ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, budget0)
         ctx.tc_set_option(tc.TC_OPT_SPLIT_QUEUE, 1 << 17)
         ctx.tc_set_option(tc.TC_OPT_SPLIT_WAVES, 4)
         ctx.tc_set_option(tc.TC_OPT_TILE_ORDER, 2)
@@ -305,6 +307,7 @@ def test_inline_tables(ctx):
     budgets and queues (overflowing ones too), and calls too large to travel
     inline are interleaved over more calls than the ring has slots; every
     record equals the oracle's."""
+    budget0 = ctx.tc_get_option(tc.TC_OPT_SPLIT_BUDGET)
     F, B, T = synth.make_map_from_config(1)
     load(ctx, F, B, T)
     rng = np.random.default_rng(17)
@@ -326,7 +329,7 @@ def test_inline_tables(ctx):
                 k, inline, budget, queue, len(vs)))
     finally:
         ctx.tc_set_option(tc.TC_OPT_INLINE_TABLES, 1)
-        ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 120)
+        ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, budget0)
         ctx.tc_set_option(tc.TC_OPT_SPLIT_QUEUE, 1 << 17)
     for bad in (-1, 2):
         with pytest.raises(tc.TCError):
@@ -337,6 +340,7 @@ def test_inline_tables(ctx):
 def test_split_pass_edge_rays_and_large_map(ctx):
     """Split walks on rays from outside the map, along cell edges and over
     the 2048x2048 map's long horizon rays."""
+    budget0 = ctx.tc_get_option(tc.TC_OPT_SPLIT_BUDGET)
     F, B, T = synth.make_map(61, 45, 3, dual=0.35, period=16)
     load(ctx, F, B, T)
     views = [
@@ -361,7 +365,7 @@ def test_split_pass_edge_rays_and_large_map(ctx):
             wg, dg = gpu_render(ctx, v, "hier")
             assert_parity(wg, dg, wo, do, "split c2 budget %d waves %d" % (budget, waves))
     finally:
-        ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 120)
+        ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, budget0)
         ctx.tc_set_option(tc.TC_OPT_SPLIT_WAVES, 4)
 
 
@@ -686,6 +690,7 @@ def test_renders_allocate_nothing(ctx):
     """After tc_create and tc_load_columns, renders (split pass on and off,
     every exact mode), edits and shading make no device or pinned
     allocation: the staging ring and its split queues exist from the start."""
+    budget0 = ctx.tc_get_option(tc.TC_OPT_SPLIT_BUDGET)
     F, B, T = synth.make_map_from_config(2)
     load(ctx, F, B, T)
     views = synth.config_views(2, F, B)
@@ -705,7 +710,7 @@ def test_renders_allocate_nothing(ctx):
                                rgba.data_ptr())
     torch.cuda.synchronize()
     ctx.tc_set_option(tc.TC_OPT_RENDER_MODE, 0)
-    ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, 120)
+    ctx.tc_set_option(tc.TC_OPT_SPLIT_BUDGET, budget0)
     assert ctx.tc_get_option(tc.TC_INFO_ALLOCATIONS) == before
     # a split queue longer than the ring's (earlier tests may have grown
     # it) re-sizes the ring's queues in tc_set_option, not in renders
